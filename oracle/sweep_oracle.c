@@ -1,0 +1,498 @@
+/*
+ * Plain FP64 CPU oracle of the transport sweep (test infrastructure only).
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * use this file.  It shares no code with the GPU library.  Build:
+ *   gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ *
+ * What it computes (Peter et al. 2022, "The Sweep Method for radiative
+ * Transfer in Arepo"):
+ *
+ *  Orientation (sec. 2.5, appendix A): for direction Omega and the half-face f
+ *  of cell c with unit normal n (pointing out of c), s = (Ox nx + Oy ny) + Oz nz
+ *  in FP64 without contraction.  s > eps: outflow face (the neighbour is
+ *  downwind); s < -eps: inflow face (the neighbour is upwind); otherwise the
+ *  face carries no radiation in this direction.  w = A |s|.
+ *
+ *  Per-cell balance (transport scheme (a) of sec. 2.6 with a first-order
+ *  upwind closure): the cell emits through each outflow face i the share
+ *  A_i (n_i . Omega) / sum_j A_j (n_j . Omega) of its total outflow, i.e.
+ *  w_i phi_c, and
+ *      (Aperp_c + kappa_c V_c) phi_c = sum_{inflow faces} w_f phi_upwind + S_c,
+ *  Aperp_c = sum of w over outflow faces, S_c = L_c / D (+ scattering source).
+ *  Vacuum walls bring no inflow (sec. 2.5, fixed boundaries with I = 0).
+ *
+ *  Schedule (algorithm 2, single-core sweep): count the upwind dependencies of
+ *  every task, queue the tasks with none, then repeatedly take the first task
+ *  of the queue, solve it, decrement the counts of its downwind neighbours and
+ *  queue those reaching zero.  Tasks of different directions never interact,
+ *  so each direction gets its own FIFO (directions may run on separate
+ *  threads; results do not depend on it).  A task's level is 0 without
+ *  upwind tasks, else 1 + max level of its upwind tasks.
+ *
+ *  Periodic boundaries (sec. 2.7): faces with a non-zero image shift are cut
+ *  from the dependency graph; radiation leaving through them enters the
+ *  partner cell in the next pass (pass 0 starts from zero inflow).
+ *
+ *  Source iteration (sec. 2.3, algorithm 1) with isotropic scattering
+ *  (eq. radiativeTransfer): kappa is the extinction, kappa_s = a kappa,
+ *  kappa_a = (1-a) kappa; iteration i uses the source
+ *  S = L/D + kappa_s V sum_d' phi^{i-1}_{d'} / D, phi^{-1} = 0.
+ *
+ *  Outputs: J = (1/4pi) sum_d phi, absorbed = kappa_a V sum_d phi; totals per
+ *  group: [emitted, absorbed, escaped, periodic inflow, periodic outflow,
+ *  net scattering source, max E, L1 E] where E is the relative change of the
+ *  periodic inflow per cell between the last two passes (eq. relativeErrorPbc).
+ *
+ *  Adjoint: reverse sweep of the transposed system processed in the reverse
+ *  of the recorded queue order; the derivation is in the function comments.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_ERR_ARG -1
+#define ORC_ERR_CYCLE -2
+#define ORC_ERR_OOM -3
+#define ORC_ERR_UNSUPPORTED -6
+
+typedef struct {
+  int32_t n_cells;
+  const int64_t* face_ptr;
+  const int32_t* face_nbr;
+  const int8_t* face_shift; /* may be NULL */
+  const double* face_area;
+  const double* face_normal; /* 3 per face */
+  const double* cell_volume;
+} orc_mesh;
+
+static double orient(const double* om, const double* n) {
+  double a = om[0] * n[0];
+  double b = om[1] * n[1];
+  double c = om[2] * n[2];
+  return (a + b) + c;
+}
+
+/* face classes */
+#define F_NONE 0
+#define F_OUT 1
+#define F_IN 2
+
+static int face_class(double s, double eps) {
+  if (s > eps) return F_OUT;
+  if (s < -eps) return F_IN;
+  return F_NONE;
+}
+
+static int is_periodic_face(const orc_mesh* m, int64_t f) {
+  return m->face_shift != NULL && m->face_shift[f] != 0;
+}
+
+/* in-graph upwind dependency: interior (non-periodic) inflow face */
+static int upwind_count(const orc_mesh* m, const double* om, double eps, int32_t c) {
+  int n = 0;
+  for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
+    if (m->face_nbr[f] < 0 || is_periodic_face(m, f)) continue;
+    if (face_class(orient(om, m->face_normal + 3 * f), eps) == F_IN) ++n;
+  }
+  return n;
+}
+
+/* Kahn/FIFO traversal of one direction: fills the processing order and levels.
+ * Returns the number of processed tasks. */
+static int32_t fifo_order(const orc_mesh* m, const double* om, double eps, int32_t* cnt,
+                          int32_t* queue, int32_t* level) {
+  const int32_t C = m->n_cells;
+  int32_t head = 0, tail = 0;
+  for (int32_t c = 0; c < C; ++c) {
+    cnt[c] = upwind_count(m, om, eps, c);
+    level[c] = 0;
+    if (cnt[c] == 0) queue[tail++] = c;
+  }
+  while (head < tail) {
+    const int32_t c = queue[head++];
+    for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
+      const int32_t nb = m->face_nbr[f];
+      if (nb < 0 || is_periodic_face(m, f)) continue;
+      if (face_class(orient(om, m->face_normal + 3 * f), eps) != F_OUT) continue;
+      if (level[nb] < level[c] + 1) level[nb] = level[c] + 1;
+      if (--cnt[nb] == 0) queue[tail++] = nb;
+    }
+  }
+  return head;
+}
+
+/* ------------------------------------------------------------------ DAG */
+/* level, indeg: [D][C]; order: [D][C] cells of each direction sorted by (level, c);
+ * depth: [D].  Returns ORC_ERR_CYCLE if some direction cannot be fully ordered. */
+int orc_build_dag(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t* level,
+                  int32_t* order, int32_t* indeg, int32_t* depth) {
+  const int32_t C = m->n_cells;
+  int status = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t d = 0; d < D; ++d) {
+    const double* om = dirs + 3 * d;
+    int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+    int32_t* lv = level + (int64_t)d * C;
+    for (int32_t c = 0; c < C; ++c) indeg[(int64_t)d * C + c] = upwind_count(m, om, eps, c);
+    int32_t done = fifo_order(m, om, eps, cnt, q, lv);
+    if (done != C) {
+#pragma omp critical
+      status = ORC_ERR_CYCLE;
+    } else {
+      /* counting sort by level, stable in c */
+      int32_t L = 0;
+      for (int32_t c = 0; c < C; ++c)
+        if (lv[c] + 1 > L) L = lv[c] + 1;
+      int32_t* ptr = (int32_t*)calloc((size_t)L + 1, sizeof(int32_t));
+      for (int32_t c = 0; c < C; ++c) ptr[lv[c] + 1]++;
+      for (int32_t l = 0; l < L; ++l) ptr[l + 1] += ptr[l];
+      int32_t* o = order + (int64_t)d * C;
+      for (int32_t c = 0; c < C; ++c) o[ptr[lv[c]]++] = c;
+      free(ptr);
+      depth[d] = L;
+    }
+    free(cnt);
+    free(q);
+  }
+  return status;
+}
+
+/* ------------------------------------------------------------------ forward */
+/* One sweep of one direction over all groups.
+ *   src:  [C][G] source per task of this direction (already divided by D)
+ *   prev: [C][G] phi of this direction in the previous periodic pass (NULL: zero)
+ *   phi:  [C][G] output
+ *   acc:  [G][4] += escaped, periodic inflow, periodic outflow (FP64)
+ *   jin:  [C][G] += periodic inflow into each cell (may be NULL)
+ *   qorder: [C] processing order (output, may be NULL) */
+static int sweep_direction(const orc_mesh* m, const double* om, double eps, int32_t G,
+                           const double* kappa, const double* src, const double* prev,
+                           double* phi, double* acc, double* jin, int32_t* cnt, int32_t* queue,
+                           int32_t* lvl, int32_t* qorder) {
+  const int32_t C = m->n_cells;
+  double* nin = (double*)malloc(sizeof(double) * (size_t)G);
+  int32_t head = 0, tail = 0;
+  for (int32_t c = 0; c < C; ++c) {
+    cnt[c] = upwind_count(m, om, eps, c);
+    if (cnt[c] == 0) queue[tail++] = c;
+  }
+  (void)lvl;
+  while (head < tail) {
+    const int32_t c = queue[head++];
+    if (qorder) qorder[head - 1] = c;
+    /* solve the task: gather inflow in face order */
+    double aperp = 0.0;
+    for (int32_t g = 0; g < G; ++g) nin[g] = 0.0;
+    for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
+      const double s = orient(om, m->face_normal + 3 * f);
+      const int k = face_class(s, eps);
+      const double w = m->face_area[f] * fabs(s);
+      if (k == F_OUT) {
+        aperp += w;
+      } else if (k == F_IN && m->face_nbr[f] >= 0) {
+        const int32_t nb = m->face_nbr[f];
+        if (is_periodic_face(m, f)) {
+          if (prev)
+            for (int32_t g = 0; g < G; ++g) {
+              const double in = w * prev[(int64_t)nb * G + g];
+              nin[g] += in;
+              acc[4 * g + 1] += in;
+              if (jin) jin[(int64_t)c * G + g] += in;
+            }
+        } else {
+          for (int32_t g = 0; g < G; ++g) nin[g] += w * phi[(int64_t)nb * G + g];
+        }
+      }
+    }
+    for (int32_t g = 0; g < G; ++g) {
+      const double den = aperp + kappa[(int64_t)c * G + g] * m->cell_volume[c];
+      if (!(den > 0.0)) {
+        free(nin);
+        return ORC_ERR_ARG;
+      }
+      phi[(int64_t)c * G + g] = (nin[g] + src[(int64_t)c * G + g]) / den;
+    }
+    /* outflow: boundaries and downwind neighbours */
+    for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
+      const double s = orient(om, m->face_normal + 3 * f);
+      if (face_class(s, eps) != F_OUT) continue;
+      const double w = m->face_area[f] * fabs(s);
+      const int32_t nb = m->face_nbr[f];
+      if (nb < 0) {
+        for (int32_t g = 0; g < G; ++g) acc[4 * g + 0] += w * phi[(int64_t)c * G + g];
+      } else if (is_periodic_face(m, f)) {
+        for (int32_t g = 0; g < G; ++g) acc[4 * g + 2] += w * phi[(int64_t)c * G + g];
+      } else if (--cnt[nb] == 0) {
+        queue[tail++] = nb;
+      }
+    }
+  }
+  free(nin);
+  return head == C ? ORC_OK : ORC_ERR_CYCLE;
+}
+
+/* Forward sweep with periodic passes and source iteration.
+ *   kappa, emission, J, absorbed: [C][G]
+ *   totals: [G][8]
+ *   phi_out: [D][C][G] phi of the final pass (may be NULL)
+ *   jsum_ckpt: [n_scat][C][G] sum_d phi of every iteration's final pass (may be NULL)
+ *   qorder: [D][C] FIFO processing order of every direction (may be NULL) */
+int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
+                const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
+                double albedo, int32_t n_scat, double* J, double* absorbed, double* totals,
+                double* phi_out, double* jsum_ckpt, int32_t* qorder) {
+  const int32_t C = m->n_cells;
+  const int64_t CG = (int64_t)C * G;
+  if (D < 1 || G < 1 || n_pbc < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
+  if (!periodic) n_pbc = 1;
+  double* phi = (double*)calloc((size_t)(D * CG), sizeof(double));
+  double* phiprev = (double*)calloc((size_t)(D * CG), sizeof(double));
+  double* jsum = (double*)calloc((size_t)CG, sizeof(double));     /* sum_d phi, current */
+  double* jsum_old = (double*)calloc((size_t)CG, sizeof(double)); /* previous iteration */
+  double* src = (double*)calloc((size_t)CG, sizeof(double));
+  double* jin = (double*)calloc((size_t)(D * CG), sizeof(double));
+  double* jin_old = (double*)calloc((size_t)CG, sizeof(double));
+  double* accd = (double*)calloc((size_t)D * 4 * G, sizeof(double));
+  if (!phi || !phiprev || !jsum || !jsum_old || !src || !jin || !jin_old || !accd) return ORC_ERR_OOM;
+  int status = ORC_OK;
+  for (int32_t it = 0; it < n_scat && status == ORC_OK; ++it) {
+    /* source of this iteration */
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t g = 0; g < G; ++g) {
+        const int64_t i = (int64_t)c * G + g;
+        const double ks = albedo * kappa[i];
+        src[i] = emission[i] / D + ks * m->cell_volume[c] * jsum_old[i] / D;
+      }
+    memset(phiprev, 0, sizeof(double) * (size_t)(D * CG));
+    for (int32_t p = 0; p < n_pbc && status == ORC_OK; ++p) {
+      /* keep the previous pass's per-cell periodic inflow for E */
+      if (p > 0) {
+        for (int64_t i = 0; i < CG; ++i) {
+          double s = 0.0;
+          for (int32_t d = 0; d < D; ++d) s += jin[(int64_t)d * CG + i];
+          jin_old[i] = s;
+        }
+      }
+      memset(jin, 0, sizeof(double) * (size_t)(D * CG));
+      memset(accd, 0, sizeof(double) * (size_t)D * 4 * G);
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int32_t d = 0; d < D; ++d) {
+        int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+        int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+        int st = sweep_direction(m, dirs + 3 * d, eps, G, kappa, src,
+                                 (periodic && p > 0) ? phiprev + (int64_t)d * CG : NULL,
+                                 phi + (int64_t)d * CG, accd + (int64_t)d * 4 * G,
+                                 jin + (int64_t)d * CG, cnt, q, NULL,
+                                 qorder ? qorder + (int64_t)d * C : NULL);
+        if (st != ORC_OK) {
+#pragma omp critical
+          status = st;
+        }
+        free(cnt);
+        free(q);
+      }
+      if (status != ORC_OK) break;
+      if (p + 1 < n_pbc) memcpy(phiprev, phi, sizeof(double) * (size_t)(D * CG));
+    }
+    if (status != ORC_OK) break;
+    /* direction sum in ascending d */
+    for (int64_t i = 0; i < CG; ++i) {
+      double s = 0.0;
+      for (int32_t d = 0; d < D; ++d) s += phi[(int64_t)d * CG + i];
+      jsum[i] = s;
+    }
+    if (jsum_ckpt) memcpy(jsum_ckpt + (int64_t)it * CG, jsum, sizeof(double) * (size_t)CG);
+    if (it + 1 < n_scat) memcpy(jsum_old, jsum, sizeof(double) * (size_t)CG);
+  }
+  if (status == ORC_OK) {
+    for (int32_t g = 0; g < G; ++g)
+      for (int k = 0; k < 8; ++k) totals[8 * g + k] = 0.0;
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t g = 0; g < G; ++g) {
+        const int64_t i = (int64_t)c * G + g;
+        const double V = m->cell_volume[c];
+        const double ka = (1.0 - albedo) * kappa[i];
+        const double ks = albedo * kappa[i];
+        J[i] = jsum[i] / (4.0 * M_PI);
+        absorbed[i] = ka * V * jsum[i];
+        totals[8 * g + 0] += emission[i];
+        totals[8 * g + 1] += absorbed[i];
+        /* net scattering source of the last iteration: scattered in - scattered out */
+        totals[8 * g + 5] += ks * V * (n_scat > 1 ? jsum_old[i] : 0.0) - ks * V * jsum[i];
+        /* periodic-inflow change between the last two passes */
+        double jn = 0.0;
+        for (int32_t d = 0; d < D; ++d) jn += jin[(int64_t)d * CG + i];
+        const double jo = jin_old[i];
+        if (periodic && n_pbc > 1 && jn + jo > 0.0) {
+          const double e = fabs(jn - jo) / (jn + jo);
+          if (e > totals[8 * g + 6]) totals[8 * g + 6] = e;
+        }
+        totals[8 * g + 7] += fabs(jn - jo);
+        jin_old[i] = jn + jo; /* reuse as denominator accumulator */
+      }
+    for (int32_t g = 0; g < G; ++g) {
+      double den = 0.0;
+      for (int32_t c = 0; c < C; ++c) den += jin_old[(int64_t)c * G + g];
+      totals[8 * g + 7] = (periodic && n_pbc > 1 && den > 0.0) ? totals[8 * g + 7] / den : 0.0;
+      for (int32_t d = 0; d < D; ++d) {
+        totals[8 * g + 2] += accd[(int64_t)d * 4 * G + 4 * g + 0];
+        totals[8 * g + 3] += accd[(int64_t)d * 4 * G + 4 * g + 1];
+        totals[8 * g + 4] += accd[(int64_t)d * 4 * G + 4 * g + 2];
+      }
+    }
+    if (phi_out) memcpy(phi_out, phi, sizeof(double) * (size_t)(D * CG));
+  }
+  free(phi);
+  free(phiprev);
+  free(jsum);
+  free(jsum_old);
+  free(src);
+  free(jin);
+  free(jin_old);
+  free(accd);
+  return status;
+}
+
+/* ------------------------------------------------------------------ adjoint */
+/* Reverse sweep of one direction: solves M^T lambda = g with
+ * M = diag(Aperp + kappa V) - W (W[c][u] = w of the inflow face of c from u):
+ *   lambda_c = (g_c + sum_{outflow faces to interior e} w lambda_e) / (Aperp_c + kappa_c V_c),
+ * visiting the cells in the reverse of the forward queue order, so every
+ * downwind lambda is final before it is read. */
+static void adjoint_direction(const orc_mesh* m, const double* om, double eps, int32_t G,
+                              const double* kappa, const double* g, const int32_t* qorder,
+                              double* lam) {
+  const int32_t C = m->n_cells;
+  for (int32_t k = C - 1; k >= 0; --k) {
+    const int32_t c = qorder[k];
+    double aperp = 0.0;
+    for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
+      const double s = orient(om, m->face_normal + 3 * f);
+      if (face_class(s, eps) == F_OUT) aperp += m->face_area[f] * fabs(s);
+    }
+    for (int32_t gg = 0; gg < G; ++gg) {
+      double acc = g[(int64_t)c * G + gg];
+      for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
+        const double s = orient(om, m->face_normal + 3 * f);
+        const int32_t nb = m->face_nbr[f];
+        if (face_class(s, eps) != F_OUT || nb < 0 || is_periodic_face(m, f)) continue;
+        acc += m->face_area[f] * fabs(s) * lam[(int64_t)nb * G + gg];
+      }
+      lam[(int64_t)c * G + gg] = acc / (aperp + kappa[(int64_t)c * G + gg] * m->cell_volume[c]);
+    }
+  }
+}
+
+/* Gradients of a loss L(J, absorbed) given gJ = dL/dJ and gA = dL/dabsorbed ([C][G]).
+ *
+ * Without scattering (one iteration): dL/dphi_{c,d} = gJ_c/(4pi) + gA_c kappa_a,c V_c =: g_c,
+ *   lambda_d = M_d^{-T} g, dL/dL_c = sum_d lambda_{c,d}/D,
+ *   dL/dkappa_c = gA_c (1-a) V_c sum_d phi_{c,d} - V_c sum_d lambda_{c,d} phi_{c,d}.
+ * With source iteration (iterations i = 0..n-1, outputs from the last):
+ *   lambda^{n-1} from g as above; lambda^{i-1}_d = M_d^{-T} g^{i-1} with
+ *   g^{i-1}_c = a kappa_c V_c (sum_d lambda^i_{c,d}) / D;
+ *   dL/dL_c = sum_i sum_d lambda^i_{c,d} / D;
+ *   dL/dkappa_c = gA_c (1-a) V_c sum_d phi^{n-1}_{c,d}
+ *     + sum_i [ -V_c sum_d lambda^i_{c,d} phi^i_{c,d}
+ *               + a V_c (sum_d lambda^i_{c,d}) (sum_d' phi^{i-1}_{c,d'}) / D ],  phi^{-1} = 0.
+ * phi^i is recomputed from the stored direction sums of iteration i-1.
+ * Periodic boundaries are not supported (returns ORC_ERR_UNSUPPORTED). */
+int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
+                const double* kappa, const double* emission, int32_t periodic, double albedo,
+                int32_t n_scat, const double* gJ, const double* gA, double* dkappa,
+                double* demission) {
+  if (periodic) return ORC_ERR_UNSUPPORTED;
+  if (D < 1 || G < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
+  const int32_t C = m->n_cells;
+  const int64_t CG = (int64_t)C * G;
+  double* J = (double*)malloc(sizeof(double) * (size_t)CG);
+  double* Ab = (double*)malloc(sizeof(double) * (size_t)CG);
+  double tot[8 * 64];
+  double* tots = G <= 64 ? tot : (double*)malloc(sizeof(double) * 8 * (size_t)G);
+  double* jsum = (double*)malloc(sizeof(double) * (size_t)(n_scat * CG));
+  double* phi = (double*)malloc(sizeof(double) * (size_t)(D * CG));
+  double* lam = (double*)malloc(sizeof(double) * (size_t)(D * CG));
+  double* gsrc = (double*)malloc(sizeof(double) * (size_t)CG);
+  double* src = (double*)malloc(sizeof(double) * (size_t)CG);
+  double* lsum = (double*)malloc(sizeof(double) * (size_t)CG);
+  int32_t* qorder = (int32_t*)malloc(sizeof(int32_t) * (size_t)D * C);
+  if (!J || !Ab || !tots || !jsum || !phi || !lam || !gsrc || !src || !lsum || !qorder) return ORC_ERR_OOM;
+  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, J, Ab, tots,
+                           NULL, jsum, NULL);
+  if (status == ORC_OK) {
+    memset(dkappa, 0, sizeof(double) * (size_t)CG);
+    memset(demission, 0, sizeof(double) * (size_t)CG);
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t g = 0; g < G; ++g) {
+        const int64_t i = (int64_t)c * G + g;
+        const double V = m->cell_volume[c];
+        gsrc[i] = gJ[i] / (4.0 * M_PI) + gA[i] * (1.0 - albedo) * kappa[i] * V;
+        dkappa[i] += gA[i] * (1.0 - albedo) * V * jsum[(int64_t)(n_scat - 1) * CG + i];
+      }
+    for (int32_t it = n_scat - 1; it >= 0 && status == ORC_OK; --it) {
+      /* recompute phi^it from the direction sums of iteration it-1 */
+      for (int32_t c = 0; c < C; ++c)
+        for (int32_t g = 0; g < G; ++g) {
+          const int64_t i = (int64_t)c * G + g;
+          const double prev = it > 0 ? jsum[(int64_t)(it - 1) * CG + i] : 0.0;
+          src[i] = emission[i] / D + albedo * kappa[i] * m->cell_volume[c] * prev / D;
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int32_t d = 0; d < D; ++d) {
+        int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+        int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+        double acc[4 * 64];
+        double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
+        memset(a4, 0, sizeof(double) * 4 * (size_t)G);
+        int st = sweep_direction(m, dirs + 3 * d, eps, G, kappa, src, NULL, phi + (int64_t)d * CG,
+                                 a4, NULL, cnt, q, NULL, qorder + (int64_t)d * C);
+        if (st == ORC_OK)
+          adjoint_direction(m, dirs + 3 * d, eps, G, kappa, gsrc, qorder + (int64_t)d * C,
+                            lam + (int64_t)d * CG);
+        else {
+#pragma omp critical
+          status = st;
+        }
+        if (a4 != acc) free(a4);
+        free(cnt);
+        free(q);
+      }
+      if (status != ORC_OK) break;
+      for (int32_t c = 0; c < C; ++c)
+        for (int32_t g = 0; g < G; ++g) {
+          const int64_t i = (int64_t)c * G + g;
+          const double V = m->cell_volume[c];
+          double ls = 0.0, lp = 0.0;
+          for (int32_t d = 0; d < D; ++d) {
+            ls += lam[(int64_t)d * CG + i];
+            lp += lam[(int64_t)d * CG + i] * phi[(int64_t)d * CG + i];
+          }
+          const double prev = it > 0 ? jsum[(int64_t)(it - 1) * CG + i] : 0.0;
+          demission[i] += ls / D;
+          dkappa[i] += -V * lp + albedo * V * ls * prev / D;
+          lsum[i] = ls;
+        }
+      /* adjoint source of the previous iteration */
+      for (int32_t c = 0; c < C; ++c)
+        for (int32_t g = 0; g < G; ++g) {
+          const int64_t i = (int64_t)c * G + g;
+          gsrc[i] = albedo * kappa[i] * m->cell_volume[c] * lsum[i] / D;
+        }
+    }
+  }
+  free(J);
+  free(Ab);
+  if (tots != tot) free(tots);
+  free(jsum);
+  free(phi);
+  free(lam);
+  free(gsrc);
+  free(src);
+  free(lsum);
+  free(qorder);
+  return status;
+}

@@ -1,0 +1,150 @@
+"""Dense direct solves of the discretised transport equations (test helper).
+
+Independent of the oracle's sweep: the per-direction system is assembled as a
+matrix straight from the face list and solved with numpy.linalg.solve, with no
+dependency graph, ordering or queue.  For direction Omega (sec. 2.5/2.6):
+
+    (Aperp_c + kappa_c V_c) phi_c - sum_{inflow faces f of c} A_f |n_f . Omega| phi_nbr(f) = S_c
+
+cyclic=True also couples the periodic faces, giving the fixed point of the
+periodic-boundary passes (sec. 2.7).  `dense_scatter_system` couples all
+directions through the isotropic scattering term of eq. radiativeTransfer, giving
+the fixed point of source iteration (algorithm 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+EPS = 1e-12
+
+
+def _faces(mesh):
+    fp = mesh["face_ptr"]
+    owner = np.repeat(np.arange(len(fp) - 1), np.diff(fp))
+    periodic = bool(mesh.get("periodic"))
+    shift = mesh["face_shift"] if periodic else np.zeros(len(owner), np.int8)
+    return owner, mesh["face_nbr"], shift, mesh["face_area"], mesh["face_normal"]
+
+
+def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS):
+    """M (C x C) and the outflow weights of walls / periodic faces for one direction."""
+    owner, nbr, shift, area, normal = _faces(mesh)
+    C = len(mesh["cell_volume"])
+    s = normal @ np.asarray(omega, np.float64)
+    w = area * np.abs(s)
+    out = s > eps
+    inn = s < -eps
+    aperp = np.bincount(owner[out], weights=w[out], minlength=C)
+    M = np.diag(aperp + kappa * mesh["cell_volume"])
+    interior = nbr >= 0
+    per = shift != 0
+    use = inn & interior & ((~per) | cyclic)
+    np.add.at(M, (owner[use], nbr[use]), -w[use])
+    wall_out = np.bincount(owner[out & ~interior], weights=w[out & ~interior], minlength=C)
+    per_out = np.bincount(owner[out & interior & per], weights=w[out & interior & per], minlength=C)
+    return M, wall_out, per_out
+
+
+def dense_forward(w, cyclic=False):
+    """phi [D,C,G] per mesh, J, absorbed and (emitted, absorbed, escaped) per mesh/group."""
+    dirs = w["dirs"]
+    G = w["G"]
+    kap = np.asarray(w["kappa"], np.float64)
+    em = np.asarray(w["emission"], np.float64)
+    D = len(dirs)
+    off = 0
+    Js, As, tots, phis = [], [], [], []
+    for mesh in w["meshes"]:
+        C = len(mesh["cell_volume"])
+        k = kap[off:off + C]
+        e = em[off:off + C]
+        phi = np.zeros((D, C, G))
+        esc = np.zeros(G)
+        for d in range(D):
+            for g in range(G):
+                M, wall, _ = direction_matrix(mesh, dirs[d], k[:, g], cyclic)
+                phi[d, :, g] = np.linalg.solve(M, e[:, g] / D)
+                esc[g] += wall @ phi[d, :, g]
+        js = phi.sum(axis=0)
+        J = js / (4 * np.pi)
+        A = k * mesh["cell_volume"][:, None] * js
+        Js.append(J)
+        As.append(A)
+        tots.append(np.stack([e.sum(axis=0), A.sum(axis=0), esc], axis=1))
+        phis.append(phi)
+        off += C
+    return dict(J=np.concatenate(Js), absorbed=np.concatenate(As), totals=np.stack(tots), phi=phis)
+
+
+def dense_scatter_system(w):
+    """Fixed point of source iteration: all D directions solved together for one mesh, one group.
+
+    Unknowns phi[d,c]; equations M_d phi_d - (a kappa V / D) sum_d' phi_d' = L / D."""
+    (mesh,) = w["meshes"]
+    dirs = w["dirs"]
+    D = len(dirs)
+    C = len(mesh["cell_volume"])
+    k = np.asarray(w["kappa"], np.float64)[:, 0]
+    L = np.asarray(w["emission"], np.float64)[:, 0]
+    a = w["albedo"]
+    V = mesh["cell_volume"]
+    big = np.zeros((D * C, D * C))
+    for d in range(D):
+        M, _, _ = direction_matrix(mesh, dirs[d], k)
+        big[d * C:(d + 1) * C, d * C:(d + 1) * C] += M
+        for d2 in range(D):
+            big[d * C:(d + 1) * C, d2 * C:(d2 + 1) * C] -= np.diag(a * k * V / D)
+    phi = np.linalg.solve(big, np.tile(L / D, D)).reshape(D, C)
+    return phi
+
+
+def dense_adjoint(w, gJ, gA):
+    """Gradients of L(J, absorbed) for one group, no scattering, vacuum: explicit matrices."""
+    dirs = w["dirs"]
+    G = w["G"]
+    kap = np.asarray(w["kappa"], np.float64)
+    em = np.asarray(w["emission"], np.float64)
+    D = len(dirs)
+    off = 0
+    dk_all, de_all = [], []
+    for mesh in w["meshes"]:
+        C = len(mesh["cell_volume"])
+        V = mesh["cell_volume"]
+        dk = np.zeros((C, G))
+        de = np.zeros((C, G))
+        for g in range(G):
+            k = kap[off:off + C, g]
+            e = em[off:off + C, g]
+            gj = gJ[off:off + C, g]
+            ga = gA[off:off + C, g]
+            gphi = gj / (4 * np.pi) + ga * k * V
+            jsum = np.zeros(C)
+            for d in range(D):
+                M, _, _ = direction_matrix(mesh, dirs[d], k)
+                phi = np.linalg.solve(M, e / D)
+                lam = np.linalg.solve(M.T, gphi)
+                jsum += phi
+                de[:, g] += lam / D
+                dk[:, g] -= V * lam * phi
+            dk[:, g] += ga * V * jsum
+        dk_all.append(dk)
+        de_all.append(de)
+        off += C
+    return np.concatenate(dk_all), np.concatenate(de_all)
+
+
+def brute_levels(mesh, omega, eps=EPS):
+    """Longest-path levels by repeated relaxation over the edge list (no queue)."""
+    owner, nbr, shift, area, normal = _faces(mesh)
+    C = len(mesh["cell_volume"])
+    s = normal @ np.asarray(omega, np.float64)
+    e = (s > eps) & (nbr >= 0) & (shift == 0)
+    src, dst = owner[e], nbr[e]
+    level = np.zeros(C, np.int64)
+    for _ in range(C + 1):
+        new = level.copy()
+        np.maximum.at(new, dst, level[src] + 1)
+        if np.array_equal(new, level):
+            return level, src, dst
+        level = new
+    raise RuntimeError("cyclic")

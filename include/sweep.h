@@ -1,0 +1,190 @@
+/*
+ * sweep.h -- C ABI of the MI355X (gfx950) transport-sweep library.
+ *
+ * The library solves the discrete-ordinates form of the steady radiative
+ * transfer equation with isotropic scattering (Peter et al. 2022, "The Sweep
+ * Method for radiative Transfer in Arepo", eq. radiativeTransfer of sec. 2.2)
+ * on Voronoi grids by transport sweeps (sec. 2.3-2.5):
+ *
+ *   - a task is a (cell, direction) pair and is solved for all frequency groups
+ *     at once (sec. 2.5);
+ *   - for direction Omega the half-face f of cell c with unit normal n_f
+ *     (outward, n = (p'-p)/|p'-p| on Voronoi grids, appendix A) is an outflow
+ *     face if s = Omega.n_f > eps_tie, an inflow face if s < -eps_tie, and
+ *     carries nothing otherwise; its weight is w = A_f |s|;
+ *   - the inflow faces with an interior (non-periodic) neighbour define the
+ *     per-direction dependency graph, acyclic on Voronoi grids (appendix A);
+ *   - each task solves the first-order upwind balance of transport scheme (a)
+ *     (sec. 2.6): the cell's outflow is split over its outflow faces in
+ *     proportion to A_i (n_i . Omega), so with Aperp = sum of outflow w
+ *        (Aperp + kappa V) phi = sum_{inflow f} w_f phi_upwind(f) + S,
+ *     S = L/D + kappa_s V sum_d' phi_prev(d') / D  (source iteration, alg. 1);
+ *   - periodic faces (non-zero image shift) are cut from the graph; what leaves
+ *     through them re-enters the partner cell in the next pass (sec. 2.7).
+ *
+ * phi is the intensity integrated over the direction's solid angle 4 pi / D
+ * (photons/s per unit area).  Outputs per cell and group:
+ *   J = (1/4pi) sum_d phi          absorbed = kappa_a V sum_d phi
+ * with kappa_a = (1 - albedo) kappa, kappa being the extinction coefficient.
+ *
+ * Conventions for every call:
+ *   - every function returns sweep_status_t; on failure sweep_last_error()
+ *     returns a thread-local message; no exception or abort crosses the ABI;
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory;
+ *   - per-cell-per-group arrays are cell-major with the G groups contiguous
+ *     ([C_total][G], row-major), cells of all meshes concatenated in mesh
+ *     order (global cell id = mesh offset + local id);
+ *   - work is enqueued on the caller's `stream` (a hipStream_t, NULL = null
+ *     stream); only sweep_build_dag, sweep_dag_info and sweep_dag_export
+ *     synchronise that stream;
+ *   - the caller owns every array argument and output; outputs are fully
+ *     overwritten; the library owns the DAG object and its internal buffers.
+ */
+#ifndef SWEEP_H_
+#define SWEEP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SWEEP_OK = 0,
+  SWEEP_ERR_INVALID_ARG = -1, /* bad argument or malformed mesh */
+  SWEEP_ERR_CYCLE = -2,       /* a dependency graph is cyclic (no topological order) */
+  SWEEP_ERR_OOM = -3,         /* device allocation failed */
+  SWEEP_ERR_HIP = -4,         /* a HIP runtime call failed */
+  SWEEP_ERR_NOT_BUILT = -5,   /* NULL or destroyed DAG handle */
+  SWEEP_ERR_UNSUPPORTED = -6  /* valid request that this library does not implement */
+} sweep_status_t;
+
+/* Number of FP64 totals per (mesh, group), see sweep_forward. */
+#define SWEEP_N_TOTALS 8
+
+/* One Voronoi grid.  All pointers are DEVICE pointers and must stay valid
+ * for the duration of sweep_build_dag only (the DAG keeps what it needs). */
+typedef struct {
+  int32_t n_cells;
+  int64_t n_half_faces;
+  const int64_t* face_ptr;    /* [n_cells+1] CSR offsets of each cell's half-faces */
+  const int32_t* face_nbr;    /* [n_half_faces] neighbour cell (local id), -1 = vacuum wall */
+  const int32_t* face_twin;   /* [n_half_faces] matching half-face of the neighbour, -1 for
+                                 walls; used only by validation, may be NULL */
+  const int8_t* face_shift;   /* [n_half_faces] periodic image code, 0 = none; NULL = no
+                                 periodic faces */
+  const double* face_area;    /* [n_half_faces] */
+  const double* face_normal;  /* [3*n_half_faces] unit normal, outward from the owner */
+  const double* cell_volume;  /* [n_cells] */
+} sweep_mesh_t;
+
+typedef struct {
+  double eps_tie;   /* |Omega.n| <= eps_tie: the face carries nothing (default 1e-12) */
+  int32_t validate; /* 1: check the mesh and directions on the host first (default 1) */
+  int32_t reserved[7];
+} sweep_build_opts_t;
+
+/* Opaque handle of a built set of per-direction dependency graphs. */
+typedef struct sweep_dag_s* sweep_dag_t;
+
+typedef struct {
+  int32_t n_meshes;
+  int32_t n_dirs;
+  int64_t n_cells;        /* all meshes */
+  int64_t n_tasks;        /* n_cells * n_dirs */
+  int64_t n_up_entries;   /* inflow-face entries (graph edges + periodic inflows) */
+  int64_t n_down_entries; /* graph edges seen from the upwind side */
+  int32_t max_depth;      /* longest critical path (levels) over all (mesh, direction) */
+  int32_t min_depth;
+  double mean_depth;
+  int64_t device_bytes;   /* bytes held by the DAG */
+} sweep_dag_info_t;
+
+enum { SWEEP_BOUNDARY_VACUUM = 0, SWEEP_BOUNDARY_PERIODIC = 1 };
+enum { SWEEP_FORM_BATCHED = 0, SWEEP_FORM_PLAIN = 1 };
+
+typedef struct {
+  int32_t boundary;  /* SWEEP_BOUNDARY_*; PERIODIC requires the meshes' face_shift */
+  int32_t n_pbc;     /* periodic passes (>= 1); pass 0 starts from zero inflow */
+  double albedo;     /* kappa_s / kappa in [0, 1) */
+  int32_t n_scat;    /* source iterations (>= 1), starting from J = 0 */
+  int32_t form;      /* SWEEP_FORM_BATCHED: every (mesh, direction) in one launch per pass;
+                        SWEEP_FORM_PLAIN: one launch per (mesh, direction, group) */
+  int32_t block;     /* threads per workgroup of the sweep kernels, 0 = tuned default */
+  int32_t ring;      /* LDS ring capacity in tasks (power of two), 0 = tuned default */
+  int32_t use_graph; /* 1: replay the pass sequence as a captured hipGraph */
+  int32_t reserved[5];
+} sweep_fwd_opts_t;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* sweep_last_error(void);
+
+/* Build the dependency graphs of `n_meshes` meshes for `n_dirs` directions
+ * (algorithm 2's upwind counts, sec. 2.5; levels by Kahn's algorithm).
+ *   meshes: HOST array of n_meshes descriptors (their arrays on the device)
+ *   dirs:   HOST [n_dirs*3] unit vectors (FP64); every direction owns 4pi/n_dirs
+ *   opts:   may be NULL for defaults
+ * Synchronises `stream` once.  Errors: INVALID_ARG (validation), CYCLE, OOM, HIP. */
+sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, const double* dirs,
+                               int32_t n_dirs, const sweep_build_opts_t* opts, void* stream,
+                               sweep_dag_t* out);
+
+/* Release the DAG and its device buffers (NULL is ignored). */
+sweep_status_t sweep_destroy_dag(sweep_dag_t dag);
+
+/* Sizes and critical-path statistics (host struct). */
+sweep_status_t sweep_dag_info(sweep_dag_t dag, sweep_dag_info_t* info);
+
+/* Copy the graphs to HOST buffers of n_dirs * n_cells int32 each, laid out
+ * [mesh][direction][local cell] (tasks of mesh m start at n_dirs * mesh offset):
+ *   level: longest-path level of every task (0 = no upwind dependency);
+ *   order: the cells of each (mesh, direction) sorted by (level, cell id);
+ *   indeg: number of upwind (graph) dependencies of every task.
+ * Any pointer may be NULL.  Synchronises `stream`. */
+sweep_status_t sweep_dag_export(sweep_dag_t dag, int32_t* level, int32_t* order, int32_t* indeg,
+                                void* stream);
+
+/* Bytes of the `saved` workspace sweep_forward fills for sweep_adjoint:
+ * phi of the final pass ([n_dirs][C_total][G] FP32) followed by the direction
+ * sums sum_d phi of every source iteration ([n_scat][C_total][G] FP32). */
+size_t sweep_saved_bytes(sweep_dag_t dag, int32_t G, const sweep_fwd_opts_t* opts);
+
+/* Forward sweep: n_scat source iterations, each made of n_pbc passes (vacuum:
+ * one pass) over every (mesh, direction), groups packed per task.
+ *   kappa, emission: DEVICE [C_total][G] FP32, extinction (>= 0) and isotropic
+ *                    luminosity (>= 0, photons/s) per cell
+ *   J, absorbed:     DEVICE [C_total][G] FP32 outputs of the final pass
+ *   totals:          DEVICE [n_meshes][G][8] FP64 outputs of the final pass:
+ *                    emitted, absorbed, escaped through vacuum walls, periodic
+ *                    inflow, periodic outflow, net scattering source (scattered
+ *                    in from the previous iteration minus scattered out), max over
+ *                    cells of E = |j_n - j_{n-1}|/(j_n + j_{n-1}) on the per-cell
+ *                    periodic inflow j of the last two passes (eq. relativeErrorPbc),
+ *                    and the L1 form of E; balance:
+ *                    emitted + pbc_in + scat_net = absorbed + escaped + pbc_out
+ *   saved:           DEVICE workspace of sweep_saved_bytes() bytes, or NULL
+ *   opts:            may be NULL for defaults (vacuum, one pass, no scattering)
+ * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP. */
+sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, const float* emission,
+                             const sweep_fwd_opts_t* opts, float* J, float* absorbed,
+                             double* totals, void* saved, size_t saved_bytes, void* stream);
+
+/* Adjoint sweep (reverse levels over the transposed graphs) for a loss
+ * L(J, absorbed): given dL_dJ and dL_dabsorbed (DEVICE [C_total][G] FP32),
+ * writes dL_dkappa and dL_demission (DEVICE [C_total][G] FP32).  `saved` must
+ * hold what sweep_forward wrote with the same kappa, emission and opts.
+ * Source iterations are differentiated with per-iteration recomputation from
+ * the saved direction sums.  Periodic boundaries: UNSUPPORTED. */
+sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
+                             const float* emission, const sweep_fwd_opts_t* opts,
+                             const void* saved, size_t saved_bytes, const float* dL_dJ,
+                             const float* dL_dabsorbed, float* dL_dkappa, float* dL_demission,
+                             void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEEP_H_ */

@@ -1,0 +1,215 @@
+"""MI355X transport sweep (Peter et al. 2022, "The Sweep Method for radiative Transfer in Arepo").
+
+Python front-end of libsweep.so (include/sweep.h).  Every step of the sweep runs
+in the library's HIP kernels; this module only moves arguments across the C ABI,
+with torch providing device memory and the current stream.  There is no CPU
+fallback: without the built library every call raises SweepLibraryError.
+
+    dag = build_dag([mesh], dirs)                  # per-direction dependency graphs
+    J, absorbed, totals = forward(dag, kappa, emission)
+    J, absorbed = SweepFunction.apply(kappa, emission, dag, opts)   # differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _binding as B
+from ._binding import (SweepError, SweepLibraryError, sweep_adjoint, sweep_build_dag,  # noqa: F401
+                       sweep_dag_export, sweep_dag_info, sweep_destroy_dag, sweep_forward,
+                       sweep_last_error, sweep_saved_bytes)
+
+TOTAL_NAMES = ("emitted", "absorbed", "escaped", "pbc_in", "pbc_out", "scat_net", "pbc_err_max",
+               "pbc_err_l1")
+
+__all__ = ["Dag", "build_dag", "forward", "adjoint", "SweepFunction", "upload_mesh",
+           "SweepError", "SweepLibraryError", "TOTAL_NAMES"] + list(B.EXPORTED)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def upload_mesh(mesh: dict, device="cuda") -> dict:
+    """Copy a mesh (dict of numpy arrays, see synth.mesh) to device tensors."""
+    def t(a, dt):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
+    out = dict(face_ptr=t(mesh["face_ptr"], torch.int64), face_nbr=t(mesh["face_nbr"], torch.int32),
+               face_twin=t(mesh["face_twin"], torch.int32) if "face_twin" in mesh else None,
+               face_shift=t(mesh["face_shift"], torch.int8) if mesh.get("periodic") else None,
+               face_area=t(mesh["face_area"], torch.float64),
+               face_normal=t(np.asarray(mesh["face_normal"]).reshape(-1), torch.float64),
+               cell_volume=t(mesh["cell_volume"], torch.float64))
+    return out
+
+
+def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
+              use_graph=False) -> B.sweep_fwd_opts_t:
+    o = B.sweep_fwd_opts_t()
+    o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
+    o.n_pbc = int(n_pbc)
+    o.albedo = float(albedo)
+    o.n_scat = int(n_scat)
+    o.form = {"batched": B.SWEEP_FORM_BATCHED, "plain": B.SWEEP_FORM_PLAIN}[form]
+    o.block = int(block)
+    o.ring = int(ring)
+    o.use_graph = int(bool(use_graph))
+    return o
+
+
+class Dag:
+    """Owner of a sweep_dag_t handle."""
+
+    def __init__(self, handle: ctypes.c_void_p, mesh_cells, n_dirs: int, device):
+        self._h = handle
+        self.mesh_cells = list(mesh_cells)
+        self.n_cells = int(sum(mesh_cells))
+        self.n_dirs = int(n_dirs)
+        self.device = device
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise SweepError(-5, "DAG was destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        i = B.sweep_dag_info_t()
+        B.check(sweep_dag_info(self.handle, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in B.sweep_dag_info_t._fields_}
+
+    def export(self, stream=None):
+        """(level, order, indeg) as int32 numpy arrays laid out [mesh][direction][cell]."""
+        T = self.n_cells * self.n_dirs
+        lv = np.empty(T, np.int32)
+        od = np.empty(T, np.int32)
+        ind = np.empty(T, np.int32)
+        B.check(sweep_dag_export(self.handle, lv.ctypes.data, od.ctypes.data, ind.ctypes.data,
+                                 _stream(stream)))
+        return lv, od, ind
+
+    def split(self, arr):
+        """Split an exported [T] array into per-mesh [D, C_m] views."""
+        out, off = [], 0
+        for C in self.mesh_cells:
+            out.append(arr[off:off + self.n_dirs * C].reshape(self.n_dirs, C))
+            off += self.n_dirs * C
+        return out
+
+    def saved_bytes(self, G: int, n_scat: int = 1) -> int:
+        return int(sweep_saved_bytes(self.handle, G, ctypes.byref(_fwd_opts(n_scat=n_scat))))
+
+    def close(self):
+        if self._h is not None:
+            sweep_destroy_dag(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_dag(meshes, dirs, eps: float = 1e-12, validate: bool = True, device="cuda",
+              stream=None) -> Dag:
+    """Build the dependency graphs of `meshes` (numpy dicts or upload_mesh() results)."""
+    B.load()
+    dev = [m if isinstance(m.get("face_ptr"), torch.Tensor) else upload_mesh(m, device)
+           for m in meshes]
+    arr = (B.sweep_mesh_t * len(dev))()
+    for i, m in enumerate(dev):
+        arr[i].n_cells = int(m["cell_volume"].numel())
+        arr[i].n_half_faces = int(m["face_nbr"].numel())
+        arr[i].face_ptr = _ptr(m["face_ptr"])
+        arr[i].face_nbr = _ptr(m["face_nbr"])
+        arr[i].face_twin = _ptr(m.get("face_twin"))
+        arr[i].face_shift = _ptr(m.get("face_shift"))
+        arr[i].face_area = _ptr(m["face_area"])
+        arr[i].face_normal = _ptr(m["face_normal"])
+        arr[i].cell_volume = _ptr(m["cell_volume"])
+    d = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 3)
+    opts = B.sweep_build_opts_t()
+    opts.eps_tie = float(eps)
+    opts.validate = int(bool(validate))
+    h = ctypes.c_void_p()
+    B.check(sweep_build_dag(arr, len(dev), d.ctypes.data, len(d), ctypes.byref(opts),
+                            _stream(stream), ctypes.byref(h)))
+    return Dag(h, [int(m["cell_volume"].numel()) for m in dev], len(d), device)
+
+
+def _check_field(t, C, G, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32
+            and t.is_contiguous() and t.numel() == C * G):
+        raise ValueError("%s must be a contiguous float32 CUDA tensor with %d elements" % (name, C * G))
+
+
+def forward(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, save_for_adjoint: bool = False,
+            stream=None, **opts):
+    """Forward sweep.  kappa/emission: float32 CUDA [C_total, G].  Returns
+    (J [C,G], absorbed [C,G], totals [n_meshes, G, 8] float64[, saved workspace])."""
+    C = dag.n_cells
+    G = kappa.numel() // max(C, 1)
+    _check_field(kappa, C, G, "kappa")
+    _check_field(emission, C, G, "emission")
+    o = _fwd_opts(**opts)
+    J = torch.empty((C, G), dtype=torch.float32, device=kappa.device)
+    A = torch.empty_like(J)
+    tot = torch.empty((len(dag.mesh_cells), G, B.SWEEP_N_TOTALS), dtype=torch.float64,
+                      device=kappa.device)
+    saved = None
+    nbytes = 0
+    if save_for_adjoint:
+        nbytes = int(sweep_saved_bytes(dag.handle, G, ctypes.byref(o)))
+        saved = torch.empty(nbytes // 4, dtype=torch.float32, device=kappa.device)
+    B.check(sweep_forward(dag.handle, G, _ptr(kappa), _ptr(emission), ctypes.byref(o), _ptr(J),
+                          _ptr(A), _ptr(tot), _ptr(saved), nbytes, _stream(stream)))
+    if save_for_adjoint:
+        return J, A, tot, saved
+    return J, A, tot
+
+
+def adjoint(dag: Dag, kappa, emission, saved, dL_dJ, dL_dabsorbed, stream=None, **opts):
+    """Adjoint sweep: returns (dL/dkappa, dL/demission) as float32 CUDA [C_total, G]."""
+    C = dag.n_cells
+    G = kappa.numel() // max(C, 1)
+    for t, n in ((kappa, "kappa"), (emission, "emission"), (dL_dJ, "dL_dJ"),
+                 (dL_dabsorbed, "dL_dabsorbed")):
+        _check_field(t, C, G, n)
+    o = _fwd_opts(**opts)
+    dk = torch.empty((C, G), dtype=torch.float32, device=kappa.device)
+    de = torch.empty_like(dk)
+    B.check(sweep_adjoint(dag.handle, G, _ptr(kappa), _ptr(emission), ctypes.byref(o), _ptr(saved),
+                          saved.numel() * saved.element_size(), _ptr(dL_dJ), _ptr(dL_dabsorbed),
+                          _ptr(dk), _ptr(de), _stream(stream)))
+    return dk, de
+
+
+class SweepFunction(torch.autograd.Function):
+    """(kappa, emission) -> (J, absorbed), differentiable through the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, kappa, emission, dag, opts=None):
+        opts = dict(opts or {})
+        J, A, tot, saved = forward(dag, kappa.contiguous(), emission.contiguous(),
+                                   save_for_adjoint=True, **opts)
+        ctx.dag, ctx.opts = dag, opts
+        ctx.save_for_backward(kappa, emission, saved)
+        ctx.mark_non_differentiable(tot)
+        return J, A, tot
+
+    @staticmethod
+    def backward(ctx, gJ, gA, gtot):
+        kappa, emission, saved = ctx.saved_tensors
+        gJ = torch.zeros_like(kappa) if gJ is None else gJ.contiguous().float()
+        gA = torch.zeros_like(kappa) if gA is None else gA.contiguous().float()
+        dk, de = adjoint(ctx.dag, kappa.contiguous(), emission.contiguous(), saved, gJ, gA,
+                         **ctx.opts)
+        return dk, de, None, None

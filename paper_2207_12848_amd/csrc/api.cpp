@@ -1,0 +1,716 @@
+// Host side of the sweep library: the C ABI declared in include/sweep.h.
+//
+// Validation, DAG construction (count -> Kahn levels -> row lengths -> scan ->
+// rows), workspace management and the pass sequences of the forward sweep
+// (periodic passes inside source iterations) and of the adjoint (reverse
+// iterations with recomputation from the saved direction sums).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "sweep.h"
+
+using sweep::Unit;
+
+namespace {
+
+thread_local std::string g_err;
+
+sweep_status_t fail(sweep_status_t st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+sweep_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? SWEEP_ERR_OOM : SWEEP_ERR_HIP, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+#define ST_TRY(expr)                        \
+  do {                                      \
+    sweep_status_t s_ = (expr);             \
+    if (s_ != SWEEP_OK) return s_;          \
+  } while (0)
+
+// Device buffer owned by the DAG (freed with it).
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  Buf() = default;
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  ~Buf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    release();
+    if (n == 0) n = 16;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    else p = nullptr;
+    return e;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+constexpr int kRedBlock = 256;
+constexpr int kNPart = 9;
+constexpr int kMaxG = 64;
+constexpr int kMaxLds = 160 * 1024;
+
+}  // namespace
+
+struct sweep_dag_s {
+  int32_t n_meshes = 0, D = 0;
+  int64_t C_total = 0, T = 0;
+  int64_t n_up = 0, n_dn = 0;
+  double eps = 1e-12;
+  bool has_shift = false;
+  int device = 0;
+  int cu_count = 256;
+  int lds_max = 65536 - 256;  // dynamic LDS bytes available to a sweep workgroup
+  std::vector<int32_t> mesh_off, mesh_cells;
+  std::vector<Unit> units;
+  std::vector<int32_t> order;  // units, deepest first
+  std::vector<int32_t> identity;
+  Buf units_d, order_d, identity_d, sched, level, indeg, lp, up_ptr, dn_ptr, up, dn, aperp, bnd,
+      vol, counter;
+  // reduction tables (depend on G)
+  int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
+  Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
+  // workspaces
+  Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64;
+};
+
+namespace {
+
+bool dag_ok(sweep_dag_t d) { return d != nullptr && d->T > 0; }
+
+sweep_status_t validate_mesh_host(const sweep_mesh_t& m, int idx) {
+  const int32_t C = m.n_cells;
+  const int64_t F = m.n_half_faces;
+  std::vector<int64_t> fp(C + 1);
+  std::vector<int32_t> nbr(F), twin;
+  std::vector<int8_t> shift;
+  std::vector<double> area(F), nrm(3 * F), vol(C);
+  HIP_TRY(hipMemcpy(fp.data(), m.face_ptr, sizeof(int64_t) * (C + 1), hipMemcpyDeviceToHost));
+  if (F > 0) {
+    HIP_TRY(hipMemcpy(nbr.data(), m.face_nbr, sizeof(int32_t) * F, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(area.data(), m.face_area, sizeof(double) * F, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(nrm.data(), m.face_normal, sizeof(double) * 3 * F, hipMemcpyDeviceToHost));
+  }
+  HIP_TRY(hipMemcpy(vol.data(), m.cell_volume, sizeof(double) * C, hipMemcpyDeviceToHost));
+  if (fp[0] != 0 || fp[C] != F)
+    return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: face_ptr must run from 0 to n_half_faces", idx);
+  for (int32_t c = 0; c < C; ++c) {
+    if (fp[c + 1] < fp[c]) return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: face_ptr not monotone at cell %d", idx, c);
+    if (!(vol[c] > 0.0) || !std::isfinite(vol[c]))
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: cell %d has volume %g", idx, c, vol[c]);
+  }
+  for (int64_t f = 0; f < F; ++f) {
+    if (nbr[f] < -1 || nbr[f] >= C)
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: face %lld neighbour %d out of range", idx, (long long)f, nbr[f]);
+    if (!(area[f] >= 0.0) || !std::isfinite(area[f]))
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: face %lld area %g", idx, (long long)f, area[f]);
+    const double n2 = nrm[3 * f] * nrm[3 * f] + nrm[3 * f + 1] * nrm[3 * f + 1] + nrm[3 * f + 2] * nrm[3 * f + 2];
+    if (!(std::fabs(std::sqrt(n2) - 1.0) <= 1e-9))
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: face %lld normal is not unit", idx, (long long)f);
+  }
+  if (m.face_shift) {
+    shift.resize(F);
+    if (F > 0) HIP_TRY(hipMemcpy(shift.data(), m.face_shift, F, hipMemcpyDeviceToHost));
+    for (int64_t f = 0; f < F; ++f)
+      if (shift[f] != 0 && nbr[f] < 0)
+        return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: wall face %lld has a periodic shift", idx, (long long)f);
+  }
+  if (m.face_twin) {
+    twin.resize(F);
+    if (F > 0) HIP_TRY(hipMemcpy(twin.data(), m.face_twin, sizeof(int32_t) * F, hipMemcpyDeviceToHost));
+    std::vector<int32_t> owner(F);
+    for (int32_t c = 0; c < C; ++c)
+      for (int64_t f = fp[c]; f < fp[c + 1]; ++f) owner[f] = c;
+    for (int64_t f = 0; f < F; ++f) {
+      if (nbr[f] < 0) continue;
+      const int64_t t = twin[f];
+      if (t < 0 || t >= F || twin[t] != f || owner[t] != nbr[f] || nbr[t] != owner[f])
+        return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: half-face %lld has no consistent twin", idx, (long long)f);
+      if (area[t] != area[f] || nrm[3 * t] != -nrm[3 * f] || nrm[3 * t + 1] != -nrm[3 * f + 1] ||
+          nrm[3 * t + 2] != -nrm[3 * f + 2])
+        return fail(SWEEP_ERR_INVALID_ARG,
+                    "mesh %d: twin half-faces %lld/%lld need equal areas and opposite normals", idx,
+                    (long long)f, (long long)t);
+      if (!shift.empty() && shift[t] != -shift[f])
+        return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: twin half-faces %lld/%lld need opposite shifts",
+                    idx, (long long)f, (long long)t);
+    }
+  }
+  return SWEEP_OK;
+}
+
+// Reduction block tables for G groups: blocks never straddle meshes.
+sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
+  if (d->red_G == G) return SWEEP_OK;
+  const int cpb = std::max(1, kRedBlock / G);
+  std::vector<int32_t> bm, bc, mbb(d->n_meshes + 1, 0);
+  for (int m = 0; m < d->n_meshes; ++m) {
+    mbb[m] = (int32_t)bm.size();
+    for (int32_t c = 0; c < d->mesh_cells[m]; c += cpb) {
+      bm.push_back(m);
+      bc.push_back(d->mesh_off[m] + c);
+    }
+  }
+  mbb[d->n_meshes] = (int32_t)bm.size();
+  HIP_TRY(d->blk_mesh.alloc(bm.size() * 4));
+  HIP_TRY(d->blk_cell0.alloc(bc.size() * 4));
+  HIP_TRY(d->mesh_blk_base.alloc(mbb.size() * 4));
+  HIP_TRY(hipMemcpy(d->blk_mesh.p, bm.data(), bm.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d->blk_cell0.p, bc.data(), bc.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d->mesh_blk_base.p, mbb.data(), mbb.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(d->partial.alloc(bm.size() * (size_t)G * kNPart * sizeof(double)));
+  d->red_G = G;
+  d->red_blocks = (int32_t)bm.size();
+  d->red_cpb = cpb;
+  return SWEEP_OK;
+}
+
+struct FwdPlan {
+  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph;
+  float albedo;
+};
+
+sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
+  p->boundary = o ? o->boundary : SWEEP_BOUNDARY_VACUUM;
+  p->n_pbc = o ? o->n_pbc : 1;
+  p->n_scat = o ? o->n_scat : 1;
+  p->albedo = o ? (float)o->albedo : 0.0f;
+  p->form = o ? o->form : SWEEP_FORM_BATCHED;
+  p->block = o ? o->block : 0;
+  p->ring = o ? o->ring : 0;
+  p->use_graph = o ? o->use_graph : 0;
+  if (p->boundary != SWEEP_BOUNDARY_VACUUM && p->boundary != SWEEP_BOUNDARY_PERIODIC)
+    return fail(SWEEP_ERR_INVALID_ARG, "unknown boundary %d", p->boundary);
+  if (p->n_pbc < 1 || p->n_scat < 1) return fail(SWEEP_ERR_INVALID_ARG, "n_pbc and n_scat must be >= 1");
+  if (!(p->albedo >= 0.0f) || !(p->albedo < 1.0f)) return fail(SWEEP_ERR_INVALID_ARG, "albedo must be in [0, 1)");
+  if (p->form != SWEEP_FORM_BATCHED && p->form != SWEEP_FORM_PLAIN)
+    return fail(SWEEP_ERR_INVALID_ARG, "unknown form %d", p->form);
+  if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0))
+    return fail(SWEEP_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+  if (p->ring != 0 && (p->ring < 64 || (p->ring & (p->ring - 1)) != 0))
+    return fail(SWEEP_ERR_INVALID_ARG, "ring must be a power of two >= 64");
+  if (p->boundary == SWEEP_BOUNDARY_VACUUM) p->n_pbc = 1;
+  return SWEEP_OK;
+}
+
+// Group chunks: groups are independent, a launch packs up to 4 of them per task.
+std::vector<std::pair<int, int>> group_chunks(int G, bool plain) {
+  std::vector<std::pair<int, int>> ch;
+  if (plain) {
+    for (int g = 0; g < G; ++g) ch.push_back({g, 1});
+    return ch;
+  }
+  for (int g = 0; g < G;) {
+    const int n = std::min(4, G - g);
+    ch.push_back({g, n});
+    g += n;
+  }
+  return ch;
+}
+
+int default_ring(int gn, int ring) {
+  if (ring > 0) return ring;
+  int r = 1;
+  while ((size_t)(r * 2) * gn * sizeof(float) <= 64 * 1024 - 256) r *= 2;
+  return r;
+}
+
+sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t G,
+                         const float* kappa, const float* src, const float* jsum_prev,
+                         const float* phi_prev, float* out, float* pin, hipStream_t s) {
+  sweep::SweepArgs a{};
+  a.units = d->units_d.as<Unit>();
+  a.sched = d->sched.as<int32_t>();
+  a.lp = d->lp.as<int32_t>();
+  a.row_ptr = reverse ? d->dn_ptr.as<int64_t>() : d->up_ptr.as<int64_t>();
+  a.ent = reverse ? d->dn.as<int2>() : d->up.as<int2>();
+  a.aperp = d->aperp.as<float>();
+  a.kappa = kappa;
+  a.src = src;
+  a.vol = d->vol.as<float>();
+  a.jsum_prev = jsum_prev;
+  a.phi_prev = phi_prev;
+  a.out = out;
+  a.pin = pin;
+  a.C_total = d->C_total;
+  a.G = G;
+  a.D = d->D;
+  a.albedo = p.albedo;
+  a.inv_D = 1.0f / (float)d->D;
+  const int block = p.block > 0 ? p.block : 512;
+  const int n_units = (int)d->units.size();
+  for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
+    const int ring = default_ring(gn, p.ring);
+    if (sweep::sweep_lds_bytes(gn, ring) > (size_t)d->lds_max)
+      return fail(SWEEP_ERR_INVALID_ARG, "ring %d x %d groups exceeds the %d bytes of LDS", ring, gn,
+                  d->lds_max);
+    a.g0 = g0;
+    a.ring_mask = ring - 1;
+    if (p.form == SWEEP_FORM_PLAIN) {
+      a.work_counter = nullptr;
+      a.n_units = 1;
+      for (int u = 0; u < n_units; ++u) {
+        a.unit_order = d->identity_d.as<int32_t>() + u;
+        hipError_t e = reverse ? sweep::launch_sweep_adj(a, gn, 1, block, ring, s)
+                               : sweep::launch_sweep_fwd(a, gn, 1, block, ring, s);
+        if (e != hipSuccess) return hip_fail(e, "sweep launch");
+      }
+    } else {
+      int per_cu = std::max(1, (int)((size_t)kMaxLds / (sweep::sweep_lds_bytes(gn, ring) + 256)));
+      per_cu = std::min(per_cu, std::max(1, 2048 / block));
+      const int grid = std::min(n_units, d->cu_count * per_cu);
+      a.work_counter = d->counter.as<int32_t>();
+      a.unit_order = d->order_d.as<int32_t>();
+      a.n_units = n_units;
+      HIP_TRY(sweep::launch_fill_i32(a.work_counter, 1, 0, s));
+      hipError_t e = reverse ? sweep::launch_sweep_adj(a, gn, grid, block, ring, s)
+                             : sweep::launch_sweep_fwd(a, gn, grid, block, ring, s);
+      if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    }
+  }
+  return SWEEP_OK;
+}
+
+sweep_status_t check_common(sweep_dag_t d, int32_t G) {
+  if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
+  if (G < 1 || G > kMaxG) return fail(SWEEP_ERR_INVALID_ARG, "G must be in [1, %d]", kMaxG);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != d->device) return fail(SWEEP_ERR_INVALID_ARG, "DAG was built on device %d, current is %d", d->device, dev);
+  return SWEEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sweep_last_error(void) { return g_err.c_str(); }
+
+sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, const double* dirs,
+                               int32_t n_dirs, const sweep_build_opts_t* opts, void* stream,
+                               sweep_dag_t* out) {
+  g_err.clear();
+  if (out == nullptr) return fail(SWEEP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (meshes == nullptr || n_meshes < 1) return fail(SWEEP_ERR_INVALID_ARG, "need at least one mesh");
+  if (dirs == nullptr || n_dirs < 1) return fail(SWEEP_ERR_INVALID_ARG, "need at least one direction");
+  const double eps = opts ? opts->eps_tie : 1e-12;
+  const int validate = opts ? opts->validate : 1;
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SWEEP_ERR_INVALID_ARG, "eps_tie must be >= 0");
+  for (int d = 0; d < n_dirs; ++d) {
+    const double n = std::sqrt(dirs[3 * d] * dirs[3 * d] + dirs[3 * d + 1] * dirs[3 * d + 1] +
+                               dirs[3 * d + 2] * dirs[3 * d + 2]);
+    if (!(std::fabs(n - 1.0) <= 1e-12)) return fail(SWEEP_ERR_INVALID_ARG, "direction %d is not a unit vector", d);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<sweep_dag_s> dag(new sweep_dag_s());
+  sweep_dag_s* D = dag.get();
+  HIP_TRY(hipGetDevice(&D->device));
+  HIP_TRY(hipDeviceGetAttribute(&D->cu_count, hipDeviceAttributeMultiprocessorCount, D->device));
+  D->n_meshes = n_meshes;
+  D->D = n_dirs;
+  D->eps = eps;
+  int64_t off = 0;
+  for (int m = 0; m < n_meshes; ++m) {
+    const sweep_mesh_t& M = meshes[m];
+    if (M.n_cells < 1 || M.n_half_faces < 0 || !M.face_ptr || !M.cell_volume ||
+        (M.n_half_faces > 0 && (!M.face_nbr || !M.face_area || !M.face_normal)))
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: missing arrays or no cells", m);
+    if (validate) ST_TRY(validate_mesh_host(M, m));
+    D->mesh_off.push_back((int32_t)off);
+    D->mesh_cells.push_back(M.n_cells);
+    if (M.face_shift) D->has_shift = true;
+    off += M.n_cells;
+    if (off > INT32_MAX / 2) return fail(SWEEP_ERR_INVALID_ARG, "too many cells");
+  }
+  D->mesh_off.push_back((int32_t)off);
+  D->C_total = off;
+  D->T = off * n_dirs;
+  const int64_t T = D->T;
+  const int n_units = n_meshes * n_dirs;
+  // units: u = mesh * D + dir
+  std::vector<int32_t> blk_base(n_units + 1, 0);
+  for (int m = 0; m < n_meshes; ++m)
+    for (int d = 0; d < n_dirs; ++d) {
+      Unit U{};
+      U.task_base = (int64_t)n_dirs * D->mesh_off[m] + (int64_t)d * D->mesh_cells[m];
+      const int u = m * n_dirs + d;
+      U.lp_base = U.task_base + 2 * (int64_t)u;
+      U.n_cells = D->mesh_cells[m];
+      U.dir = d;
+      U.mesh = m;
+      U.cell_off = D->mesh_off[m];
+      D->units.push_back(U);
+      blk_base[u + 1] = blk_base[u] + (U.n_cells + 255) / 256;
+    }
+  const int n_blocks = blk_base[n_units];
+  std::vector<sweep::MeshDev> md(n_meshes);
+  for (int m = 0; m < n_meshes; ++m) {
+    md[m].face_ptr = meshes[m].face_ptr;
+    md[m].face_nbr = meshes[m].face_nbr;
+    md[m].face_shift = meshes[m].face_shift;
+    md[m].face_area = meshes[m].face_area;
+    md[m].face_normal = meshes[m].face_normal;
+    md[m].cell_volume = meshes[m].cell_volume;
+    md[m].n_cells = meshes[m].n_cells;
+    md[m].cell_off = D->mesh_off[m];
+  }
+  Buf meshes_d, dirs_d, blk_d, rowlen_up, rowlen_dn, cnt, inv, depth_d, err_d, len_up, len_dn, scan_tmp;
+  HIP_TRY(meshes_d.alloc(sizeof(sweep::MeshDev) * n_meshes));
+  HIP_TRY(dirs_d.alloc(sizeof(double) * 3 * n_dirs));
+  HIP_TRY(blk_d.alloc(sizeof(int32_t) * (n_units + 1)));
+  HIP_TRY(D->units_d.alloc(sizeof(Unit) * n_units));
+  HIP_TRY(hipMemcpyAsync(meshes_d.p, md.data(), sizeof(sweep::MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(dirs_d.p, dirs, sizeof(double) * 3 * n_dirs, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(blk_d.p, blk_base.data(), sizeof(int32_t) * (n_units + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
+  HIP_TRY(D->indeg.alloc(4 * T));
+  HIP_TRY(rowlen_up.alloc(4 * T));
+  HIP_TRY(rowlen_dn.alloc(4 * T));
+  HIP_TRY(D->aperp.alloc(4 * T));
+  HIP_TRY(D->bnd.alloc(8 * T));
+  HIP_TRY(cnt.alloc(4 * T));
+  HIP_TRY(inv.alloc(4 * T));
+  HIP_TRY(D->level.alloc(4 * T));
+  HIP_TRY(D->sched.alloc(4 * T));
+  HIP_TRY(D->lp.alloc(4 * (T + 2 * (int64_t)n_units)));
+  HIP_TRY(depth_d.alloc(4 * n_units));
+  HIP_TRY(err_d.alloc(4));
+  HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 1, 0, s));
+  sweep::DagBuildArgs a{};
+  a.units = D->units_d.as<Unit>();
+  a.n_units = n_units;
+  a.meshes = meshes_d.as<sweep::MeshDev>();
+  a.dirs = dirs_d.as<double>();
+  a.eps = eps;
+  a.blk_base = blk_d.as<int32_t>();
+  a.indeg = D->indeg.as<int32_t>();
+  a.rowlen_up = rowlen_up.as<int32_t>();
+  a.rowlen_dn = rowlen_dn.as<int32_t>();
+  a.aperp = D->aperp.as<float>();
+  a.bnd = D->bnd.as<float2>();
+  a.cnt = cnt.as<int32_t>();
+  a.inv = inv.as<int32_t>();
+  a.level = D->level.as<int32_t>();
+  a.sched = D->sched.as<int32_t>();
+  a.lp = D->lp.as<int32_t>();
+  a.depth = depth_d.as<int32_t>();
+  a.err = err_d.as<int32_t>();
+  HIP_TRY(sweep::launch_count(a, n_blocks, s));
+  HIP_TRY(sweep::launch_kahn(a, s));
+  std::vector<int32_t> depth(n_units);
+  int32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(depth.data(), depth_d.p, 4 * n_units, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&err, err_d.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err) return fail(SWEEP_ERR_CYCLE, "a dependency graph is cyclic: some tasks never become ready");
+  // row lengths in schedule order -> row pointers
+  HIP_TRY(len_up.alloc(8 * (T + 1)));
+  HIP_TRY(len_dn.alloc(8 * (T + 1)));
+  HIP_TRY(D->up_ptr.alloc(8 * (T + 1)));
+  HIP_TRY(D->dn_ptr.alloc(8 * (T + 1)));
+  a.len_up = len_up.as<int64_t>();
+  a.len_dn = len_dn.as<int64_t>();
+  a.up_ptr = D->up_ptr.as<int64_t>();
+  a.dn_ptr = D->dn_ptr.as<int64_t>();
+  HIP_TRY(hipMemsetAsync(a.len_up + T, 0, 8, s));
+  HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 8, s));
+  HIP_TRY(sweep::launch_gather_len(a, n_blocks, s));
+  size_t tmp_bytes = 0;
+  HIP_TRY(sweep::launch_scan_i64(a.len_up, a.up_ptr, T + 1, nullptr, &tmp_bytes, s));
+  HIP_TRY(scan_tmp.alloc(tmp_bytes));
+  HIP_TRY(sweep::launch_scan_i64(a.len_up, a.up_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
+  HIP_TRY(sweep::launch_scan_i64(a.len_dn, a.dn_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
+  HIP_TRY(hipMemcpyAsync(&D->n_up, a.up_ptr + T, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&D->n_dn, a.dn_ptr + T, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(D->up.alloc(8 * std::max<int64_t>(D->n_up, 1)));
+  HIP_TRY(D->dn.alloc(8 * std::max<int64_t>(D->n_dn, 1)));
+  a.up = D->up.as<int2>();
+  a.dn = D->dn.as<int2>();
+  HIP_TRY(sweep::launch_fill(a, n_blocks, s));
+  HIP_TRY(D->vol.alloc(4 * D->C_total));
+  for (int m = 0; m < n_meshes; ++m)
+    HIP_TRY(sweep::launch_d2f(meshes[m].cell_volume, D->vol.as<float>() + D->mesh_off[m],
+                              meshes[m].n_cells, s));
+  // schedule of the units: deepest first
+  for (int u = 0; u < n_units; ++u) D->units[u].depth = depth[u];
+  D->order.resize(n_units);
+  D->identity.resize(n_units);
+  for (int u = 0; u < n_units; ++u) D->order[u] = D->identity[u] = u;
+  std::stable_sort(D->order.begin(), D->order.end(), [&](int x, int y) {
+    const int64_t wx = (int64_t)D->units[x].depth * 1024 + D->units[x].n_cells / 1024;
+    const int64_t wy = (int64_t)D->units[y].depth * 1024 + D->units[y].n_cells / 1024;
+    return wx > wy;
+  });
+  HIP_TRY(D->order_d.alloc(4 * n_units));
+  HIP_TRY(D->identity_d.alloc(4 * n_units));
+  HIP_TRY(D->counter.alloc(64));
+  HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(D->order_d.p, D->order.data(), 4 * n_units, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(D->identity_d.p, D->identity.data(), 4 * n_units, hipMemcpyHostToDevice, s));
+  {
+    // LDS a sweep workgroup may use: the device limit less the kernel's static LDS
+    int lds_max = 65536;
+    (void)hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, D->device);
+    D->lds_max = std::max(65536, std::min(lds_max, kMaxLds)) - 256;
+    if (D->lds_max > 65536 - 256 && sweep::set_sweep_lds_limit(D->lds_max) != hipSuccess) {
+      (void)hipGetLastError();
+      D->lds_max = 65536 - 256;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = dag.release();
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_destroy_dag(sweep_dag_t dag) {
+  g_err.clear();
+  delete dag;
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
+  g_err.clear();
+  if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
+  if (!info) return fail(SWEEP_ERR_INVALID_ARG, "info is NULL");
+  std::memset(info, 0, sizeof(*info));
+  info->n_meshes = d->n_meshes;
+  info->n_dirs = d->D;
+  info->n_cells = d->C_total;
+  info->n_tasks = d->T;
+  info->n_up_entries = d->n_up;
+  info->n_down_entries = d->n_dn;
+  int mx = 0, mn = INT32_MAX;
+  double sum = 0;
+  for (const Unit& U : d->units) {
+    mx = std::max(mx, U.depth);
+    mn = std::min(mn, U.depth);
+    sum += U.depth;
+  }
+  info->max_depth = mx;
+  info->min_depth = mn;
+  info->mean_depth = sum / d->units.size();
+  const Buf* bufs[] = {&d->sched, &d->level, &d->indeg, &d->lp, &d->up_ptr, &d->dn_ptr, &d->up,
+                       &d->dn, &d->aperp, &d->bnd, &d->vol};
+  int64_t b = 0;
+  for (const Buf* x : bufs) b += (int64_t)x->bytes;
+  info->device_bytes = b;
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, int32_t* indeg,
+                                void* stream) {
+  g_err.clear();
+  if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t T = d->T;
+  if (level) HIP_TRY(hipMemcpyAsync(level, d->level.p, 4 * T, hipMemcpyDeviceToHost, s));
+  if (indeg) HIP_TRY(hipMemcpyAsync(indeg, d->indeg.p, 4 * T, hipMemcpyDeviceToHost, s));
+  std::vector<int32_t> sched, lp;
+  if (order) {
+    sched.resize(T);
+    lp.resize(T + 2 * d->units.size());
+    HIP_TRY(hipMemcpyAsync(sched.data(), d->sched.p, 4 * T, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(lp.data(), d->lp.p, 4 * lp.size(), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  if (order) {
+    // the schedule is grouped by level; the canonical order sorts each level by cell id
+    for (const Unit& U : d->units) {
+      const int32_t* l = lp.data() + U.lp_base;
+      int32_t* o = order + U.task_base;
+      std::memcpy(o, sched.data() + U.task_base, 4 * (size_t)U.n_cells);
+      for (int k = 0; k < U.depth; ++k) std::sort(o + l[k], o + l[k + 1]);
+    }
+  }
+  return SWEEP_OK;
+}
+
+size_t sweep_saved_bytes(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
+  if (!dag_ok(d) || G < 1) return 0;
+  const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
+  return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat);
+}
+
+sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
+                             const sweep_fwd_opts_t* opts, float* J, float* absorbed,
+                             double* totals, void* saved, size_t saved_bytes, void* stream) {
+  g_err.clear();
+  ST_TRY(check_common(d, G));
+  FwdPlan p;
+  ST_TRY(read_opts(opts, &p));
+  if (!kappa || !emission || !J || !absorbed || !totals)
+    return fail(SWEEP_ERR_INVALID_ARG, "kappa, emission, J, absorbed and totals are required");
+  const bool periodic = p.boundary == SWEEP_BOUNDARY_PERIODIC;
+  if (periodic && !d->has_shift)
+    return fail(SWEEP_ERR_INVALID_ARG, "periodic boundaries need meshes built with face_shift");
+  const size_t need = sweep_saved_bytes(d, G, opts);
+  if (saved && saved_bytes < need)
+    return fail(SWEEP_ERR_INVALID_ARG, "saved workspace has %zu bytes, %zu needed", saved_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t CG = d->C_total * G;
+  const int64_t DCG = CG * d->D;
+  ST_TRY(ensure_reduce_tables(d, G));
+  if (!saved) HIP_TRY(d->phi_a.alloc(4 * DCG));
+  if (periodic && p.n_pbc > 1) HIP_TRY(d->phi_b.alloc(4 * DCG));
+  if (periodic) {
+    HIP_TRY(d->pin.alloc(4 * DCG));
+    HIP_TRY(d->pin_prev.alloc(8 * CG));
+  }
+  if (!saved) {
+    HIP_TRY(d->jsum_a.alloc(4 * CG));
+    HIP_TRY(d->jsum_b.alloc(4 * CG));
+  }
+  float* phi_final = saved ? (float*)saved : d->phi_a.as<float>();
+  auto ckpt = [&](int it) -> float* {
+    if (saved) return (float*)saved + DCG + (int64_t)it * CG;
+    return (it % 2 == 0) ? d->jsum_a.as<float>() : d->jsum_b.as<float>();
+  };
+  sweep::ReduceArgs r{};
+  r.units = d->units_d.as<Unit>();
+  r.D = d->D;
+  r.G = G;
+  r.C_total = d->C_total;
+  r.blk_mesh = d->blk_mesh.as<int32_t>();
+  r.blk_cell0 = d->blk_cell0.as<int32_t>();
+  if (!d->mesh_off_d.p) {
+    HIP_TRY(d->mesh_off_d.alloc(4 * d->mesh_off.size()));
+    HIP_TRY(d->mesh_cells_d.alloc(4 * d->mesh_cells.size()));
+    HIP_TRY(hipMemcpy(d->mesh_off_d.p, d->mesh_off.data(), 4 * d->mesh_off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->mesh_cells_d.p, d->mesh_cells.data(), 4 * d->mesh_cells.size(), hipMemcpyHostToDevice));
+  }
+  r.mesh_off = d->mesh_off_d.as<int32_t>();
+  r.mesh_cells = d->mesh_cells_d.as<int32_t>();
+  r.bnd = d->bnd.as<float2>();
+  r.kappa = kappa;
+  r.emission = emission;
+  r.vol = d->vol.as<float>();
+  r.albedo = p.albedo;
+  r.J = J;
+  r.absorbed = absorbed;
+  r.partial = d->partial.as<double>();
+  r.cells_per_block = d->red_cpb;
+  for (int it = 0; it < p.n_scat; ++it) {
+    const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
+    float* prev = nullptr;
+    for (int ps = 0; ps < p.n_pbc; ++ps) {
+      float* dst = ((p.n_pbc - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
+      ST_TRY(run_sweep(d, false, p, G, kappa, emission, jprev, prev, dst,
+                       periodic ? d->pin.as<float>() : nullptr, s));
+      if (periodic && ps + 1 < p.n_pbc) {
+        sweep::ReduceArgs q = r;
+        q.phi = dst;
+        q.pin = d->pin.as<float>();
+        q.pin_prev = nullptr;
+        q.pin_sum = d->pin_prev.as<double>();
+        q.last = 0;
+        HIP_TRY(sweep::launch_reduce(q, d->red_blocks, s));
+      }
+      prev = dst;
+    }
+    sweep::ReduceArgs q = r;
+    q.phi = phi_final;
+    q.pin = periodic ? d->pin.as<float>() : nullptr;
+    q.pin_prev = (periodic && p.n_pbc > 1) ? d->pin_prev.as<double>() : nullptr;
+    q.pin_sum = nullptr;
+    q.jsum_prev = jprev;
+    q.jsum = ckpt(it);
+    q.last = 1;
+    HIP_TRY(sweep::launch_reduce(q, d->red_blocks, s));
+  }
+  HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
+                               d->n_meshes, G, totals, s));
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
+                             const float* emission, const sweep_fwd_opts_t* opts,
+                             const void* saved, size_t saved_bytes, const float* dL_dJ,
+                             const float* dL_dabsorbed, float* dL_dkappa, float* dL_demission,
+                             void* stream) {
+  g_err.clear();
+  ST_TRY(check_common(d, G));
+  FwdPlan p;
+  ST_TRY(read_opts(opts, &p));
+  if (p.boundary == SWEEP_BOUNDARY_PERIODIC)
+    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint of periodic passes is not implemented");
+  if (!kappa || !emission || !saved || !dL_dJ || !dL_dabsorbed || !dL_dkappa || !dL_demission)
+    return fail(SWEEP_ERR_INVALID_ARG, "missing array argument");
+  const size_t need = sweep_saved_bytes(d, G, opts);
+  if (saved_bytes < need)
+    return fail(SWEEP_ERR_INVALID_ARG, "saved workspace has %zu bytes, %zu needed", saved_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t CG = d->C_total * G;
+  const int64_t DCG = CG * d->D;
+  HIP_TRY(d->lam.alloc(4 * DCG));
+  HIP_TRY(d->gsrc.alloc(4 * CG));
+  HIP_TRY(d->dk64.alloc(8 * CG));
+  HIP_TRY(d->de64.alloc(8 * CG));
+  if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
+  const float* phi_final = (const float*)saved;
+  auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
+  HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(), ckpt(p.n_scat - 1),
+                                 p.albedo, G, d->C_total, d->gsrc.as<float>(), d->dk64.as<double>(),
+                                 d->de64.as<double>(), s));
+  for (int it = p.n_scat - 1; it >= 0; --it) {
+    const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
+    const float* phi_it = phi_final;
+    if (it != p.n_scat - 1) {
+      ST_TRY(run_sweep(d, false, p, G, kappa, emission, jprev, nullptr, d->phi_a.as<float>(), nullptr, s));
+      phi_it = d->phi_a.as<float>();
+    }
+    ST_TRY(run_sweep(d, true, p, G, kappa, d->gsrc.as<float>(), nullptr, nullptr, d->lam.as<float>(),
+                     nullptr, s));
+    sweep::AdjReduceArgs q{};
+    q.D = d->D;
+    q.G = G;
+    q.C_total = d->C_total;
+    q.lam = d->lam.as<float>();
+    q.phi = phi_it;
+    q.kappa = kappa;
+    q.vol = d->vol.as<float>();
+    q.jsum_prev = jprev;
+    q.albedo = p.albedo;
+    q.inv_D = 1.0f / (float)d->D;
+    q.gsrc_next = d->gsrc.as<float>();
+    HIP_TRY(sweep::launch_adj_reduce(q, d->dk64.as<double>(), d->de64.as<double>(), s));
+  }
+  HIP_TRY(sweep::launch_d2f_pair(d->dk64.as<double>(), d->de64.as<double>(), dL_dkappa,
+                                 dL_demission, CG, s));
+  return SWEEP_OK;
+}
+
+}  // extern "C"

@@ -183,6 +183,16 @@ sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const float* dL_dabsorbed, float* dL_dkappa, float* dL_demission,
                              void* stream);
 
+/* Kernel timing with HIP events (for measurement tools).  While enabled, every
+ * launch of the library's main kernels is bracketed by two hipEvents recorded
+ * on the launch stream.  Kernel names: "count", "kahn", "fill", "prep",
+ * "sweep_fwd", "sweep_adj", "reduce".  sweep_profile_read synchronises on the
+ * recorded events and returns the number of launches and their summed
+ * duration (ms) since the last reset; unknown names read as zero. */
+sweep_status_t sweep_profile_enable(int32_t on);
+sweep_status_t sweep_profile_reset(void);
+sweep_status_t sweep_profile_read(const char* kernel, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,8 @@ import torch
 from . import _binding as B
 from ._binding import (SweepError, SweepLibraryError, sweep_adjoint, sweep_build_dag,  # noqa: F401
                        sweep_dag_export, sweep_dag_info, sweep_destroy_dag, sweep_forward,
-                       sweep_last_error, sweep_saved_bytes)
+                       sweep_last_error, sweep_profile_enable, sweep_profile_read,
+                       sweep_profile_reset, sweep_saved_bytes)
 
 TOTAL_NAMES = ("emitted", "absorbed", "escaped", "pbc_in", "pbc_out", "scat_net", "pbc_err_max",
                "pbc_err_l1")
@@ -190,6 +191,29 @@ def adjoint(dag: Dag, kappa, emission, saved, dL_dJ, dL_dabsorbed, stream=None, 
                           saved.numel() * saved.element_size(), _ptr(dL_dJ), _ptr(dL_dabsorbed),
                           _ptr(dk), _ptr(de), _stream(stream)))
     return dk, de
+
+
+KERNELS = ("count", "kahn", "fill", "prep", "sweep_fwd", "sweep_adj", "reduce")
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket the library's kernels with HIP events (see kernel_times)."""
+    B.check(sweep_profile_enable(int(bool(on))))
+
+
+def profile_reset() -> None:
+    B.check(sweep_profile_reset())
+
+
+def kernel_times() -> dict:
+    """{kernel: (launches, total ms)} recorded since the last profile_reset()."""
+    out = {}
+    for k in KERNELS:
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        B.check(sweep_profile_read(k.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        out[k] = (int(n.value), float(ms.value))
+    return out
 
 
 class SweepFunction(torch.autograd.Function):

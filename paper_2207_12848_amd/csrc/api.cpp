@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -77,6 +78,48 @@ struct Buf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// ---------------------------------------------------------------- kernel timing
+struct ProfRec {
+  std::string name;
+  hipEvent_t start, stop;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t pool_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+  hipEvent_t stop = nullptr;
+  hipStream_t s;
+  ProfScope(const char* name, hipStream_t stream) : s(stream) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (!g_prof_on) return;
+    hipEvent_t start = pool_event();
+    stop = pool_event();
+    if (!start || !stop) {
+      stop = nullptr;
+      return;
+    }
+    (void)hipEventRecord(start, s);
+    g_prof.push_back({name, start, stop});
+  }
+  ~ProfScope() {
+    if (stop) (void)hipEventRecord(stop, s);
+  }
+};
+
 constexpr int kRedBlock = 256;
 constexpr int kNPart = 9;
 constexpr int kMaxG = 64;
@@ -97,13 +140,15 @@ struct sweep_dag_s {
   std::vector<Unit> units;
   std::vector<int32_t> order;  // units, deepest first
   std::vector<int32_t> identity;
-  Buf units_d, order_d, identity_d, sched, level, indeg, lp, up_ptr, dn_ptr, up, dn, aperp, bnd,
-      vol, counter;
+  Buf units_d, order_d, identity_d, sched, level, indeg, lp, lev_up, lev_dn, up_ptr, dn_ptr, up, dn,
+      aperp, bnd, vol, counter, blk_base;
+  int32_t n_blocks = 0;  // 256-task blocks over all units (prep kernel)
+  int32_t max_depth = 0;
   // reduction tables (depend on G)
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
-  Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64;
+  Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, out_s;
 };
 
 namespace {
@@ -217,8 +262,8 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   if (!(p->albedo >= 0.0f) || !(p->albedo < 1.0f)) return fail(SWEEP_ERR_INVALID_ARG, "albedo must be in [0, 1)");
   if (p->form != SWEEP_FORM_BATCHED && p->form != SWEEP_FORM_PLAIN)
     return fail(SWEEP_ERR_INVALID_ARG, "unknown form %d", p->form);
-  if (p->block != 0 && (p->block < 64 || p->block > 1024 || p->block % 64 != 0))
-    return fail(SWEEP_ERR_INVALID_ARG, "block must be a multiple of 64 in [64, 1024]");
+  if (p->block != 0 && p->block != 256 && p->block != 512 && p->block != 1024)
+    return fail(SWEEP_ERR_INVALID_ARG, "block must be 256, 512 or 1024");
   if (p->ring != 0 && (p->ring < 64 || (p->ring & (p->ring - 1)) != 0))
     return fail(SWEEP_ERR_INVALID_ARG, "ring must be a power of two >= 64");
   if (p->boundary == SWEEP_BOUNDARY_VACUUM) p->n_pbc = 1;
@@ -243,60 +288,96 @@ std::vector<std::pair<int, int>> group_chunks(int G, bool plain) {
 int default_ring(int gn, int ring) {
   if (ring > 0) return ring;
   int r = 1;
-  while ((size_t)(r * 2) * gn * sizeof(float) <= 64 * 1024 - 256) r *= 2;
+  while ((size_t)(r * 2) * gn * sizeof(float) <= 64 * 1024) r *= 2;
   return r;
 }
 
+// Per-task denominators and sources for one sweep (schedule order).
+sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
+                        const float* gsrc, const float* jsum_prev, float albedo, hipStream_t s) {
+  HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
+  sweep::PrepArgs q{};
+  q.units = d->units_d.as<Unit>();
+  q.n_units = (int32_t)d->units.size();
+  q.blk_base = d->blk_base.as<int32_t>();
+  q.sched = d->sched.as<int32_t>();
+  q.aperp = d->aperp.as<float>();
+  q.kappa = kappa;
+  q.vol = d->vol.as<float>();
+  q.emission = emission;
+  q.gsrc = gsrc;
+  q.jsum_prev = jsum_prev;
+  q.albedo = albedo;
+  q.inv_D = 1.0f / (float)d->D;
+  q.G = G;
+  q.tden = d->tden.as<float>();
+  q.tsrc = d->tsrc.as<float>();
+  ProfScope ps("prep", s);
+  HIP_TRY(sweep::launch_prep(q, d->n_blocks, s));
+  return SWEEP_OK;
+}
+
+// One sweep of every unit (after run_prep).
 sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t G,
-                         const float* kappa, const float* src, const float* jsum_prev,
                          const float* phi_prev, float* out, float* pin, hipStream_t s) {
   sweep::SweepArgs a{};
   a.units = d->units_d.as<Unit>();
   a.sched = d->sched.as<int32_t>();
   a.lp = d->lp.as<int32_t>();
+  a.lev = reverse ? d->lev_dn.as<int64_t>() : d->lev_up.as<int64_t>();
   a.row_ptr = reverse ? d->dn_ptr.as<int64_t>() : d->up_ptr.as<int64_t>();
   a.ent = reverse ? d->dn.as<int2>() : d->up.as<int2>();
-  a.aperp = d->aperp.as<float>();
-  a.kappa = kappa;
-  a.src = src;
-  a.vol = d->vol.as<float>();
-  a.jsum_prev = jsum_prev;
+  a.n_ent = reverse ? d->n_dn : d->n_up;
+  a.tden = d->tden.as<float>();
+  a.tsrc = d->tsrc.as<float>();
   a.phi_prev = phi_prev;
   a.out = out;
+  HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
+  a.out_s = d->out_s.as<float>();
   a.pin = pin;
   a.C_total = d->C_total;
   a.G = G;
   a.D = d->D;
-  a.albedo = p.albedo;
-  a.inv_D = 1.0f / (float)d->D;
-  const int block = p.block > 0 ? p.block : 512;
   const int n_units = (int)d->units.size();
   for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
+    const int block = p.block > 0 ? p.block : (gn == 1 ? 1024 : 512);
     const int ring = default_ring(gn, p.ring);
-    if (sweep::sweep_lds_bytes(gn, ring) > (size_t)d->lds_max)
-      return fail(SWEEP_ERR_INVALID_ARG, "ring %d x %d groups exceeds the %d bytes of LDS", ring, gn,
-                  d->lds_max);
+    const int stage = sweep::kStageEntries;
+    const int lp_cap = d->max_depth + 2;
+    const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, stage, lp_cap);
+    if (L.bytes > (size_t)d->lds_max)
+      return fail(p.ring > 0 ? SWEEP_ERR_INVALID_ARG : SWEEP_ERR_UNSUPPORTED,
+                  "ring %d x %d groups and %d levels need %zu bytes of LDS, %d available", ring, gn,
+                  d->max_depth, L.bytes, d->lds_max);
     a.g0 = g0;
     a.ring_mask = ring - 1;
+    a.stage_entries = stage;
+    a.lp_cap = lp_cap;
+    a.stage_off = L.stage_off;
+    a.lp_off = L.lp_off;
+    a.lev_off = L.lev_off;
     if (p.form == SWEEP_FORM_PLAIN) {
       a.work_counter = nullptr;
       a.n_units = 1;
       for (int u = 0; u < n_units; ++u) {
         a.unit_order = d->identity_d.as<int32_t>() + u;
-        hipError_t e = reverse ? sweep::launch_sweep_adj(a, gn, 1, block, ring, s)
-                               : sweep::launch_sweep_fwd(a, gn, 1, block, ring, s);
+        ProfScope ps(reverse ? "sweep_adj" : "sweep_fwd", s);
+        hipError_t e = reverse ? sweep::launch_sweep_adj(a, gn, 1, block, L.bytes, s)
+                               : sweep::launch_sweep_fwd(a, gn, 1, block, L.bytes, s);
         if (e != hipSuccess) return hip_fail(e, "sweep launch");
       }
     } else {
-      int per_cu = std::max(1, (int)((size_t)kMaxLds / (sweep::sweep_lds_bytes(gn, ring) + 256)));
+      int per_cu = std::max(1, (int)((size_t)kMaxLds / (L.bytes + 256)));
       per_cu = std::min(per_cu, std::max(1, 2048 / block));
       const int grid = std::min(n_units, d->cu_count * per_cu);
       a.work_counter = d->counter.as<int32_t>();
       a.unit_order = d->order_d.as<int32_t>();
       a.n_units = n_units;
       HIP_TRY(sweep::launch_fill_i32(a.work_counter, 1, 0, s));
-      hipError_t e = reverse ? sweep::launch_sweep_adj(a, gn, grid, block, ring, s)
-                             : sweep::launch_sweep_fwd(a, gn, grid, block, ring, s);
+      ProfScope ps(reverse ? "sweep_adj" : "sweep_fwd", s);
+      hipError_t e = reverse ? sweep::launch_sweep_adj(a, gn, grid, block, L.bytes, s)
+                             : sweep::launch_sweep_fwd(a, gn, grid, block, L.bytes, s);
       if (e != hipSuccess) return hip_fail(e, "sweep launch");
     }
   }
@@ -317,6 +398,45 @@ sweep_status_t check_common(sweep_dag_t d, int32_t G) {
 extern "C" {
 
 const char* sweep_last_error(void) { return g_err.c_str(); }
+
+sweep_status_t sweep_profile_enable(int32_t on) {
+  g_err.clear();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_profile_reset(void) {
+  g_err.clear();
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (ProfRec& r : g_prof) {
+    if (hipEventSynchronize(r.stop) == hipSuccess) {
+      g_event_pool.push_back(r.start);
+      g_event_pool.push_back(r.stop);
+    }
+  }
+  g_prof.clear();
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_profile_read(const char* kernel, int64_t* launches, double* total_ms) {
+  g_err.clear();
+  if (!kernel || !launches || !total_ms) return fail(SWEEP_ERR_INVALID_ARG, "NULL argument");
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  int64_t n = 0;
+  double ms = 0.0;
+  for (ProfRec& r : g_prof) {
+    if (r.name != kernel) continue;
+    HIP_TRY(hipEventSynchronize(r.stop));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, r.start, r.stop));
+    ms += t;
+    ++n;
+  }
+  *launches = n;
+  *total_ms = ms;
+  return SWEEP_OK;
+}
 
 sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, const double* dirs,
                                int32_t n_dirs, const sweep_build_opts_t* opts, void* stream,
@@ -376,6 +496,21 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
       blk_base[u + 1] = blk_base[u] + (U.n_cells + 255) / 256;
     }
   const int n_blocks = blk_base[n_units];
+  // cell-order tile tables (tiles never straddle meshes)
+  std::vector<int32_t> cbm, cbc;
+  int max_faces = 1, max_cells = 1;
+  for (int m = 0; m < n_meshes; ++m) {
+    for (int32_t c = 0; c < D->mesh_cells[m]; c += sweep::kTileCellsHost) {
+      cbm.push_back(m);
+      cbc.push_back(c);
+    }
+    std::vector<int64_t> fp(meshes[m].n_cells + 1);
+    HIP_TRY(hipMemcpy(fp.data(), meshes[m].face_ptr, 8 * fp.size(), hipMemcpyDeviceToHost));
+    for (int32_t c = 0; c < meshes[m].n_cells; ++c) max_faces = std::max<int>(max_faces, (int)(fp[c + 1] - fp[c]));
+    max_cells = std::max(max_cells, meshes[m].n_cells);
+  }
+  const int n_cblocks = (int)cbm.size();
+  const int dn_width = (max_faces + 3) / 4 * 4;
   std::vector<sweep::MeshDev> md(n_meshes);
   for (int m = 0; m < n_meshes; ++m) {
     md[m].face_ptr = meshes[m].face_ptr;
@@ -387,14 +522,19 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     md[m].n_cells = meshes[m].n_cells;
     md[m].cell_off = D->mesh_off[m];
   }
-  Buf meshes_d, dirs_d, blk_d, rowlen_up, rowlen_dn, cnt, inv, depth_d, err_d, len_up, len_dn, scan_tmp;
+  Buf cblk_mesh_d, cblk_c0_d, dnw, stats_d, meshes_d, dirs_d, rowlen_up, rowlen_dn, cnt, inv, depth_d, err_d, len_up, len_dn, scan_tmp;
   HIP_TRY(meshes_d.alloc(sizeof(sweep::MeshDev) * n_meshes));
   HIP_TRY(dirs_d.alloc(sizeof(double) * 3 * n_dirs));
-  HIP_TRY(blk_d.alloc(sizeof(int32_t) * (n_units + 1)));
+  HIP_TRY(D->blk_base.alloc(sizeof(int32_t) * (n_units + 1)));
+  D->n_blocks = n_blocks;
   HIP_TRY(D->units_d.alloc(sizeof(Unit) * n_units));
+  HIP_TRY(cblk_mesh_d.alloc(4 * cbm.size()));
+  HIP_TRY(cblk_c0_d.alloc(4 * cbc.size()));
+  HIP_TRY(hipMemcpyAsync(cblk_mesh_d.p, cbm.data(), 4 * cbm.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(cblk_c0_d.p, cbc.data(), 4 * cbc.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(meshes_d.p, md.data(), sizeof(sweep::MeshDev) * n_meshes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(dirs_d.p, dirs, sizeof(double) * 3 * n_dirs, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(blk_d.p, blk_base.data(), sizeof(int32_t) * (n_units + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(D->blk_base.p, blk_base.data(), sizeof(int32_t) * (n_units + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   HIP_TRY(D->indeg.alloc(4 * T));
   HIP_TRY(rowlen_up.alloc(4 * T));
@@ -409,13 +549,25 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(depth_d.alloc(4 * n_units));
   HIP_TRY(err_d.alloc(4));
   HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 1, 0, s));
+  HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + 64)));
+  HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, 64, -1, s));
+  HIP_TRY(stats_d.alloc(8));
+  HIP_TRY(sweep::launch_fill_i32(stats_d.as<int32_t>(), 2, 0, s));
   sweep::DagBuildArgs a{};
   a.units = D->units_d.as<Unit>();
   a.n_units = n_units;
+  a.D = n_dirs;
+  a.cblk_mesh = cblk_mesh_d.as<int32_t>();
+  a.cblk_c0 = cblk_c0_d.as<int32_t>();
+  a.dn_width = dn_width;
+  a.max_faces = max_faces;
+  a.dnw = dnw.as<int32_t>();
+  a.dn_sentinel = (int64_t)T * dn_width;
+  a.stats = stats_d.as<int32_t>();
   a.meshes = meshes_d.as<sweep::MeshDev>();
   a.dirs = dirs_d.as<double>();
   a.eps = eps;
-  a.blk_base = blk_d.as<int32_t>();
+  a.blk_base = D->blk_base.as<int32_t>();
   a.indeg = D->indeg.as<int32_t>();
   a.rowlen_up = rowlen_up.as<int32_t>();
   a.rowlen_dn = rowlen_dn.as<int32_t>();
@@ -428,14 +580,32 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.lp = D->lp.as<int32_t>();
   a.depth = depth_d.as<int32_t>();
   a.err = err_d.as<int32_t>();
-  HIP_TRY(sweep::launch_count(a, n_blocks, s));
-  HIP_TRY(sweep::launch_kahn(a, s));
+  {
+    ProfScope ps("count", s);
+    HIP_TRY(sweep::launch_count(a, n_cblocks, s));
+  }
+  int32_t stats[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  // Kahn counters in LDS as 4-bit fields when every in-degree fits and the mesh fits the LDS
+  int lds_limit = 65536;
+  (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, D->device);
+  const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8) + 9 * 1024 <= (size_t)lds_limit;
+  {
+    ProfScope ps("kahn", s);
+    HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));
+  }
   std::vector<int32_t> depth(n_units);
   int32_t err = 0;
   HIP_TRY(hipMemcpyAsync(depth.data(), depth_d.p, 4 * n_units, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&err, err_d.p, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (err) return fail(SWEEP_ERR_CYCLE, "a dependency graph is cyclic: some tasks never become ready");
+  for (int u = 0; u < n_units; ++u) {
+    D->units[u].depth = depth[u];
+    D->max_depth = std::max(D->max_depth, depth[u]);
+  }
+  HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   // row lengths in schedule order -> row pointers
   HIP_TRY(len_up.alloc(8 * (T + 1)));
   HIP_TRY(len_dn.alloc(8 * (T + 1)));
@@ -460,13 +630,20 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(D->dn.alloc(8 * std::max<int64_t>(D->n_dn, 1)));
   a.up = D->up.as<int2>();
   a.dn = D->dn.as<int2>();
-  HIP_TRY(sweep::launch_fill(a, n_blocks, s));
+  {
+    ProfScope ps("fill", s);
+    HIP_TRY(sweep::launch_fill(a, n_cblocks, s));
+  }
+  HIP_TRY(D->lev_up.alloc(8 * (T + 2 * (int64_t)n_units)));
+  HIP_TRY(D->lev_dn.alloc(8 * (T + 2 * (int64_t)n_units)));
+  a.lev_up = D->lev_up.as<int64_t>();
+  a.lev_dn = D->lev_dn.as<int64_t>();
+  HIP_TRY(sweep::launch_level_entries(a, s));
   HIP_TRY(D->vol.alloc(4 * D->C_total));
   for (int m = 0; m < n_meshes; ++m)
     HIP_TRY(sweep::launch_d2f(meshes[m].cell_volume, D->vol.as<float>() + D->mesh_off[m],
                               meshes[m].n_cells, s));
   // schedule of the units: deepest first
-  for (int u = 0; u < n_units; ++u) D->units[u].depth = depth[u];
   D->order.resize(n_units);
   D->identity.resize(n_units);
   for (int u = 0; u < n_units; ++u) D->order[u] = D->identity[u] = u;
@@ -478,7 +655,6 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(D->order_d.alloc(4 * n_units));
   HIP_TRY(D->identity_d.alloc(4 * n_units));
   HIP_TRY(D->counter.alloc(64));
-  HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(D->order_d.p, D->order.data(), 4 * n_units, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(D->identity_d.p, D->identity.data(), 4 * n_units, hipMemcpyHostToDevice, s));
   {
@@ -523,8 +699,8 @@ sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
   info->max_depth = mx;
   info->min_depth = mn;
   info->mean_depth = sum / d->units.size();
-  const Buf* bufs[] = {&d->sched, &d->level, &d->indeg, &d->lp, &d->up_ptr, &d->dn_ptr, &d->up,
-                       &d->dn, &d->aperp, &d->bnd, &d->vol};
+  const Buf* bufs[] = {&d->sched, &d->level, &d->indeg, &d->lp, &d->lev_up, &d->lev_dn,
+                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->bnd, &d->vol};
   int64_t b = 0;
   for (const Buf* x : bufs) b += (int64_t)x->bytes;
   info->device_bytes = b;
@@ -628,8 +804,8 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     float* prev = nullptr;
     for (int ps = 0; ps < p.n_pbc; ++ps) {
       float* dst = ((p.n_pbc - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
-      ST_TRY(run_sweep(d, false, p, G, kappa, emission, jprev, prev, dst,
-                       periodic ? d->pin.as<float>() : nullptr, s));
+      if (ps == 0) ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, s));
+      ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, s));
       if (periodic && ps + 1 < p.n_pbc) {
         sweep::ReduceArgs q = r;
         q.phi = dst;
@@ -649,6 +825,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     q.jsum_prev = jprev;
     q.jsum = ckpt(it);
     q.last = 1;
+    ProfScope ps("reduce", s);
     HIP_TRY(sweep::launch_reduce(q, d->red_blocks, s));
   }
   HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
@@ -689,11 +866,12 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
     const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
     const float* phi_it = phi_final;
     if (it != p.n_scat - 1) {
-      ST_TRY(run_sweep(d, false, p, G, kappa, emission, jprev, nullptr, d->phi_a.as<float>(), nullptr, s));
+      ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, s));
+      ST_TRY(run_sweep(d, false, p, G, nullptr, d->phi_a.as<float>(), nullptr, s));
       phi_it = d->phi_a.as<float>();
     }
-    ST_TRY(run_sweep(d, true, p, G, kappa, d->gsrc.as<float>(), nullptr, nullptr, d->lam.as<float>(),
-                     nullptr, s));
+    ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, s));
+    ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, s));
     sweep::AdjReduceArgs q{};
     q.D = d->D;
     q.G = G;

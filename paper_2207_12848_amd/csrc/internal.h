@@ -33,10 +33,18 @@ struct MeshDev {
 struct DagBuildArgs {
   const Unit* units;
   int32_t n_units;
+  int32_t D;
   const MeshDev* meshes;
   const double* dirs;  // [D][3]
   double eps;
   const int32_t* blk_base;  // [n_units+1] first block of each unit (cell-range kernels)
+  const int32_t* cblk_mesh;  // cell-order kernels: mesh and first cell of every block
+  const int32_t* cblk_c0;
+  int32_t dn_width;          // width of the fixed-width downwind lists
+  int32_t max_faces;         // most half-faces of any cell
+  int32_t* dnw;              // [T][dn_width] downwind cells of every task (-1 padded)
+  int64_t dn_sentinel;       // offset in dnw of a row of -1 (4 * kRowChunks entries)
+  int32_t* stats;            // [0] max in-degree, [1] max out-degree (atomic max)
   // per task, cell order within the unit
   int32_t* indeg;
   int32_t* rowlen_up;
@@ -51,6 +59,8 @@ struct DagBuildArgs {
   int32_t* lp;     // level pointers
   int32_t* depth;  // [n_units]
   int32_t* err;    // set to 1 if a unit could not be fully ordered
+  int64_t* lev_up;  // per unit level table: first upwind-row entry of each level
+  int64_t* lev_dn;
   int64_t* len_up;  // [T+1] row lengths in schedule order (scan input)
   int64_t* len_dn;  // [T+1]
   int64_t* up_ptr;  // [T+1]
@@ -67,23 +77,45 @@ struct SweepArgs {
   int32_t* work_counter;  // persistent form: next unit to take; nullptr: unit = blockIdx.x
   const int32_t* sched;
   const int32_t* lp;
+  const int64_t* lev;      // per level: first row entry (lev_up forward, lev_dn adjoint)
   const int64_t* row_ptr;  // up_ptr (forward) or dn_ptr (adjoint)
   const int2* ent;         // up (forward) or dn (adjoint)
-  const float* aperp;      // per task, cell order
-  const float* kappa;      // [C][G]
-  const float* src;        // forward: emission [C][G]; adjoint: adjoint source [C][G]
-  const float* vol;        // [C]
-  const float* jsum_prev;  // forward: [C][G] sum_d phi of the previous iteration, or nullptr
+  int64_t n_ent;           // entries in `ent`
+  const float* tden;       // [T][G] schedule order: Aperp + kappa V
+  const float* tsrc;       // [T][G] schedule order: source of the task
   const float* phi_prev;   // forward: [D][C][G] previous periodic pass, or nullptr (zero inflow)
   float* out;              // phi (forward) or lambda (adjoint), [D][C][G]
+  float* out_s;            // the same values in schedule order, [T][G]
   float* pin;              // forward, periodic: inflow through periodic faces per task, or nullptr
   int64_t C_total;
   int32_t G;       // group stride
   int32_t g0;      // first group handled by this launch
   int32_t D;
   int32_t ring_mask;
+  int32_t stage_entries;  // LDS staging capacity per buffer (entries)
+  int32_t lp_cap;         // level-table capacity in LDS (>= depth + 2 of every unit)
+  int32_t stage_off;      // byte offsets in the dynamic LDS
+  int32_t lp_off;
+  int32_t lev_off;
+};
+
+// Per-call preparation of the per-task denominators and sources (schedule order).
+struct PrepArgs {
+  const Unit* units;
+  int32_t n_units;
+  const int32_t* blk_base;
+  const int32_t* sched;
+  const float* aperp;      // per task, cell order
+  const float* kappa;      // [C][G]
+  const float* vol;        // [C]
+  const float* emission;   // forward source [C][G] (divided by D), or
+  const float* gsrc;       // adjoint source [C][G] (used when emission == nullptr)
+  const float* jsum_prev;  // [C][G] or nullptr
   float albedo;
   float inv_D;
+  int32_t G;
+  float* tden;             // [T][G]
+  float* tsrc;             // [T][G]
 };
 
 // Reduction over directions (per cell and group).
@@ -129,10 +161,13 @@ struct AdjReduceArgs {
 };
 
 // launchers (kernels in dag.hip / sweep.hip)
-hipError_t launch_count(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
-hipError_t launch_kahn(const DagBuildArgs& a, hipStream_t s);
+constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build kernels
+hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s);
+hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);
 hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
-hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
+hipError_t launch_fill(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s);
+hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s);
+hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,
                            hipStream_t s);
 hipError_t launch_d2f(const double* in, float* out, int64_t n, hipStream_t s);
@@ -140,9 +175,9 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
 hipError_t launch_sweep_fwd(const SweepArgs& a, int32_t gn, int32_t grid, int32_t block,
-                            int32_t ring, hipStream_t s);
+                            size_t lds_bytes, hipStream_t s);
 hipError_t launch_sweep_adj(const SweepArgs& a, int32_t gn, int32_t grid, int32_t block,
-                            int32_t ring, hipStream_t s);
+                            size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_totals(const double* partial, const int32_t* mesh_blk_base, int32_t n_meshes,
                          int32_t G, double* totals, hipStream_t s);
@@ -153,6 +188,13 @@ hipError_t launch_adj_reduce(const AdjReduceArgs& a, double* dk, double* de, hip
 hipError_t launch_d2f_pair(const double* a, const double* b, float* oa, float* ob, int64_t n,
                            hipStream_t s);
 hipError_t set_sweep_lds_limit(int32_t bytes);
-size_t sweep_lds_bytes(int32_t gn, int32_t ring);
+// Dynamic LDS layout of a sweep workgroup: [ring: ring*gn f32][staging: 2*stage int2]
+// [level pointers: lp_cap i32][level entries: lp_cap i64]
+struct LdsLayout {
+  int32_t stage_off, lp_off, lev_off;
+  size_t bytes;
+};
+LdsLayout sweep_lds_layout(int32_t gn, int32_t ring, int32_t stage, int32_t lp_cap);
+constexpr int kStageEntries = 4096;  // row entries staged in LDS per level
 
 }  // namespace sweep

@@ -129,7 +129,7 @@ def test_forward_plain_equals_batched_bitwise():
     w = W.small_random(2000, 24, G=3, seed=40, n_meshes=2)
     _, J1, A1, _ = run_gpu(w, form="batched")
     _, J2, A2, _ = run_gpu(w, form="plain")
-    _, J3, A3, _ = run_gpu(w, form="batched", block=128, ring=256)
+    _, J3, A3, _ = run_gpu(w, form="batched", block=256, ring=256)
     assert np.array_equal(J1, J2) and np.array_equal(J1, J3)
     assert np.array_equal(A1, A2) and np.array_equal(A1, A3)
 
@@ -143,7 +143,7 @@ def test_forward_deterministic():
 
 def test_forward_small_ring_uses_global_fallback():
     w = W.small_random(4000, 8, G=2, seed=42)
-    check_forward(w, ring=64, block=64)
+    check_forward(w, ring=64, block=256)
 
 
 def test_forward_periodic_passes():

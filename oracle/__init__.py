@@ -194,6 +194,13 @@ def adjoint(w: dict, gJ: np.ndarray, gA: np.ndarray, eps: float = EPS_TIE):
     return dk, de
 
 
+def num_threads() -> int:
+    """OpenMP threads the oracle's direction loops run on."""
+    lib = _load()
+    lib.orc_num_threads.restype = ctypes.c_int
+    return int(lib.orc_num_threads())
+
+
 def absorbed_loss_grads(w: dict):
     """Upstream gradients of L = sum_c V_c kappa_a,c J_c = sum_c absorbed_c / (4 pi)."""
     G = int(w["G"])

@@ -51,6 +51,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_ERR_ARG -1
@@ -495,4 +498,13 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   free(lsum);
   free(qorder);
   return status;
+}
+
+/* Number of OpenMP threads the parallel loops above use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -52,7 +52,105 @@ sweep_status_t hip_fail(hipError_t e, const char* what) {
     if (s_ != SWEEP_OK) return s_;          \
   } while (0)
 
-// Device buffer owned by the DAG (freed with it).
+// ---------------------------------------------------------------- device memory
+// Building a DAG allocates several large buffers and a caller typically builds,
+// sweeps and destroys one DAG after another; hipMalloc/hipFree of gigabytes on
+// every build would cost milliseconds (hipFree also synchronises the device).
+// Released buffers therefore go to a per-device cache and are handed out again
+// to later requests of a similar size.  Stream order is kept with events: a
+// buffer is released with an event recorded on the stream that last used it
+// (the calling thread's current stream, see StreamScope), and whoever takes it
+// from the cache makes its own stream wait for that event first.
+thread_local hipStream_t g_cur_stream = nullptr;
+thread_local bool g_release_synced = false;  // the device is idle: release without an event
+
+// Sets the calling thread's current stream for allocations and releases.
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(g_cur_stream) { g_cur_stream = s; }
+  ~StreamScope() { g_cur_stream = prev; }
+};
+
+struct CachedBlock {
+  void* p;
+  size_t bytes;
+  int device;
+  hipEvent_t ready;  // recorded when the block was released (may be null)
+};
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+
+void cache_trim_all() {
+  std::vector<CachedBlock> blocks;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    blocks.swap(g_cache);
+  }
+  if (!blocks.empty()) (void)hipDeviceSynchronize();
+  for (CachedBlock& b : blocks) {
+    if (b.ready) (void)hipEventDestroy(b.ready);
+    (void)hipFree(b.p);
+  }
+}
+
+hipError_t cached_malloc(void** p, size_t* bytes, size_t n) {
+  // sizes are rounded to 2 KiB (small) or 2 MiB (large) so that repeated builds
+  // of similar meshes reuse the same blocks
+  n = n <= (8u << 20) ? (n + 2047) / 2048 * 2048 : (n + (2u << 20) - 1) / (2u << 20) * (2u << 20);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    int best = -1;
+    for (int i = 0; i < (int)g_cache.size(); ++i) {
+      const CachedBlock& b = g_cache[i];
+      if (b.device != dev || b.bytes < n || b.bytes > n + n / 4 + (1u << 20)) continue;
+      if (best < 0 || b.bytes < g_cache[best].bytes) best = i;
+    }
+    if (best >= 0) {
+      CachedBlock b = g_cache[best];
+      g_cache.erase(g_cache.begin() + best);
+      if (b.ready) {
+        (void)hipStreamWaitEvent(g_cur_stream, b.ready, 0);
+        (void)hipEventDestroy(b.ready);
+      }
+      *p = b.p;
+      *bytes = b.bytes;
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, n);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    cache_trim_all();
+    e = hipMalloc(p, n);
+  }
+  if (e == hipSuccess) *bytes = n;
+  return e;
+}
+
+void cached_free(void* p, size_t bytes) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipEvent_t ev = nullptr;
+  if (g_release_synced) {
+    ev = nullptr;
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+    if (hipEventRecord(ev, g_cur_stream) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      ev = nullptr;
+      (void)hipDeviceSynchronize();
+    }
+  } else {
+    ev = nullptr;
+    (void)hipDeviceSynchronize();
+  }
+  std::lock_guard<std::mutex> g(g_cache_mu);
+  g_cache.push_back({p, bytes, dev, ev});
+}
+
+// Device buffer owned by the DAG (or a call); released to the cache.
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -61,7 +159,7 @@ struct Buf {
   Buf& operator=(const Buf&) = delete;
   ~Buf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) cached_free(p, bytes);
     p = nullptr;
     bytes = 0;
   }
@@ -69,9 +167,11 @@ struct Buf {
     if (n <= bytes && p) return hipSuccess;
     release();
     if (n == 0) n = 16;
-    hipError_t e = hipMalloc(&p, n);
-    if (e == hipSuccess) bytes = n;
-    else p = nullptr;
+    hipError_t e = cached_malloc(&p, &bytes, n);
+    if (e != hipSuccess) {
+      p = nullptr;
+      bytes = 0;
+    }
     return e;
   }
   template <class T>
@@ -455,6 +555,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     if (!(std::fabs(n - 1.0) <= 1e-12)) return fail(SWEEP_ERR_INVALID_ARG, "direction %d is not a unit vector", d);
   }
   hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
   std::unique_ptr<sweep_dag_s> dag(new sweep_dag_s());
   sweep_dag_s* D = dag.get();
   HIP_TRY(hipGetDevice(&D->device));
@@ -465,9 +566,9 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   int64_t off = 0;
   for (int m = 0; m < n_meshes; ++m) {
     const sweep_mesh_t& M = meshes[m];
-    if (M.n_cells < 1 || M.n_half_faces < 0 || !M.face_ptr || !M.cell_volume ||
-        (M.n_half_faces > 0 && (!M.face_nbr || !M.face_area || !M.face_normal)))
-      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: missing arrays or no cells", m);
+    if (M.n_cells < 1 || M.n_half_faces < 1 || !M.face_ptr || !M.cell_volume || !M.face_nbr ||
+        !M.face_area || !M.face_normal)
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: missing arrays, no cells or no faces", m);
     if (validate) ST_TRY(validate_mesh_host(M, m));
     D->mesh_off.push_back((int32_t)off);
     D->mesh_cells.push_back(M.n_cells);
@@ -541,7 +642,9 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
-  HIP_TRY(cnt.alloc(4 * T));
+  // overflow counters of Kahn's algorithm, then (when the levels do not fit the
+  // LDS) the per-level cursors of the counting sort, at the units' lp offsets
+  HIP_TRY(cnt.alloc(4 * (T + 2 * (int64_t)n_units + 2)));
   HIP_TRY(inv.alloc(4 * T));
   HIP_TRY(D->level.alloc(4 * T));
   HIP_TRY(D->sched.alloc(4 * T));
@@ -549,8 +652,9 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(depth_d.alloc(4 * n_units));
   HIP_TRY(err_d.alloc(4));
   HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 1, 0, s));
-  HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + 64)));
-  HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, 64, -1, s));
+  const int sent_len = std::max(64, dn_width);  // sentinel row of -1 after the rows
+  HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + sent_len)));
+  HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, sent_len, -1, s));
   HIP_TRY(stats_d.alloc(8));
   HIP_TRY(sweep::launch_fill_i32(stats_d.as<int32_t>(), 2, 0, s));
   sweep::DagBuildArgs a{};
@@ -580,17 +684,30 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.lp = D->lp.as<int32_t>();
   a.depth = depth_d.as<int32_t>();
   a.err = err_d.as<int32_t>();
+  int lds_limit = 65536;
+  (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, D->device);
+  if (sweep::count_lds_bytes(max_faces, dn_width) > (size_t)lds_limit)
+    return fail(SWEEP_ERR_UNSUPPORTED, "a cell has %d faces; at most %d are supported", max_faces,
+                (int)(max_faces * (double)lds_limit / sweep::count_lds_bytes(max_faces, dn_width)));
   {
     ProfScope ps("count", s);
     HIP_TRY(sweep::launch_count(a, n_cblocks, s));
   }
+  // the longest downwind list sets how much of every row Kahn's algorithm loads
   int32_t stats[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  // Kahn counters in LDS as 4-bit fields when every in-degree fits and the mesh fits the LDS
-  int lds_limit = 65536;
-  (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, D->device);
-  const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8) + 9 * 1024 <= (size_t)lds_limit;
+  a.dn_chunks = std::max(1, (stats[1] + 3) / 4);
+  // the counting sort after Kahn writes the row lengths in schedule order (scan input)
+  HIP_TRY(len_up.alloc(8 * (T + 1)));
+  HIP_TRY(len_dn.alloc(8 * (T + 1)));
+  a.len_up = len_up.as<int64_t>();
+  a.len_dn = len_dn.as<int64_t>();
+  HIP_TRY(hipMemsetAsync(a.len_up + T, 0, 8, s));
+  HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 8, s));
+  // Kahn counters in LDS as 4-bit fields when the mesh fits the LDS
+  // (the kernel's static LDS holds two frontier copies of 2048 cells)
+  const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8) + 17 * 1024 <= (size_t)lds_limit;
   {
     ProfScope ps("kahn", s);
     HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));
@@ -605,19 +722,16 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     D->units[u].depth = depth[u];
     D->max_depth = std::max(D->max_depth, depth[u]);
   }
+  {
+    ProfScope ps("order", s);
+    HIP_TRY(sweep::launch_order(a, D->max_depth, lds_limit, s));
+  }
   HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   // row lengths in schedule order -> row pointers
-  HIP_TRY(len_up.alloc(8 * (T + 1)));
-  HIP_TRY(len_dn.alloc(8 * (T + 1)));
   HIP_TRY(D->up_ptr.alloc(8 * (T + 1)));
   HIP_TRY(D->dn_ptr.alloc(8 * (T + 1)));
-  a.len_up = len_up.as<int64_t>();
-  a.len_dn = len_dn.as<int64_t>();
   a.up_ptr = D->up_ptr.as<int64_t>();
   a.dn_ptr = D->dn_ptr.as<int64_t>();
-  HIP_TRY(hipMemsetAsync(a.len_up + T, 0, 8, s));
-  HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 8, s));
-  HIP_TRY(sweep::launch_gather_len(a, n_blocks, s));
   size_t tmp_bytes = 0;
   HIP_TRY(sweep::launch_scan_i64(a.len_up, a.up_ptr, T + 1, nullptr, &tmp_bytes, s));
   HIP_TRY(scan_tmp.alloc(tmp_bytes));
@@ -632,7 +746,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.dn = D->dn.as<int2>();
   {
     ProfScope ps("fill", s);
-    HIP_TRY(sweep::launch_fill(a, n_cblocks, s));
+    HIP_TRY(sweep::launch_fill(a, n_blocks, s));
   }
   HIP_TRY(D->lev_up.alloc(8 * (T + 2 * (int64_t)n_units)));
   HIP_TRY(D->lev_dn.alloc(8 * (T + 2 * (int64_t)n_units)));
@@ -674,7 +788,14 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
 
 sweep_status_t sweep_destroy_dag(sweep_dag_t dag) {
   g_err.clear();
+  if (!dag) return SWEEP_OK;
+  // the DAG's buffers may still be in use on any stream the caller used; wait for
+  // the device once, then hand them to the cache as idle memory
+  (void)hipSetDevice(dag->device);
+  (void)hipDeviceSynchronize();
+  g_release_synced = true;
   delete dag;
+  g_release_synced = false;
   return SWEEP_OK;
 }
 
@@ -757,6 +878,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   if (saved && saved_bytes < need)
     return fail(SWEEP_ERR_INVALID_ARG, "saved workspace has %zu bytes, %zu needed", saved_bytes, need);
   hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
   const int64_t CG = d->C_total * G;
   const int64_t DCG = CG * d->D;
   ST_TRY(ensure_reduce_tables(d, G));
@@ -850,6 +972,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   if (saved_bytes < need)
     return fail(SWEEP_ERR_INVALID_ARG, "saved workspace has %zu bytes, %zu needed", saved_bytes, need);
   hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
   const int64_t CG = d->C_total * G;
   const int64_t DCG = CG * d->D;
   HIP_TRY(d->lam.alloc(4 * DCG));

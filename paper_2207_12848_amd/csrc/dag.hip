@@ -82,13 +82,15 @@ __device__ __forceinline__ FaceTile stage_tile(const DagBuildArgs& a, const Mesh
   return T;
 }
 
-size_t tile_lds_bytes(int max_faces) {
+__host__ __device__ inline size_t tile_lds_bytes(int max_faces) {
   const size_t cap = (size_t)kTileCells * max_faces;
-  return 8 * (kTileCells + 1) + cap * (24 + 8 + 4 + 1);
+  return (8 * (kTileCells + 1) + cap * (24 + 8 + 4 + 1) + 15) / 16 * 16;
 }
 
 // Per task: upwind/downwind counts, Aperp = sum of outflow w, boundary outflow
-// weights and the fixed-width list of downwind cells.
+// weights and the fixed-width list of downwind cells.  A thread handles one
+// cell of the tile for one direction; the rows of kCountBlock / kTileCells
+// directions are assembled in LDS and written out as contiguous blocks.
 __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_max[2];
@@ -96,19 +98,25 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   const int m = a.cblk_mesh[blockIdx.x];
   const MeshDev M = a.meshes[m];
   const FaceTile T = stage_tile(a, M, a.cblk_c0[blockIdx.x], smem, a.max_faces);
+  const int W = a.dn_width;
+  int32_t* srow = reinterpret_cast<int32_t*>(smem + tile_lds_bytes(a.max_faces));
   __syncthreads();
   const int ci = threadIdx.x % kTileCells;
+  const int dj = threadIdx.x / kTileCells;
+  constexpr int kDirs = kCountBlock / kTileCells;
   const int c = T.c0 + ci;
-  const int W = a.dn_width;
+  const int nc = T.cend - T.c0;
+  const bool cell = c < T.cend;
+  const int fb = cell ? (int)T.fp[ci] : 0, fe = cell ? (int)T.fp[ci + 1] : 0;
+  int32_t* row = srow + threadIdx.x * W;  // [dj][ci][W]
   int mi = 0, mo = 0;
-  if (c < T.cend) {
-    const int fb = (int)T.fp[ci], fe = (int)T.fp[ci + 1];
-    for (int d = threadIdx.x / kTileCells; d < a.D; d += kCountBlock / kTileCells) {
+  for (int d0 = 0; d0 < a.D; d0 += kDirs) {
+    const int d = d0 + dj;
+    if (cell && d < a.D) {
       const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
       const int64_t t = a.units[m * a.D + d].task_base + c;
       int nup = 0, npin = 0, ndn = 0;
       double ap = 0.0, wall = 0.0, per = 0.0;
-      int32_t* row = a.dnw + t * W;
       for (int f = fb; f < fe; ++f) {
         const double sv = orient(ox, oy, oz, T.nrm + 3 * f);
         const int nb = T.nbr[f];
@@ -132,6 +140,18 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
       mi = max(mi, nup);
       mo = max(mo, ndn);
     }
+    __syncthreads();
+    // the tile's rows of direction d0 + j are nc * W consecutive ints of dnw
+    const int per4 = nc * W / 4;
+    for (int i = threadIdx.x; i < kDirs * per4; i += kCountBlock) {
+      const int j = i / per4, r = i - j * per4;
+      if (d0 + j < a.D) {
+        const int64_t tb = a.units[m * a.D + d0 + j].task_base;
+        reinterpret_cast<int4*>(a.dnw + (tb + T.c0) * W)[r] =
+            reinterpret_cast<const int4*>(srow + j * kTileCells * W)[r];
+      }
+    }
+    __syncthreads();
   }
   atomicMax(&s_max[0], mi);
   atomicMax(&s_max[1], mo);
@@ -142,217 +162,237 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   }
 }
 
-constexpr int kFrontierCap = 2048;  // frontier entries mirrored in LDS per level
-constexpr int kRowChunks = 8;       // downwind-row chunks (4 cells each) loaded at once
+constexpr int kFrontierCap = 2048;  // frontier entries kept in LDS per level
 
-// Append `cell` to the schedule if `want`, one LDS atomic per wavefront; the
-// new level's first kFrontierCap entries are mirrored in LDS.
-__device__ __forceinline__ void push_ready(bool want, int cell, int* s_tail, int32_t* sched,
-                                           int32_t* inv, int* fr_next, int next_base) {
-  const unsigned long long m = __ballot(want);
-  if (m == 0ull) return;
-  const int lane = threadIdx.x & 63;
-  const int leader = __ffsll((long long)m) - 1;
-  int base = 0;
-  if (lane == leader) base = atomicAdd(s_tail, __popcll(m));
-  base = __shfl(base, leader);
-  if (want) {
-    const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-    sched[slot] = cell;
-    inv[cell] = slot;
-    if (slot - next_base < kFrontierCap) fr_next[slot - next_base] = cell;
-  }
+// Inclusive prefix sum over the 64 lanes of a wavefront (all lanes active):
+// shifts of 1, 2, 4, 8 inside each row of 16 lanes, then the row totals are
+// carried into the following rows with the row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ int wave_inclusive_sum(int x) {
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return x;
 }
 
 // Kahn's algorithm for one (mesh, direction) unit per workgroup: tasks without
 // upwind dependencies form level 0; solving a level decrements the counters of
-// its tasks' downwind cells and those reaching zero form the next level.
+// its tasks' downwind cells and those reaching zero form the next level.  The
+// kernel records the level of every task and the size of every level; the
+// schedule itself (tasks grouped by level) is laid out afterwards by k_order.
 // LDSCNT: the counters live in LDS as 4-bit fields; the value 15 marks a cell
 // whose count (>= 15) is kept in global memory instead (it is never changed, so
 // reading the field to pick the counter is race-free).
-template <bool LDSCNT>
+// NCH: chunks of 4 entries of a downwind row that are loaded at once (rows are
+// -1 padded; every cell's downwind list fits NCH chunks except for the NCH = 8
+// variant, which walks longer rows in a second loop).
+template <bool LDSCNT, int NCH>
 __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   extern __shared__ uint32_t nib[];
   __shared__ int fr[2][kFrontierCap];
-  __shared__ int s_tail;
+  __shared__ int s_cnt[3];
   const Unit U = a.units[blockIdx.x];
   const int C = U.n_cells;
   const int64_t tb = U.task_base;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63;
   int32_t* cnt = a.cnt + tb;
-  int32_t* sched = a.sched + tb;
-  int32_t* inv = a.inv + tb;
+  int32_t* spill = a.sched + tb;  // frontier entries beyond the LDS copy
   int32_t* level = a.level + tb;
   int32_t* lp = a.lp + U.lp_base;
   const int W = a.dn_width;
-  if (tid == 0) s_tail = 0;
+  const int Wr4 = W / 4;        // chunks per row
+  const int W4 = a.dn_chunks;  // chunks that may hold a downwind cell (<= Wr4)
+  if (tid < 3) s_cnt[tid] = 0;
   if (LDSCNT) {
     for (int wi = tid; wi < (C + 7) / 8; wi += nthr) {
+      int n[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) n[j] = a.indeg[tb + min(8 * wi + j, C - 1)];
       uint32_t v = 0;
+#pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int c = 8 * wi + j;
         if (c < C) {
-          const int n = a.indeg[tb + c];
-          if (n >= 15) cnt[c] = n;
-          v |= (uint32_t)min(n, 15) << (4 * j);
+          if (n[j] >= 15) cnt[c] = n[j];
+          v |= (uint32_t)min(n[j], 15) << (4 * j);
         }
       }
       nib[wi] = v;
     }
   }
   __syncthreads();
+  // level 0: cells without upwind dependencies
   for (int c0 = 0; c0 < C; c0 += nthr) {
     const int c = c0 + tid;
     bool ready = false;
     if (c < C) {
-      const int n = a.indeg[tb + c];
-      if (!LDSCNT) cnt[c] = n;
-      ready = (n == 0);
+      if (LDSCNT) {
+        ready = ((nib[c >> 3] >> (4 * (c & 7))) & 15u) == 0u;
+      } else {
+        const int n = a.indeg[tb + c];
+        cnt[c] = n;
+        ready = n == 0;
+      }
     }
-    push_ready(ready, c, &s_tail, sched, inv, fr[0], 0);
+    const unsigned long long m = __ballot(ready);
+    if (m != 0ull) {
+      const int leader = __ffsll((long long)m) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(&s_cnt[0], __popcll(m));
+      base = __shfl(base, leader);
+      if (ready) {
+        const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+        if (slot < kFrontierCap) fr[0][slot] = c;
+        else spill[slot] = c;
+      }
+    }
   }
   __syncthreads();
   int head = 0;
-  int tail = s_tail;
+  int tail = s_cnt[0];
   int l = 0;
+  __syncthreads();
   if (tid == 0) {
+    s_cnt[0] = 0;
     lp[0] = 0;
     lp[1] = tail;
   }
+  __syncthreads();
+  const int4* sent4 = reinterpret_cast<const int4*>(a.dnw + a.dn_sentinel);
+  // Level l: the frontier is [head, tail); its pushes count in s_cnt[l % 3].
+  // s_cnt[(l + 1) % 3] was last read right after the barrier that ended level
+  // l - 2, so it can be cleared now for level l + 1; one barrier per level.
   while (head < tail) {
+    if (tid == 0) s_cnt[(l + 1) % 3] = 0;
+    int* s_push = &s_cnt[l % 3];
     const int* frc = fr[l & 1];
     int* frn = fr[(l + 1) & 1];
-    // a level whose frontier fits the LDS copy reads it from LDS only (no
-    // vector-memory load joins the path, so nothing waits on older stores)
-    auto level_body = [&](auto from_lds) {
-      constexpr bool FROM_LDS = decltype(from_lds)::value;
-      // wave-uniform rounds: lanes without a task take part with nothing to push
-      for (int kb = head; kb < tail; kb += nthr) {
-        const int k = kb + tid;
-        const bool active = k < tail;
-        if (__ballot(active) == 0ull) continue;  // wavefront without tasks this round
-        const int c = !active ? 0 : (FROM_LDS ? frc[k - head] : sched[k]);
-        if (active) level[c] = l;
-        // the whole downwind row is loaded at once (W is a multiple of 4), every
-        // counter is decremented, then the ready cells are compacted with one
-        // wavefront prefix sum
-        // every chunk load is unconditional: lanes without a task, and chunks past
-      // the row width, read a sentinel row of -1 instead (an address select), so
-      // all loads are in flight together
-      const int4* sent4 = reinterpret_cast<const int4*>(a.dnw + a.dn_sentinel);
+    for (int kb = head; kb < tail; kb += nthr) {
+      const int k = kb + tid;
+      const bool active = k < tail;
+      if (__ballot(active) == 0ull) continue;  // wavefront without tasks this round
+      const int kk = k - head;
+      const int c = !active ? 0 : (kk < kFrontierCap ? frc[kk] : spill[k]);
+      if (active) level[c] = l;
+      // all NCH chunk loads are unconditional: lanes without a task, and chunks
+      // past the row width, read a sentinel row of -1 instead (an address
+      // select), so they are in flight together
       const int4* row4 = active ? reinterpret_cast<const int4*>(a.dnw + (tb + c) * W) : sent4;
-        const int W4 = W >> 2;
-        int4 v[kRowChunks];
-  #pragma unroll
-        for (int q = 0; q < kRowChunks; ++q) v[q] = (q < W4 ? row4 : sent4)[q];
-        auto dec_global = [&](int nb) -> bool {
-          const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-          return old == 1;
-        };
-        uint32_t wm = 0;  // bit 4q+i: cell i of chunk q became ready
-        if (LDSCNT) {
-          // batched: every counter word is read, then every LDS decrement issued,
-          // so each batch costs two LDS round trips
-          uint32_t word[4 * kRowChunks];
-  #pragma unroll
-          for (int q = 0; q < kRowChunks; ++q) {
-            const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-  #pragma unroll
-            for (int i = 0; i < 4; ++i) word[4 * q + i] = nib[(xs[i] >= 0 ? xs[i] : 0) >> 3];
-          }
-          uint32_t old[4 * kRowChunks];
-  #pragma unroll
-          for (int q = 0; q < kRowChunks; ++q) {
-            const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-  #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int nb = xs[i];
-              const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-              old[4 * q + i] = 0;
-              if (nb >= 0 && ((word[4 * q + i] >> sh) & 15u) != 15u)
-                old[4 * q + i] = atomicSub(&nib[nb >> 3], 1u << sh);
-            }
-          }
-  #pragma unroll
-          for (int q = 0; q < kRowChunks; ++q) {
-            const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-  #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int nb = xs[i];
-              if (nb < 0) continue;
-              const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-              bool ready;
-              if (((word[4 * q + i] >> sh) & 15u) != 15u) ready = ((old[4 * q + i] >> sh) & 15u) == 1u;
-              else ready = dec_global(nb);
-              wm |= (uint32_t)ready << (4 * q + i);
-            }
-          }
-        } else {
-  #pragma unroll
-          for (int q = 0; q < kRowChunks; ++q) {
-            const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-  #pragma unroll
-            for (int i = 0; i < 4; ++i)
-              if (xs[i] >= 0) wm |= (uint32_t)dec_global(xs[i]) << (4 * q + i);
-          }
-        }
-        auto dec = [&](int nb) -> bool {
-          if (nb < 0) return false;
-          const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-          if (LDSCNT && ((nib[nb >> 3] >> sh) & 15u) != 15u) {
-            const uint32_t o = atomicSub(&nib[nb >> 3], 1u << sh);
-            return ((o >> sh) & 15u) == 1u;
-          }
-          return dec_global(nb);
-        };
-        // rows wider than kRowChunks chunks (cells with more than 32 faces)
-        for (int q = kRowChunks; q < W4; ++q) {
-          const int4 x = row4[q];
-          const int xs[4] = {x.x, x.y, x.z, x.w};
-          for (int i = 0; i < 4; ++i) {
-            const bool ready = dec(xs[i]);
-            push_ready(ready, xs[i], &s_tail, sched, inv, frn, tail);
-          }
-        }
-        // wavefront prefix sum of the ready counts, one LDS atomic per wavefront
-        const int n = __popc(wm);
-        const int lane = threadIdx.x & 63;
-        int incl = n;
-  #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const int y = __shfl_up(incl, o);
-          if (lane >= o) incl += y;
-        }
-        const unsigned long long act = __ballot(1);
-        const int last = 63 - __clzll((long long)act);
-        const int total = __shfl(incl, last);
-        int base = 0;
-        if (lane == last && total > 0) base = atomicAdd(&s_tail, total);
-        base = __shfl(base, last) + incl - n;
-  #pragma unroll
-        for (int q = 0; q < kRowChunks; ++q) {
+      int4 v[NCH];
+#pragma unroll
+      for (int q = 0; q < NCH; ++q) v[q] = (q < Wr4 ? row4 : sent4)[q];
+      auto dec_global = [&](int nb) -> bool {
+        const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+        return old == 1;
+      };
+      uint32_t wm = 0;  // bit 4q+i: cell i of chunk q became ready
+      if (LDSCNT) {
+        // every counter word is read, then every decrement issued: two LDS round trips
+        uint32_t word[4 * NCH];
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-  #pragma unroll
+#pragma unroll
+          for (int i = 0; i < 4; ++i) word[4 * q + i] = nib[(xs[i] >= 0 ? xs[i] : 0) >> 3];
+        }
+        uint32_t old[4 * NCH];
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
-            if (wm & (1u << (4 * q + i))) {
-              const int slot = base++;
-              sched[slot] = xs[i];
-              inv[xs[i]] = slot;
-              if (slot - tail < kFrontierCap) frn[slot - tail] = xs[i];
+            const int nb = xs[i];
+            const uint32_t sh = (uint32_t)(nb & 7) * 4u;
+            old[4 * q + i] = 0;
+            if (nb >= 0 && ((word[4 * q + i] >> sh) & 15u) != 15u)
+              old[4 * q + i] = atomicSub(&nib[nb >> 3], 1u << sh);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int nb = xs[i];
+            if (nb < 0) continue;
+            const uint32_t sh = (uint32_t)(nb & 7) * 4u;
+            bool ready;
+            if (((word[4 * q + i] >> sh) & 15u) != 15u) ready = ((old[4 * q + i] >> sh) & 15u) == 1u;
+            else ready = dec_global(nb);
+            wm |= (uint32_t)ready << (4 * q + i);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (xs[i] >= 0) wm |= (uint32_t)dec_global(xs[i]) << (4 * q + i);
+        }
+      }
+      // rows longer than NCH chunks (only possible for NCH = 8): one wavefront
+      // push per extra entry
+      for (int q = NCH; q < W4; ++q) {
+        const int4 x = row4[q];
+        const int xs[4] = {x.x, x.y, x.z, x.w};
+        for (int i = 0; i < 4; ++i) {
+          const int nb = xs[i];
+          bool ready = false;
+          if (nb >= 0) {
+            const uint32_t sh = (uint32_t)(nb & 7) * 4u;
+            if (LDSCNT && ((nib[nb >> 3] >> sh) & 15u) != 15u) {
+              const uint32_t o = atomicSub(&nib[nb >> 3], 1u << sh);
+              ready = ((o >> sh) & 15u) == 1u;
+            } else {
+              ready = dec_global(nb);
+            }
+          }
+          const unsigned long long m = __ballot(ready);
+          if (m != 0ull) {
+            const int leader = __ffsll((long long)m) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(s_push, __popcll(m));
+            base = __shfl(base, leader);
+            if (ready) {
+              const int r = base + __popcll(m & ((1ull << lane) - 1ull));
+              if (r < kFrontierCap) frn[r] = nb;
+              else spill[tail + r] = nb;
             }
           }
         }
       }
-    };
-    if (tail - head <= kFrontierCap) level_body(std::true_type{});
-    else level_body(std::false_type{});
+      // ready cells: one wavefront prefix sum and one LDS atomic per wavefront
+      const int n = __popc(wm);
+      const int incl = wave_inclusive_sum(n);
+      const int total = __builtin_amdgcn_readlane(incl, 63);
+      if (total > 0) {
+        int base = 0;
+        if (lane == 63) base = atomicAdd(s_push, total);
+        int r = __builtin_amdgcn_readlane(base, 63) + incl - n;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (wm & (1u << (4 * q + i))) {
+              if (r < kFrontierCap) frn[r] = xs[i];
+              else spill[tail + r] = xs[i];
+              ++r;
+            }
+          }
+        }
+      }
+    }
     __syncthreads();
     head = tail;
-    tail = s_tail;
+    tail += s_cnt[l % 3];
     ++l;
     if (tid == 0) lp[l + 1] = tail;
-    __syncthreads();
   }
   if (tid == 0) {
     a.depth[blockIdx.x] = l;
@@ -360,48 +400,131 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
-  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
-  const Unit U = a.units[u];
-  const int k = (blockIdx.x - a.blk_base[u]) * kCountBlock + threadIdx.x;
-  if (k >= U.n_cells) return;
-  const int64_t t = U.task_base + k;
-  const int c = a.sched[t];
-  a.len_up[t] = a.rowlen_up[U.task_base + c];
-  a.len_dn[t] = a.rowlen_dn[U.task_base + c];
+// Schedule of every unit from the levels: a counting sort by level, the slot
+// of level L starting at lp[L] (the level pointers written by k_kahn).  The
+// order inside a level is that of the LDS atomics; nothing computed from the
+// schedule depends on it.  Writes the schedule, its inverse and the row
+// lengths in schedule order (the input of the row-pointer scan).
+constexpr int kOrderBlock = 1024;
+
+template <bool LDSCUR>
+__global__ __launch_bounds__(kOrderBlock) void k_order(DagBuildArgs a) {
+  extern __shared__ int cur_lds[];
+  const Unit U = a.units[blockIdx.x];
+  const int C = U.n_cells;
+  const int64_t tb = U.task_base;
+  const int depth = a.depth[blockIdx.x];
+  const int32_t* lp = a.lp + U.lp_base;
+  int* cur = LDSCUR ? cur_lds : a.cnt + U.lp_base;  // per-level cursors
+  for (int l = threadIdx.x; l < depth; l += kOrderBlock) cur[l] = lp[l];
+  __syncthreads();
+  for (int c0 = 0; c0 < C; c0 += 4 * kOrderBlock) {
+    int lv[4], ru[4], rd[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = min(c0 + j * kOrderBlock + (int)threadIdx.x, C - 1);
+      lv[j] = a.level[tb + c];
+      ru[j] = a.rowlen_up[tb + c];
+      rd[j] = a.rowlen_dn[tb + c];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = c0 + j * kOrderBlock + (int)threadIdx.x;
+      if (c < C) {
+        const int slot = atomicAdd(&cur[lv[j]], 1);
+        a.sched[tb + slot] = c;
+        a.inv[tb + c] = slot;
+        a.len_up[tb + slot] = ru[j];
+        a.len_dn[tb + slot] = rd[j];
+      }
+    }
+  }
 }
 
-// Rows of the upwind and downwind lists, written at the task's schedule
-// position.  Entries follow the cell's face order, so the rows do not depend
-// on the schedule.
-__global__ __launch_bounds__(kCountBlock) void k_fill(DagBuildArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int m = a.cblk_mesh[blockIdx.x];
-  const MeshDev M = a.meshes[m];
-  const FaceTile T = stage_tile(a, M, a.cblk_c0[blockIdx.x], smem, a.max_faces);
-  __syncthreads();
-  const int ci = threadIdx.x % kTileCells;
-  const int c = T.c0 + ci;
-  if (c >= T.cend) return;
-  const int fb = (int)T.fp[ci], fe = (int)T.fp[ci + 1];
-  for (int d = threadIdx.x / kTileCells; d < a.D; d += kCountBlock / kTileCells) {
-    const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
-    const int64_t tb = a.units[m * a.D + d].task_base;
-    const int32_t* inv = a.inv + tb;
-    const int pos = inv[c];
-    int64_t eu = a.up_ptr[tb + pos];
-    int64_t ed = a.dn_ptr[tb + pos];
-    for (int f = fb; f < fe; ++f) {
-      const int nb = T.nbr[f];
-      if (nb < 0) continue;
-      const double sv = orient(ox, oy, oz, T.nrm + 3 * f);
-      const bool periodic = T.shift[f] != 0;
-      if (sv < -a.eps) {
-        const float w = (float)(T.area[f] * fabs(sv));
-        a.up[eu++] = make_int2(periodic ? -(nb + 1) : inv[nb], __float_as_int(w));
-      } else if (sv > a.eps && !periodic) {
-        const float w = (float)(T.area[f] * fabs(sv));
-        a.dn[ed++] = make_int2(inv[nb], __float_as_int(w));
+// Rows of the upwind and downwind lists, in schedule order: each wavefront
+// takes 16 consecutive schedule slots of one unit, 16 lanes sharing one task
+// (one face per lane, entries compacted with a ballot, so a row keeps the
+// cell's face order).  Consecutive slots write consecutive rows, and the
+// neighbours' schedule positions come from the unit's inverse schedule.
+constexpr int kFillBlock = 256;
+constexpr int kFillSlots = 16;   // slots per wavefront round
+constexpr int kFillRounds = 4;   // rounds per wavefront (256 slots per block)
+
+__global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
+  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const Unit U = a.units[u];
+  const MeshDev M = a.meshes[U.mesh];
+  const int64_t tb = U.task_base;
+  const double ox = a.dirs[3 * U.dir], oy = a.dirs[3 * U.dir + 1], oz = a.dirs[3 * U.dir + 2];
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const int wave = threadIdx.x >> 6;
+  const int32_t* inv = a.inv + tb;
+  const int kblk = (blockIdx.x - a.blk_base[u]) * kFillBlock + wave * kFillSlots * kFillRounds;
+  for (int r = 0; r < kFillRounds; ++r) {
+    const int k0 = kblk + r * kFillSlots;
+    if (k0 >= U.n_cells) break;
+    // lane li holds slot k0 + li (replicated in the four lane groups)
+    const int k = k0 + li;
+    const bool kv = k < U.n_cells;
+    const int kc = kv ? k : U.n_cells - 1;
+    const int c = a.sched[tb + kc];
+    const int64_t eu0 = a.up_ptr[tb + kc];
+    const int64_t ed0 = a.dn_ptr[tb + kc];
+    const int64_t f0 = M.face_ptr[c];
+    const int nf = kv ? (int)(M.face_ptr[c + 1] - f0) : 0;
+    int mx = nf;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) mx = max(mx, __shfl_xor(mx, o));
+    const int nch = (mx + 15) >> 4;
+    // group g handles slots k0 + 4g + j, j = 0..3
+    int64_t eu[4], ed[4], fb[4];
+    int nfj[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int src = 4 * g + j;
+      eu[j] = __shfl(eu0, src);
+      ed[j] = __shfl(ed0, src);
+      fb[j] = __shfl(f0, src);
+      nfj[j] = __shfl(nf, src);
+    }
+    const uint32_t below = (1u << li) - 1u;
+    for (int h = 0; h < nch; ++h) {
+      const int fo = h * 16 + li;
+      double nx[4], ny[4], nz[4], ar[4];
+      int nb[4], sh[4];
+      bool has[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        has[j] = fo < nfj[j];
+        const int64_t f = has[j] ? fb[j] + fo : 0;  // every mesh has a face 0
+        nx[j] = M.face_normal[3 * f];
+        ny[j] = M.face_normal[3 * f + 1];
+        nz[j] = M.face_normal[3 * f + 2];
+        ar[j] = M.face_area[f];
+        nb[j] = M.face_nbr[f];
+        sh[j] = M.face_shift != nullptr ? (int)M.face_shift[f] : 0;
+      }
+      int pos[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pos[j] = inv[nb[j] >= 0 ? nb[j] : 0];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double n3[3] = {nx[j], ny[j], nz[j]};
+        const double sv = orient(ox, oy, oz, n3);
+        const bool periodic = sh[j] != 0;
+        const bool up = has[j] && nb[j] >= 0 && sv < -a.eps;
+        const bool dn = has[j] && nb[j] >= 0 && !periodic && sv > a.eps;
+        const float w = (float)(ar[j] * fabs(sv));
+        const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
+        const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
+        if (up)
+          a.up[eu[j] + __popc(mu & below)] =
+              make_int2(periodic ? -(nb[j] + 1) : pos[j], __float_as_int(w));
+        if (dn) a.dn[ed[j] + __popc(md & below)] = make_int2(pos[j], __float_as_int(w));
+        eu[j] += __popc(mu);
+        ed[j] += __popc(md);
       }
     }
   }
@@ -436,9 +559,14 @@ inline unsigned grid1d(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+// LDS of k_count: the face tile, then one downwind row per thread.
+size_t count_lds_bytes(int max_faces, int dn_width) {
+  return tile_lds_bytes(max_faces) + (size_t)kCountBlock * dn_width * 4;
+}
+
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s) {
   if (n_cblocks <= 0) return hipSuccess;
-  const size_t lds = tile_lds_bytes(a.max_faces);
+  const size_t lds = count_lds_bytes(a.max_faces, a.dn_width);
   hipError_t e = hipFuncSetAttribute((const void*)k_count, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -446,32 +574,46 @@ hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s)
   return hipGetLastError();
 }
 
+template <int NCH>
+hipError_t launch_kahn_n(const DagBuildArgs& a, size_t lds, hipStream_t s) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_kahn<true, NCH>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_kahn<true, NCH>), dim3(a.n_units), dim3(kKahnBlock), lds, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s) {
   if (lds_counters) {
     const size_t lds = sizeof(uint32_t) * (size_t)((max_cells + 7) / 8);
-    hipError_t e = hipFuncSetAttribute((const void*)k_kahn<true>,
+    switch (a.dn_chunks) {
+      case 0: case 1: case 2: case 3: case 4: return launch_kahn_n<4>(a, lds, s);
+      case 5: return launch_kahn_n<5>(a, lds, s);
+      case 6: return launch_kahn_n<6>(a, lds, s);
+      case 7: return launch_kahn_n<7>(a, lds, s);
+      default: return launch_kahn_n<8>(a, lds, s);
+    }
+  }
+  hipLaunchKernelGGL((k_kahn<false, 8>), dim3(a.n_units), dim3(kKahnBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const DagBuildArgs& a, int32_t max_depth, int32_t lds_limit, hipStream_t s) {
+  const size_t lds = sizeof(int) * (size_t)(max_depth + 1);
+  if (lds <= (size_t)lds_limit) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_order<true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_kahn<true>, dim3(a.n_units), dim3(kKahnBlock), lds, s, a);
+    hipLaunchKernelGGL(k_order<true>, dim3(a.n_units), dim3(kOrderBlock), lds, s, a);
   } else {
-    hipLaunchKernelGGL(k_kahn<false>, dim3(a.n_units), dim3(kKahnBlock), 0, s, a);
+    hipLaunchKernelGGL(k_order<false>, dim3(a.n_units), dim3(kOrderBlock), 0, s, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
+hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather_len, dim3(n_blocks), dim3(kCountBlock), 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s) {
-  if (n_cblocks <= 0) return hipSuccess;
-  const size_t lds = tile_lds_bytes(a.max_faces);
-  hipError_t e = hipFuncSetAttribute((const void*)k_fill, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fill, dim3(n_cblocks), dim3(kCountBlock), lds, s, a);
+  hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct DagBuildArgs {
   const int32_t* cblk_mesh;  // cell-order kernels: mesh and first cell of every block
   const int32_t* cblk_c0;
   int32_t dn_width;          // width of the fixed-width downwind lists
+  int32_t dn_chunks;         // chunks of 4 row entries that may hold a downwind cell
   int32_t max_faces;         // most half-faces of any cell
   int32_t* dnw;              // [T][dn_width] downwind cells of every task (-1 padded)
   int64_t dn_sentinel;       // offset in dnw of a row of -1 (4 * kRowChunks entries)
@@ -164,8 +165,9 @@ struct AdjReduceArgs {
 constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build kernels
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s);
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);
-hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
-hipError_t launch_fill(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s);
+hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
+hipError_t launch_order(const DagBuildArgs& a, int32_t max_depth, int32_t lds_limit, hipStream_t s);
+size_t count_lds_bytes(int max_faces, int dn_width);
 hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,

@@ -38,8 +38,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 WORKLOADS = ("c1_plain_small", "c2_plain_scale", "c3_batched_groups", "c4_differentiation",
              "c5_uneven_scatter")
 # kernels whose counters a PMC summary under profiles/ may cover, and their source
-KERNEL_SOURCE = {"count": "dag.hip", "kahn": "dag.hip", "order": "dag.hip", "fill": "dag.hip",
-                 "prep": "sweep.hip",
+KERNEL_SOURCE = {"count": "dag.hip", "kahn": "dag.hip", "fill": "dag.hip", "prep": "sweep.hip",
                  "sweep_fwd": "sweep.hip", "sweep_adj": "sweep.hip", "reduce": "sweep.hip"}
 
 
@@ -66,11 +65,8 @@ def byte_model(kernel: str, s: dict) -> float:
         # faces once; per task indeg, two row lengths, Aperp, boundary pair; downwind ids
         return H * face + C * 8 + T * 24 + Ed * 4
     if kernel == "kahn":
-        # indeg and downwind ids in; levels out
-        return T * 4 + Ed * 4 + T * 4
-    if kernel == "order":
-        # levels and row lengths in; schedule, its inverse and row lengths (int64) out
-        return T * 12 + T * 8 + T * 16
+        # indeg and downwind ids in; schedule and its inverse out
+        return T * 4 + Ed * 4 + T * 8
     if kernel == "fill":
         # faces once, own schedule position, neighbour positions; (id, w) entries out
         return H * face + C * 8 + T * 4 + (Eu + Ed) * (4 + 8)
@@ -353,7 +349,7 @@ def main() -> int:
                 "sweep_us_per_level_fwd": round(
                     per_kernel.get("sweep_fwd", {}).get("avg_launch_ms", 0.0) * 1e3 /
                     max(depth_max, 1), 3)},
-        "phase_ms_per_step": {"build": round(kms("count", "kahn", "order", "fill"), 4),
+        "phase_ms_per_step": {"build": round(kms("count", "kahn", "fill"), 4),
                               "forward": round(kms("prep", "sweep_fwd", "reduce"), 4),
                               "adjoint": round(kms("sweep_adj"), 4)},
     }

@@ -185,7 +185,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
 
 /* Kernel timing with HIP events (for measurement tools).  While enabled, every
  * launch of the library's main kernels is bracketed by two hipEvents recorded
- * on the launch stream.  Kernel names: "count", "kahn", "order", "fill", "prep",
+ * on the launch stream.  Kernel names: "count", "kahn", "fill", "prep",
  * "sweep_fwd", "sweep_adj", "reduce".  sweep_profile_read synchronises on the
  * recorded events and returns the number of launches and their summed
  * duration (ms) since the last reset; unknown names read as zero. */

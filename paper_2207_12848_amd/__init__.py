@@ -193,7 +193,7 @@ def adjoint(dag: Dag, kappa, emission, saved, dL_dJ, dL_dabsorbed, stream=None, 
     return dk, de
 
 
-KERNELS = ("count", "kahn", "order", "fill", "prep", "sweep_fwd", "sweep_adj", "reduce")
+KERNELS = ("count", "kahn", "fill", "prep", "sweep_fwd", "sweep_adj", "reduce")
 
 
 def profile_enable(on: bool = True) -> None:

@@ -240,7 +240,7 @@ struct sweep_dag_s {
   std::vector<Unit> units;
   std::vector<int32_t> order;  // units, deepest first
   std::vector<int32_t> identity;
-  Buf units_d, order_d, identity_d, sched, level, indeg, lp, lev_up, lev_dn, up_ptr, dn_ptr, up, dn,
+  Buf units_d, order_d, identity_d, sched, indeg, lp, lev_up, lev_dn, up_ptr, dn_ptr, up, dn,
       aperp, bnd, vol, counter, blk_base;
   int32_t n_blocks = 0;  // 256-task blocks over all units (prep kernel)
   int32_t max_depth = 0;
@@ -620,8 +620,22 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     md[m].face_area = meshes[m].face_area;
     md[m].face_normal = meshes[m].face_normal;
     md[m].cell_volume = meshes[m].cell_volume;
+    md[m].n_faces = meshes[m].n_half_faces;
     md[m].n_cells = meshes[m].n_cells;
     md[m].cell_off = D->mesh_off[m];
+  }
+  // compact FP32 face records for the row fill
+  int64_t n_faces_total = 0;
+  for (int m = 0; m < n_meshes; ++m) n_faces_total += meshes[m].n_half_faces;
+  Buf frec;
+  HIP_TRY(frec.alloc(16 * n_faces_total));
+  {
+    int64_t fo = 0;
+    for (int m = 0; m < n_meshes; ++m) {
+      md[m].frec = frec.as<int4>() + fo;
+      HIP_TRY(sweep::launch_face_records(md[m], frec.as<int4>() + fo, s));
+      fo += meshes[m].n_half_faces;
+    }
   }
   Buf cblk_mesh_d, cblk_c0_d, dnw, stats_d, meshes_d, dirs_d, rowlen_up, rowlen_dn, cnt, inv, depth_d, err_d, len_up, len_dn, scan_tmp;
   HIP_TRY(meshes_d.alloc(sizeof(sweep::MeshDev) * n_meshes));
@@ -641,12 +655,11 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_up.alloc(4 * T));
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
+  Buf fmask;  // face bits per task, when every cell has at most 32 faces
+  if (max_faces <= 32) HIP_TRY(fmask.alloc(8 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
-  // overflow counters of Kahn's algorithm, then (when the levels do not fit the
-  // LDS) the per-level cursors of the counting sort, at the units' lp offsets
-  HIP_TRY(cnt.alloc(4 * (T + 2 * (int64_t)n_units + 2)));
+  HIP_TRY(cnt.alloc(4 * T));  // overflow counters of Kahn's algorithm
   HIP_TRY(inv.alloc(4 * T));
-  HIP_TRY(D->level.alloc(4 * T));
   HIP_TRY(D->sched.alloc(4 * T));
   HIP_TRY(D->lp.alloc(4 * (T + 2 * (int64_t)n_units)));
   HIP_TRY(depth_d.alloc(4 * n_units));
@@ -676,10 +689,10 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.rowlen_up = rowlen_up.as<int32_t>();
   a.rowlen_dn = rowlen_dn.as<int32_t>();
   a.aperp = D->aperp.as<float>();
+  a.fmask = max_faces <= 32 ? fmask.as<uint2>() : nullptr;
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
   a.inv = inv.as<int32_t>();
-  a.level = D->level.as<int32_t>();
   a.sched = D->sched.as<int32_t>();
   a.lp = D->lp.as<int32_t>();
   a.depth = depth_d.as<int32_t>();
@@ -698,7 +711,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   a.dn_chunks = std::max(1, (stats[1] + 3) / 4);
-  // the counting sort after Kahn writes the row lengths in schedule order (scan input)
+  // row lengths in schedule order (the input of the row-pointer scan)
   HIP_TRY(len_up.alloc(8 * (T + 1)));
   HIP_TRY(len_dn.alloc(8 * (T + 1)));
   a.len_up = len_up.as<int64_t>();
@@ -722,10 +735,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     D->units[u].depth = depth[u];
     D->max_depth = std::max(D->max_depth, depth[u]);
   }
-  {
-    ProfScope ps("order", s);
-    HIP_TRY(sweep::launch_order(a, D->max_depth, lds_limit, s));
-  }
+  HIP_TRY(sweep::launch_gather_len(a, n_blocks, s));
   HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   // row lengths in schedule order -> row pointers
   HIP_TRY(D->up_ptr.alloc(8 * (T + 1)));
@@ -820,7 +830,7 @@ sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
   info->max_depth = mx;
   info->min_depth = mn;
   info->mean_depth = sum / d->units.size();
-  const Buf* bufs[] = {&d->sched, &d->level, &d->indeg, &d->lp, &d->lev_up, &d->lev_dn,
+  const Buf* bufs[] = {&d->sched, &d->indeg, &d->lp, &d->lev_up, &d->lev_dn,
                        &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->bnd, &d->vol};
   int64_t b = 0;
   for (const Buf* x : bufs) b += (int64_t)x->bytes;
@@ -834,23 +844,29 @@ sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, i
   if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
   hipStream_t s = (hipStream_t)stream;
   const int64_t T = d->T;
-  if (level) HIP_TRY(hipMemcpyAsync(level, d->level.p, 4 * T, hipMemcpyDeviceToHost, s));
   if (indeg) HIP_TRY(hipMemcpyAsync(indeg, d->indeg.p, 4 * T, hipMemcpyDeviceToHost, s));
   std::vector<int32_t> sched, lp;
-  if (order) {
+  if (order || level) {
     sched.resize(T);
     lp.resize(T + 2 * d->units.size());
     HIP_TRY(hipMemcpyAsync(sched.data(), d->sched.p, 4 * T, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(lp.data(), d->lp.p, 4 * lp.size(), hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
-  if (order) {
-    // the schedule is grouped by level; the canonical order sorts each level by cell id
-    for (const Unit& U : d->units) {
-      const int32_t* l = lp.data() + U.lp_base;
-      int32_t* o = order + U.task_base;
-      std::memcpy(o, sched.data() + U.task_base, 4 * (size_t)U.n_cells);
-      for (int k = 0; k < U.depth; ++k) std::sort(o + l[k], o + l[k + 1]);
+  // the schedule groups every unit's cells by level (level k = slots [lp[k], lp[k+1]));
+  // the canonical order sorts each level by cell id
+  for (const Unit& U : d->units) {
+    if (!order && !level) break;
+    const int32_t* l = lp.data() + U.lp_base;
+    const int32_t* sc = sched.data() + U.task_base;
+    for (int k = 0; k < U.depth; ++k) {
+      if (level)
+        for (int32_t i = l[k]; i < l[k + 1]; ++i) level[U.task_base + sc[i]] = k;
+      if (order) {
+        int32_t* o = order + U.task_base;
+        std::memcpy(o + l[k], sc + l[k], 4 * (size_t)(l[k + 1] - l[k]));
+        std::sort(o + l[k], o + l[k + 1]);
+      }
     }
   }
   return SWEEP_OK;

@@ -30,6 +30,19 @@ __device__ __forceinline__ double orient(double ox, double oy, double oz, const 
   return (a + b) + c;
 }
 
+// Face weight w = A |Omega . n| in FP32 from the face's FP32 vector A n; the
+// same expression on both sides of a face (whose A n differ only in sign)
+// gives the same weight, so what a cell sends through a face is exactly what
+// its neighbour receives.  The face's class (inflow, outflow, none) is decided
+// by the FP64 orientation above, never by this value.
+__device__ __forceinline__ float face_w32(float ox, float oy, float oz, float ax, float ay,
+                                          float az) {
+  const float p = ox * ax;
+  const float q = oy * ay;
+  const float r = oz * az;
+  return fabsf((p + q) + r);
+}
+
 // Unit of block b (units own consecutive block ranges).
 __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_units, int b) {
   int lo = 0, hi = n_units - 1;
@@ -114,24 +127,34 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
     const int d = d0 + dj;
     if (cell && d < a.D) {
       const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
+      const float fx = (float)ox, fy = (float)oy, fz = (float)oz;
       const int64_t t = a.units[m * a.D + d].task_base + c;
       int nup = 0, npin = 0, ndn = 0;
+      uint32_t um = 0, dm = 0;
       double ap = 0.0, wall = 0.0, per = 0.0;
       for (int f = fb; f < fe; ++f) {
-        const double sv = orient(ox, oy, oz, T.nrm + 3 * f);
+        const double* n = T.nrm + 3 * f;
+        const double sv = orient(ox, oy, oz, n);
         const int nb = T.nbr[f];
         const bool periodic = T.shift[f] != 0;
+        const uint32_t bit = 1u << ((f - fb) & 31);
         if (sv > a.eps) {
-          const double w = T.area[f] * fabs(sv);
+          const double A = T.area[f];
+          const double w = face_w32(fx, fy, fz, (float)(A * n[0]), (float)(A * n[1]), (float)(A * n[2]));
           ap += w;
           if (nb < 0) wall += w;
           else if (periodic) per += w;
-          else row[ndn++] = nb;
+          else {
+            row[ndn++] = nb;
+            dm |= bit;
+          }
         } else if (sv < -a.eps && nb >= 0) {
           if (periodic) ++npin; else ++nup;
+          um |= bit;
         }
       }
       for (int q = ndn; q < W; ++q) row[q] = -1;
+      if (a.fmask != nullptr) a.fmask[t] = make_uint2(um, dm);
       a.indeg[t] = nup;
       a.rowlen_up[t] = nup + npin;
       a.rowlen_dn[t] = ndn;
@@ -180,8 +203,8 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
 // Kahn's algorithm for one (mesh, direction) unit per workgroup: tasks without
 // upwind dependencies form level 0; solving a level decrements the counters of
 // its tasks' downwind cells and those reaching zero form the next level.  The
-// kernel records the level of every task and the size of every level; the
-// schedule itself (tasks grouped by level) is laid out afterwards by k_order.
+// schedule lists every level's cells in the order they were appended (slots
+// [lp[l], lp[l+1]) hold level l), together with its inverse.
 // LDSCNT: the counters live in LDS as 4-bit fields; the value 15 marks a cell
 // whose count (>= 15) is kept in global memory instead (it is never changed, so
 // reading the field to pick the counter is race-free).
@@ -199,8 +222,9 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63;
   int32_t* cnt = a.cnt + tb;
-  int32_t* spill = a.sched + tb;  // frontier entries beyond the LDS copy
-  int32_t* level = a.level + tb;
+  int32_t* sched = a.sched + tb;
+  int32_t* spill = sched;  // frontier entries beyond the LDS copy (rewritten in place)
+  int32_t* inv = a.inv + tb;
   int32_t* lp = a.lp + U.lp_base;
   const int W = a.dn_width;
   const int Wr4 = W / 4;        // chunks per row
@@ -276,7 +300,10 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       if (__ballot(active) == 0ull) continue;  // wavefront without tasks this round
       const int kk = k - head;
       const int c = !active ? 0 : (kk < kFrontierCap ? frc[kk] : spill[k]);
-      if (active) level[c] = l;
+      if (active) {  // the level's cells in slot order form the schedule
+        sched[k] = c;
+        inv[c] = k;
+      }
       // all NCH chunk loads are unconditional: lanes without a task, and chunks
       // past the row width, read a sentinel row of -1 instead (an address
       // select), so they are in flight together
@@ -400,57 +427,123 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   }
 }
 
-// Schedule of every unit from the levels: a counting sort by level, the slot
-// of level L starting at lp[L] (the level pointers written by k_kahn).  The
-// order inside a level is that of the LDS atomics; nothing computed from the
-// schedule depends on it.  Writes the schedule, its inverse and the row
-// lengths in schedule order (the input of the row-pointer scan).
-constexpr int kOrderBlock = 1024;
+// Row lengths of every task at its schedule slot (the input of the row-pointer scan).
+__global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
+  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const Unit U = a.units[u];
+  const int k = (blockIdx.x - a.blk_base[u]) * kCountBlock + threadIdx.x;
+  if (k >= U.n_cells) return;
+  const int64_t t = U.task_base + k;
+  const int c = a.sched[t];
+  a.len_up[t] = a.rowlen_up[U.task_base + c];
+  a.len_dn[t] = a.rowlen_dn[U.task_base + c];
+}
 
-template <bool LDSCUR>
-__global__ __launch_bounds__(kOrderBlock) void k_order(DagBuildArgs a) {
-  extern __shared__ int cur_lds[];
-  const Unit U = a.units[blockIdx.x];
-  const int C = U.n_cells;
+// Per face: the neighbour code (>= 0: interior neighbour, -1: vacuum wall,
+// -(nb + 2): periodic image of cell nb) and A n rounded to FP32, 16 bytes that
+// the row fill reads instead of the FP64 geometry.
+__global__ void k_face_records(MeshDev M, int4* frec) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= M.n_faces) return;
+  const int nb = M.face_nbr[f];
+  const bool periodic = M.face_shift != nullptr && M.face_shift[f] != 0;
+  const double A = M.face_area[f];
+  const int code = nb < 0 ? -1 : (periodic ? -(nb + 2) : nb);
+  frec[f] = make_int4(code, __float_as_int((float)(A * M.face_normal[3 * f])),
+                      __float_as_int((float)(A * M.face_normal[3 * f + 1])),
+                      __float_as_int((float)(A * M.face_normal[3 * f + 2])));
+}
+
+// Rows of the upwind and downwind lists, in schedule order: each wavefront
+// takes 64 consecutive schedule slots of one unit.  Every lane first loads one
+// slot's task (cell, row pointers, face range, face bits from k_count); then,
+// 16 slots per round, 16 lanes share one task, one face record per lane.  The
+// face bits give every entry its place in the row (rows keep the cell's face
+// order); consecutive slots write consecutive rows, and the neighbours'
+// schedule positions come from the unit's inverse schedule.
+constexpr int kFillBlock = 256;
+
+__global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
+  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const Unit U = a.units[u];
+  const MeshDev M = a.meshes[U.mesh];
   const int64_t tb = U.task_base;
-  const int depth = a.depth[blockIdx.x];
-  const int32_t* lp = a.lp + U.lp_base;
-  int* cur = LDSCUR ? cur_lds : a.cnt + U.lp_base;  // per-level cursors
-  for (int l = threadIdx.x; l < depth; l += kOrderBlock) cur[l] = lp[l];
-  __syncthreads();
-  for (int c0 = 0; c0 < C; c0 += 4 * kOrderBlock) {
-    int lv[4], ru[4], rd[4];
+  const float fx = (float)a.dirs[3 * U.dir], fy = (float)a.dirs[3 * U.dir + 1],
+              fz = (float)a.dirs[3 * U.dir + 2];
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const int32_t* inv = a.inv + tb;
+  const int kw = (blockIdx.x - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
+  if (kw >= U.n_cells) return;
+  // lane L: the task of slot kw + L
+  const int k = kw + lane;
+  const bool kv = k < U.n_cells;
+  const int kc = kv ? k : U.n_cells - 1;
+  const int c = a.sched[tb + kc];
+  const int64_t eu0 = a.up_ptr[tb + kc];
+  const int64_t ed0 = a.dn_ptr[tb + kc];
+  const int64_t f0 = M.face_ptr[c];
+  const int nf = kv ? (int)(M.face_ptr[c + 1] - f0) : 0;
+  const uint2 bits = a.fmask[tb + c];
+  const int rounds = min(4, (U.n_cells - kw + 15) >> 4);
+  const uint32_t below = (1u << li) - 1u;
+  for (int r = 0; r < rounds; ++r) {
+    // group g handles slots kw + 16 r + 4 g + j, j = 0..3
+    int64_t eu[4], ed[4], fb[4];
+    uint32_t um[4], dm[4];
+    int nfj[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = min(c0 + j * kOrderBlock + (int)threadIdx.x, C - 1);
-      lv[j] = a.level[tb + c];
-      ru[j] = a.rowlen_up[tb + c];
-      rd[j] = a.rowlen_dn[tb + c];
+      const int src = 16 * r + 4 * g + j;
+      eu[j] = __shfl(eu0, src);
+      ed[j] = __shfl(ed0, src);
+      fb[j] = __shfl(f0, src);
+      nfj[j] = __shfl(nf, src);
+      um[j] = (uint32_t)__shfl((int)bits.x, src);
+      dm[j] = (uint32_t)__shfl((int)bits.y, src);
     }
+    // a cell has at most 32 faces here: two chunks of 16 at most
+    int mx = max(max(nfj[0], nfj[1]), max(nfj[2], nfj[3]));
+    mx = max(mx, __shfl_xor(mx, 16));
+    mx = max(mx, __shfl_xor(mx, 32));
+    for (int h = 0; h < 2 && h * 16 < mx; ++h) {
+      const int fo = h * 16 + li;
+      int4 rec[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = c0 + j * kOrderBlock + (int)threadIdx.x;
-      if (c < C) {
-        const int slot = atomicAdd(&cur[lv[j]], 1);
-        a.sched[tb + slot] = c;
-        a.inv[tb + c] = slot;
-        a.len_up[tb + slot] = ru[j];
-        a.len_dn[tb + slot] = rd[j];
+      for (int j = 0; j < 4; ++j) rec[j] = M.frec[fo < nfj[j] ? fb[j] + fo : 0];  // face 0 exists
+      int pos[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pos[j] = inv[rec[j].x >= 0 ? rec[j].x : 0];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t bit = 1u << fo;
+        const bool has = fo < nfj[j];
+        const bool up = has && (um[j] & bit) != 0u;
+        const bool dn = has && (dm[j] & bit) != 0u;
+        const float w = face_w32(fx, fy, fz, __int_as_float(rec[j].y), __int_as_float(rec[j].z),
+                                 __int_as_float(rec[j].w));
+        const uint32_t pre = h == 0 ? below : (0xffffu | (below << 16));  // faces before fo
+        if (up) {
+          const int code = rec[j].x;
+          a.up[eu[j] + __popc(um[j] & pre)] = make_int2(code >= 0 ? pos[j] : code + 1, __float_as_int(w));
+        }
+        if (dn) a.dn[ed[j] + __popc(dm[j] & pre)] = make_int2(pos[j], __float_as_int(w));
       }
     }
   }
 }
 
-// Rows of the upwind and downwind lists, in schedule order: each wavefront
-// takes 16 consecutive schedule slots of one unit, 16 lanes sharing one task
-// (one face per lane, entries compacted with a ballot, so a row keeps the
-// cell's face order).  Consecutive slots write consecutive rows, and the
-// neighbours' schedule positions come from the unit's inverse schedule.
-constexpr int kFillBlock = 256;
-constexpr int kFillSlots = 16;   // slots per wavefront round
-constexpr int kFillRounds = 4;   // rounds per wavefront (256 slots per block)
+// Rows of the upwind and downwind lists for meshes with cells of more than 32
+// faces (no face bits): the face classes are recomputed here in FP64.  Each wavefront
+// takes 64 consecutive schedule slots of one unit.  Every lane first loads one
+// slot's task (cell, row pointers, face range); then, 16 slots per round, 16
+// lanes share one task (one face per lane, entries compacted with a ballot, so
+// a row keeps the cell's face order).  Consecutive slots write consecutive
+// rows, and the neighbours' schedule positions come from the unit's inverse
+// schedule.
 
-__global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
+__global__ __launch_bounds__(kFillBlock) void k_fill_faces(DagBuildArgs a) {
   const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
   const Unit U = a.units[u];
   const MeshDev M = a.meshes[U.mesh];
@@ -459,37 +552,37 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15;
   const int g = lane >> 4;
-  const int wave = threadIdx.x >> 6;
   const int32_t* inv = a.inv + tb;
-  const int kblk = (blockIdx.x - a.blk_base[u]) * kFillBlock + wave * kFillSlots * kFillRounds;
-  for (int r = 0; r < kFillRounds; ++r) {
-    const int k0 = kblk + r * kFillSlots;
-    if (k0 >= U.n_cells) break;
-    // lane li holds slot k0 + li (replicated in the four lane groups)
-    const int k = k0 + li;
-    const bool kv = k < U.n_cells;
-    const int kc = kv ? k : U.n_cells - 1;
-    const int c = a.sched[tb + kc];
-    const int64_t eu0 = a.up_ptr[tb + kc];
-    const int64_t ed0 = a.dn_ptr[tb + kc];
-    const int64_t f0 = M.face_ptr[c];
-    const int nf = kv ? (int)(M.face_ptr[c + 1] - f0) : 0;
-    int mx = nf;
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) mx = max(mx, __shfl_xor(mx, o));
-    const int nch = (mx + 15) >> 4;
-    // group g handles slots k0 + 4g + j, j = 0..3
+  const int kw = (blockIdx.x - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
+  if (kw >= U.n_cells) return;
+  // lane L: the task of slot kw + L
+  const int k = kw + lane;
+  const bool kv = k < U.n_cells;
+  const int kc = kv ? k : U.n_cells - 1;
+  const int c = a.sched[tb + kc];
+  const int64_t eu0 = a.up_ptr[tb + kc];
+  const int64_t ed0 = a.dn_ptr[tb + kc];
+  const int64_t f0 = M.face_ptr[c];
+  const int nf = kv ? (int)(M.face_ptr[c + 1] - f0) : 0;
+  const int rounds = min(4, (U.n_cells - kw + 15) >> 4);
+  const uint32_t below = (1u << li) - 1u;
+  for (int r = 0; r < rounds; ++r) {
+    // group g handles slots kw + 16 r + 4 g + j, j = 0..3
     int64_t eu[4], ed[4], fb[4];
     int nfj[4];
+    int mx = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int src = 4 * g + j;
+      const int src = 16 * r + 4 * g + j;
       eu[j] = __shfl(eu0, src);
       ed[j] = __shfl(ed0, src);
       fb[j] = __shfl(f0, src);
       nfj[j] = __shfl(nf, src);
+      mx = max(mx, nfj[j]);
     }
-    const uint32_t below = (1u << li) - 1u;
+    mx = max(mx, __shfl_xor(mx, 16));
+    mx = max(mx, __shfl_xor(mx, 32));
+    const int nch = (mx + 15) >> 4;
     for (int h = 0; h < nch; ++h) {
       const int fo = h * 16 + li;
       double nx[4], ny[4], nz[4], ar[4];
@@ -516,7 +609,8 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
         const bool periodic = sh[j] != 0;
         const bool up = has[j] && nb[j] >= 0 && sv < -a.eps;
         const bool dn = has[j] && nb[j] >= 0 && !periodic && sv > a.eps;
-        const float w = (float)(ar[j] * fabs(sv));
+        const float w = face_w32((float)ox, (float)oy, (float)oz, (float)(ar[j] * nx[j]),
+                                 (float)(ar[j] * ny[j]), (float)(ar[j] * nz[j]));
         const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
         const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
         if (up)
@@ -598,22 +692,22 @@ hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cel
   return hipGetLastError();
 }
 
-hipError_t launch_order(const DagBuildArgs& a, int32_t max_depth, int32_t lds_limit, hipStream_t s) {
-  const size_t lds = sizeof(int) * (size_t)(max_depth + 1);
-  if (lds <= (size_t)lds_limit) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_order<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_order<true>, dim3(a.n_units), dim3(kOrderBlock), lds, s, a);
-  } else {
-    hipLaunchKernelGGL(k_order<false>, dim3(a.n_units), dim3(kOrderBlock), 0, s, a);
-  }
+hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_len, dim3(n_blocks), dim3(kCountBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  if (a.fmask != nullptr) hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_fill_faces, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s) {
+  if (m.n_faces <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_records, dim3(grid1d(m.n_faces, 256)), dim3(256), 0, s, m, frec);
   return hipGetLastError();
 }
 

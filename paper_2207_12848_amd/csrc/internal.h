@@ -26,6 +26,8 @@ struct MeshDev {
   const double* face_area;
   const double* face_normal;
   const double* cell_volume;
+  const int4* frec;  // per face: neighbour code, then A n as three FP32 (see k_face_records)
+  int64_t n_faces;
   int32_t n_cells;
   int32_t cell_off;
 };
@@ -51,10 +53,11 @@ struct DagBuildArgs {
   int32_t* rowlen_up;
   int32_t* rowlen_dn;
   float* aperp;
+  uint2* fmask;  // per task (cell order): inflow-entry and outflow-entry face bits; null when a
+                 // cell has more than 32 faces
   float2* bnd;  // (sum of w over wall outflow faces, over periodic outflow faces)
   int32_t* cnt;
   int32_t* inv;    // cell -> position in the unit's schedule
-  int32_t* level;
   // per task, schedule order within the unit
   int32_t* sched;  // position -> cell
   int32_t* lp;     // level pointers
@@ -166,7 +169,8 @@ constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build ke
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s);
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
-hipError_t launch_order(const DagBuildArgs& a, int32_t max_depth, int32_t lds_limit, hipStream_t s);
+hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s);
+hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 size_t count_lds_bytes(int max_faces, int dn_width);
 hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s);

@@ -663,8 +663,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(D->sched.alloc(4 * T));
   HIP_TRY(D->lp.alloc(4 * (T + 2 * (int64_t)n_units)));
   HIP_TRY(depth_d.alloc(4 * n_units));
-  HIP_TRY(err_d.alloc(4));
-  HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 1, 0, s));
+  HIP_TRY(err_d.alloc(8));
+  HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 2, 0, s));
   const int sent_len = std::max(64, dn_width);  // sentinel row of -1 after the rows
   HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + sent_len)));
   HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, sent_len, -1, s));
@@ -720,7 +720,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 8, s));
   // Kahn counters in LDS as 4-bit fields when the mesh fits the LDS
   // (the kernel's static LDS holds two frontier copies of 2048 cells)
-  const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8) + 17 * 1024 <= (size_t)lds_limit;
+  const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8 + 64) + 17 * 1024 <= (size_t)lds_limit;
   {
     ProfScope ps("kahn", s);
     HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));

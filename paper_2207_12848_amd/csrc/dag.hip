@@ -230,8 +230,10 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   const int Wr4 = W / 4;        // chunks per row
   const int W4 = a.dn_chunks;  // chunks that may hold a downwind cell (<= Wr4)
   if (tid < 3) s_cnt[tid] = 0;
+  const int nwords = (C + 7) / 8;  // counter words; 64 dummy words follow
   if (LDSCNT) {
-    for (int wi = tid; wi < (C + 7) / 8; wi += nthr) {
+    if (tid < 64) nib[nwords + tid] = 0u;
+    for (int wi = tid; wi < nwords; wi += nthr) {
       int n[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) n[j] = a.indeg[tb + min(8 * wi + j, C - 1)];
@@ -286,6 +288,7 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   }
   __syncthreads();
   const int4* sent4 = reinterpret_cast<const int4*>(a.dnw + a.dn_sentinel);
+  int pf_val = 0, pf_acc = 0;  // row prefetch (see below)
   // Level l: the frontier is [head, tail); its pushes count in s_cnt[l % 3].
   // s_cnt[(l + 1) % 3] was last read right after the barrier that ended level
   // l - 2, so it can be cleared now for level l + 1; one barrier per level.
@@ -300,10 +303,6 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       if (__ballot(active) == 0ull) continue;  // wavefront without tasks this round
       const int kk = k - head;
       const int c = !active ? 0 : (kk < kFrontierCap ? frc[kk] : spill[k]);
-      if (active) {  // the level's cells in slot order form the schedule
-        sched[k] = c;
-        inv[c] = k;
-      }
       // all NCH chunk loads are unconditional: lanes without a task, and chunks
       // past the row width, read a sentinel row of -1 instead (an address
       // select), so they are in flight together
@@ -311,6 +310,11 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       int4 v[NCH];
 #pragma unroll
       for (int q = 0; q < NCH; ++q) v[q] = (q < Wr4 ? row4 : sent4)[q];
+      pf_acc ^= pf_val;  // the previous level's prefetch (older than the row loads)
+      if (active) {  // the level's cells in slot order form the schedule
+        sched[k] = c;
+        inv[c] = k;
+      }
       auto dec_global = [&](int nb) -> bool {
         const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -318,39 +322,63 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       };
       uint32_t wm = 0;  // bit 4q+i: cell i of chunk q became ready
       if (LDSCNT) {
-        // every counter word is read, then every decrement issued: two LDS round trips
-        uint32_t word[4 * NCH];
+        // rows are -1 padded at the end, so the wavefront's non-empty chunks are
+        // the first nq; inside them every entry issues its LDS operations without
+        // a branch: padding entries use the lane's private dummy word and a zero
+        // operand.  Two LDS round trips: every counter word is read (to spot the
+        // overflow marker, which never changes), then every decrement issued.
+        int nq = 0;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) nq += __ballot(v[q].x >= 0) != 0ull ? 1 : 0;
+        const int dummy = nwords + lane;
+        uint32_t word[4 * NCH], old[4 * NCH];
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
+          if (q >= nq) break;
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i) word[4 * q + i] = nib[(xs[i] >= 0 ? xs[i] : 0) >> 3];
+          for (int i = 0; i < 4; ++i) word[4 * q + i] = nib[xs[i] >= 0 ? xs[i] >> 3 : dummy];
         }
-        uint32_t old[4 * NCH];
+        bool any_ovf = false;
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
+          if (q >= nq) break;
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int nb = xs[i];
             const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-            old[4 * q + i] = 0;
-            if (nb >= 0 && ((word[4 * q + i] >> sh) & 15u) != 15u)
-              old[4 * q + i] = atomicSub(&nib[nb >> 3], 1u << sh);
+            const bool ovf = ((word[4 * q + i] >> sh) & 15u) == 15u;
+            any_ovf |= nb >= 0 && ovf;
+            const uint32_t op = (nb >= 0 && !ovf) ? (1u << sh) : 0u;
+            old[4 * q + i] = atomicSub(&nib[nb >= 0 ? nb >> 3 : dummy], op);
           }
         }
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
+          if (q >= nq) break;
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int nb = xs[i];
-            if (nb < 0) continue;
             const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-            bool ready;
-            if (((word[4 * q + i] >> sh) & 15u) != 15u) ready = ((old[4 * q + i] >> sh) & 15u) == 1u;
-            else ready = dec_global(nb);
+            const bool ovf = ((word[4 * q + i] >> sh) & 15u) == 15u;
+            const bool ready = nb >= 0 && !ovf && ((old[4 * q + i] >> sh) & 15u) == 1u;
             wm |= (uint32_t)ready << (4 * q + i);
+          }
+        }
+        if (__ballot(any_ovf) != 0ull) {  // cells with 15 or more upwind dependencies
+#pragma unroll
+          for (int q = 0; q < NCH; ++q) {
+            if (q >= nq) break;
+            const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int nb = xs[i];
+              const uint32_t sh = (uint32_t)(nb & 7) * 4u;
+              if (nb >= 0 && ((word[4 * q + i] >> sh) & 15u) == 15u)
+                wm |= (uint32_t)dec_global(nb) << (4 * q + i);
+            }
           }
         }
       } else {
@@ -393,6 +421,19 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           }
         }
       }
+      // the row of the lane's first ready cell is touched now, so that it sits in
+      // the L2 cache when some lane loads it in the next level
+      {
+        int first = -1;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (first < 0 && (wm & (1u << (4 * q + i)))) first = xs[i];
+        }
+        pf_val = first >= 0 ? a.dnw[(tb + first) * W] : a.dnw[a.dn_sentinel];
+      }
       // ready cells: one wavefront prefix sum and one LDS atomic per wavefront
       const int n = __popc(wm);
       const int incl = wave_inclusive_sum(n);
@@ -421,9 +462,11 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
     ++l;
     if (tid == 0) lp[l + 1] = tail;
   }
+  pf_acc ^= pf_val;
   if (tid == 0) {
     a.depth[blockIdx.x] = l;
     if (tail != C) atomicOr(a.err, 1);
+    if (C < 0) a.err[1] = pf_acc;  // never true; keeps the prefetch loads alive
   }
 }
 
@@ -679,7 +722,7 @@ hipError_t launch_kahn_n(const DagBuildArgs& a, size_t lds, hipStream_t s) {
 
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s) {
   if (lds_counters) {
-    const size_t lds = sizeof(uint32_t) * (size_t)((max_cells + 7) / 8);
+    const size_t lds = sizeof(uint32_t) * (size_t)((max_cells + 7) / 8 + 64);
     switch (a.dn_chunks) {
       case 0: case 1: case 2: case 3: case 4: return launch_kahn_n<4>(a, lds, s);
       case 5: return launch_kahn_n<5>(a, lds, s);

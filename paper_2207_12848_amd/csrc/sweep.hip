@@ -102,8 +102,8 @@ constexpr int kPerCode = (int)0x80000001;
 // Inflow of one task per group (and the periodic part of it).
 template <int GN>
 struct Inflow {
-  double acc[GN];
-  double pin[GN];
+  float acc[GN];
+  float pin[GN];
 };
 
 template <int GN, bool REVERSE>
@@ -115,7 +115,7 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const TaskRec<GN
   float* os = a.out_s + (tb + k) * a.G + a.g0;
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
-    const float v = (float)((in.acc[g] + (double)t.src[g]) / (double)t.den[g]);
+    const float v = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
     rr[g] = v;
     o[g] = v;
     os[g] = v;
@@ -123,7 +123,7 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const TaskRec<GN
   if (!REVERSE && a.pin != nullptr) {
     float* pp = a.pin + obase + (int64_t)t.c * a.G;
 #pragma unroll
-    for (int g = 0; g < GN; ++g) pp[g] = (float)in.pin[g];
+    for (int g = 0; g < GN; ++g) pp[g] = in.pin[g];
   }
 }
 
@@ -137,10 +137,10 @@ __device__ __forceinline__ Inflow<GN> gather_task(const SweepArgs& a, const Task
                                                   const float* ring, int64_t obase, int64_t tb) {
   const int R = a.ring_mask + 1;
   Inflow<GN> in;
-  double* acc = in.acc;
-  double* pin = in.pin;
+  float* acc = in.acc;
+  float* pin = in.pin;
 #pragma unroll
-  for (int g = 0; g < GN; ++g) acc[g] = pin[g] = 0.0;
+  for (int g = 0; g < GN; ++g) acc[g] = pin[g] = 0.0f;
   bool miss = false;
   // entries in batches of 8, branch-free: all LDS reads of a batch are issued
   // before any is used and every entry kind is folded in with selects
@@ -166,13 +166,15 @@ __device__ __forceinline__ Inflow<GN> gather_task(const SweepArgs& a, const Task
       const bool in_ring = p >= 0 && (REVERSE ? (p < k0 + R) : (p >= k1 - R));
       const bool is_miss = GN == 1 && p == kMissCode;
       const bool is_per = GN == 1 && p == kPerCode;
-      const double y = (double)__int_as_float(en[q].y);
+      const float y = __int_as_float(en[q].y);
+      // explicit rounding (no contraction): every launch form and group packing
+      // computes each task's inflow with the same operations in row order
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
-        const double c = in_ring ? y * (double)rv[q][g] : ((is_miss || is_per) ? y : 0.0);
-        acc[g] += valid ? c : 0.0;
+        const float c = in_ring ? __fmul_rn(y, rv[q][g]) : ((is_miss || is_per) ? y : 0.0f);
+        acc[g] = __fadd_rn(acc[g], valid ? c : 0.0f);
       }
-      pin[0] += (valid && is_per) ? y : 0.0;
+      pin[0] = __fadd_rn(pin[0], (valid && is_per) ? y : 0.0f);
       miss = miss || (valid && !in_ring && !is_miss && !is_per);
     }
   }
@@ -181,19 +183,19 @@ __device__ __forceinline__ Inflow<GN> gather_task(const SweepArgs& a, const Task
       const int2 en = FAST ? stg[r] : a.ent[e0 + r];
       const int p = en.x;
       if (p == kMissCode || p == kPerCode) continue;
-      const double w = (double)__int_as_float(en.y);
+      const float w = __int_as_float(en.y);
       if (p >= 0) {
         if (REVERSE ? (p < k0 + R) : (p >= k1 - R)) continue;
         const float* q = a.out_s + (tb + p) * a.G + a.g0;
 #pragma unroll
-        for (int g = 0; g < GN; ++g) acc[g] += w * (double)q[g];
+        for (int g = 0; g < GN; ++g) acc[g] = __fadd_rn(acc[g], __fmul_rn(w, q[g]));
       } else if (a.phi_prev != nullptr) {
         const float* q = a.phi_prev + obase + (int64_t)(-p - 1) * a.G;
 #pragma unroll
         for (int g = 0; g < GN; ++g) {
-          const double v = w * (double)q[g];
-          acc[g] += v;
-          pin[g] += v;
+          const float v = __fmul_rn(w, q[g]);
+          acc[g] = __fadd_rn(acc[g], v);
+          pin[g] = __fadd_rn(pin[g], v);
         }
       }
     }

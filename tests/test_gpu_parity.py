@@ -126,12 +126,18 @@ def test_forward_groups_multimesh(G):
 
 
 def test_forward_plain_equals_batched_bitwise():
+    # the plain form (one group per launch) and the batched form (groups packed
+    # per task) perform the same FP32 operations in the same order
     w = W.small_random(2000, 24, G=3, seed=40, n_meshes=2)
     _, J1, A1, _ = run_gpu(w, form="batched")
     _, J2, A2, _ = run_gpu(w, form="plain")
+    assert np.array_equal(J1, J2) and np.array_equal(A1, A2)
+    # a small ring adds the inflow of ring misses after the rest of the row: the
+    # same terms in another order, so equal to FP32 rounding of the sums
     _, J3, A3, _ = run_gpu(w, form="batched", block=256, ring=256)
-    assert np.array_equal(J1, J2) and np.array_equal(J1, J3)
-    assert np.array_equal(A1, A2) and np.array_equal(A1, A3)
+    for x, y in ((J3, J1), (A3, A1)):
+        big = np.abs(y) >= 1e-20 * np.abs(y).max()
+        assert (np.abs(x - y)[big] / np.abs(y)[big]).max() <= 2e-6
 
 
 def test_forward_deterministic():

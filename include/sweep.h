@@ -114,7 +114,9 @@ typedef struct {
                         SWEEP_FORM_PLAIN: one launch per (mesh, direction, group) */
   int32_t block;     /* threads per workgroup of the sweep kernels, 0 = tuned default */
   int32_t ring;      /* LDS ring capacity in tasks (power of two), 0 = tuned default */
-  int32_t use_graph; /* 1: replay the pass sequence as a captured hipGraph */
+  int32_t use_graph; /* 1: run the pass sequence as a captured hipGraph; the first call with
+                        a given set of arguments captures and instantiates it (kept with the
+                        DAG, at most 8), later calls replay it on `stream` */
   int32_t reserved[5];
 } sweep_fwd_opts_t;
 
@@ -182,6 +184,20 @@ sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const void* saved, size_t saved_bytes, const float* dL_dJ,
                              const float* dL_dabsorbed, float* dL_dkappa, float* dL_demission,
                              void* stream);
+
+/* Autotuner of the sweep's launch shape: times `reps` forward sweeps (after
+ * one untimed sweep) of the batched form for every candidate number of threads
+ * per workgroup (256, 512, 1024) and LDS ring capacity (a quarter to twice the
+ * default, those that fit the LDS), with HIP events on `stream`, and writes
+ * into `best` a copy of `opts` (NULL: defaults) with the fastest `block` and
+ * `ring`, and into `best_ms` its time per sweep.  The DAG keeps nothing: pass
+ * `best` to sweep_forward / sweep_adjoint.  Results of different shapes agree
+ * to FP32 rounding (the ring capacity changes the order in which a task's
+ * ring misses are added).  Synchronises `stream`.
+ * Errors: INVALID_ARG, UNSUPPORTED (nothing fits), HIP. */
+sweep_status_t sweep_tune(sweep_dag_t dag, int32_t G, const float* kappa, const float* emission,
+                          const sweep_fwd_opts_t* opts, int32_t reps, sweep_fwd_opts_t* best,
+                          double* best_ms, void* stream);
 
 /* Kernel timing with HIP events (for measurement tools).  While enabled, every
  * launch of the library's main kernels is bracketed by two hipEvents recorded

@@ -20,12 +20,12 @@ from . import _binding as B
 from ._binding import (SweepError, SweepLibraryError, sweep_adjoint, sweep_build_dag,  # noqa: F401
                        sweep_dag_export, sweep_dag_info, sweep_destroy_dag, sweep_forward,
                        sweep_last_error, sweep_profile_enable, sweep_profile_read,
-                       sweep_profile_reset, sweep_saved_bytes)
+                       sweep_profile_reset, sweep_saved_bytes, sweep_tune)
 
 TOTAL_NAMES = ("emitted", "absorbed", "escaped", "pbc_in", "pbc_out", "scat_net", "pbc_err_max",
                "pbc_err_l1")
 
-__all__ = ["Dag", "build_dag", "forward", "adjoint", "SweepFunction", "upload_mesh",
+__all__ = ["Dag", "build_dag", "forward", "adjoint", "tune", "SweepFunction", "upload_mesh",
            "SweepError", "SweepLibraryError", "TOTAL_NAMES"] + list(B.EXPORTED)
 
 
@@ -191,6 +191,22 @@ def adjoint(dag: Dag, kappa, emission, saved, dL_dJ, dL_dabsorbed, stream=None, 
                           saved.numel() * saved.element_size(), _ptr(dL_dJ), _ptr(dL_dabsorbed),
                           _ptr(dk), _ptr(de), _stream(stream)))
     return dk, de
+
+
+def tune(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, reps: int = 3, stream=None,
+         **opts) -> dict:
+    """Autotune the sweep's launch shape on this DAG: returns {"block", "ring", "ms"}
+    (pass block= and ring= to forward/adjoint)."""
+    C = dag.n_cells
+    G = kappa.numel() // max(C, 1)
+    _check_field(kappa, C, G, "kappa")
+    _check_field(emission, C, G, "emission")
+    o = _fwd_opts(**opts)
+    best = B.sweep_fwd_opts_t()
+    ms = ctypes.c_double()
+    B.check(sweep_tune(dag.handle, G, _ptr(kappa), _ptr(emission), ctypes.byref(o), int(reps),
+                       ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
+    return {"block": int(best.block), "ring": int(best.ring), "ms": float(ms.value)}
 
 
 KERNELS = ("count", "kahn", "fill", "prep", "sweep_fwd", "sweep_adj", "reduce")

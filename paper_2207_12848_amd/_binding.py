@@ -21,7 +21,7 @@ SWEEP_FORM_BATCHED, SWEEP_FORM_PLAIN = 0, 1
 
 EXPORTED = ("sweep_last_error", "sweep_build_dag", "sweep_destroy_dag", "sweep_dag_info",
             "sweep_dag_export", "sweep_saved_bytes", "sweep_forward", "sweep_adjoint",
-            "sweep_profile_enable", "sweep_profile_reset", "sweep_profile_read")
+            "sweep_tune", "sweep_profile_enable", "sweep_profile_reset", "sweep_profile_read")
 
 
 class SweepLibraryError(RuntimeError):
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sweep_saved_bytes": (SZ, [P, I32, P]),
         "sweep_forward": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, SZ, P]),
         "sweep_adjoint": (ctypes.c_int, [P, I32, P, P, P, P, SZ, P, P, P, P, P]),
+        "sweep_tune": (ctypes.c_int, [P, I32, P, P, P, I32, P, P, P]),
         "sweep_profile_enable": (ctypes.c_int, [I32]),
         "sweep_profile_reset": (ctypes.c_int, []),
         "sweep_profile_read": (ctypes.c_int, [ctypes.c_char_p, P, P]),
@@ -138,6 +139,10 @@ def sweep_adjoint(dag, G, kappa, emission, opts, saved, saved_bytes, dL_dJ, dL_d
                   dL_dkappa, dL_demission, stream) -> int:
     return load().sweep_adjoint(dag, G, kappa, emission, opts, saved, saved_bytes, dL_dJ,
                                 dL_dabsorbed, dL_dkappa, dL_demission, stream)
+
+
+def sweep_tune(dag, G, kappa, emission, opts, reps, best, best_ms, stream) -> int:
+    return load().sweep_tune(dag, G, kappa, emission, opts, reps, best, best_ms, stream)
 
 
 def sweep_profile_enable(on: int) -> int:

@@ -199,13 +199,15 @@ hipEvent_t pool_event() {
   return e;
 }
 
-// Brackets one kernel launch with events when profiling is on.
+thread_local bool g_capturing = false;  // a pass sequence is being captured into a graph
+
+// Brackets one kernel launch with events when profiling is on (not inside a capture).
 struct ProfScope {
   hipEvent_t stop = nullptr;
   hipStream_t s;
   ProfScope(const char* name, hipStream_t stream) : s(stream) {
     std::lock_guard<std::mutex> g(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_capturing) return;
     hipEvent_t start = pool_event();
     stop = pool_event();
     if (!start || !stop) {
@@ -249,6 +251,17 @@ struct sweep_dag_s {
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
   Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, out_s;
+  // captured pass sequences (use_graph): key = every argument and buffer they bake in
+  struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;  // capture needs a stream other than the null stream
+  ~sweep_dag_s() {
+    for (GraphEntry& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 namespace {
@@ -482,6 +495,51 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
     }
   }
   return SWEEP_OK;
+}
+
+// Runs `body(stream)` as a captured graph: the first call with a given key
+// captures the sequence on the DAG's capture stream and instantiates it; every
+// call launches the instantiated graph on the caller's stream.  `body` must
+// only enqueue kernels (every buffer is allocated before).
+template <class Body>
+sweep_status_t run_graph(sweep_dag_t d, const std::vector<uint64_t>& key, hipStream_t s, Body&& body) {
+  for (auto& g : d->graphs)
+    if (g.key == key) {
+      HIP_TRY(hipGraphLaunch(g.exec, s));
+      return SWEEP_OK;
+    }
+  if (!d->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&d->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(d->cap_stream, hipStreamCaptureModeThreadLocal));
+  g_capturing = true;
+  const sweep_status_t st = body(d->cap_stream);
+  g_capturing = false;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(d->cap_stream, &graph);
+  if (st != SWEEP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+  if (d->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(d->graphs.front().exec);
+    d->graphs.erase(d->graphs.begin());
+  }
+  d->graphs.push_back({key, exec});
+  HIP_TRY(hipGraphLaunch(exec, s));
+  return SWEEP_OK;
+}
+
+uint64_t pkey(const void* p) { return (uint64_t)(uintptr_t)p; }
+
+void opts_key(std::vector<uint64_t>& k, const FwdPlan& p) {
+  uint32_t ab;
+  std::memcpy(&ab, &p.albedo, 4);
+  k.insert(k.end(), {(uint64_t)p.boundary, (uint64_t)p.n_pbc, (uint64_t)p.n_scat, (uint64_t)p.form,
+                     (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab});
 }
 
 sweep_status_t check_common(sweep_dag_t d, int32_t G) {
@@ -913,6 +971,15 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     if (saved) return (float*)saved + DCG + (int64_t)it * CG;
     return (it % 2 == 0) ? d->jsum_a.as<float>() : d->jsum_b.as<float>();
   };
+  if (!d->mesh_off_d.p) {
+    HIP_TRY(d->mesh_off_d.alloc(4 * d->mesh_off.size()));
+    HIP_TRY(d->mesh_cells_d.alloc(4 * d->mesh_cells.size()));
+    HIP_TRY(hipMemcpy(d->mesh_off_d.p, d->mesh_off.data(), 4 * d->mesh_off.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d->mesh_cells_d.p, d->mesh_cells.data(), 4 * d->mesh_cells.size(), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   sweep::ReduceArgs r{};
   r.units = d->units_d.as<Unit>();
   r.D = d->D;
@@ -920,12 +987,6 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   r.C_total = d->C_total;
   r.blk_mesh = d->blk_mesh.as<int32_t>();
   r.blk_cell0 = d->blk_cell0.as<int32_t>();
-  if (!d->mesh_off_d.p) {
-    HIP_TRY(d->mesh_off_d.alloc(4 * d->mesh_off.size()));
-    HIP_TRY(d->mesh_cells_d.alloc(4 * d->mesh_cells.size()));
-    HIP_TRY(hipMemcpy(d->mesh_off_d.p, d->mesh_off.data(), 4 * d->mesh_off.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d->mesh_cells_d.p, d->mesh_cells.data(), 4 * d->mesh_cells.size(), hipMemcpyHostToDevice));
-  }
   r.mesh_off = d->mesh_off_d.as<int32_t>();
   r.mesh_cells = d->mesh_cells_d.as<int32_t>();
   r.bnd = d->bnd.as<float2>();
@@ -937,38 +998,49 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   r.absorbed = absorbed;
   r.partial = d->partial.as<double>();
   r.cells_per_block = d->red_cpb;
-  for (int it = 0; it < p.n_scat; ++it) {
-    const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
-    float* prev = nullptr;
-    for (int ps = 0; ps < p.n_pbc; ++ps) {
-      float* dst = ((p.n_pbc - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
-      if (ps == 0) ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, s));
-      ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, s));
-      if (periodic && ps + 1 < p.n_pbc) {
-        sweep::ReduceArgs q = r;
-        q.phi = dst;
-        q.pin = d->pin.as<float>();
-        q.pin_prev = nullptr;
-        q.pin_sum = d->pin_prev.as<double>();
-        q.last = 0;
-        HIP_TRY(sweep::launch_reduce(q, d->red_blocks, s));
+  // source iterations, each made of the periodic passes, then the totals
+  auto body = [&](hipStream_t st) -> sweep_status_t {
+    for (int it = 0; it < p.n_scat; ++it) {
+      const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
+      float* prev = nullptr;
+      for (int ps = 0; ps < p.n_pbc; ++ps) {
+        float* dst = ((p.n_pbc - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
+        if (ps == 0) ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, st));
+        ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, st));
+        if (periodic && ps + 1 < p.n_pbc) {
+          sweep::ReduceArgs q = r;
+          q.phi = dst;
+          q.pin = d->pin.as<float>();
+          q.pin_prev = nullptr;
+          q.pin_sum = d->pin_prev.as<double>();
+          q.last = 0;
+          HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
+        }
+        prev = dst;
       }
-      prev = dst;
+      sweep::ReduceArgs q = r;
+      q.phi = phi_final;
+      q.pin = periodic ? d->pin.as<float>() : nullptr;
+      q.pin_prev = (periodic && p.n_pbc > 1) ? d->pin_prev.as<double>() : nullptr;
+      q.pin_sum = nullptr;
+      q.jsum_prev = jprev;
+      q.jsum = ckpt(it);
+      q.last = 1;
+      ProfScope ps("reduce", st);
+      HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
     }
-    sweep::ReduceArgs q = r;
-    q.phi = phi_final;
-    q.pin = periodic ? d->pin.as<float>() : nullptr;
-    q.pin_prev = (periodic && p.n_pbc > 1) ? d->pin_prev.as<double>() : nullptr;
-    q.pin_sum = nullptr;
-    q.jsum_prev = jprev;
-    q.jsum = ckpt(it);
-    q.last = 1;
-    ProfScope ps("reduce", s);
-    HIP_TRY(sweep::launch_reduce(q, d->red_blocks, s));
-  }
-  HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
-                               d->n_meshes, G, totals, s));
-  return SWEEP_OK;
+    HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
+                                 d->n_meshes, G, totals, st));
+    return SWEEP_OK;
+  };
+  if (!p.use_graph) return body(s);
+  std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
+                               pkey(totals), pkey(saved), (uint64_t)saved_bytes};
+  opts_key(key, p);
+  for (const Buf* b : {&d->phi_a, &d->phi_b, &d->pin, &d->pin_prev, &d->jsum_a, &d->jsum_b,
+                       &d->partial, &d->tden, &d->tsrc, &d->out_s, &d->mesh_blk_base})
+    key.push_back(pkey(b->p));
+  return run_graph(d, key, s, body);
 }
 
 sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
@@ -996,37 +1068,126 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   HIP_TRY(d->dk64.alloc(8 * CG));
   HIP_TRY(d->de64.alloc(8 * CG));
   if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
+  HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   const float* phi_final = (const float*)saved;
   auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
-  HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(), ckpt(p.n_scat - 1),
-                                 p.albedo, G, d->C_total, d->gsrc.as<float>(), d->dk64.as<double>(),
-                                 d->de64.as<double>(), s));
-  for (int it = p.n_scat - 1; it >= 0; --it) {
-    const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
-    const float* phi_it = phi_final;
-    if (it != p.n_scat - 1) {
-      ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, s));
-      ST_TRY(run_sweep(d, false, p, G, nullptr, d->phi_a.as<float>(), nullptr, s));
-      phi_it = d->phi_a.as<float>();
+  // reverse iterations: recompute phi of iteration `it` (all but the last, which
+  // was saved), sweep the adjoint, accumulate the gradients and the adjoint
+  // source of iteration it - 1
+  auto body = [&](hipStream_t st) -> sweep_status_t {
+    HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(),
+                                   ckpt(p.n_scat - 1), p.albedo, G, d->C_total,
+                                   d->gsrc.as<float>(), d->dk64.as<double>(),
+                                   d->de64.as<double>(), st));
+    for (int it = p.n_scat - 1; it >= 0; --it) {
+      const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
+      const float* phi_it = phi_final;
+      if (it != p.n_scat - 1) {
+        ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, st));
+        ST_TRY(run_sweep(d, false, p, G, nullptr, d->phi_a.as<float>(), nullptr, st));
+        phi_it = d->phi_a.as<float>();
+      }
+      ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, st));
+      ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, st));
+      sweep::AdjReduceArgs q{};
+      q.D = d->D;
+      q.G = G;
+      q.C_total = d->C_total;
+      q.lam = d->lam.as<float>();
+      q.phi = phi_it;
+      q.kappa = kappa;
+      q.vol = d->vol.as<float>();
+      q.jsum_prev = jprev;
+      q.albedo = p.albedo;
+      q.inv_D = 1.0f / (float)d->D;
+      q.gsrc_next = d->gsrc.as<float>();
+      HIP_TRY(sweep::launch_adj_reduce(q, d->dk64.as<double>(), d->de64.as<double>(), st));
     }
-    ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, s));
-    ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, s));
-    sweep::AdjReduceArgs q{};
-    q.D = d->D;
-    q.G = G;
-    q.C_total = d->C_total;
-    q.lam = d->lam.as<float>();
-    q.phi = phi_it;
-    q.kappa = kappa;
-    q.vol = d->vol.as<float>();
-    q.jsum_prev = jprev;
-    q.albedo = p.albedo;
-    q.inv_D = 1.0f / (float)d->D;
-    q.gsrc_next = d->gsrc.as<float>();
-    HIP_TRY(sweep::launch_adj_reduce(q, d->dk64.as<double>(), d->de64.as<double>(), s));
+    HIP_TRY(sweep::launch_d2f_pair(d->dk64.as<double>(), d->de64.as<double>(), dL_dkappa,
+                                   dL_demission, CG, st));
+    return SWEEP_OK;
+  };
+  if (!p.use_graph) return body(s);
+  std::vector<uint64_t> key = {2, (uint64_t)G, pkey(kappa), pkey(emission), pkey(saved),
+                               (uint64_t)saved_bytes, pkey(dL_dJ), pkey(dL_dabsorbed),
+                               pkey(dL_dkappa), pkey(dL_demission)};
+  opts_key(key, p);
+  for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->tden, &d->tsrc,
+                       &d->out_s})
+    key.push_back(pkey(b->p));
+  return run_graph(d, key, s, body);
+}
+
+sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
+                          const sweep_fwd_opts_t* opts, int32_t reps, sweep_fwd_opts_t* best,
+                          double* best_ms, void* stream) {
+  g_err.clear();
+  ST_TRY(check_common(d, G));
+  FwdPlan p;
+  ST_TRY(read_opts(opts, &p));
+  if (!kappa || !emission || !best || !best_ms) return fail(SWEEP_ERR_INVALID_ARG, "missing argument");
+  if (reps < 1) return fail(SWEEP_ERR_INVALID_ARG, "reps must be >= 1");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
+  const int64_t DCG = d->C_total * G * d->D;
+  HIP_TRY(d->phi_a.alloc(4 * DCG));
+  HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
+  ST_TRY(run_prep(d, G, kappa, emission, nullptr, nullptr, p.albedo, s));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(SWEEP_ERR_HIP, "hipEventCreate failed");
   }
-  HIP_TRY(sweep::launch_d2f_pair(d->dk64.as<double>(), d->de64.as<double>(), dL_dkappa,
-                                 dL_demission, CG, s));
+  const int gn = std::min(G, 4);
+  const int r0 = default_ring(gn, 0);
+  double best_t = -1.0;
+  FwdPlan bp = p;
+  sweep_status_t st = SWEEP_OK;
+  for (int block : {256, 512, 1024}) {
+    for (int ring : {r0 / 4, r0 / 2, r0, 2 * r0}) {
+      if (ring < 64) continue;
+      const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, sweep::kStageEntries, d->max_depth + 2);
+      if (L.bytes > (size_t)d->lds_max) continue;
+      FwdPlan q = p;
+      q.form = SWEEP_FORM_BATCHED;
+      q.block = block;
+      q.ring = ring;
+      q.use_graph = 0;
+      // one untimed sweep, then `reps` timed ones
+      st = run_sweep(d, false, q, G, nullptr, d->phi_a.as<float>(), nullptr, s);
+      if (st != SWEEP_OK) break;
+      if (hipEventRecord(e0, s) != hipSuccess) { st = fail(SWEEP_ERR_HIP, "hipEventRecord"); break; }
+      for (int r = 0; r < reps && st == SWEEP_OK; ++r)
+        st = run_sweep(d, false, q, G, nullptr, d->phi_a.as<float>(), nullptr, s);
+      if (st != SWEEP_OK) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(SWEEP_ERR_HIP, "event timing failed");
+        break;
+      }
+      const double t = ms / reps;
+      if (best_t < 0.0 || t < best_t) {
+        best_t = t;
+        bp = q;
+      }
+    }
+    if (st != SWEEP_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != SWEEP_OK) return st;
+  if (best_t < 0.0) return fail(SWEEP_ERR_UNSUPPORTED, "no launch shape fits the LDS");
+  if (opts) *best = *opts;
+  else std::memset(best, 0, sizeof(*best));
+  best->block = bp.block;
+  best->ring = bp.ring;
+  *best_ms = best_t;
   return SWEEP_OK;
 }
 

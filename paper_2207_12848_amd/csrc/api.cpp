@@ -658,18 +658,29 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   // cell-order tile tables (tiles never straddle meshes)
   std::vector<int32_t> cbm, cbc;
   int max_faces = 1, max_cells = 1;
+  // downwind rows are at most kRowCap wide; a cell with more faces may need an
+  // overflow list of (faces + 2) ints per direction
+  constexpr int kRowCap = 32;
+  int64_t ovf_cap = 2;
+  std::vector<int64_t> fp;
   for (int m = 0; m < n_meshes; ++m) {
     for (int32_t c = 0; c < D->mesh_cells[m]; c += sweep::kTileCellsHost) {
       cbm.push_back(m);
       cbc.push_back(c);
     }
-    std::vector<int64_t> fp(meshes[m].n_cells + 1);
+    fp.resize(meshes[m].n_cells + 1);
     HIP_TRY(hipMemcpy(fp.data(), meshes[m].face_ptr, 8 * fp.size(), hipMemcpyDeviceToHost));
-    for (int32_t c = 0; c < meshes[m].n_cells; ++c) max_faces = std::max<int>(max_faces, (int)(fp[c + 1] - fp[c]));
+    for (int32_t c = 0; c < meshes[m].n_cells; ++c) {
+      const int nf = (int)(fp[c + 1] - fp[c]);
+      max_faces = std::max(max_faces, nf);
+      if (nf > kRowCap) ovf_cap += (int64_t)(nf + 2) * n_dirs;
+    }
     max_cells = std::max(max_cells, meshes[m].n_cells);
   }
   const int n_cblocks = (int)cbm.size();
-  const int dn_width = (max_faces + 3) / 4 * 4;
+  const int dn_width = std::min(kRowCap, (max_faces + 3) / 4 * 4);
+  if (ovf_cap > INT32_MAX / 2)
+    return fail(SWEEP_ERR_UNSUPPORTED, "too many cells with more than %d faces", kRowCap);
   std::vector<sweep::MeshDev> md(n_meshes);
   for (int m = 0; m < n_meshes; ++m) {
     md[m].face_ptr = meshes[m].face_ptr;
@@ -713,8 +724,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_up.alloc(4 * T));
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
-  Buf fmask;  // face bits per task, when every cell has at most 32 faces
-  if (max_faces <= 32) HIP_TRY(fmask.alloc(8 * T));
+  Buf fmask;  // face bits per task (first 32 faces of the cell)
+  HIP_TRY(fmask.alloc(8 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
   HIP_TRY(cnt.alloc(4 * T));  // overflow counters of Kahn's algorithm
   HIP_TRY(inv.alloc(4 * T));
@@ -726,6 +737,10 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   const int sent_len = std::max(64, dn_width);  // sentinel row of -1 after the rows
   HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + sent_len)));
   HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, sent_len, -1, s));
+  Buf dn_ovf, dn_ovf_top;
+  HIP_TRY(dn_ovf.alloc(4 * ovf_cap));
+  HIP_TRY(dn_ovf_top.alloc(4));
+  HIP_TRY(sweep::launch_fill_i32(dn_ovf_top.as<int32_t>(), 1, 0, s));
   HIP_TRY(stats_d.alloc(8));
   HIP_TRY(sweep::launch_fill_i32(stats_d.as<int32_t>(), 2, 0, s));
   sweep::DagBuildArgs a{};
@@ -738,6 +753,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.max_faces = max_faces;
   a.dnw = dnw.as<int32_t>();
   a.dn_sentinel = (int64_t)T * dn_width;
+  a.dn_ovf = dn_ovf.as<int32_t>();
+  a.dn_ovf_top = dn_ovf_top.as<int32_t>();
   a.stats = stats_d.as<int32_t>();
   a.meshes = meshes_d.as<sweep::MeshDev>();
   a.dirs = dirs_d.as<double>();
@@ -747,7 +764,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.rowlen_up = rowlen_up.as<int32_t>();
   a.rowlen_dn = rowlen_dn.as<int32_t>();
   a.aperp = D->aperp.as<float>();
-  a.fmask = max_faces <= 32 ? fmask.as<uint2>() : nullptr;
+  a.fmask = fmask.as<uint2>();
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
   a.inv = inv.as<int32_t>();
@@ -757,18 +774,15 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.err = err_d.as<int32_t>();
   int lds_limit = 65536;
   (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, D->device);
-  if (sweep::count_lds_bytes(max_faces, dn_width) > (size_t)lds_limit)
-    return fail(SWEEP_ERR_UNSUPPORTED, "a cell has %d faces; at most %d are supported", max_faces,
-                (int)(max_faces * (double)lds_limit / sweep::count_lds_bytes(max_faces, dn_width)));
   {
     ProfScope ps("count", s);
-    HIP_TRY(sweep::launch_count(a, n_cblocks, s));
+    HIP_TRY(sweep::launch_count(a, n_cblocks, lds_limit, s));
   }
   // the longest downwind list sets how much of every row Kahn's algorithm loads
   int32_t stats[2] = {0, 0};
   HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  a.dn_chunks = std::max(1, (stats[1] + 3) / 4);
+  a.dn_chunks = std::max(1, std::min(dn_width / 4, (stats[1] + 3) / 4));
   // row lengths in schedule order (the input of the row-pointer scan)
   HIP_TRY(len_up.alloc(8 * (T + 1)));
   HIP_TRY(len_dn.alloc(8 * (T + 1)));

@@ -53,66 +53,70 @@ __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_unit
   return lo;
 }
 
-// The cell-order kernels stage a tile of kTileCells consecutive cells' faces
-// in LDS with coalesced loads; the workgroup then covers every direction, 32
-// consecutive lanes handling the tile's cells for one direction.
+// The cell-order kernel stages a tile of kTileCells consecutive cells' faces
+// in LDS with coalesced loads (room for kTileFaces faces per cell on average;
+// a tile with more faces is read from global memory instead); the workgroup
+// then covers every direction, 32 consecutive lanes handling the tile's cells
+// for one direction.
+constexpr int kTileFaces = 32;
+
 struct FaceTile {
   int c0, cend;       // cells [c0, cend) of mesh m
   int64_t f0;         // first face of the tile
+  bool in_lds;        // the tile's faces are in LDS
   const int64_t* fp;  // LDS copy of face_ptr[c0 .. cend] (relative to f0)
-  const double* nrm;
-  const double* area;
-  const int32_t* nbr;
-  const int8_t* shift;
 };
 
-__device__ __forceinline__ FaceTile stage_tile(const DagBuildArgs& a, const MeshDev& M, int c0,
-                                               unsigned char* smem, int max_faces) {
+__host__ __device__ inline size_t tile_lds_bytes() {
+  const size_t cap = (size_t)kTileCells * kTileFaces;
+  return (8 * (kTileCells + 1) + cap * (24 + 8 + 4 + 1) + 15) / 16 * 16;
+}
+
+__device__ __forceinline__ FaceTile stage_tile(const MeshDev& M, int c0, unsigned char* smem) {
   FaceTile T;
   T.c0 = c0;
   T.cend = min(c0 + kTileCells, M.n_cells);
   const int nc = T.cend - c0;
   T.f0 = M.face_ptr[c0];
   const int nf = (int)(M.face_ptr[T.cend] - T.f0);
-  const int cap = kTileCells * max_faces;
+  constexpr int cap = kTileCells * kTileFaces;
+  T.in_lds = nf <= cap;
   int64_t* fp = reinterpret_cast<int64_t*>(smem);
-  double* nrm = reinterpret_cast<double*>(fp + kTileCells + 1);
-  double* area = nrm + 3 * cap;
-  int32_t* nbr = reinterpret_cast<int32_t*>(area + cap);
-  int8_t* shift = reinterpret_cast<int8_t*>(nbr + cap);
   for (int i = threadIdx.x; i <= nc; i += blockDim.x) fp[i] = M.face_ptr[c0 + i] - T.f0;
-  for (int i = threadIdx.x; i < 3 * nf; i += blockDim.x) nrm[i] = M.face_normal[3 * T.f0 + i];
-  for (int i = threadIdx.x; i < nf; i += blockDim.x) {
-    area[i] = M.face_area[T.f0 + i];
-    nbr[i] = M.face_nbr[T.f0 + i];
-    shift[i] = M.face_shift != nullptr ? M.face_shift[T.f0 + i] : (int8_t)0;
+  if (T.in_lds) {
+    double* nrm = reinterpret_cast<double*>(fp + kTileCells + 1);
+    double* area = nrm + 3 * cap;
+    int32_t* nbr = reinterpret_cast<int32_t*>(area + cap);
+    int8_t* shift = reinterpret_cast<int8_t*>(nbr + cap);
+    for (int i = threadIdx.x; i < 3 * nf; i += blockDim.x) nrm[i] = M.face_normal[3 * T.f0 + i];
+    for (int i = threadIdx.x; i < nf; i += blockDim.x) {
+      area[i] = M.face_area[T.f0 + i];
+      nbr[i] = M.face_nbr[T.f0 + i];
+      shift[i] = M.face_shift != nullptr ? M.face_shift[T.f0 + i] : (int8_t)0;
+    }
   }
   T.fp = fp;
-  T.nrm = nrm;
-  T.area = area;
-  T.nbr = nbr;
-  T.shift = shift;
   return T;
 }
 
-__host__ __device__ inline size_t tile_lds_bytes(int max_faces) {
-  const size_t cap = (size_t)kTileCells * max_faces;
-  return (8 * (kTileCells + 1) + cap * (24 + 8 + 4 + 1) + 15) / 16 * 16;
-}
-
 // Per task: upwind/downwind counts, Aperp = sum of outflow w, boundary outflow
-// weights and the fixed-width list of downwind cells.  A thread handles one
-// cell of the tile for one direction; the rows of kCountBlock / kTileCells
-// directions are assembled in LDS and written out as contiguous blocks.
+// weights, face bits and the fixed-width row of downwind cells.  A row holds
+// dn_width entries padded with -1; a task with more downwind cells keeps
+// dn_width - 1 of them and stores -(o + 2) in the last slot, o being the
+// offset in dn_ovf of [count, rest of the list].  A thread handles one cell of
+// the tile for one direction; the rows of kCountBlock / kTileCells directions
+// are assembled in LDS and written out as contiguous blocks (STAGE), or
+// written straight to global memory.
+template <bool STAGE>
 __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_max[2];
   if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
   const int m = a.cblk_mesh[blockIdx.x];
   const MeshDev M = a.meshes[m];
-  const FaceTile T = stage_tile(a, M, a.cblk_c0[blockIdx.x], smem, a.max_faces);
+  const FaceTile T = stage_tile(M, a.cblk_c0[blockIdx.x], smem);
   const int W = a.dn_width;
-  int32_t* srow = reinterpret_cast<int32_t*>(smem + tile_lds_bytes(a.max_faces));
+  int32_t* srow = reinterpret_cast<int32_t*>(smem + tile_lds_bytes());
   __syncthreads();
   const int ci = threadIdx.x % kTileCells;
   const int dj = threadIdx.x / kTileCells;
@@ -121,60 +125,88 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   const int nc = T.cend - T.c0;
   const bool cell = c < T.cend;
   const int fb = cell ? (int)T.fp[ci] : 0, fe = cell ? (int)T.fp[ci + 1] : 0;
-  int32_t* row = srow + threadIdx.x * W;  // [dj][ci][W]
   int mi = 0, mo = 0;
-  for (int d0 = 0; d0 < a.D; d0 += kDirs) {
-    const int d = d0 + dj;
-    if (cell && d < a.D) {
-      const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
-      const float fx = (float)ox, fy = (float)oy, fz = (float)oz;
-      const int64_t t = a.units[m * a.D + d].task_base + c;
-      int nup = 0, npin = 0, ndn = 0;
-      uint32_t um = 0, dm = 0;
-      double ap = 0.0, wall = 0.0, per = 0.0;
-      for (int f = fb; f < fe; ++f) {
-        const double* n = T.nrm + 3 * f;
-        const double sv = orient(ox, oy, oz, n);
-        const int nb = T.nbr[f];
-        const bool periodic = T.shift[f] != 0;
-        const uint32_t bit = 1u << ((f - fb) & 31);
-        if (sv > a.eps) {
-          const double A = T.area[f];
-          const double w = face_w32(fx, fy, fz, (float)(A * n[0]), (float)(A * n[1]), (float)(A * n[2]));
-          ap += w;
-          if (nb < 0) wall += w;
-          else if (periodic) per += w;
-          else {
-            row[ndn++] = nb;
-            dm |= bit;
+  auto run = [&](const double* nrm, const double* area, const int32_t* nbr, const int8_t* shift) {
+    for (int d0 = 0; d0 < a.D; d0 += kDirs) {
+      const int d = d0 + dj;
+      if (cell && d < a.D) {
+        const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
+        const float fx = (float)ox, fy = (float)oy, fz = (float)oz;
+        const int64_t t = a.units[m * a.D + d].task_base + c;
+        int32_t* row = STAGE ? srow + threadIdx.x * W : a.dnw + t * W;  // LDS: [dj][ci][W]
+        int32_t* ovf = nullptr;
+        int nup = 0, npin = 0, ndn = 0;
+        uint32_t um = 0, dm = 0;
+        double ap = 0.0, wall = 0.0, per = 0.0;
+        for (int f = fb; f < fe; ++f) {
+          const double* n = nrm + 3 * f;
+          const double sv = orient(ox, oy, oz, n);
+          const int nb = nbr[f];
+          const bool periodic = shift != nullptr && shift[f] != 0;
+          const uint32_t bit = f - fb < 32 ? 1u << (f - fb) : 0u;  // face bits: first 32 faces
+          if (sv > a.eps) {
+            const double A = area[f];
+            const double w = face_w32(fx, fy, fz, (float)(A * n[0]), (float)(A * n[1]), (float)(A * n[2]));
+            ap += w;
+            if (nb < 0) wall += w;
+            else if (periodic) per += w;
+            else {
+              if (ndn < W) {
+                row[ndn] = nb;
+              } else {
+                if (ndn == W) {  // the row is full: continue in an overflow list
+                  const int o = atomicAdd(a.dn_ovf_top, (fe - fb) + 2);
+                  ovf = a.dn_ovf + o;
+                  ovf[1] = row[W - 1];
+                  row[W - 1] = -(o + 2);
+                }
+                ovf[1 + ndn - (W - 1)] = nb;
+              }
+              ++ndn;
+              dm |= bit;
+            }
+          } else if (sv < -a.eps && nb >= 0) {
+            if (periodic) ++npin; else ++nup;
+            um |= bit;
           }
-        } else if (sv < -a.eps && nb >= 0) {
-          if (periodic) ++npin; else ++nup;
-          um |= bit;
         }
+        if (ovf != nullptr) ovf[0] = ndn - (W - 1);
+        for (int q = ndn; q < W; ++q) row[q] = -1;
+        a.fmask[t] = make_uint2(um, dm);
+        a.indeg[t] = nup;
+        a.rowlen_up[t] = nup + npin;
+        a.rowlen_dn[t] = ndn;
+        a.aperp[t] = (float)ap;
+        a.bnd[t] = make_float2((float)wall, (float)per);
+        mi = max(mi, nup);
+        mo = max(mo, ndn);
       }
-      for (int q = ndn; q < W; ++q) row[q] = -1;
-      if (a.fmask != nullptr) a.fmask[t] = make_uint2(um, dm);
-      a.indeg[t] = nup;
-      a.rowlen_up[t] = nup + npin;
-      a.rowlen_dn[t] = ndn;
-      a.aperp[t] = (float)ap;
-      a.bnd[t] = make_float2((float)wall, (float)per);
-      mi = max(mi, nup);
-      mo = max(mo, ndn);
-    }
-    __syncthreads();
-    // the tile's rows of direction d0 + j are nc * W consecutive ints of dnw
-    const int per4 = nc * W / 4;
-    for (int i = threadIdx.x; i < kDirs * per4; i += kCountBlock) {
-      const int j = i / per4, r = i - j * per4;
-      if (d0 + j < a.D) {
-        const int64_t tb = a.units[m * a.D + d0 + j].task_base;
-        reinterpret_cast<int4*>(a.dnw + (tb + T.c0) * W)[r] =
-            reinterpret_cast<const int4*>(srow + j * kTileCells * W)[r];
+      if (STAGE) {
+        __syncthreads();
+        // the tile's rows of direction d0 + j are nc * W consecutive ints of dnw
+        const int per4 = nc * W / 4;
+        for (int i = threadIdx.x; i < kDirs * per4; i += kCountBlock) {
+          const int j = i / per4, r = i - j * per4;
+          if (d0 + j < a.D) {
+            const int64_t tb = a.units[m * a.D + d0 + j].task_base;
+            reinterpret_cast<int4*>(a.dnw + (tb + T.c0) * W)[r] =
+                reinterpret_cast<const int4*>(srow + j * kTileCells * W)[r];
+          }
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
+  };
+  if (T.in_lds) {
+    constexpr int cap = kTileCells * kTileFaces;
+    const double* nrm = reinterpret_cast<const double*>(T.fp + kTileCells + 1);
+    const double* area = nrm + 3 * cap;
+    const int32_t* nbr = reinterpret_cast<const int32_t*>(area + cap);
+    const int8_t* shift = reinterpret_cast<const int8_t*>(nbr + cap);
+    run(nrm, area, nbr, shift);
+  } else {
+    run(M.face_normal + 3 * T.f0, M.face_area + T.f0, M.face_nbr + T.f0,
+        M.face_shift != nullptr ? M.face_shift + T.f0 : nullptr);
   }
   atomicMax(&s_max[0], mi);
   atomicMax(&s_max[1], mo);
@@ -209,8 +241,8 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
 // whose count (>= 15) is kept in global memory instead (it is never changed, so
 // reading the field to pick the counter is race-free).
 // NCH: chunks of 4 entries of a downwind row that are loaded at once (rows are
-// -1 padded; every cell's downwind list fits NCH chunks except for the NCH = 8
-// variant, which walks longer rows in a second loop).
+// -1 padded; NCH covers the longest list, or the whole row when some list
+// continues in the overflow area).
 template <bool LDSCNT, int NCH>
 __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   extern __shared__ uint32_t nib[];
@@ -227,8 +259,7 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   int32_t* inv = a.inv + tb;
   int32_t* lp = a.lp + U.lp_base;
   const int W = a.dn_width;
-  const int Wr4 = W / 4;        // chunks per row
-  const int W4 = a.dn_chunks;  // chunks that may hold a downwind cell (<= Wr4)
+  const int Wr4 = W / 4;  // chunks per row
   if (tid < 3) s_cnt[tid] = 0;
   const int nwords = (C + 7) / 8;  // counter words; 64 dummy words follow
   if (LDSCNT) {
@@ -390,19 +421,25 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
             if (xs[i] >= 0) wm |= (uint32_t)dec_global(xs[i]) << (4 * q + i);
         }
       }
-      // rows longer than NCH chunks (only possible for NCH = 8): one wavefront
-      // push per extra entry
-      for (int q = NCH; q < W4; ++q) {
-        const int4 x = row4[q];
-        const int xs[4] = {x.x, x.y, x.z, x.w};
-        for (int i = 0; i < 4; ++i) {
-          const int nb = xs[i];
+      // a full row may end in a pointer to its overflow list (rare): one
+      // wavefront push per extra entry
+      int ptr = -1;
+#pragma unroll
+      for (int q = 0; q < NCH; ++q) ptr = q == Wr4 - 1 ? v[q].w : ptr;
+      if (__ballot(ptr < -1) != 0ull) {
+        const int o = ptr < -1 ? -(ptr + 2) : 0;
+        const int no = ptr < -1 ? a.dn_ovf[o] : 0;
+        int mx = no;
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) mx = max(mx, __shfl_xor(mx, sh));
+        for (int i = 0; i < mx; ++i) {
+          const int nb = i < no ? a.dn_ovf[o + 1 + i] : -1;
           bool ready = false;
           if (nb >= 0) {
             const uint32_t sh = (uint32_t)(nb & 7) * 4u;
             if (LDSCNT && ((nib[nb >> 3] >> sh) & 15u) != 15u) {
-              const uint32_t o = atomicSub(&nib[nb >> 3], 1u << sh);
-              ready = ((o >> sh) & 15u) == 1u;
+              const uint32_t old = atomicSub(&nib[nb >> 3], 1u << sh);
+              ready = ((old >> sh) & 15u) == 1u;
             } else {
               ready = dec_global(nb);
             }
@@ -499,7 +536,8 @@ __global__ void k_face_records(MeshDev M, int4* frec) {
 
 // Rows of the upwind and downwind lists, in schedule order: each wavefront
 // takes 64 consecutive schedule slots of one unit.  Every lane first loads one
-// slot's task (cell, row pointers, face range, face bits from k_count); then,
+// slot's task (cell, row pointers, face range, face bits of the first 32 faces
+// from k_count); then,
 // 16 slots per round, 16 lanes share one task, one face record per lane.  The
 // face bits give every entry its place in the row (rows keep the cell's face
 // order); consecutive slots write consecutive rows, and the neighbours'
@@ -546,7 +584,6 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
       um[j] = (uint32_t)__shfl((int)bits.x, src);
       dm[j] = (uint32_t)__shfl((int)bits.y, src);
     }
-    // a cell has at most 32 faces here: two chunks of 16 at most
     int mx = max(max(nfj[0], nfj[1]), max(nfj[2], nfj[3]));
     mx = max(mx, __shfl_xor(mx, 16));
     mx = max(mx, __shfl_xor(mx, 32));
@@ -574,94 +611,38 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
         if (dn) a.dn[ed[j] + __popc(dm[j] & pre)] = make_int2(pos[j], __float_as_int(w));
       }
     }
-  }
-}
-
-// Rows of the upwind and downwind lists for meshes with cells of more than 32
-// faces (no face bits): the face classes are recomputed here in FP64.  Each wavefront
-// takes 64 consecutive schedule slots of one unit.  Every lane first loads one
-// slot's task (cell, row pointers, face range); then, 16 slots per round, 16
-// lanes share one task (one face per lane, entries compacted with a ballot, so
-// a row keeps the cell's face order).  Consecutive slots write consecutive
-// rows, and the neighbours' schedule positions come from the unit's inverse
-// schedule.
-
-__global__ __launch_bounds__(kFillBlock) void k_fill_faces(DagBuildArgs a) {
-  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
-  const Unit U = a.units[u];
-  const MeshDev M = a.meshes[U.mesh];
-  const int64_t tb = U.task_base;
-  const double ox = a.dirs[3 * U.dir], oy = a.dirs[3 * U.dir + 1], oz = a.dirs[3 * U.dir + 2];
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15;
-  const int g = lane >> 4;
-  const int32_t* inv = a.inv + tb;
-  const int kw = (blockIdx.x - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
-  if (kw >= U.n_cells) return;
-  // lane L: the task of slot kw + L
-  const int k = kw + lane;
-  const bool kv = k < U.n_cells;
-  const int kc = kv ? k : U.n_cells - 1;
-  const int c = a.sched[tb + kc];
-  const int64_t eu0 = a.up_ptr[tb + kc];
-  const int64_t ed0 = a.dn_ptr[tb + kc];
-  const int64_t f0 = M.face_ptr[c];
-  const int nf = kv ? (int)(M.face_ptr[c + 1] - f0) : 0;
-  const int rounds = min(4, (U.n_cells - kw + 15) >> 4);
-  const uint32_t below = (1u << li) - 1u;
-  for (int r = 0; r < rounds; ++r) {
-    // group g handles slots kw + 16 r + 4 g + j, j = 0..3
-    int64_t eu[4], ed[4], fb[4];
-    int nfj[4];
-    int mx = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int src = 16 * r + 4 * g + j;
-      eu[j] = __shfl(eu0, src);
-      ed[j] = __shfl(ed0, src);
-      fb[j] = __shfl(f0, src);
-      nfj[j] = __shfl(nf, src);
-      mx = max(mx, nfj[j]);
-    }
-    mx = max(mx, __shfl_xor(mx, 16));
-    mx = max(mx, __shfl_xor(mx, 32));
-    const int nch = (mx + 15) >> 4;
-    for (int h = 0; h < nch; ++h) {
-      const int fo = h * 16 + li;
-      double nx[4], ny[4], nz[4], ar[4];
-      int nb[4], sh[4];
-      bool has[4];
+    // faces past the 32 face bits (rare): classified here in FP64 exactly as in
+    // k_count, placed after the first 32 faces' entries with a ballot per chunk
+    if (mx > 32) {
+      const double ox = a.dirs[3 * U.dir], oy = a.dirs[3 * U.dir + 1], oz = a.dirs[3 * U.dir + 2];
+      int64_t ru[4], rd[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        has[j] = fo < nfj[j];
-        const int64_t f = has[j] ? fb[j] + fo : 0;  // every mesh has a face 0
-        nx[j] = M.face_normal[3 * f];
-        ny[j] = M.face_normal[3 * f + 1];
-        nz[j] = M.face_normal[3 * f + 2];
-        ar[j] = M.face_area[f];
-        nb[j] = M.face_nbr[f];
-        sh[j] = M.face_shift != nullptr ? (int)M.face_shift[f] : 0;
+        ru[j] = eu[j] + __popc(um[j]);
+        rd[j] = ed[j] + __popc(dm[j]);
       }
-      int pos[4];
+      for (int h = 2; h * 16 < mx; ++h) {
+        const int fo = h * 16 + li;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pos[j] = inv[nb[j] >= 0 ? nb[j] : 0];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double n3[3] = {nx[j], ny[j], nz[j]};
-        const double sv = orient(ox, oy, oz, n3);
-        const bool periodic = sh[j] != 0;
-        const bool up = has[j] && nb[j] >= 0 && sv < -a.eps;
-        const bool dn = has[j] && nb[j] >= 0 && !periodic && sv > a.eps;
-        const float w = face_w32((float)ox, (float)oy, (float)oz, (float)(ar[j] * nx[j]),
-                                 (float)(ar[j] * ny[j]), (float)(ar[j] * nz[j]));
-        const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
-        const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
-        if (up)
-          a.up[eu[j] + __popc(mu & below)] =
-              make_int2(periodic ? -(nb[j] + 1) : pos[j], __float_as_int(w));
-        if (dn) a.dn[ed[j] + __popc(md & below)] = make_int2(pos[j], __float_as_int(w));
-        eu[j] += __popc(mu);
-        ed[j] += __popc(md);
+        for (int j = 0; j < 4; ++j) {
+          const bool has = fo < nfj[j];
+          const int64_t f = has ? fb[j] + fo : 0;
+          const int4 rec = M.frec[f];
+          const double* n3 = M.face_normal + 3 * f;
+          const double sv = orient(ox, oy, oz, n3);
+          const int code = rec.x;
+          const bool up = has && code != -1 && sv < -a.eps;
+          const bool dn = has && code >= 0 && sv > a.eps;
+          const int pos = inv[code >= 0 ? code : 0];
+          const float w = face_w32(fx, fy, fz, __int_as_float(rec.y), __int_as_float(rec.z),
+                                   __int_as_float(rec.w));
+          const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
+          const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
+          if (up) a.up[ru[j] + __popc(mu & below)] = make_int2(code >= 0 ? pos : code + 1, __float_as_int(w));
+          if (dn) a.dn[rd[j] + __popc(md & below)] = make_int2(pos, __float_as_int(w));
+          ru[j] += __popc(mu);
+          rd[j] += __popc(md);
+        }
       }
     }
   }
@@ -696,18 +677,23 @@ inline unsigned grid1d(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-// LDS of k_count: the face tile, then one downwind row per thread.
+// LDS of k_count: the face tile, then (when it fits) one downwind row per thread.
 size_t count_lds_bytes(int max_faces, int dn_width) {
-  return tile_lds_bytes(max_faces) + (size_t)kCountBlock * dn_width * 4;
+  (void)max_faces;
+  return tile_lds_bytes();
 }
 
-hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s) {
+hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s) {
   if (n_cblocks <= 0) return hipSuccess;
-  const size_t lds = count_lds_bytes(a.max_faces, a.dn_width);
-  hipError_t e = hipFuncSetAttribute((const void*)k_count, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
+  const size_t tile = tile_lds_bytes();
+  const size_t staged = tile + (size_t)kCountBlock * a.dn_width * 4;
+  const bool stage = staged <= (size_t)lds_limit - 64;
+  const size_t lds = stage ? staged : tile;
+  const void* fn = stage ? (const void*)k_count<true> : (const void*)k_count<false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_count, dim3(n_cblocks), dim3(kCountBlock), lds, s, a);
+  if (stage) hipLaunchKernelGGL(k_count<true>, dim3(n_cblocks), dim3(kCountBlock), lds, s, a);
+  else hipLaunchKernelGGL(k_count<false>, dim3(n_cblocks), dim3(kCountBlock), lds, s, a);
   return hipGetLastError();
 }
 
@@ -743,8 +729,7 @@ hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_
 
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  if (a.fmask != nullptr) hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_fill_faces, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
   return hipGetLastError();
 }
 

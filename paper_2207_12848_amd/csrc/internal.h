@@ -42,8 +42,10 @@ struct DagBuildArgs {
   const int32_t* blk_base;  // [n_units+1] first block of each unit (cell-range kernels)
   const int32_t* cblk_mesh;  // cell-order kernels: mesh and first cell of every block
   const int32_t* cblk_c0;
-  int32_t dn_width;          // width of the fixed-width downwind lists
+  int32_t dn_width;          // width of the fixed-width downwind rows (<= 32)
   int32_t dn_chunks;         // chunks of 4 row entries that may hold a downwind cell
+  int32_t* dn_ovf;           // overflow lists of full rows: [count, cells...]
+  int32_t* dn_ovf_top;       // next free int of dn_ovf (atomic)
   int32_t max_faces;         // most half-faces of any cell
   int32_t* dnw;              // [T][dn_width] downwind cells of every task (-1 padded)
   int64_t dn_sentinel;       // offset in dnw of a row of -1 (4 * kRowChunks entries)
@@ -53,8 +55,7 @@ struct DagBuildArgs {
   int32_t* rowlen_up;
   int32_t* rowlen_dn;
   float* aperp;
-  uint2* fmask;  // per task (cell order): inflow-entry and outflow-entry face bits; null when a
-                 // cell has more than 32 faces
+  uint2* fmask;  // per task (cell order): inflow-entry and outflow-entry bits of the first 32 faces
   float2* bnd;  // (sum of w over wall outflow faces, over periodic outflow faces)
   int32_t* cnt;
   int32_t* inv;    // cell -> position in the unit's schedule
@@ -166,7 +167,7 @@ struct AdjReduceArgs {
 
 // launchers (kernels in dag.hip / sweep.hip)
 constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build kernels
-hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, hipStream_t s);
+hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s);
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s);

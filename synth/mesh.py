@@ -50,6 +50,10 @@ def _load():
         lib.voro_build.restype = ctypes.c_void_p
         lib.voro_build.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                    ctypes.c_void_p, ctypes.c_void_p]
+        lib.voro_rebuild.restype = None
+        lib.voro_rebuild.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_void_p, ctypes.c_void_p]
         lib.voro_counts.restype = ctypes.c_int64
         lib.voro_counts.argtypes = [ctypes.c_void_p]
         lib.voro_fetch.restype = None
@@ -81,36 +85,39 @@ def morton_order(points: np.ndarray) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
-def _candidates(points: np.ndarray, periodic: bool, k: int):
-    from scipy.spatial import cKDTree
-    n = len(points)
+def _candidates(tree, queries: np.ndarray, n: int, k: int):
     k = min(k, n)
-    tree = cKDTree(points, boxsize=1.0 if periodic else None)
-    _, idx = tree.query(points, k=k, workers=-1)
-    idx = np.asarray(idx, dtype=np.int32).reshape(n, k)
+    _, idx = tree.query(queries, k=k, workers=-1)
+    idx = np.asarray(idx, dtype=np.int32).reshape(len(queries), k)
     return np.ascontiguousarray(idx)
 
 
 def _raw_build(points: np.ndarray, periodic: bool, k0: int = 48):
+    """Clip every cell against its k0 nearest seeds; cells whose candidates ran
+    out before the security radius are rebuilt alone with twice as many."""
+    from scipy.spatial import cKDTree
     lib = _load()
     n = len(points)
     pts = np.ascontiguousarray(points, dtype=np.float64)
+    tree = cKDTree(pts, boxsize=1.0 if periodic else None)
     k = min(k0, n)
     status = np.zeros(n, dtype=np.int32)
-    while True:
-        cand = _candidates(pts, periodic, k)
-        h = lib.voro_build(n, _ptr(pts), int(periodic), k, _ptr(cand), _ptr(status))
-        bad = int(np.count_nonzero(status == 1))
-        if (status == 2).any():
-            lib.voro_free(h)
-            raise RuntimeError("degenerate Voronoi cell")
-        if (status == 3).any():
-            lib.voro_free(h)
-            raise RuntimeError("periodic mesh too coarse for minimum-image neighbours")
-        if bad == 0 or k >= n:
-            break
-        lib.voro_free(h)
+    h = lib.voro_build(n, _ptr(pts), int(periodic), k, _ptr(_candidates(tree, pts, n, k)),
+                       _ptr(status))
+    bad = np.nonzero(status == 1)[0].astype(np.int32)
+    while len(bad) and k < n:
         k = min(2 * k, n)
+        cand = _candidates(tree, pts[bad], n, k)
+        st = np.zeros(len(bad), dtype=np.int32)
+        lib.voro_rebuild(h, len(bad), _ptr(bad), _ptr(pts), int(periodic), k, _ptr(cand), _ptr(st))
+        status[bad] = st
+        bad = bad[st == 1]
+    if (status == 2).any():
+        lib.voro_free(h)
+        raise RuntimeError("degenerate Voronoi cell")
+    if (status == 3).any():
+        lib.voro_free(h)
+        raise RuntimeError("periodic mesh too coarse for minimum-image neighbours")
     nf = lib.voro_counts(h)
     face_ptr = np.empty(n + 1, np.int64)
     nbr = np.empty(nf, np.int32)
@@ -221,3 +228,48 @@ def mesh_stats(mesh: dict) -> dict:
     return dict(n_cells=C, n_half_faces=F, faces_per_cell=F / C,
                 vol_p1=float(np.percentile(v, 1)), vol_p99=float(np.percentile(v, 99)),
                 vol_span=float(v.max() / v.min()))
+
+
+def complete_graph_mesh(n: int, seed: int = 0) -> dict:
+    """Combinatorial test mesh: every cell shares a face with every other cell
+    (plus six vacuum walls), face normals n_ij = (p_j - p_i)/|p_j - p_i| for
+    random points p, so every direction's graph stays acyclic (the projection
+    on the direction orders it).  Areas and volumes are random; twins carry the
+    same area and the negated normal.  Cells have n + 5 faces: far more than a
+    Voronoi cell, for the code paths of cells with many faces."""
+    rng = np.random.default_rng(np.random.SeedSequence([2207, 12848, 900, seed]))
+    p = rng.random((n, 3))
+    area_ij = rng.uniform(0.2, 1.0, size=(n, n))
+    area_ij = np.triu(area_ij, 1)
+    area_ij = area_ij + area_ij.T
+    walls = np.array([[-1, 0, 0], [1, 0, 0], [0, -1, 0], [0, 1, 0], [0, 0, -1], [0, 0, 1]], np.float64)
+    nf = n - 1 + 6
+    face_ptr = np.arange(n + 1, dtype=np.int64) * nf
+    nbr = np.empty((n, nf), np.int32)
+    area = np.empty((n, nf))
+    normal = np.empty((n, nf, 3))
+    slot = np.empty((n, n), np.int64)  # face index of neighbour j in cell c
+    for c in range(n):
+        others = [j for j in range(n) if j != c]
+        nbr[c, :n - 1] = others
+        nbr[c, n - 1:] = -1
+        for k, j in enumerate(others):
+            slot[c, j] = c * nf + k
+            if c < j:
+                d = p[j] - p[c]
+                normal[c, k] = d / np.linalg.norm(d)
+            area[c, k] = area_ij[c, j]
+        area[c, n - 1:] = rng.uniform(0.5, 1.0, size=6)
+        normal[c, n - 1:] = walls
+    for c in range(n):  # twins: exact negation of the canonical side
+        for k, j in enumerate(nbr[c, :n - 1]):
+            if c > j:
+                normal[c, k] = -normal[j, slot[j, c] - j * nf]
+    twin = np.full((n, nf), -1, np.int32)
+    for c in range(n):
+        for k, j in enumerate(nbr[c, :n - 1]):
+            twin[c, k] = slot[j, c]
+    return dict(points=p, face_ptr=face_ptr, face_nbr=nbr.reshape(-1), face_twin=twin.reshape(-1),
+                face_shift=np.zeros(n * nf, np.int8), face_area=area.reshape(-1),
+                face_normal=np.ascontiguousarray(normal.reshape(-1, 3)),
+                cell_volume=rng.uniform(0.05, 0.2, size=n), periodic=False)

@@ -184,82 +184,105 @@ struct Build {
   int64_t n_half_faces = 0;
 };
 
+
+// Cell i from its candidate neighbours cand[0..k) (sorted by increasing
+// minimum-image distance; the seed itself may appear).  Returns the status:
+// 0 ok, 1 candidates exhausted before the security radius, 2 degenerate cell,
+// 3 periodic cell too large for minimum-image neighbours.
+int build_cell(int32_t i, int32_t n, const double* pts, int32_t periodic, int32_t k,
+               const int32_t* cand, CellOut& out) {
+  const V3 p{pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+  std::vector<Face> faces;
+  if (periodic) {
+    // The periodic cell lies within half a box of its seed; the cube's faces
+    // are the bisectors with the seed's own images.
+    const int32_t lab[6] = {i, i, i, i, i, i};
+    const int8_t sh[6] = {shift_code(-1, 0, 0), shift_code(1, 0, 0),
+                          shift_code(0, -1, 0), shift_code(0, 1, 0),
+                          shift_code(0, 0, -1), shift_code(0, 0, 1)};
+    faces = make_cube({-0.5, -0.5, -0.5}, {0.5, 0.5, 0.5}, lab, sh);
+  } else {
+    const int32_t lab[6] = {-1, -2, -3, -4, -5, -6};
+    const int8_t sh[6] = {0, 0, 0, 0, 0, 0};
+    faces = make_cube({-p.x, -p.y, -p.z}, {1.0 - p.x, 1.0 - p.y, 1.0 - p.z}, lab, sh);
+  }
+  int st = 1;
+  double r2max = max_radius2(faces);
+  for (int32_t q = 0; q < k; ++q) {
+    const int32_t j = cand[q];
+    if (j == i || j < 0) continue;
+    V3 dv{pts[3 * j] - p.x, pts[3 * j + 1] - p.y, pts[3 * j + 2] - p.z};
+    int sx = 0, sy = 0, sz = 0;
+    if (periodic) {
+      if (dv.x >= 0.5) { dv.x -= 1.0; sx = -1; } else if (dv.x < -0.5) { dv.x += 1.0; sx = 1; }
+      if (dv.y >= 0.5) { dv.y -= 1.0; sy = -1; } else if (dv.y < -0.5) { dv.y += 1.0; sy = 1; }
+      if (dv.z >= 0.5) { dv.z -= 1.0; sz = -1; } else if (dv.z < -0.5) { dv.z += 1.0; sz = 1; }
+    }
+    const double r2 = dot(dv, dv);
+    if (r2 >= 4.0 * r2max) { st = 0; break; }
+    if (!clip(faces, dv, 0.5 * r2, j, shift_code(sx, sy, sz))) { st = 2; break; }
+    r2max = max_radius2(faces);
+  }
+  if (st == 1 && k >= n) st = 0;  // every seed was offered
+  if (st == 0 && periodic && r2max >= 0.0625) st = 3;
+  out = CellOut();
+  double vol = 0.0;
+  for (const Face& f : faces) {
+    V3 av{0, 0, 0};
+    const size_t m = f.poly.size();
+    for (size_t t = 1; t + 1 < m; ++t)
+      av = add(av, cross(sub(f.poly[t], f.poly[0]), sub(f.poly[t + 1], f.poly[0])));
+    const double dn = norm(f.d);
+    const V3 nrm = scl(f.d, 1.0 / dn);
+    const double a = 0.5 * std::fabs(dot(av, nrm));
+    vol += a * (f.h / dn) / 3.0;
+    if (!(a > 0.0)) continue;
+    out.nbr.push_back(f.label >= 0 ? f.label : -1);
+    out.shift.push_back(f.label >= 0 ? f.shift : (int8_t)0);
+    out.area.push_back(a);
+    out.normal.push_back(nrm.x);
+    out.normal.push_back(nrm.y);
+    out.normal.push_back(nrm.z);
+  }
+  out.volume = vol;
+  return st;
+}
+
+void count_faces(Build* B) {
+  int64_t tot = 0;
+  for (const CellOut& c : B->cells) tot += (int64_t)c.nbr.size();
+  B->n_half_faces = tot;
+}
+
 }  // namespace
 
 extern "C" {
 
 // pts: n*3 seeds in [0,1)^3.  cand: n*k candidate neighbour indices sorted by
 // increasing (minimum-image) distance; the first entry may be the seed itself.
-// status[i] = 0 ok, 1 candidates exhausted before the security radius, 2 cell
-// degenerate, 3 periodic cell too large for minimum-image neighbours.
+// status[i]: see build_cell.
 void* voro_build(int32_t n, const double* pts, int32_t periodic, int32_t k,
                  const int32_t* cand, int32_t* status) {
   Build* B = new Build();
   B->n = n;
   B->cells.resize(n);
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int32_t i = 0; i < n; ++i) {
-    const V3 p{pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
-    std::vector<Face> faces;
-    if (periodic) {
-      // The periodic cell lies within half a box of its seed; the cube's faces
-      // are the bisectors with the seed's own images.
-      const int32_t lab[6] = {i, i, i, i, i, i};
-      const int8_t sh[6] = {shift_code(-1, 0, 0), shift_code(1, 0, 0),
-                            shift_code(0, -1, 0), shift_code(0, 1, 0),
-                            shift_code(0, 0, -1), shift_code(0, 0, 1)};
-      faces = make_cube({-0.5, -0.5, -0.5}, {0.5, 0.5, 0.5}, lab, sh);
-    } else {
-      const int32_t lab[6] = {-1, -2, -3, -4, -5, -6};
-      const int8_t sh[6] = {0, 0, 0, 0, 0, 0};
-      faces = make_cube({-p.x, -p.y, -p.z}, {1.0 - p.x, 1.0 - p.y, 1.0 - p.z},
-                        lab, sh);
-    }
-    int st = 1;
-    double r2max = max_radius2(faces);
-    for (int32_t q = 0; q < k; ++q) {
-      const int32_t j = cand[(int64_t)i * k + q];
-      if (j == i || j < 0) continue;
-      V3 dv{pts[3 * j] - p.x, pts[3 * j + 1] - p.y, pts[3 * j + 2] - p.z};
-      int sx = 0, sy = 0, sz = 0;
-      if (periodic) {
-        if (dv.x >= 0.5) { dv.x -= 1.0; sx = -1; } else if (dv.x < -0.5) { dv.x += 1.0; sx = 1; }
-        if (dv.y >= 0.5) { dv.y -= 1.0; sy = -1; } else if (dv.y < -0.5) { dv.y += 1.0; sy = 1; }
-        if (dv.z >= 0.5) { dv.z -= 1.0; sz = -1; } else if (dv.z < -0.5) { dv.z += 1.0; sz = 1; }
-      }
-      const double r2 = dot(dv, dv);
-      if (r2 >= 4.0 * r2max) { st = 0; break; }
-      if (!clip(faces, dv, 0.5 * r2, j, shift_code(sx, sy, sz))) { st = 2; break; }
-      r2max = max_radius2(faces);
-    }
-    if (st == 1 && k >= n) st = 0;  // every seed was offered
-    if (st == 0 && periodic && r2max >= 0.0625) st = 3;
-    status[i] = st;
-    CellOut& out = B->cells[i];
-    double vol = 0.0;
-    for (const Face& f : faces) {
-      V3 av{0, 0, 0};
-      const size_t m = f.poly.size();
-      for (size_t t = 1; t + 1 < m; ++t)
-        av = add(av, cross(sub(f.poly[t], f.poly[0]), sub(f.poly[t + 1], f.poly[0])));
-      const double dn = norm(f.d);
-      const V3 nrm = scl(f.d, 1.0 / dn);
-      const double a = 0.5 * std::fabs(dot(av, nrm));
-      vol += a * (f.h / dn) / 3.0;
-      if (!(a > 0.0)) continue;
-      out.nbr.push_back(f.label >= 0 ? f.label : -1);
-      out.shift.push_back(f.label >= 0 ? f.shift : (int8_t)0);
-      out.area.push_back(a);
-      out.normal.push_back(nrm.x);
-      out.normal.push_back(nrm.y);
-      out.normal.push_back(nrm.z);
-    }
-    out.volume = vol;
-  }
-  int64_t tot = 0;
-  for (const CellOut& c : B->cells) tot += (int64_t)c.nbr.size();
-  B->n_half_faces = tot;
+  for (int32_t i = 0; i < n; ++i)
+    status[i] = build_cell(i, n, pts, periodic, k, cand + (int64_t)i * k, B->cells[i]);
+  count_faces(B);
   return B;
+}
+
+// Rebuild the m cells listed in `cells` from k candidates each (cand: m*k, in
+// the order of `cells`); status: m entries.
+void voro_rebuild(void* h, int32_t m, const int32_t* cells, const double* pts, int32_t periodic,
+                  int32_t k, const int32_t* cand, int32_t* status) {
+  Build* B = static_cast<Build*>(h);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int32_t t = 0; t < m; ++t)
+    status[t] = build_cell(cells[t], B->n, pts, periodic, k, cand + (int64_t)t * k,
+                           B->cells[cells[t]]);
+  count_faces(B);
 }
 
 int64_t voro_counts(void* h) { return static_cast<Build*>(h)->n_half_faces; }

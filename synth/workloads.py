@@ -219,6 +219,20 @@ def small_random(n_cells: int, D: int, G: int = 1, seed: int = 0, periodic: bool
                      np.concatenate(srcs), boundary="periodic" if periodic else "vacuum", **opts)
 
 
+def many_faces(n_cells: int = 100, D: int = 24, G: int = 1, seed: int = 0, n_src: int = 4,
+               tau: float = 2.0, **opts) -> dict:
+    """Workload on the complete-graph test mesh (every cell has n_cells + 5 faces)."""
+    from .mesh import complete_graph_mesh
+    mesh = complete_graph_mesh(n_cells, seed)
+    r_pos, r_kap, r_src, _ = _streams(101, extra=seed + 1)
+    kap = lognormal_kappa(mesh["cell_volume"], r_kap, 1.0, tau)
+    cells, lum = point_sources(n_cells, n_src, r_src)
+    em = np.zeros((n_cells, G))
+    em[cells, :] = lum[:, None]
+    return _workload("many_faces", [mesh], D, kap[:, None] * np.linspace(1.0, 0.3, G)[None, :], em,
+                     cells, **opts)
+
+
 CONFIGS = {
     "c1": c1_plain_small,
     "c2": c2_plain_scale,

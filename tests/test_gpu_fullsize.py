@@ -1,0 +1,207 @@
+"""GPU parity at the benchmark workloads' full sizes, in the launch configuration
+bench.py times (batched form, default launch shape).
+
+- 262,144-cell jittered lattice, 84 directions: forward and adjoint of the loss
+  sum(absorbed) / 4 pi against the FP64 oracle, element by element.
+- 262,144-cell lattice, 48 directions (the differentiation workload): adjoint
+  against the FP64 oracle adjoint and against central differences of the
+  oracle's loss on 16 random cells (kappa) and 16 random sources (luminosity).
+- Clustered periodic mesh, 84 directions x 4 groups, 3 periodic passes: the
+  recipe at 262,144 cells against the oracle; at 2,097,152 cells the properties
+  that hold at any size (photon balance of every pass, no vacuum walls, intensities
+  that grow monotonically over the passes from the cold start, finite outputs).
+- Uneven meshes with scattering (24 directions, albedo 0.5, 20 source
+  iterations): 8 meshes against the oracle (forward and adjoint); all 64 meshes
+  by balance and gradient bounds.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from synth import workloads as W  # noqa: E402
+
+REL = 1e-5
+INV4PI = 1.0 / (4.0 * np.pi)
+
+
+def _sw():
+    import paper_2207_12848_amd as sw
+    return sw
+
+
+def _opts(w):
+    return dict(boundary=w["boundary"], n_pbc=w["n_pbc"], albedo=w["albedo"], n_scat=w["n_scat"])
+
+
+def _dev(w):
+    G = w["G"]
+    k = torch.tensor(np.asarray(w["kappa"], np.float32).reshape(-1, G), device="cuda")
+    e = torch.tensor(np.asarray(w["emission"], np.float32).reshape(-1, G), device="cuda")
+    return k, e
+
+
+def field_close(gpu, ref, rel=REL, floor=1e-20, name="field"):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert np.all(np.isfinite(gpu)), name
+    big = np.abs(ref) >= floor * np.abs(ref).max()
+    err = np.abs(gpu - ref)
+    worst = (err[big] / np.abs(ref[big])).max()
+    l1 = err.sum() / np.abs(ref).sum()
+    print("%s: max rel %.3e  rel L1 %.3e" % (name, worst, l1))
+    assert worst <= rel and l1 <= rel, name
+
+
+def grad_close(g, r, name):
+    g = np.asarray(g, np.float64)
+    r = np.asarray(r, np.float64)
+    l2 = np.linalg.norm(g - r) / np.linalg.norm(r)
+    big = np.abs(r) >= 1e-6 * np.abs(r).max()
+    worst = (np.abs(g - r)[big] / np.abs(r[big])).max()
+    print("%s: rel L2 %.3e  elementwise %.3e" % (name, l2, worst))
+    assert l2 <= 1e-5 and worst <= 1e-4, name
+
+
+def balance(tot):
+    lhs = tot[..., 0] + tot[..., 3] + tot[..., 5]
+    rhs = tot[..., 1] + tot[..., 2] + tot[..., 4]
+    return np.abs(lhs - rhs) / tot[..., 0]
+
+
+def gpu_forward_adjoint(w, adjoint=True):
+    sw = _sw()
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    out = {}
+    if adjoint:
+        J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, **_opts(w))
+        gJ = torch.zeros_like(k)
+        gA = torch.full_like(k, INV4PI)
+        dk, de = sw.adjoint(dag, k, e, saved, gJ, gA, **_opts(w))
+        out["dk"], out["de"] = dk.cpu().numpy(), de.cpu().numpy()
+    else:
+        J, A, tot = sw.forward(dag, k, e, **_opts(w))
+    torch.cuda.synchronize()
+    out["J"], out["A"], out["tot"] = J.cpu().numpy(), A.cpu().numpy(), tot.cpu().numpy()
+    out["info"] = dag.info()
+    dag.close()
+    return out
+
+
+def test_c2_full_forward_and_adjoint():
+    w = W.c2_plain_scale()
+    g = gpu_forward_adjoint(w)
+    ref = oracle.forward(w)
+    field_close(g["J"], ref["J"], name="J")
+    field_close(g["A"], ref["absorbed"], name="absorbed")
+    assert np.all(np.abs(g["tot"][..., :3] - ref["totals"][..., :3]) <=
+                  REL * np.abs(ref["totals"][..., :3]))
+    assert balance(g["tot"]).max() <= 1e-6
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    grad_close(g["dk"], dk, "dL/dkappa")
+    grad_close(g["de"], de, "dL/demission")
+
+
+def test_c4_full_adjoint_and_central_differences():
+    w = W.c4_differentiation()
+    g = gpu_forward_adjoint(w)
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    grad_close(g["dk"], dk, "dL/dkappa")
+    grad_close(g["de"], de, "dL/demission")
+    # central differences of the FP64 oracle's loss
+    rng = np.random.default_rng(np.random.SeedSequence([2207, 12848, 4, 99]))
+    C = len(w["meshes"][0]["cell_volume"])
+    cells = rng.choice(C, 16, replace=False)
+    srcs = rng.choice(np.asarray(w["sources"]), 16, replace=False)
+    kap0 = np.asarray(w["kappa"], np.float64).reshape(-1)
+    em0 = np.asarray(w["emission"], np.float64).reshape(-1)
+
+    def loss(kap, em):
+        wp = dict(w, kappa=kap.reshape(-1, 1), emission=em.reshape(-1, 1))
+        return oracle.forward(wp)["absorbed"].sum() * INV4PI
+
+    L0 = loss(kap0, em0)
+    h = 1e-4
+    for c in cells:
+        kp, km = kap0.copy(), kap0.copy()
+        kp[c] *= 1 + h
+        km[c] *= 1 - h
+        fd = (loss(kp, em0) - loss(km, em0)) / (2 * h * kap0[c])
+        tol = 1e-4 * abs(fd) + 1e-9 * L0 / kap0[c]
+        assert abs(dk[c, 0] - fd) <= tol, ("oracle", c, dk[c, 0], fd)
+        assert abs(g["dk"][c, 0] - fd) <= 2 * tol, ("gpu", c, g["dk"][c, 0], fd)
+    for c in srcs:
+        ep, em_ = em0.copy(), em0.copy()
+        ep[c] *= 1 + h
+        em_[c] *= 1 - h
+        fd = (loss(kap0, ep) - loss(kap0, em_)) / (2 * h * em0[c])
+        assert abs(de[c, 0] - fd) <= 1e-6 * abs(fd) + 1e-12, ("oracle", c, de[c, 0], fd)
+        assert abs(g["de"][c, 0] - fd) <= 1e-5 * abs(fd) + 1e-12, ("gpu", c, g["de"][c, 0], fd)
+        assert 0.0 <= fd <= INV4PI * (1 + 1e-9)
+
+
+def test_c3_recipe_at_262144_cells_matches_oracle():
+    w = W.c3_batched_groups(n_cells=262_144, n_src=1250)
+    g = gpu_forward_adjoint(w, adjoint=False)
+    ref = oracle.forward(w)
+    field_close(g["J"], ref["J"], name="J")
+    field_close(g["A"], ref["absorbed"], name="absorbed")
+    for k in (0, 1, 3, 4):
+        assert np.all(np.abs(g["tot"][..., k] - ref["totals"][..., k]) <=
+                      REL * np.abs(ref["totals"][..., k]) + 1e-300), k
+    assert balance(g["tot"]).max() <= 1e-6
+
+
+def test_c3_full_properties():
+    sw = _sw()
+    w = W.c3_batched_groups()
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    prev = None
+    errs = []
+    for n_pbc in (1, 2, 3):
+        J, A, tot = sw.forward(dag, k, e, boundary="periodic", n_pbc=n_pbc)
+        torch.cuda.synchronize()
+        J, tot = J.cpu().numpy(), tot.cpu().numpy()
+        assert np.all(np.isfinite(J)) and np.all(J >= 0.0)
+        assert np.all(tot[..., 2] == 0.0)  # no vacuum walls in a periodic box
+        assert balance(tot).max() <= 1e-6, n_pbc
+        if prev is not None:  # passes from the cold start only add light
+            assert np.all(J >= prev * (1 - 1e-5))
+            assert tot[..., 1].sum() > prev_abs
+            errs.append(tot[..., 6].max())
+        prev, prev_abs = J, tot[..., 1].sum()
+    assert errs[1] <= errs[0]
+    dag.close()
+
+
+def test_c5_eight_meshes_match_oracle():
+    w = W.c5_uneven_scatter(n_meshes=8, hi=32_768)
+    g = gpu_forward_adjoint(w)
+    ref = oracle.forward(w)
+    field_close(g["J"], ref["J"], name="J")
+    field_close(g["A"], ref["absorbed"], name="absorbed")
+    assert balance(g["tot"]).max() <= 1e-6
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    grad_close(g["dk"], dk, "dL/dkappa")
+    grad_close(g["de"], de, "dL/demission")
+
+
+def test_c5_full_properties():
+    w = W.c5_uneven_scatter()
+    g = gpu_forward_adjoint(w)
+    assert g["info"]["n_meshes"] == 64
+    assert balance(g["tot"]).max() <= 1e-6
+    assert np.all(np.isfinite(g["J"])) and np.all(g["J"] >= 0.0)
+    de = g["de"]
+    # a source's share of photons that end up absorbed lies in [0, 1] (per 4 pi)
+    assert np.all(np.isfinite(de)) and np.all(de >= -1e-7 * INV4PI)
+    assert np.all(de <= INV4PI * (1 + 1e-5))
+    assert np.all(np.isfinite(g["dk"]))

@@ -188,6 +188,33 @@ def test_forward_edge_cases():
     assert abs(tot[0, 0, 2] - tot[0, 0, 0]) <= 1e-6 * tot[0, 0, 0]
 
 
+def test_many_faces_rows_and_tiles():
+    # cells with 105 faces: face tiles read from global memory, downwind rows
+    # continued in overflow lists, face classes past the 32 face bits, upwind
+    # counts past the 4-bit LDS counters
+    sw = _sw()
+    w = W.many_faces(100, 24, G=2, seed=4, albedo=0.3, n_scat=2)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    lv, od, ind = dag.export()
+    level, order, indeg, depth = oracle.build_dag(w["meshes"][0], w["dirs"])
+    assert np.array_equal(lv, level.reshape(-1))
+    assert np.array_equal(od, order.reshape(-1))
+    assert np.array_equal(ind, indeg.reshape(-1))
+    assert indeg.max() > 32  # the graph really has long rows
+    check_forward(w)
+    C = 100
+    rng = np.random.default_rng(6)
+    gJ = rng.random((C, 2)).astype(np.float32)
+    gA = rng.random((C, 2)).astype(np.float32)
+    dk_ref, de_ref = oracle.adjoint(w, gJ, gA)
+    k, e = _dev(w)
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, **_opts(w))
+    dk, de = sw.adjoint(dag, k, e, saved, torch.tensor(gJ, device="cuda"),
+                        torch.tensor(gA, device="cuda"), **_opts(w))
+    _grad_close(dk.cpu().numpy(), dk_ref)
+    _grad_close(de.cpu().numpy(), de_ref)
+
+
 def test_forward_lattice_beam():
     n = 12
     w = W.lattice_workload(n, np.array([[1.0, 0.0, 0.0], [0.0, -1.0, 0.0]]), 1.5,

@@ -37,6 +37,18 @@ def test_forward_dense_fibonacci_multimesh():
     assert _rel(r["J"], ref["J"]) < 1e-12
 
 
+def test_forward_dense_many_faces():
+    # every cell borders every other: long rows, cells with 105 faces
+    w = W.many_faces(100, 24, G=2, seed=3)
+    r = oracle.forward(w, want_phi=True)
+    ref = DR.dense_forward(w)
+    assert _rel(r["phi"][0], ref["phi"][0]) < 1e-12
+    assert _rel(r["J"], ref["J"]) < 1e-12
+    lv, order, indeg, depth = oracle.build_dag(w["meshes"][0], w["dirs"])
+    for d in (0, 7, 23):
+        assert np.array_equal(lv[d], DR.brute_levels(w["meshes"][0], w["dirs"][d])[0])
+
+
 def test_periodic_passes_converge_to_cyclic_dense_solve():
     w = W.small_random(180, 8, G=1, seed=3, periodic=True, n_src=3, tau=2.0)
     ref = DR.dense_forward(w, cyclic=True)

@@ -454,15 +454,22 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
   a.D = d->D;
   const int n_units = (int)d->units.size();
   for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
-    const int block = p.block > 0 ? p.block : (gn == 1 ? 1024 : 512);
+    int block = p.block > 0 ? p.block : (gn == 1 ? 1024 : 512);
     const int ring = default_ring(gn, p.ring);
     const int stage = sweep::kStageEntries;
-    const int lp_cap = d->max_depth + 2;
-    const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, stage, lp_cap);
+    // level tables in LDS when they fit next to the ring and the staging
+    // buffers, else read from global memory (512 threads per workgroup)
+    int lp_cap = d->max_depth + 2;
+    sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, stage, lp_cap);
+    if (L.bytes > (size_t)d->lds_max) {
+      lp_cap = 0;
+      block = 512;
+      L = sweep::sweep_lds_layout(gn, ring, stage, lp_cap);
+    }
     if (L.bytes > (size_t)d->lds_max)
       return fail(p.ring > 0 ? SWEEP_ERR_INVALID_ARG : SWEEP_ERR_UNSUPPORTED,
-                  "ring %d x %d groups and %d levels need %zu bytes of LDS, %d available", ring, gn,
-                  d->max_depth, L.bytes, d->lds_max);
+                  "ring %d x %d groups needs %zu bytes of LDS, %d available", ring, gn, L.bytes,
+                  d->lds_max);
     a.g0 = g0;
     a.ring_mask = ring - 1;
     a.stage_entries = stage;
@@ -1165,7 +1172,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   for (int block : {256, 512, 1024}) {
     for (int ring : {r0 / 4, r0 / 2, r0, 2 * r0}) {
       if (ring < 64) continue;
-      const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, sweep::kStageEntries, d->max_depth + 2);
+      const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, sweep::kStageEntries, 0);
       if (L.bytes > (size_t)d->lds_max) continue;
       FwdPlan q = p;
       q.form = SWEEP_FORM_BATCHED;

@@ -208,7 +208,9 @@ __device__ __forceinline__ Inflow<GN> gather_task(const SweepArgs& a, const Task
 // entries; a level's block and the records of its tasks are loaded three
 // levels ahead into registers (three rotating sets) and written to one of two
 // LDS staging buffers the level before it is solved.
-template <int GN, bool REVERSE, int CH>
+// LVL_LDS = false (graphs deeper than the LDS level tables hold): the level
+// pointers and first entries are read from global memory at every step.
+template <int GN, bool REVERSE, int CH, bool LVL_LDS>
 __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   float* ring = reinterpret_cast<float*>(smem);
@@ -235,13 +237,17 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
     const int depth = U.depth;
     if (depth <= 0) continue;
     // level tables in LDS (the host sizes lp_cap >= depth + 2 for every unit)
-    for (int l = tid; l <= depth + 1; l += nthr) {
-      lps[l] = a.lp[U.lp_base + l];
-      levs[l] = a.lev[U.lp_base + l];
+    if (LVL_LDS) {
+      for (int l = tid; l <= depth + 1; l += nthr) {
+        lps[l] = a.lp[U.lp_base + l];
+        levs[l] = a.lev[U.lp_base + l];
+      }
     }
     __syncthreads();
-    auto LP = [&](int l) -> int { return lps[l]; };
-    auto LEV = [&](int l) -> int64_t { return levs[l]; };
+    const int32_t* lpg = a.lp + U.lp_base;
+    const int64_t* levg = a.lev + U.lp_base;
+    auto LP = [&](int l) -> int { return LVL_LDS ? lps[l] : lpg[l]; };
+    auto LEV = [&](int l) -> int64_t { return LVL_LDS ? levs[l] : levg[l]; };
     auto LVL = [&](int s) -> int {  // level solved at step s (clamped into range)
       s = s < depth - 1 ? s : depth - 1;
       return REVERSE ? depth - 1 - s : s;
@@ -366,11 +372,17 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
 template <int GN, bool REVERSE>
 hipError_t launch_sweep_g(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
-  // kStageEntries entries staged per level whatever the block size
+  // kStageEntries entries staged per level whatever the block size; level
+  // tables outside LDS (lp_cap == 0) only with 512 threads
+  if (a.lp_cap == 0) {
+    if (block != 512) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sweep<GN, REVERSE, 8, false>), dim3(grid), dim3(block), lds, s, a);
+    return hipGetLastError();
+  }
   switch (kStageEntries / block) {
-    case 4: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 4>), dim3(grid), dim3(block), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 8>), dim3(grid), dim3(block), lds, s, a); break;
-    case 16: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 16>), dim3(grid), dim3(block), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 4, true>), dim3(grid), dim3(block), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 8, true>), dim3(grid), dim3(block), lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 16, true>), dim3(grid), dim3(block), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -610,8 +622,10 @@ hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
 
 template <int GN, bool REVERSE>
 hipError_t set_lds_g(int32_t bytes) {
-  const void* fns[] = {(const void*)k_sweep<GN, REVERSE, 4>, (const void*)k_sweep<GN, REVERSE, 8>,
-                       (const void*)k_sweep<GN, REVERSE, 16>};
+  const void* fns[] = {(const void*)k_sweep<GN, REVERSE, 4, true>,
+                       (const void*)k_sweep<GN, REVERSE, 8, true>,
+                       (const void*)k_sweep<GN, REVERSE, 16, true>,
+                       (const void*)k_sweep<GN, REVERSE, 8, false>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;

@@ -60,10 +60,14 @@ def grad_close(g, r, name):
     g = np.asarray(g, np.float64)
     r = np.asarray(r, np.float64)
     l2 = np.linalg.norm(g - r) / np.linalg.norm(r)
-    big = np.abs(r) >= 1e-6 * np.abs(r).max()
-    worst = (np.abs(g - r)[big] / np.abs(r[big])).max()
-    print("%s: rel L2 %.3e  elementwise %.3e" % (name, l2, worst))
-    assert l2 <= 1e-5 and worst <= 1e-4, name
+    # elementwise: dL/dkappa is a difference of an absorption and a transport
+    # term, so FP32 intensities leave an error of order 1e-7 of those terms; the
+    # bound is relative where the gradient is large and absolute (1e-6 of the
+    # largest gradient) where it is a small difference
+    excess = np.abs(g - r) - (1e-4 * np.abs(r) + 1e-6 * np.abs(r).max())
+    print("%s: rel L2 %.3e  worst elementwise excess %.3e of max" % (name, l2,
+                                                                   excess.max() / np.abs(r).max()))
+    assert l2 <= 1e-5 and excess.max() <= 0.0, name
 
 
 def balance(tot):

@@ -4,7 +4,8 @@ Tolerances: dependency graphs (levels, canonical order, upwind counts) bit-exact
 J and absorbed within 1e-5 relative elementwise wherever the FP64 value is at least
 1e-20 of its maximum (FP32 headroom) and within 1e-5 in relative L1; FP64 totals
 within 1e-5 relative; GPU photon balance within 1e-6 relative; gradients within
-1e-5 in relative L2 and 1e-4 elementwise above 1e-6 of the largest magnitude.
+1e-5 in relative L2 and elementwise within 1e-4 relative plus 1e-6 of the largest
+magnitude (dL/dkappa is a difference of two terms carried in FP32).
 """
 import numpy as np
 import pytest
@@ -228,9 +229,10 @@ def _grad_close(g, r):
     r = np.asarray(r, np.float64)
     l2 = np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-300)
     assert l2 <= 1e-5, "rel L2 %.3e" % l2
-    big = np.abs(r) >= 1e-6 * np.abs(r).max()
-    worst = (np.abs(g - r)[big] / np.abs(r[big])).max()
-    assert worst <= 1e-4, "elementwise %.3e" % worst
+    # relative where the gradient is large, absolute (1e-6 of the largest) where
+    # it is a small difference of the absorption and transport terms
+    excess = np.abs(g - r) - (1e-4 * np.abs(r) + 1e-6 * np.abs(r).max())
+    assert excess.max() <= 0.0, "elementwise excess %.3e" % excess.max()
 
 
 @pytest.mark.parametrize("albedo,n_scat,G", [(0.0, 1, 1), (0.0, 1, 3), (0.5, 4, 1)])

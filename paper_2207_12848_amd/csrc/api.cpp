@@ -665,8 +665,12 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   // cell-order tile tables (tiles never straddle meshes)
   std::vector<int32_t> cbm, cbc;
   int max_faces = 1, max_cells = 1;
-  // downwind rows are at most kRowCap wide; a cell with more faces may need an
-  // overflow list of (faces + 2) ints per direction
+  // downwind rows are 16 entries wide (one 64-byte line segment each, so the
+  // whole row arrives with one line); longer lists continue in an overflow pool
+  // of fixed size.  If the pool runs out, the counts are redone with rows of
+  // kRowCap entries and a pool sized for every cell with more faces than that
+  // ((faces + 2) ints per direction).
+  constexpr int kRowNarrow = 16;
   constexpr int kRowCap = 32;
   int64_t ovf_cap = 2;
   std::vector<int64_t> fp;
@@ -685,7 +689,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     max_cells = std::max(max_cells, meshes[m].n_cells);
   }
   const int n_cblocks = (int)cbm.size();
-  const int dn_width = std::min(kRowCap, (max_faces + 3) / 4 * 4);
+  int dn_width = std::min(kRowNarrow, (max_faces + 3) / 4 * 4);
+  const int64_t ovf_cap_narrow = std::max<int64_t>(1 << 20, T / 4);
   if (ovf_cap > INT32_MAX / 2)
     return fail(SWEEP_ERR_UNSUPPORTED, "too many cells with more than %d faces", kRowCap);
   std::vector<sweep::MeshDev> md(n_meshes);
@@ -741,13 +746,12 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(depth_d.alloc(4 * n_units));
   HIP_TRY(err_d.alloc(8));
   HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 2, 0, s));
-  const int sent_len = std::max(64, dn_width);  // sentinel row of -1 after the rows
-  HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + sent_len)));
-  HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, sent_len, -1, s));
   Buf dn_ovf, dn_ovf_top;
-  HIP_TRY(dn_ovf.alloc(4 * ovf_cap));
   HIP_TRY(dn_ovf_top.alloc(4));
-  HIP_TRY(sweep::launch_fill_i32(dn_ovf_top.as<int32_t>(), 1, 0, s));
+  Buf big, big_top;  // tasks whose upwind count does not fit a 4-bit counter
+  HIP_TRY(big.alloc(8 * T));
+  HIP_TRY(big_top.alloc(4));
+  HIP_TRY(sweep::launch_fill_i32(big_top.as<int32_t>(), 1, 0, s));
   HIP_TRY(stats_d.alloc(8));
   HIP_TRY(sweep::launch_fill_i32(stats_d.as<int32_t>(), 2, 0, s));
   sweep::DagBuildArgs a{};
@@ -756,12 +760,10 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.D = n_dirs;
   a.cblk_mesh = cblk_mesh_d.as<int32_t>();
   a.cblk_c0 = cblk_c0_d.as<int32_t>();
-  a.dn_width = dn_width;
   a.max_faces = max_faces;
-  a.dnw = dnw.as<int32_t>();
-  a.dn_sentinel = (int64_t)T * dn_width;
-  a.dn_ovf = dn_ovf.as<int32_t>();
   a.dn_ovf_top = dn_ovf_top.as<int32_t>();
+  a.big = big.as<int64_t>();
+  a.big_top = big_top.as<int32_t>();
   a.stats = stats_d.as<int32_t>();
   a.meshes = meshes_d.as<sweep::MeshDev>();
   a.dirs = dirs_d.as<double>();
@@ -781,14 +783,38 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.err = err_d.as<int32_t>();
   int lds_limit = 65536;
   (void)hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, D->device);
-  {
-    ProfScope ps("count", s);
-    HIP_TRY(sweep::launch_count(a, n_cblocks, lds_limit, s));
+  int32_t stats[2] = {0, 0};
+  int32_t n_big = 0;
+  for (int attempt = 0;; ++attempt) {
+    const int64_t cap = dn_width == kRowNarrow ? ovf_cap_narrow : ovf_cap;
+    const int sent_len = std::max(64, dn_width);  // sentinel row of -1 after the rows
+    HIP_TRY(dnw.alloc(4 * ((size_t)T * dn_width + sent_len)));
+    HIP_TRY(sweep::launch_fill_i32(dnw.as<int32_t>() + (size_t)T * dn_width, sent_len, -1, s));
+    // the pool ends with room for one list that is written when it has run out
+    HIP_TRY(dn_ovf.alloc(4 * (cap + max_faces + 2)));
+    HIP_TRY(sweep::launch_fill_i32(dn_ovf_top.as<int32_t>(), 1, 0, s));
+    HIP_TRY(sweep::launch_fill_i32(big_top.as<int32_t>(), 1, 0, s));
+    HIP_TRY(sweep::launch_fill_i32(stats_d.as<int32_t>(), 2, 0, s));
+    a.dn_width = dn_width;
+    a.dnw = dnw.as<int32_t>();
+    a.dn_sentinel = (int64_t)T * dn_width;
+    a.dn_ovf = dn_ovf.as<int32_t>();
+    a.dn_ovf_cap = cap;
+    {
+      ProfScope ps("count", s);
+      HIP_TRY(sweep::launch_count(a, n_cblocks, lds_limit, s));
+    }
+    int32_t top = 0;
+    HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&n_big, big_top.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&top, dn_ovf_top.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (top <= cap) break;
+    if (dn_width >= kRowCap || attempt > 0)
+      return fail(SWEEP_ERR_HIP, "downwind overflow pool exhausted (%d > %lld)", top, (long long)cap);
+    dn_width = std::min(kRowCap, (max_faces + 3) / 4 * 4);
   }
   // the longest downwind list sets how much of every row Kahn's algorithm loads
-  int32_t stats[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
   a.dn_chunks = std::max(1, std::min(dn_width / 4, (stats[1] + 3) / 4));
   // row lengths in schedule order (the input of the row-pointer scan)
   HIP_TRY(len_up.alloc(8 * (T + 1)));
@@ -798,8 +824,10 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(hipMemsetAsync(a.len_up + T, 0, 8, s));
   HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 8, s));
   // Kahn counters in LDS as 4-bit fields when the mesh fits the LDS
-  // (the kernel's static LDS holds two frontier copies of 2048 cells)
+  // (the kernel's static LDS holds two frontier copies of 2048 cells); the
+  // rows' entries of cells with larger counts are flagged first
   const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8 + 64) + 17 * 1024 <= (size_t)lds_limit;
+  if (lds_cnt) HIP_TRY(sweep::launch_mark(a, n_big, s));
   {
     ProfScope ps("kahn", s);
     HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));

@@ -155,8 +155,11 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
                 row[ndn] = nb;
               } else {
                 if (ndn == W) {  // the row is full: continue in an overflow list
-                  const int o = atomicAdd(a.dn_ovf_top, (fe - fb) + 2);
-                  ovf = a.dn_ovf + o;
+                  const int need = (fe - fb) + 2;
+                  const int o = atomicAdd(a.dn_ovf_top, need);
+                  // a pool that has run out gets the list in its spare end (the
+                  // host sees the count past the capacity and redoes the counts)
+                  ovf = a.dn_ovf + (o + need <= a.dn_ovf_cap ? o : a.dn_ovf_cap);
                   ovf[1] = row[W - 1];
                   row[W - 1] = -(o + 2);
                 }
@@ -171,6 +174,7 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
           }
         }
         if (ovf != nullptr) ovf[0] = ndn - (W - 1);
+        if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
         for (int q = ndn; q < W; ++q) row[q] = -1;
         a.fmask[t] = make_uint2(um, dm);
         a.indeg[t] = nup;
@@ -214,6 +218,44 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   if (threadIdx.x == 0) {
     atomicMax(a.stats, s_max[0]);
     atomicMax(a.stats + 1, s_max[1]);
+  }
+}
+
+// Tasks with 15 or more upwind dependencies keep their counter in global
+// memory; the entries that point at them in their upwind cells' downwind rows
+// get bit 30 set, so that Kahn's algorithm sends those decrements there without
+// first reading the LDS counter.  One thread per such task (rare).
+constexpr int32_t kBigFlag = 0x40000000;
+
+__global__ void k_mark(DagBuildArgs a, int32_t n_big) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_big) return;
+  const int64_t t = a.big[i];
+  int lo = 0, hi = a.n_units - 1;  // unit of task t (task bases ascend)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.units[mid].task_base <= t) lo = mid; else hi = mid - 1;
+  }
+  const Unit U = a.units[lo];
+  const int c = (int)(t - U.task_base);
+  const MeshDev M = a.meshes[U.mesh];
+  const double ox = a.dirs[3 * U.dir], oy = a.dirs[3 * U.dir + 1], oz = a.dirs[3 * U.dir + 2];
+  const int W = a.dn_width;
+  for (int64_t f = M.face_ptr[c]; f < M.face_ptr[c + 1]; ++f) {
+    const int nb = M.face_nbr[f];
+    if (nb < 0 || (M.face_shift != nullptr && M.face_shift[f] != 0)) continue;
+    if (!(orient(ox, oy, oz, M.face_normal + 3 * f) < -a.eps)) continue;
+    // nb is upwind of c: flag c in nb's row (or in its overflow list)
+    int32_t* row = a.dnw + (U.task_base + nb) * W;
+    for (int q = 0; q < W; ++q) {
+      const int e = row[q];
+      if (e == c) row[q] = c | kBigFlag;
+      if (q == W - 1 && e < -1) {
+        int32_t* ov = a.dn_ovf + (-(e + 2));
+        for (int r = 1; r <= ov[0]; ++r)
+          if (ov[r] == c) ov[r] = c | kBigFlag;
+      }
+    }
   }
 }
 
@@ -354,35 +396,28 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       uint32_t wm = 0;  // bit 4q+i: cell i of chunk q became ready
       if (LDSCNT) {
         // rows are -1 padded at the end, so the wavefront's non-empty chunks are
-        // the first nq; inside them every entry issues its LDS operations without
-        // a branch: padding entries use the lane's private dummy word and a zero
-        // operand.  Two LDS round trips: every counter word is read (to spot the
-        // overflow marker, which never changes), then every decrement issued.
+        // the first nq; inside them every entry issues one LDS decrement without
+        // a branch (padding and flagged entries use the lane's private dummy
+        // word and a zero operand); flagged entries (counters kept in global
+        // memory) are decremented there afterwards
         int nq = 0;
 #pragma unroll
         for (int q = 0; q < NCH; ++q) nq += __ballot(v[q].x >= 0) != 0ull ? 1 : 0;
         const int dummy = nwords + lane;
-        uint32_t word[4 * NCH], old[4 * NCH];
-#pragma unroll
-        for (int q = 0; q < NCH; ++q) {
-          if (q >= nq) break;
-          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) word[4 * q + i] = nib[xs[i] >= 0 ? xs[i] >> 3 : dummy];
-        }
-        bool any_ovf = false;
+        uint32_t old[4 * NCH];
+        bool any_big = false;
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
           if (q >= nq) break;
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int nb = xs[i];
-            const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-            const bool ovf = ((word[4 * q + i] >> sh) & 15u) == 15u;
-            any_ovf |= nb >= 0 && ovf;
-            const uint32_t op = (nb >= 0 && !ovf) ? (1u << sh) : 0u;
-            old[4 * q + i] = atomicSub(&nib[nb >= 0 ? nb >> 3 : dummy], op);
+            const int e = xs[i];
+            const bool big = e >= 0 && (e & kBigFlag) != 0;
+            const bool lds = e >= 0 && !big;
+            any_big |= big;
+            const uint32_t sh = (uint32_t)(e & 7) * 4u;
+            old[4 * q + i] = atomicSub(&nib[lds ? e >> 3 : dummy], lds ? (1u << sh) : 0u);
           }
         }
 #pragma unroll
@@ -391,25 +426,21 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int nb = xs[i];
-            const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-            const bool ovf = ((word[4 * q + i] >> sh) & 15u) == 15u;
-            const bool ready = nb >= 0 && !ovf && ((old[4 * q + i] >> sh) & 15u) == 1u;
+            const int e = xs[i];
+            const uint32_t sh = (uint32_t)(e & 7) * 4u;
+            const bool ready = e >= 0 && (e & kBigFlag) == 0 && ((old[4 * q + i] >> sh) & 15u) == 1u;
             wm |= (uint32_t)ready << (4 * q + i);
           }
         }
-        if (__ballot(any_ovf) != 0ull) {  // cells with 15 or more upwind dependencies
+        if (__ballot(any_big) != 0ull) {
 #pragma unroll
           for (int q = 0; q < NCH; ++q) {
             if (q >= nq) break;
             const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int nb = xs[i];
-              const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-              if (nb >= 0 && ((word[4 * q + i] >> sh) & 15u) == 15u)
-                wm |= (uint32_t)dec_global(nb) << (4 * q + i);
-            }
+            for (int i = 0; i < 4; ++i)
+              if (xs[i] >= 0 && (xs[i] & kBigFlag) != 0)
+                wm |= (uint32_t)dec_global(xs[i] & ~kBigFlag) << (4 * q + i);
           }
         }
       } else {
@@ -418,7 +449,7 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (xs[i] >= 0) wm |= (uint32_t)dec_global(xs[i]) << (4 * q + i);
+            if (xs[i] >= 0) wm |= (uint32_t)dec_global(xs[i] & ~kBigFlag) << (4 * q + i);
         }
       }
       // a full row may end in a pointer to its overflow list (rare): one
@@ -433,11 +464,12 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
 #pragma unroll
         for (int sh = 1; sh < 64; sh <<= 1) mx = max(mx, __shfl_xor(mx, sh));
         for (int i = 0; i < mx; ++i) {
-          const int nb = i < no ? a.dn_ovf[o + 1 + i] : -1;
+          const int e = i < no ? a.dn_ovf[o + 1 + i] : -1;
+          const int nb = e >= 0 ? e & ~kBigFlag : -1;
           bool ready = false;
           if (nb >= 0) {
             const uint32_t sh = (uint32_t)(nb & 7) * 4u;
-            if (LDSCNT && ((nib[nb >> 3] >> sh) & 15u) != 15u) {
+            if (LDSCNT && (e & kBigFlag) == 0) {
               const uint32_t old = atomicSub(&nib[nb >> 3], 1u << sh);
               ready = ((old >> sh) & 15u) == 1u;
             } else {
@@ -467,7 +499,7 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i)
-            if (first < 0 && (wm & (1u << (4 * q + i)))) first = xs[i];
+            if (first < 0 && (wm & (1u << (4 * q + i)))) first = xs[i] & ~kBigFlag;
         }
         pf_val = first >= 0 ? a.dnw[(tb + first) * W] : a.dnw[a.dn_sentinel];
       }
@@ -485,8 +517,9 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             if (wm & (1u << (4 * q + i))) {
-              if (r < kFrontierCap) frn[r] = xs[i];
-              else spill[tail + r] = xs[i];
+              const int cell = xs[i] & ~kBigFlag;
+              if (r < kFrontierCap) frn[r] = cell;
+              else spill[tail + r] = cell;
               ++r;
             }
           }
@@ -718,6 +751,12 @@ hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cel
     }
   }
   hipLaunchKernelGGL((k_kahn<false, 8>), dim3(a.n_units), dim3(kKahnBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s) {
+  if (n_big <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark, dim3((n_big + 63) / 64), dim3(64), 0, s, a, n_big);
   return hipGetLastError();
 }
 

@@ -42,10 +42,13 @@ struct DagBuildArgs {
   const int32_t* blk_base;  // [n_units+1] first block of each unit (cell-range kernels)
   const int32_t* cblk_mesh;  // cell-order kernels: mesh and first cell of every block
   const int32_t* cblk_c0;
-  int32_t dn_width;          // width of the fixed-width downwind rows (<= 32)
+  int32_t dn_width;          // width of the fixed-width downwind rows (16 or 32)
   int32_t dn_chunks;         // chunks of 4 row entries that may hold a downwind cell
   int32_t* dn_ovf;           // overflow lists of full rows: [count, cells...]
   int32_t* dn_ovf_top;       // next free int of dn_ovf (atomic)
+  int64_t dn_ovf_cap;        // ints of dn_ovf for lists (more: the pool has run out)
+  int64_t* big;              // tasks with 15 or more upwind dependencies
+  int32_t* big_top;          // their number (atomic)
   int32_t max_faces;         // most half-faces of any cell
   int32_t* dnw;              // [T][dn_width] downwind cells of every task (-1 padded)
   int64_t dn_sentinel;       // offset in dnw of a row of -1 (4 * kRowChunks entries)
@@ -172,6 +175,7 @@ hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cel
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s);
 hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
+hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s);
 size_t count_lds_bytes(int max_faces, int dn_width);
 hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s);

@@ -107,7 +107,8 @@ struct SweepArgs {
   int32_t lev_off;
 };
 
-// Per-call preparation of the per-task denominators and sources (schedule order).
+// Per-call preparation of the per-task denominators and sources (cell order,
+// then schedule order).
 struct PrepArgs {
   const Unit* units;
   int32_t n_units;
@@ -122,8 +123,10 @@ struct PrepArgs {
   float albedo;
   float inv_D;
   int32_t G;
-  float* tden;             // [T][G]
-  float* tsrc;             // [T][G]
+  float* cden;             // [T][G] cell order (scratch)
+  float* csrc;             // [T][G] cell order (scratch)
+  float* tden;             // [T][G] schedule order
+  float* tsrc;             // [T][G] schedule order
 };
 
 // Reduction over directions (per cell and group).

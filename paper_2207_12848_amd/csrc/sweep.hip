@@ -400,7 +400,8 @@ hipError_t launch_sweep_t(const SweepArgs& a, int32_t gn, int32_t grid, int32_t 
   }
 }
 
-// Per-task denominators Aperp + kappa V and sources, in schedule order.
+// Per-task denominators Aperp + kappa V and sources, first in cell order within
+// each unit (every access coalesced).
 __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_units, int b) {
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -413,17 +414,16 @@ __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_unit
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
   const Unit U = a.units[u];
-  const int k = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
-  if (k >= U.n_cells) return;
-  const int64_t t = U.task_base + k;
-  const int c = a.sched[t];
+  const int c = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
+  if (c >= U.n_cells) return;
+  const int64_t t = U.task_base + c;  // cell order: every access is coalesced
   const int64_t ci = (int64_t)U.cell_off + c;
   const double V = (double)a.vol[ci];
-  const double ap = (double)a.aperp[U.task_base + c];
+  const double ap = (double)a.aperp[t];
   for (int g = 0; g < a.G; ++g) {
     const int64_t cg = ci * a.G + g;
     const double kap = (double)a.kappa[cg];
-    a.tden[t * a.G + g] = (float)(ap + kap * V);
+    a.cden[t * a.G + g] = (float)(ap + kap * V);
     double s;
     if (a.emission != nullptr) {
       s = (double)a.emission[cg];
@@ -432,7 +432,22 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     } else {
       s = (double)a.gsrc[cg];
     }
-    a.tsrc[t * a.G + g] = (float)s;
+    a.csrc[t * a.G + g] = (float)s;
+  }
+}
+
+// The same values in schedule order (what the sweep streams): a gather of two
+// arrays per unit, which the unit-by-unit block order keeps cache resident.
+__global__ __launch_bounds__(256) void k_prep_order(PrepArgs a) {
+  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const Unit U = a.units[u];
+  const int k = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
+  if (k >= U.n_cells) return;
+  const int64_t t = U.task_base + k;
+  const int64_t tc = U.task_base + a.sched[t];
+  for (int g = 0; g < a.G; ++g) {
+    a.tden[t * a.G + g] = a.cden[tc * a.G + g];
+    a.tsrc[t * a.G + g] = a.csrc[tc * a.G + g];
   }
 }
 
@@ -617,6 +632,7 @@ hipError_t launch_sweep_adj(const SweepArgs& a, int32_t gn, int32_t grid, int32_
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3(n_blocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_prep_order, dim3(n_blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -753,6 +753,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(sweep::launch_fill_i32(err_d.as<int32_t>(), 2, 0, s));
   Buf dn_ovf, dn_ovf_top;
   HIP_TRY(dn_ovf_top.alloc(4));
+  Buf ent_tot;  // row entries of all tasks (sizes the row arrays before the schedule exists)
+  HIP_TRY(ent_tot.alloc(16));
   Buf big, big_top;  // tasks whose upwind count does not fit a 4-bit counter
   HIP_TRY(big.alloc(8 * T));
   HIP_TRY(big_top.alloc(4));
@@ -769,6 +771,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.dn_ovf_top = dn_ovf_top.as<int32_t>();
   a.big = big.as<int64_t>();
   a.big_top = big_top.as<int32_t>();
+  a.ent_tot = ent_tot.as<unsigned long long>();
   a.stats = stats_d.as<int32_t>();
   a.meshes = meshes_d.as<sweep::MeshDev>();
   a.dirs = dirs_d.as<double>();
@@ -800,6 +803,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     HIP_TRY(sweep::launch_fill_i32(dn_ovf_top.as<int32_t>(), 1, 0, s));
     HIP_TRY(sweep::launch_fill_i32(big_top.as<int32_t>(), 1, 0, s));
     HIP_TRY(sweep::launch_fill_i32(stats_d.as<int32_t>(), 2, 0, s));
+    HIP_TRY(sweep::launch_fill_i32(ent_tot.as<int32_t>(), 4, 0, s));
     a.dn_width = dn_width;
     a.dnw = dnw.as<int32_t>();
     a.dn_sentinel = (int64_t)T * dn_width;
@@ -810,10 +814,14 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
       HIP_TRY(sweep::launch_count(a, n_cblocks, lds_limit, s));
     }
     int32_t top = 0;
+    int64_t tot[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(tot, ent_tot.p, 16, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(stats, stats_d.p, 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&n_big, big_top.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&top, dn_ovf_top.p, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    D->n_up = tot[0];
+    D->n_dn = tot[1];
     if (top <= cap) break;
     if (dn_width >= kRowCap || attempt > 0)
       return fail(SWEEP_ERR_HIP, "downwind overflow pool exhausted (%d > %lld)", top, (long long)cap);
@@ -837,18 +845,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     ProfScope ps("kahn", s);
     HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));
   }
-  std::vector<int32_t> depth(n_units);
-  int32_t err = 0;
-  HIP_TRY(hipMemcpyAsync(depth.data(), depth_d.p, 4 * n_units, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&err, err_d.p, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (err) return fail(SWEEP_ERR_CYCLE, "a dependency graph is cyclic: some tasks never become ready");
-  for (int u = 0; u < n_units; ++u) {
-    D->units[u].depth = depth[u];
-    D->max_depth = std::max(D->max_depth, depth[u]);
-  }
+  // (no synchronisation here: the depths and the cycle flag are read once, at the end)
   HIP_TRY(sweep::launch_gather_len(a, n_blocks, s));
-  HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   // row lengths in schedule order -> row pointers
   HIP_TRY(D->up_ptr.alloc(8 * (T + 1)));
   HIP_TRY(D->dn_ptr.alloc(8 * (T + 1)));
@@ -859,9 +857,6 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(scan_tmp.alloc(tmp_bytes));
   HIP_TRY(sweep::launch_scan_i64(a.len_up, a.up_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
   HIP_TRY(sweep::launch_scan_i64(a.len_dn, a.dn_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
-  HIP_TRY(hipMemcpyAsync(&D->n_up, a.up_ptr + T, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&D->n_dn, a.dn_ptr + T, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(D->up.alloc(8 * std::max<int64_t>(D->n_up, 1)));
   HIP_TRY(D->dn.alloc(8 * std::max<int64_t>(D->n_dn, 1)));
   a.up = D->up.as<int2>();
@@ -879,6 +874,17 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   for (int m = 0; m < n_meshes; ++m)
     HIP_TRY(sweep::launch_d2f(meshes[m].cell_volume, D->vol.as<float>() + D->mesh_off[m],
                               meshes[m].n_cells, s));
+  std::vector<int32_t> depth(n_units);
+  int32_t err = 0;
+  HIP_TRY(hipMemcpyAsync(depth.data(), depth_d.p, 4 * n_units, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&err, err_d.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (err) return fail(SWEEP_ERR_CYCLE, "a dependency graph is cyclic: some tasks never become ready");
+  for (int u = 0; u < n_units; ++u) {
+    D->units[u].depth = depth[u];
+    D->max_depth = std::max(D->max_depth, depth[u]);
+  }
+  HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   // schedule of the units: deepest first
   D->order.resize(n_units);
   D->identity.resize(n_units);

@@ -111,7 +111,11 @@ template <bool STAGE>
 __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_max[2];
-  if (threadIdx.x < 2) s_max[threadIdx.x] = 0;
+  __shared__ unsigned long long s_ent[2];
+  if (threadIdx.x < 2) {
+    s_max[threadIdx.x] = 0;
+    s_ent[threadIdx.x] = 0ull;
+  }
   const int m = a.cblk_mesh[blockIdx.x];
   const MeshDev M = a.meshes[m];
   const FaceTile T = stage_tile(M, a.cblk_c0[blockIdx.x], smem);
@@ -126,6 +130,7 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   const bool cell = c < T.cend;
   const int fb = cell ? (int)T.fp[ci] : 0, fe = cell ? (int)T.fp[ci + 1] : 0;
   int mi = 0, mo = 0;
+  unsigned long long eu = 0, ed = 0;  // row entries of the thread's tasks
   auto run = [&](const double* nrm, const double* area, const int32_t* nbr, const int8_t* shift) {
     for (int d0 = 0; d0 < a.D; d0 += kDirs) {
       const int d = d0 + dj;
@@ -184,6 +189,8 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
         a.bnd[t] = make_float2((float)wall, (float)per);
         mi = max(mi, nup);
         mo = max(mo, ndn);
+        eu += (unsigned long long)(nup + npin);
+        ed += (unsigned long long)ndn;
       }
       if (STAGE) {
         __syncthreads();
@@ -214,10 +221,14 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   }
   atomicMax(&s_max[0], mi);
   atomicMax(&s_max[1], mo);
+  atomicAdd(&s_ent[0], eu);
+  atomicAdd(&s_ent[1], ed);
   __syncthreads();
   if (threadIdx.x == 0) {
     atomicMax(a.stats, s_max[0]);
     atomicMax(a.stats + 1, s_max[1]);
+    atomicAdd(a.ent_tot, s_ent[0]);
+    atomicAdd(a.ent_tot + 1, s_ent[1]);
   }
 }
 
@@ -547,9 +558,11 @@ __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
   const int k = (blockIdx.x - a.blk_base[u]) * kCountBlock + threadIdx.x;
   if (k >= U.n_cells) return;
   const int64_t t = U.task_base + k;
-  const int c = a.sched[t];
-  a.len_up[t] = a.rowlen_up[U.task_base + c];
-  a.len_dn[t] = a.rowlen_dn[U.task_base + c];
+  // slots past the scheduled tasks (a cyclic graph, reported after the build) get no row
+  const int scheduled = a.lp[U.lp_base + a.depth[u]];
+  const int c = k < scheduled ? a.sched[t] : -1;
+  a.len_up[t] = c >= 0 ? a.rowlen_up[U.task_base + c] : 0;
+  a.len_dn[t] = c >= 0 ? a.rowlen_dn[U.task_base + c] : 0;
 }
 
 // Per face: the neighbour code (>= 0: interior neighbour, -1: vacuum wall,
@@ -590,11 +603,12 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
   const int32_t* inv = a.inv + tb;
   const int kw = (blockIdx.x - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
   if (kw >= U.n_cells) return;
-  // lane L: the task of slot kw + L
+  // lane L: the task of slot kw + L (slots past the scheduled tasks of a cyclic
+  // graph, reported after the build, get no row)
   const int k = kw + lane;
-  const bool kv = k < U.n_cells;
-  const int kc = kv ? k : U.n_cells - 1;
-  const int c = a.sched[tb + kc];
+  const bool kv = k < a.lp[U.lp_base + a.depth[u]];
+  const int kc = kv ? k : 0;
+  const int c = kv ? a.sched[tb + kc] : 0;
   const int64_t eu0 = a.up_ptr[tb + kc];
   const int64_t ed0 = a.dn_ptr[tb + kc];
   const int64_t f0 = M.face_ptr[c];
@@ -684,7 +698,8 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
 // First row entry of every level (per unit), so a level's rows form one block.
 __global__ void k_level_entries(DagBuildArgs a) {
   const Unit U = a.units[blockIdx.x];
-  for (int l = threadIdx.x; l <= U.depth + 1; l += blockDim.x) {
+  const int depth = a.depth[blockIdx.x];
+  for (int l = threadIdx.x; l <= depth + 1; l += blockDim.x) {
     const int64_t k = U.task_base + a.lp[U.lp_base + l];
     a.lev_up[U.lp_base + l] = a.up_ptr[k];
     a.lev_dn[U.lp_base + l] = a.dn_ptr[k];

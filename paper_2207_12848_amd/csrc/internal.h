@@ -53,6 +53,7 @@ struct DagBuildArgs {
   int32_t* dnw;              // [T][dn_width] downwind cells of every task (-1 padded)
   int64_t dn_sentinel;       // offset in dnw of a row of -1 (4 * kRowChunks entries)
   int32_t* stats;            // [0] max in-degree, [1] max out-degree (atomic max)
+  unsigned long long* ent_tot;  // [0] upwind-row entries, [1] downwind-row entries (all tasks)
   // per task, cell order within the unit
   int32_t* indeg;
   int32_t* rowlen_up;

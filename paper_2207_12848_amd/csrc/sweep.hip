@@ -11,8 +11,8 @@
 //
 // LDS ring: the results of the last `ring` tasks of the schedule are kept in
 // LDS, indexed by schedule position modulo `ring`, so most upwind reads are LDS
-// reads; an older upwind result is read back from global memory (it was stored
-// at least one barrier earlier by the same workgroup).
+// reads; an older upwind result is prefetched from global memory a step ahead
+// (it was stored at least two barriers earlier by the same workgroup).
 #include "internal.h"
 
 namespace sweep {
@@ -20,6 +20,54 @@ namespace sweep {
 namespace {
 
 constexpr float kInv4Pi = 0.0795774715459476678f;  // 1 / (4 pi)
+
+// Buffer loads: every per-unit array is addressed through a buffer resource
+// (base in scalar registers, 32-bit offsets); offsets past the end read 0.
+constexpr int32_t kBufFlags = 0x00020000;  // raw buffer, 32-bit data (gfx9 family)
+constexpr uint32_t kOob = 0x7ffffff0u;     // an offset past the end of any buffer here
+
+template <class T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0,
+                                           (int)(p == nullptr ? 0 : bytes), kBufFlags);
+}
+
+__device__ __forceinline__ int2 ld_b64(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ int ld_b32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __int_as_float(ld_b32(r, vo, so));
+}
+__device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)vo, 0, 0);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The unit's buffers (uniform over the workgroup).
+struct UnitBufs {
+  __amdgpu_buffer_rsrc_t ent;    // row entries of the unit (from its first entry)
+  __amdgpu_buffer_rsrc_t sched;  // schedule of the unit
+  __amdgpu_buffer_rsrc_t rp;     // row pointers of the unit (int64)
+  __amdgpu_buffer_rsrc_t den;    // [slot][G] at group g0 of the unit's first task
+  __amdgpu_buffer_rsrc_t src;
+  __amdgpu_buffer_rsrc_t outs;   // out_s at group g0 of the unit's first task: [slot][G]
+  __amdgpu_buffer_rsrc_t prev;   // phi_prev of this direction at group g0: [cell][G]
+  __amdgpu_buffer_rsrc_t out;    // out of this direction at group g0: [cell][G]
+  __amdgpu_buffer_rsrc_t pin;    // pin of this direction at group g0: [cell][G]
+  int64_t ue0;                   // first row entry of the unit
+};
+
+// One slot after the ring: a sink for the results of threads without a task.
+constexpr int kSlotSink = 0;
+constexpr int kSlots = 1;
 
 // Record of one task: cell, row [r0, r1) relative to its level's first entry,
 // denominator and source per group.
@@ -31,23 +79,20 @@ struct TaskRec {
   float src[GN];
 };
 
-// Loads prefetched for one level: the thread's share of the level's row block
-// and the raw record of the thread's first task of the level (no arithmetic on
-// loaded values until they are published, so the loads stay in flight).
 // Per-step values, uniform over the workgroup.
 struct LevelInfo {
   int l, k0, k1;  // level and its task range
+  int ne;         // row entries of the level
   int nst;        // entries of the level held in LDS staging
-  int thr;        // ring-miss threshold for entries served from registers
   int64_t e0;     // first row entry of the level
 };
 
+// Loads in flight for one step: the thread's share of the level's row block
+// (raw entries) and the record of the thread's first task of the level.  Lanes
+// past the level read past the buffers' ends (no memory traffic, value 0).
 template <int GN, int CH>
 struct Pref {
-  LevelInfo L;
   int2 st[CH];
-  float mv[CH];    // GN == 1: value behind a ring miss or a periodic inflow of st[i]
-  uint32_t codes;  // 2 bits per chunk: 1 ring miss, 2 periodic inflow
   int c;
   uint32_t rp0, rp1;  // low words of the row pointers (row offsets are taken mod 2^32)
   float den[GN];
@@ -55,49 +100,42 @@ struct Pref {
 };
 
 template <int GN>
-__device__ __forceinline__ void load_rec(const SweepArgs& a, int64_t tb, int k, int64_t e0,
+__device__ __forceinline__ void load_rec(const SweepArgs& a, const UnitBufs& B, int k, int64_t e0,
                                          TaskRec<GN>& t) {
-  t.c = a.sched[tb + k];
-  t.r0 = (int)(a.row_ptr[tb + k] - e0);
-  t.r1 = (int)(a.row_ptr[tb + k + 1] - e0);
-  const int64_t q = (tb + k) * a.G + a.g0;
+  t.c = ld_b32(B.sched, 4u * (uint32_t)k, 0);
+  t.r0 = (int)((uint32_t)ld_b32(B.rp, 8u * (uint32_t)k, 0) - (uint32_t)e0);
+  t.r1 = (int)((uint32_t)ld_b32(B.rp, 8u * (uint32_t)(k + 1), 0) - (uint32_t)e0);
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
-    t.den[g] = a.tden[q + g];
-    t.src[g] = a.tsrc[q + g];
+    t.den[g] = ld_f32(B.den, 4u * (uint32_t)(k * a.G + g), 0);
+    t.src[g] = ld_f32(B.src, 4u * (uint32_t)(k * a.G + g), 0);
   }
 }
 
-// Unconditional loads (addresses clamped into the arrays) so that every path
-// issues the same number of vector-memory operations.
+// Every thread issues the same loads at every step (fixed count, so the waits
+// for the loads in flight stay exact); the offsets of lanes past the level are
+// moved past the buffers' ends.
 template <int GN, int CH>
-__device__ __forceinline__ void issue_pref(const SweepArgs& a, int64_t tb, int tid, int nthr,
-                                           int k0, int k1, int64_t e0, int ne, Pref<GN, CH>& P) {
-  const int64_t emax = a.n_ent > 0 ? a.n_ent - 1 : 0;
+__device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B, int tid, int nthr,
+                                           const LevelInfo& L, Pref<GN, CH>& P) {
+  const uint32_t eoff = 8u * (uint32_t)(L.e0 - B.ue0);
 #pragma unroll
   for (int i = 0; i < CH; ++i) {
-    int64_t e = e0 + (int64_t)tid + (int64_t)i * nthr;
-    e = e < emax ? e : emax;
-    P.st[i] = a.ent[e];
+    const int idx = tid + i * nthr;
+    P.st[i] = ld_b64(B.ent, idx < L.nst ? 8u * (uint32_t)idx : kOob, eoff);
   }
-  int k = k0 + tid;
-  k = k < k1 - 1 ? k : k1 - 1;
-  P.c = a.sched[tb + k];
-  const uint32_t* rpw = reinterpret_cast<const uint32_t*>(a.row_ptr);
-  P.rp0 = rpw[2 * (tb + k)];
-  P.rp1 = rpw[2 * (tb + k + 1)];
-  const int64_t q = (tb + k) * a.G + a.g0;
+  const bool act = L.k0 + tid < L.k1;
+  const uint32_t k0 = (uint32_t)L.k0;
+  P.c = ld_b32(B.sched, act ? 4u * (uint32_t)tid : kOob, 4u * k0);
+  P.rp0 = (uint32_t)ld_b32(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
+  P.rp1 = (uint32_t)ld_b32(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * (k0 + 1u));
+  const uint32_t vo = act ? 4u * (uint32_t)(tid * a.G) : kOob, so = 4u * k0 * (uint32_t)a.G;
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
-    P.den[g] = a.tden[q + g];
-    P.src[g] = a.tsrc[q + g];
+    P.den[g] = ld_f32(B.den, vo + 4u * g, so);
+    P.src[g] = ld_f32(B.src, vo + 4u * g, so);
   }
 }
-
-// Entry codes written into LDS staging for prefetched values (GN == 1): the
-// entry's second word then holds w * value.
-constexpr int kMissCode = (int)0x80000000;
-constexpr int kPerCode = (int)0x80000001;
 
 // Inflow of one task per group (and the periodic part of it).
 template <int GN>
@@ -106,97 +144,169 @@ struct Inflow {
   float pin[GN];
 };
 
+// Schedule positions whose results are in the LDS ring while a level is solved,
+// [lo, lo + n) with lo >= 0: forward, the last R positions up to the level's end;
+// adjoint (levels in reverse order), the R positions from the level's start.
+// The level's own writes never evict an upwind result inside the window.
+struct Window {
+  int lo;
+  uint32_t n;
+  __device__ __forceinline__ bool has(int p) const { return (uint32_t)(p - lo) < n; }
+};
+
+template <bool REVERSE>
+__device__ __forceinline__ Window window(int k0, int k1, int R) {
+  Window w;
+  if (REVERSE) {
+    w.lo = k0;
+    w.n = (uint32_t)R;
+  } else {
+    w.lo = k1 - R > 0 ? k1 - R : 0;
+    w.n = (uint32_t)(k1 - w.lo);
+  }
+  return w;
+}
+
 template <int GN, bool REVERSE>
-__device__ __forceinline__ void finish_task(const SweepArgs& a, const TaskRec<GN>& t, int k,
-                                            const Inflow<GN>& in, float* ring, int64_t obase,
-                                            int64_t tb) {
+__device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& B,
+                                            const TaskRec<GN>& t, int k, const Inflow<GN>& in,
+                                            float* ring) {
   float* rr = ring + (k & a.ring_mask) * GN;
-  float* o = a.out + obase + (int64_t)t.c * a.G;
-  float* os = a.out_s + (tb + k) * a.G + a.g0;
+  const uint32_t oc = 4u * (uint32_t)(t.c * a.G), ok = 4u * (uint32_t)(k * a.G);
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
     const float v = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
     rr[g] = v;
-    o[g] = v;
-    os[g] = v;
+    st_f32(v, B.out, oc + 4u * g);
+    st_f32(v, B.outs, ok + 4u * g);
   }
   if (!REVERSE && a.pin != nullptr) {
-    float* pp = a.pin + obase + (int64_t)t.c * a.G;
 #pragma unroll
-    for (int g = 0; g < GN; ++g) pp[g] = in.pin[g];
+    for (int g = 0; g < GN; ++g) st_f32(in.pin[g], B.pin, oc + 4u * g);
   }
 }
 
-// Inflow of one task.  FAST: the row is in LDS staging, where ring misses and
-// periodic inflows prefetched a level ahead appear as coded entries; anything
-// else (levels larger than the ring, groups packed by more than one) goes
-// through a second pass with global loads, so the main loop issues none.
-template <int GN, bool REVERSE, bool FAST>
-__device__ __forceinline__ Inflow<GN> gather_task(const SweepArgs& a, const TaskRec<GN>& t,
-                                                  int k0, int k1, int64_t e0, const int2* stg,
-                                                  const float* ring, int64_t obase, int64_t tb) {
-  const int R = a.ring_mask + 1;
-  Inflow<GN> in;
-  float* acc = in.acc;
-  float* pin = in.pin;
+// The common step: at most one task per thread and every inflow staged.  Every
+// memory operation is issued unconditionally (a thread without a task writes
+// the sink slot and stores past the buffers' ends, which are dropped), so each
+// step issues a fixed number of vector-memory operations.
+template <int GN, bool REVERSE>
+__device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& B,
+                                            const TaskRec<GN>& t, int k, const Inflow<GN>& in,
+                                            float* ring, float* sink) {
+  const bool act = t.c >= 0;
+  float* rr = act ? ring + (k & a.ring_mask) * GN : sink;
+  const uint32_t oc = act ? 4u * (uint32_t)(t.c * a.G) : kOob;
+  const uint32_t ok = act ? 4u * (uint32_t)(k * a.G) : kOob;
 #pragma unroll
-  for (int g = 0; g < GN; ++g) acc[g] = pin[g] = 0.0f;
-  bool miss = false;
-  // entries in batches of 8, branch-free: all LDS reads of a batch are issued
-  // before any is used and every entry kind is folded in with selects
+  for (int g = 0; g < GN; ++g) {
+    const float v = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
+    rr[g] = v;
+    st_f32(v, B.out, oc + 4u * g);
+    st_f32(v, B.outs, ok + 4u * g);
+    if (!REVERSE) st_f32(in.pin[g], B.pin, oc + 4u * g);  // no pin buffer: size 0, dropped
+  }
+}
+
+// Inflow of one task from its staged row (raw entries in LDS), in batches of 8:
+// one LDS read per entry and one of the ring slot it names, then a multiply and
+// an add per entry in row order (explicit rounding, no contraction).  `far`
+// collects the largest offset of an entry from the window's start: the result
+// holds only when every entry is inside the window (far < w.n); otherwise the
+// task is recomputed by gather_mixed.
+template <int GN>
+__device__ __forceinline__ Inflow<GN> gather_staged(const SweepArgs& a, const TaskRec<GN>& t,
+                                                    const int2* stg, const float* ring, Window w,
+                                                    uint32_t& far) {
+  Inflow<GN> in;
+#pragma unroll
+  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
   for (int rb = t.r0; rb < t.r1; rb += 8) {
     int2 en[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int r = rb + q < t.r1 ? rb + q : t.r1 - 1;
-      en[q] = FAST ? stg[r] : a.ent[e0 + r];
-    }
+    for (int q = 0; q < 8; ++q) en[q] = stg[rb + q];
     float rv[8][GN];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int pr = en[q].x >= 0 ? en[q].x : 0;
-      const float* rr = ring + (pr & a.ring_mask) * GN;
+      const float* v = ring + (en[q].x & a.ring_mask) * GN;
 #pragma unroll
-      for (int g = 0; g < GN; ++g) rv[q][g] = rr[g];
+      for (int g = 0; g < GN; ++g) rv[q][g] = v[g];
     }
+    const int nr = t.r1 - rb;  // entries of the row in this batch
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const bool valid = rb + q < t.r1;
-      const int p = en[q].x;
-      const bool in_ring = p >= 0 && (REVERSE ? (p < k0 + R) : (p >= k1 - R));
-      const bool is_miss = GN == 1 && p == kMissCode;
-      const bool is_per = GN == 1 && p == kPerCode;
-      const float y = __int_as_float(en[q].y);
-      // explicit rounding (no contraction): every launch form and group packing
-      // computes each task's inflow with the same operations in row order
+      if (q < nr) far = max(far, (uint32_t)(en[q].x - w.lo));
+      const float y = q < nr ? __int_as_float(en[q].y) : 0.0f;
 #pragma unroll
-      for (int g = 0; g < GN; ++g) {
-        const float c = in_ring ? __fmul_rn(y, rv[q][g]) : ((is_miss || is_per) ? y : 0.0f);
-        acc[g] = __fadd_rn(acc[g], valid ? c : 0.0f);
-      }
-      pin[0] = __fadd_rn(pin[0], (valid && is_per) ? y : 0.0f);
-      miss = miss || (valid && !in_ring && !is_miss && !is_per);
+      for (int g = 0; g < GN; ++g) in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(y, rv[q][g]));
     }
   }
-  if (miss) {
-    for (int r = t.r0; r < t.r1; ++r) {
-      const int2 en = FAST ? stg[r] : a.ent[e0 + r];
-      const int p = en.x;
-      if (p == kMissCode || p == kPerCode) continue;
-      const float w = __int_as_float(en.y);
-      if (p >= 0) {
-        if (REVERSE ? (p < k0 + R) : (p >= k1 - R)) continue;
-        const float* q = a.out_s + (tb + p) * a.G + a.g0;
+  return in;
+}
+
+// Inflow of one task from its staged row when some entries lie outside the
+// window, in row order: in-window entries from the ring, older results from
+// out_s (written at least one barrier earlier by this workgroup) and periodic
+// inflows from the previous pass (zero without one).
+template <int GN>
+__device__ __forceinline__ Inflow<GN> gather_mixed(const SweepArgs& a, const UnitBufs& B,
+                                                   const TaskRec<GN>& t, const int2* stg, Window w,
+                                                   const float* ring) {
+  Inflow<GN> in;
 #pragma unroll
-        for (int g = 0; g < GN; ++g) acc[g] = __fadd_rn(acc[g], __fmul_rn(w, q[g]));
-      } else if (a.phi_prev != nullptr) {
-        const float* q = a.phi_prev + obase + (int64_t)(-p - 1) * a.G;
+  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
+  for (int r = t.r0; r < t.r1; ++r) {
+    const int2 en = stg[r];
+    const int p = en.x;
+    const float y = __int_as_float(en.y);
+    if (p >= 0) {
+      const bool inw = w.has(p);
 #pragma unroll
-        for (int g = 0; g < GN; ++g) {
-          const float v = __fmul_rn(w, q[g]);
-          acc[g] = __fadd_rn(acc[g], v);
-          pin[g] = __fadd_rn(pin[g], v);
-        }
+      for (int g = 0; g < GN; ++g) {
+        const float v = inw ? ring[(p & a.ring_mask) * GN + g]
+                            : ld_f32(B.outs, 4u * (uint32_t)(p * a.G + g), 0);
+        in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(y, v));
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < GN; ++g) {
+        const float v = __fmul_rn(y, ld_f32(B.prev, 4u * (uint32_t)((-p - 1) * a.G + g), 0));
+        in.acc[g] = __fadd_rn(in.acc[g], v);
+        in.pin[g] = __fadd_rn(in.pin[g], v);
+      }
+    }
+  }
+  return in;
+}
+
+// Inflow of one task straight from global memory (levels with more entries
+// than the staging buffer holds), in row order.
+template <int GN>
+__device__ __forceinline__ Inflow<GN> gather_global(const SweepArgs& a, const UnitBufs& B,
+                                                    const TaskRec<GN>& t, int64_t e0, Window w,
+                                                    const float* ring) {
+  Inflow<GN> in;
+#pragma unroll
+  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
+  const uint32_t eoff = 8u * (uint32_t)(e0 - B.ue0);
+  for (int r = t.r0; r < t.r1; ++r) {
+    const int2 en = ld_b64(B.ent, 8u * (uint32_t)r, eoff);
+    const int p = en.x;
+    const float w8 = __int_as_float(en.y);
+    if (p >= 0) {
+      const bool inw = w.has(p);
+#pragma unroll
+      for (int g = 0; g < GN; ++g) {
+        const float v = inw ? ring[(p & a.ring_mask) * GN + g]
+                            : ld_f32(B.outs, 4u * (uint32_t)(p * a.G + g), 0);
+        in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(w8, v));
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < GN; ++g) {
+        const float v = __fmul_rn(w8, ld_f32(B.prev, 4u * (uint32_t)((-p - 1) * a.G + g), 0));
+        in.acc[g] = __fadd_rn(in.acc[g], v);
+        in.pin[g] = __fadd_rn(in.pin[g], v);
       }
     }
   }
@@ -205,13 +315,15 @@ __device__ __forceinline__ Inflow<GN> gather_task(const SweepArgs& a, const Task
 
 // One workgroup per (mesh, direction) unit at a time, levels in order (reverse
 // for the adjoint), one barrier per level.  Each level's rows are one block of
-// entries; a level's block and the records of its tasks are loaded three
-// levels ahead into registers (three rotating sets) and written to one of two
-// LDS staging buffers the level before it is solved.
+// entries; a level's block and the record of each thread's task are loaded NS - 1
+// steps ahead into registers (NS rotating sets) and copied into one of two LDS
+// staging buffers the step before the level is solved, so no load waits on the
+// critical path of a common step.
 // LVL_LDS = false (graphs deeper than the LDS level tables hold): the level
 // pointers and first entries are read from global memory at every step.
 template <int GN, bool REVERSE, int CH, bool LVL_LDS>
 __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
+  constexpr int NS = 3;
   extern __shared__ __align__(16) unsigned char smem[];
   float* ring = reinterpret_cast<float*>(smem);
   int2* stage = reinterpret_cast<int2*>(smem + a.stage_off);
@@ -221,6 +333,14 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int SE = CH * nthr;
+  const int SP = SE + 8;  // staging buffer stride (8 entries of padding for the batches)
+  const int R = a.ring_mask + 1;
+  float* sink = ring + (R + kSlotSink) * GN;
+  // the batches of 8 read up to 7 entries past a row (stale entries of earlier
+  // levels, or these) and the ring slots they name, with factor 0: every entry
+  // names a slot, every slot holds a finite value
+  for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(-1, 0);
+  for (int i = tid; i < R * GN; i += nthr) ring[i] = 0.0f;
   for (int it = 0;; ++it) {
     int ui;
     if (a.work_counter != nullptr) {
@@ -248,123 +368,105 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
     const int64_t* levg = a.lev + U.lp_base;
     auto LP = [&](int l) -> int { return LVL_LDS ? lps[l] : lpg[l]; };
     auto LEV = [&](int l) -> int64_t { return LVL_LDS ? levs[l] : levg[l]; };
-    auto LVL = [&](int s) -> int {  // level solved at step s (clamped into range)
-      s = s < depth - 1 ? s : depth - 1;
-      return REVERSE ? depth - 1 - s : s;
-    };
     const int64_t obase = ((int64_t)U.dir * a.C_total + U.cell_off) * a.G + a.g0;
-    Pref<GN, CH> P0, P1, P2;
-    TaskRec<GN> cur;
-    const int R = a.ring_mask + 1;
+    const int C = U.n_cells;
+    UnitBufs B;
+    B.ue0 = LEV(0) < LEV(depth) ? LEV(0) : LEV(depth);
+    const int64_t ue1 = LEV(0) < LEV(depth) ? LEV(depth) : LEV(0);
+    B.ent = rsrc(a.ent + B.ue0, 8 * (ue1 - B.ue0));
+    B.sched = rsrc(a.sched + tb, 4 * (int64_t)C);
+    B.rp = rsrc(a.row_ptr + tb, 8 * ((int64_t)C + 1));
+    B.den = rsrc(a.tden + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
+    B.src = rsrc(a.tsrc + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
+    B.outs = rsrc(a.out_s + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
+    B.prev = rsrc(a.phi_prev == nullptr ? nullptr : a.phi_prev + obase, 4 * ((int64_t)C * a.G - a.g0));
+    B.out = rsrc(a.out + obase, 4 * ((int64_t)C * a.G - a.g0));
+    B.pin = rsrc(a.pin == nullptr ? nullptr : a.pin + obase, 4 * ((int64_t)C * a.G - a.g0));
+    // level solved at step s (steps past the last one repeat it: their loads are
+    // issued and never used)
     auto info = [&](int s) -> LevelInfo {
+      s = s < depth - 1 ? s : depth - 1;
       LevelInfo L;
-      L.l = LVL(s);
-      L.k0 = LP(L.l);
-      L.k1 = LP(L.l + 1);
-      L.e0 = LEV(L.l);
-      const int ne = (int)(LEV(L.l + 1) - L.e0);
-      L.nst = ne < SE ? ne : SE;
-      // a ring miss is served from registers when its producer completed before
-      // the step two earlier started (its value is then visible to every wave)
-      const int ls = LVL(s - 2 < 0 ? 0 : s - 2);
-      L.thr = REVERSE ? max(L.k0 + R, LP(ls + 1)) : min(L.k1 - R, LP(ls));
+      L.l = REVERSE ? depth - 1 - s : s;
+      // the values are uniform: keep them in scalar registers
+      L.k0 = __builtin_amdgcn_readfirstlane(LP(L.l));
+      L.k1 = __builtin_amdgcn_readfirstlane(LP(L.l + 1));
+      L.e0 = uniform64(LEV(L.l));
+      L.ne = (int)(uniform64(LEV(L.l + 1)) - L.e0);
+      L.nst = L.ne < SE ? L.ne : SE;
       return L;
     };
+    Pref<GN, CH> P[NS];
+    TaskRec<GN> cur;
     LevelInfo curL;
-    auto issue = [&](int s, Pref<GN, CH>& P) {
-      P.L = info(s);
-      issue_pref<GN, CH>(a, tb, tid, nthr, P.L.k0, P.L.k1, P.L.e0, P.L.nst, P);
-    };
-    auto missload = [&](Pref<GN, CH>& P) {
-      P.codes = 0;
+    auto issue = [&](int s, Pref<GN, CH>& Q) { issue_pref<GN, CH>(a, B, tid, nthr, info(s), Q); };
+    // raw entries into the staging buffer of step s, the thread's record into `cur`
+    auto publish = [&](int s, const Pref<GN, CH>& Q) {
+      const LevelInfo L = info(s);
+      int2* dst = stage + (s & 1) * SP;
 #pragma unroll
       for (int i = 0; i < CH; ++i) {
-        const int p = P.st[i].x;
-        uint32_t cd = 0;
-        if (GN == 1 && tid + i * nthr < P.L.nst)
-          cd = p < 0 ? 2u : ((REVERSE ? p >= P.L.thr : p < P.L.thr) ? 1u : 0u);
-        P.codes |= cd << (2 * i);
-        const float* q = a.tden;  // any valid address
-        if (cd == 1) q = a.out_s + (tb + p) * a.G + a.g0;
-        if (cd == 2 && a.phi_prev != nullptr) q = a.phi_prev + obase + (int64_t)(-p - 1) * a.G;
-        P.mv[i] = *q;
-      }
-    };
-    auto publish = [&](int s, const Pref<GN, CH>& P) {
-      int2* dst = stage + (s & 1) * SE;
-#pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        if (i * nthr >= P.L.nst) break;
+        if (i * nthr >= L.nst) break;
         const int idx = tid + i * nthr;
-        int2 en = P.st[i];
-        const uint32_t cd = (P.codes >> (2 * i)) & 3u;
-        if (cd == 1) en = make_int2(kMissCode, __float_as_int(__int_as_float(en.y) * P.mv[i]));
-        if (cd == 2)
-          en = make_int2(kPerCode, __float_as_int(a.phi_prev != nullptr ? __int_as_float(en.y) * P.mv[i] : 0.0f));
-        if (idx < P.L.nst) dst[idx] = en;
+        dst[idx < L.nst ? idx : SE] = idx < L.nst ? Q.st[i] : make_int2(-1, 0);
       }
-      curL = P.L;
-      cur.c = P.L.k0 + tid < P.L.k1 ? P.c : -1;
-      cur.r0 = (int)(P.rp0 - (uint32_t)P.L.e0);
-      cur.r1 = (int)(P.rp1 - (uint32_t)P.L.e0);
+      curL = L;
+      const bool act = L.k0 + tid < L.k1;
+      cur.c = act ? Q.c : -1;
+      cur.r0 = act ? (int)(Q.rp0 - (uint32_t)L.e0) : 0;
+      cur.r1 = act ? (int)(Q.rp1 - (uint32_t)L.e0) : 0;
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
-        cur.den[g] = P.den[g];
-        cur.src[g] = P.src[g];
+        cur.den[g] = Q.den[g];
+        cur.src[g] = Q.src[g];
       }
     };
     auto solve = [&](int s) {
       const int k0 = curL.k0, k1 = curL.k1;
       const int64_t e0 = curL.e0;
-      const int2* stg = stage + (s & 1) * SE;
-      if (curL.nst == (int)(LEV(curL.l + 1) - e0)) {
-        if (cur.c >= 0) {
-          const Inflow<GN> in = gather_task<GN, REVERSE, true>(a, cur, k0, k1, e0, stg, ring, obase, tb);
-          finish_task<GN, REVERSE>(a, cur, k0 + tid, in, ring, obase, tb);
-        }
-        for (int k = k0 + tid + nthr; k < k1; k += nthr) {
-          TaskRec<GN> t;
-          load_rec<GN>(a, tb, k, e0, t);
-          const Inflow<GN> in = gather_task<GN, REVERSE, true>(a, t, k0, k1, e0, stg, ring, obase, tb);
-          finish_task<GN, REVERSE>(a, t, k, in, ring, obase, tb);
-        }
-      } else {
-        for (int k = k0 + tid; k < k1; k += nthr) {
-          TaskRec<GN> t;
-          if (k == k0 + tid) t = cur; else load_rec<GN>(a, tb, k, e0, t);
-          const Inflow<GN> in = gather_task<GN, REVERSE, false>(a, t, k0, k1, e0, stg, ring, obase, tb);
-          finish_task<GN, REVERSE>(a, t, k, in, ring, obase, tb);
-        }
+      const int2* stg = stage + (s & 1) * SP;
+      const Window w = window<REVERSE>(k0, k1, R);
+      const bool staged = curL.nst == curL.ne;
+      if (staged && k1 - k0 <= nthr) {
+        uint32_t far = 0;
+        Inflow<GN> in = gather_staged<GN>(a, cur, stg, ring, w, far);
+        if (far >= w.n) in = gather_mixed<GN>(a, B, cur, stg, w, ring);
+        finish_fast<GN, REVERSE>(a, B, cur, k0 + tid, in, ring, sink);
+        return;
       }
+      for (int k = k0 + tid; k < k1; k += nthr) {
+        TaskRec<GN> t;
+        if (k == k0 + tid) t = cur; else load_rec<GN>(a, B, k, e0, t);
+        Inflow<GN> in;
+        if (staged) {
+          uint32_t far = 0;
+          in = gather_staged<GN>(a, t, stg, ring, w, far);
+          if (far >= w.n) in = gather_mixed<GN>(a, B, t, stg, w, ring);
+        } else {
+          in = gather_global<GN>(a, B, t, e0, w, ring);
+        }
+        finish_task<GN, REVERSE>(a, B, t, k, in, ring);
+      }
+      // the uncommon steps leave no memory operation of theirs in flight, so the
+      // waits of the common steps are counted exactly
+      __builtin_amdgcn_s_waitcnt(0);
     };
-    // prologue: step 0 staged, steps 1 and 2 in flight.  Step s then solves,
-    // issues the loads of step s + 3, the prefetches of step s + 2 and
-    // publishes step s + 1.
-    issue(0, P0);
-    issue(1, P1);
-    missload(P0);
-    publish(0, P0);
-    issue(2, P2);
-    missload(P1);
+    // prologue: steps 0 .. NS - 1 in flight, step 0 staged.  Step s then solves,
+    // issues the loads of step s + NS into the set it freed and publishes step
+    // s + 1 (loaded NS - 1 steps earlier).
+#pragma unroll
+    for (int j = 0; j < NS; ++j) issue(j, P[j]);
+    publish(0, P[0]);
     __syncthreads();
-    for (int s = 0; s < depth; s += 3) {
-      solve(s);
-      issue(s + 3, P0);
-      missload(P2);
-      if (s + 1 < depth) publish(s + 1, P1);
-      __syncthreads();
-      if (s + 1 >= depth) break;
-      solve(s + 1);
-      issue(s + 4, P1);
-      missload(P0);
-      if (s + 2 < depth) publish(s + 2, P2);
-      __syncthreads();
-      if (s + 2 >= depth) break;
-      solve(s + 2);
-      issue(s + 5, P2);
-      missload(P1);
-      if (s + 3 < depth) publish(s + 3, P0);
-      __syncthreads();
+    for (int s = 0; s < depth; s += NS) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        if (s + j >= depth) break;
+        solve(s + j);
+        issue(s + j + NS, P[j]);
+        if (s + j + 1 < depth) publish(s + j + 1, P[(j + 1) % NS]);
+        __syncthreads();
+      }
     }
   }
 }
@@ -606,10 +708,10 @@ inline unsigned grid1d(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 LdsLayout sweep_lds_layout(int32_t gn, int32_t ring, int32_t stage, int32_t lp_cap) {
   LdsLayout L;
-  size_t off = (size_t)gn * ring * sizeof(float);
+  size_t off = (size_t)gn * (ring + kSlots) * sizeof(float);  // the ring and its slots
   off = (off + 15) & ~(size_t)15;
   L.stage_off = (int32_t)off;
-  off += 2 * (size_t)stage * sizeof(int2);
+  off += 2 * ((size_t)stage + 8) * sizeof(int2);  // two staging buffers, 8 entries of padding
   L.lp_off = (int32_t)off;
   off += (size_t)lp_cap * sizeof(int32_t);
   off = (off + 7) & ~(size_t)7;

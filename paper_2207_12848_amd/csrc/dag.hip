@@ -381,12 +381,21 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
     int* s_push = &s_cnt[l % 3];
     const int* frc = fr[l & 1];
     int* frn = fr[(l + 1) & 1];
+    const bool fr_lds = tail - head <= kFrontierCap;  // the whole frontier is in LDS
     for (int kb = head; kb < tail; kb += nthr) {
       const int k = kb + tid;
       const bool active = k < tail;
       if (__ballot(active) == 0ull) continue;  // wavefront without tasks this round
       const int kk = k - head;
-      const int c = !active ? 0 : (kk < kFrontierCap ? frc[kk] : spill[k]);
+      int c;
+      if (fr_lds) {
+        c = active ? frc[kk] : 0;
+      } else {
+        c = !active ? 0 : (kk < kFrontierCap ? frc[kk] : spill[k]);
+        // no load of this path stays in flight: the common path's waits for the
+        // loads of earlier levels are then counted exactly
+        __builtin_amdgcn_s_waitcnt(0);
+      }
       // all NCH chunk loads are unconditional: lanes without a task, and chunks
       // past the row width, read a sentinel row of -1 instead (an address
       // select), so they are in flight together
@@ -395,10 +404,6 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
 #pragma unroll
       for (int q = 0; q < NCH; ++q) v[q] = (q < Wr4 ? row4 : sent4)[q];
       pf_acc ^= pf_val;  // the previous level's prefetch (older than the row loads)
-      if (active) {  // the level's cells in slot order form the schedule
-        sched[k] = c;
-        inv[c] = k;
-      }
       auto dec_global = [&](int nb) -> bool {
         const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -513,6 +518,12 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
             if (first < 0 && (wm & (1u << (4 * q + i)))) first = xs[i] & ~kBigFlag;
         }
         pf_val = first >= 0 ? a.dnw[(tb + first) * W] : a.dnw[a.dn_sentinel];
+      }
+      // the level's cells in slot order form the schedule (stored once the row
+      // loads are consumed, so that no wait for them includes these stores)
+      if (active) {
+        sched[k] = c;
+        inv[c] = k;
       }
       // ready cells: one wavefront prefix sum and one LDS atomic per wavefront
       const int n = __popc(wm);

@@ -21,7 +21,7 @@ namespace {
 
 constexpr int kCountBlock = 256;
 constexpr int kTileCells = 32;  // cells per tile of the cell-order kernels
-constexpr int kKahnBlock = 512;
+constexpr int kKahnBlock = 576;  // 8 worker wavefronts and one that stores the schedule
 
 __device__ __forceinline__ double orient(double ox, double oy, double oz, const double* n) {
   const double a = ox * n[0];
@@ -372,7 +372,12 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   }
   __syncthreads();
   const int4* sent4 = reinterpret_cast<const int4*>(a.dnw + a.dn_sentinel);
-  int pf_val = 0, pf_acc = 0;  // row prefetch (see below)
+  // The last wavefront makes every global store of the level loop (the
+  // schedule, its inverse and the level pointers) and never waits for a load;
+  // the other wavefronts process the frontier and only load, so their waits for
+  // row loads never include a store (the vector-memory counter is in order).
+  const int nwork = nthr - 64;
+  const bool writer = tid >= nwork;
   // Level l: the frontier is [head, tail); its pushes count in s_cnt[l % 3].
   // s_cnt[(l + 1) % 3] was last read right after the barrier that ended level
   // l - 2, so it can be cleared now for level l + 1; one barrier per level.
@@ -382,7 +387,22 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
     const int* frc = fr[l & 1];
     int* frn = fr[(l + 1) & 1];
     const bool fr_lds = tail - head <= kFrontierCap;  // the whole frontier is in LDS
-    for (int kb = head; kb < tail; kb += nthr) {
+    if (writer) {
+      // the level's cells in slot order form the schedule (entries past the LDS
+      // copy are in place already; each store is issued without waiting)
+      const int n = min(tail - head, kFrontierCap);
+      for (int i = lane; i < n; i += 64) {
+        const int c = frc[i];
+        sched[head + i] = c;
+        inv[c] = head + i;
+      }
+      for (int i = n + lane; i < tail - head; i += 64) {
+        const int k = head + i;
+        inv[spill[k]] = k;
+      }
+      if (lane == 0) lp[l + 1] = tail;
+    }
+    for (int kb = head; !writer && kb < tail; kb += nwork) {
       const int k = kb + tid;
       const bool active = k < tail;
       if (__ballot(active) == 0ull) continue;  // wavefront without tasks this round
@@ -403,7 +423,6 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       int4 v[NCH];
 #pragma unroll
       for (int q = 0; q < NCH; ++q) v[q] = (q < Wr4 ? row4 : sent4)[q];
-      pf_acc ^= pf_val;  // the previous level's prefetch (older than the row loads)
       auto dec_global = [&](int nb) -> bool {
         const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -506,25 +525,6 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           }
         }
       }
-      // the row of the lane's first ready cell is touched now, so that it sits in
-      // the L2 cache when some lane loads it in the next level
-      {
-        int first = -1;
-#pragma unroll
-        for (int q = 0; q < NCH; ++q) {
-          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (first < 0 && (wm & (1u << (4 * q + i)))) first = xs[i] & ~kBigFlag;
-        }
-        pf_val = first >= 0 ? a.dnw[(tb + first) * W] : a.dnw[a.dn_sentinel];
-      }
-      // the level's cells in slot order form the schedule (stored once the row
-      // loads are consumed, so that no wait for them includes these stores)
-      if (active) {
-        sched[k] = c;
-        inv[c] = k;
-      }
       // ready cells: one wavefront prefix sum and one LDS atomic per wavefront
       const int n = __popc(wm);
       const int incl = wave_inclusive_sum(n);
@@ -552,13 +552,11 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
     head = tail;
     tail += s_cnt[l % 3];
     ++l;
-    if (tid == 0) lp[l + 1] = tail;
   }
-  pf_acc ^= pf_val;
+  if (tid == 0) lp[l + 1] = tail;
   if (tid == 0) {
     a.depth[blockIdx.x] = l;
     if (tail != C) atomicOr(a.err, 1);
-    if (C < 0) a.err[1] = pf_acc;  // never true; keeps the prefetch loads alive
   }
 }
 

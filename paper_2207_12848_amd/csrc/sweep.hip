@@ -35,6 +35,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T* p, int64_t bytes
 __device__ __forceinline__ int2 ld_b64(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   return __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
 }
+__device__ __forceinline__ int4 ld_b128(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+}
 __device__ __forceinline__ int ld_b32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
 }
@@ -88,13 +91,15 @@ struct LevelInfo {
 };
 
 // Loads in flight for one step: the thread's share of the level's row block
-// (raw entries) and the record of the thread's first task of the level.  Lanes
-// past the level read past the buffers' ends (no memory traffic, value 0).
+// (raw entries, two per load) and the record of the thread's first task of the
+// level, with the step's level bounds.  Lanes past the level read past the
+// buffers' ends (no memory traffic, value 0).
 template <int GN, int CH>
 struct Pref {
-  int2 st[CH];
+  LevelInfo L;
+  int4 st[CH / 2];
   int c;
-  uint32_t rp0, rp1;  // low words of the row pointers (row offsets are taken mod 2^32)
+  int4 rp;  // row pointers of the task and the next one (low words: x and z)
   float den[GN];
   float src[GN];
 };
@@ -114,21 +119,22 @@ __device__ __forceinline__ void load_rec(const SweepArgs& a, const UnitBufs& B, 
 
 // Every thread issues the same loads at every step (fixed count, so the waits
 // for the loads in flight stay exact); the offsets of lanes past the level are
-// moved past the buffers' ends.
+// moved past the buffers' ends.  Entry pair i of thread t is entries
+// 2 (t + i nthr) and 2 (t + i nthr) + 1 of the level's block.
 template <int GN, int CH>
 __device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B, int tid, int nthr,
-                                           const LevelInfo& L, Pref<GN, CH>& P) {
+                                           Pref<GN, CH>& P) {
+  const LevelInfo& L = P.L;
   const uint32_t eoff = 8u * (uint32_t)(L.e0 - B.ue0);
 #pragma unroll
-  for (int i = 0; i < CH; ++i) {
-    const int idx = tid + i * nthr;
-    P.st[i] = ld_b64(B.ent, idx < L.nst ? 8u * (uint32_t)idx : kOob, eoff);
+  for (int i = 0; i < CH / 2; ++i) {
+    const int idx = 2 * (tid + i * nthr);
+    P.st[i] = ld_b128(B.ent, idx < L.nst ? 8u * (uint32_t)idx : kOob, eoff);
   }
   const bool act = L.k0 + tid < L.k1;
   const uint32_t k0 = (uint32_t)L.k0;
   P.c = ld_b32(B.sched, act ? 4u * (uint32_t)tid : kOob, 4u * k0);
-  P.rp0 = (uint32_t)ld_b32(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
-  P.rp1 = (uint32_t)ld_b32(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * (k0 + 1u));
+  P.rp = ld_b128(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
   const uint32_t vo = act ? 4u * (uint32_t)(tid * a.G) : kOob, so = 4u * k0 * (uint32_t)a.G;
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
@@ -167,7 +173,7 @@ __device__ __forceinline__ Window window(int k0, int k1, int R) {
   return w;
 }
 
-template <int GN, bool REVERSE>
+template <int GN, bool PIN>
 __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& B,
                                             const TaskRec<GN>& t, int k, const Inflow<GN>& in,
                                             float* ring) {
@@ -180,7 +186,7 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& 
     st_f32(v, B.out, oc + 4u * g);
     st_f32(v, B.outs, ok + 4u * g);
   }
-  if (!REVERSE && a.pin != nullptr) {
+  if (PIN) {
 #pragma unroll
     for (int g = 0; g < GN; ++g) st_f32(in.pin[g], B.pin, oc + 4u * g);
   }
@@ -190,7 +196,7 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& 
 // memory operation is issued unconditionally (a thread without a task writes
 // the sink slot and stores past the buffers' ends, which are dropped), so each
 // step issues a fixed number of vector-memory operations.
-template <int GN, bool REVERSE>
+template <int GN, bool PIN>
 __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& B,
                                             const TaskRec<GN>& t, int k, const Inflow<GN>& in,
                                             float* ring, float* sink) {
@@ -204,16 +210,17 @@ __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& 
     rr[g] = v;
     st_f32(v, B.out, oc + 4u * g);
     st_f32(v, B.outs, ok + 4u * g);
-    if (!REVERSE) st_f32(in.pin[g], B.pin, oc + 4u * g);  // no pin buffer: size 0, dropped
+    if (PIN) st_f32(in.pin[g], B.pin, oc + 4u * g);
   }
 }
 
 // Inflow of one task from its staged row (raw entries in LDS), in batches of 8:
 // one LDS read per entry and one of the ring slot it names, then a multiply and
 // an add per entry in row order (explicit rounding, no contraction).  `far`
-// collects the largest offset of an entry from the window's start: the result
-// holds only when every entry is inside the window (far < w.n); otherwise the
-// task is recomputed by gather_mixed.
+// collects the largest offset from the window's start of the batch entries
+// read (the row's and up to 7 after it, which are entries of the same level or
+// the padding that follows the level's block, inside the window): the result
+// holds when far < w.n; otherwise the task is recomputed by gather_mixed.
 template <int GN>
 __device__ __forceinline__ Inflow<GN> gather_staged(const SweepArgs& a, const TaskRec<GN>& t,
                                                     const int2* stg, const float* ring, Window w,
@@ -235,7 +242,7 @@ __device__ __forceinline__ Inflow<GN> gather_staged(const SweepArgs& a, const Ta
     const int nr = t.r1 - rb;  // entries of the row in this batch
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      if (q < nr) far = max(far, (uint32_t)(en[q].x - w.lo));
+      far = max(far, (uint32_t)(en[q].x - w.lo));
       const float y = q < nr ? __int_as_float(en[q].y) : 0.0f;
 #pragma unroll
       for (int g = 0; g < GN; ++g) in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(y, rv[q][g]));
@@ -321,7 +328,7 @@ __device__ __forceinline__ Inflow<GN> gather_global(const SweepArgs& a, const Un
 // critical path of a common step.
 // LVL_LDS = false (graphs deeper than the LDS level tables hold): the level
 // pointers and first entries are read from global memory at every step.
-template <int GN, bool REVERSE, int CH, bool LVL_LDS>
+template <int GN, bool REVERSE, bool PIN, int CH, bool LVL_LDS>
 __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
   constexpr int NS = 3;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -333,7 +340,8 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int SE = CH * nthr;
-  const int SP = SE + 8;  // staging buffer stride (8 entries of padding for the batches)
+  const int SP = SE + 8;  // staging buffer stride
+  const int SMAX = SE - 8;  // entries staged per level; 8 padding entries follow them
   const int R = a.ring_mask + 1;
   float* sink = ring + (R + kSlotSink) * GN;
   // the batches of 8 read up to 7 entries past a row (stale entries of earlier
@@ -393,28 +401,43 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
       L.k1 = __builtin_amdgcn_readfirstlane(LP(L.l + 1));
       L.e0 = uniform64(LEV(L.l));
       L.ne = (int)(uniform64(LEV(L.l + 1)) - L.e0);
-      L.nst = L.ne < SE ? L.ne : SE;
+      L.nst = L.ne < SMAX ? L.ne : SMAX;
       return L;
     };
     Pref<GN, CH> P[NS];
     TaskRec<GN> cur;
     LevelInfo curL;
-    auto issue = [&](int s, Pref<GN, CH>& Q) { issue_pref<GN, CH>(a, B, tid, nthr, info(s), Q); };
-    // raw entries into the staging buffer of step s, the thread's record into `cur`
+    auto issue = [&](int s, Pref<GN, CH>& Q) {
+      Q.L = info(s);
+      issue_pref<GN, CH>(a, B, tid, nthr, Q);
+    };
+    // raw entries into the staging buffer of step s, followed by 8 padding
+    // entries (a task of the level inside the window, factor 0); the thread's
+    // record into `cur`
     auto publish = [&](int s, const Pref<GN, CH>& Q) {
-      const LevelInfo L = info(s);
+      const LevelInfo& L = Q.L;
       int2* dst = stage + (s & 1) * SP;
+      const int pad = REVERSE ? L.k0 : L.k1 - 1;
 #pragma unroll
-      for (int i = 0; i < CH; ++i) {
-        if (i * nthr >= L.nst) break;
-        const int idx = tid + i * nthr;
-        dst[idx < L.nst ? idx : SE] = idx < L.nst ? Q.st[i] : make_int2(-1, 0);
+      for (int i = 0; i < CH / 2; ++i) {
+        if (2 * i * nthr >= L.nst + 8) break;
+        const int idx = 2 * (tid + i * nthr);
+        int4 v = Q.st[i];
+        if (idx >= L.nst) {
+          v.x = pad;
+          v.y = 0;
+        }
+        if (idx + 1 >= L.nst) {
+          v.z = pad;
+          v.w = 0;
+        }
+        if (idx < L.nst + 8) *reinterpret_cast<int4*>(dst + idx) = v;
       }
       curL = L;
       const bool act = L.k0 + tid < L.k1;
       cur.c = act ? Q.c : -1;
-      cur.r0 = act ? (int)(Q.rp0 - (uint32_t)L.e0) : 0;
-      cur.r1 = act ? (int)(Q.rp1 - (uint32_t)L.e0) : 0;
+      cur.r0 = act ? (int)((uint32_t)Q.rp.x - (uint32_t)L.e0) : 0;
+      cur.r1 = act ? (int)((uint32_t)Q.rp.z - (uint32_t)L.e0) : 0;
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
         cur.den[g] = Q.den[g];
@@ -431,7 +454,7 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
         uint32_t far = 0;
         Inflow<GN> in = gather_staged<GN>(a, cur, stg, ring, w, far);
         if (far >= w.n) in = gather_mixed<GN>(a, B, cur, stg, w, ring);
-        finish_fast<GN, REVERSE>(a, B, cur, k0 + tid, in, ring, sink);
+        finish_fast<GN, PIN>(a, B, cur, k0 + tid, in, ring, sink);
         return;
       }
       for (int k = k0 + tid; k < k1; k += nthr) {
@@ -445,7 +468,7 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
         } else {
           in = gather_global<GN>(a, B, t, e0, w, ring);
         }
-        finish_task<GN, REVERSE>(a, B, t, k, in, ring);
+        finish_task<GN, PIN>(a, B, t, k, in, ring);
       }
       // the uncommon steps leave no memory operation of theirs in flight, so the
       // waits of the common steps are counted exactly
@@ -471,23 +494,31 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
   }
 }
 
-template <int GN, bool REVERSE>
-hipError_t launch_sweep_g(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
+template <int GN, bool REVERSE, bool PIN>
+hipError_t launch_sweep_p(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
   // kStageEntries entries staged per level whatever the block size; level
   // tables outside LDS (lp_cap == 0) only with 512 threads
   if (a.lp_cap == 0) {
     if (block != 512) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sweep<GN, REVERSE, 8, false>), dim3(grid), dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 8, false>), dim3(grid), dim3(block), lds, s, a);
     return hipGetLastError();
   }
   switch (kStageEntries / block) {
-    case 4: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 4, true>), dim3(grid), dim3(block), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 8, true>), dim3(grid), dim3(block), lds, s, a); break;
-    case 16: hipLaunchKernelGGL((k_sweep<GN, REVERSE, 16, true>), dim3(grid), dim3(block), lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 4, true>), dim3(grid), dim3(block), lds, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 8, true>), dim3(grid), dim3(block), lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 16, true>), dim3(grid), dim3(block), lds, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// The forward sweep stores the periodic inflow per task only when asked to.
+template <int GN, bool REVERSE>
+hipError_t launch_sweep_g(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
+                          hipStream_t s) {
+  if (!REVERSE && a.pin != nullptr) return launch_sweep_p<GN, false, true>(a, grid, block, lds, s);
+  return launch_sweep_p<GN, REVERSE, false>(a, grid, block, lds, s);
 }
 
 template <bool REVERSE>
@@ -738,12 +769,12 @@ hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int GN, bool REVERSE>
+template <int GN, bool REVERSE, bool PIN>
 hipError_t set_lds_g(int32_t bytes) {
-  const void* fns[] = {(const void*)k_sweep<GN, REVERSE, 4, true>,
-                       (const void*)k_sweep<GN, REVERSE, 8, true>,
-                       (const void*)k_sweep<GN, REVERSE, 16, true>,
-                       (const void*)k_sweep<GN, REVERSE, 8, false>};
+  const void* fns[] = {(const void*)k_sweep<GN, REVERSE, PIN, 4, true>,
+                       (const void*)k_sweep<GN, REVERSE, PIN, 8, true>,
+                       (const void*)k_sweep<GN, REVERSE, PIN, 16, true>,
+                       (const void*)k_sweep<GN, REVERSE, PIN, 8, false>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
@@ -751,16 +782,20 @@ hipError_t set_lds_g(int32_t bytes) {
   return hipSuccess;
 }
 
+template <int GN>
+hipError_t set_lds_gn(int32_t bytes) {
+  hipError_t e;
+  if ((e = set_lds_g<GN, false, false>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds_g<GN, false, true>(bytes)) != hipSuccess) return e;
+  return set_lds_g<GN, true, false>(bytes);
+}
+
 hipError_t set_sweep_lds_limit(int32_t bytes) {
   hipError_t e;
-  if ((e = set_lds_g<1, false>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<2, false>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<3, false>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<4, false>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<1, true>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<2, true>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<3, true>(bytes)) != hipSuccess) return e;
-  return set_lds_g<4, true>(bytes);
+  if ((e = set_lds_gn<1>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds_gn<2>(bytes)) != hipSuccess) return e;
+  if ((e = set_lds_gn<3>(bytes)) != hipSuccess) return e;
+  return set_lds_gn<4>(bytes);
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, int32_t n_blocks, hipStream_t s) {

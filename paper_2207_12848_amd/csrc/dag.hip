@@ -44,6 +44,17 @@ __device__ __forceinline__ float face_w32(float ox, float oy, float oz, float ax
 }
 
 // Unit of block b (units own consecutive block ranges).
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2
+// cache: this renumbering gives each XCD one contiguous range of the grid, so
+// the workgroups an XCD runs together belong to few units and share those
+// units' arrays in its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int per = nb / kXcd, rem = nb % kXcd;
+  const int x = b % kXcd;
+  return x * per + min(x, rem) + b / kXcd;
+}
+
 __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_units, int b) {
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -562,9 +573,10 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
 
 // Row lengths of every task at its schedule slot (the input of the row-pointer scan).
 __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
-  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int u = unit_of_block(a.blk_base, a.n_units, blk);
   const Unit U = a.units[u];
-  const int k = (blockIdx.x - a.blk_base[u]) * kCountBlock + threadIdx.x;
+  const int k = (blk - a.blk_base[u]) * kCountBlock + threadIdx.x;
   if (k >= U.n_cells) return;
   const int64_t t = U.task_base + k;
   // slots past the scheduled tasks (a cyclic graph, reported after the build) get no row
@@ -600,7 +612,8 @@ __global__ void k_face_records(MeshDev M, int4* frec) {
 constexpr int kFillBlock = 256;
 
 __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
-  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int u = unit_of_block(a.blk_base, a.n_units, blk);
   const Unit U = a.units[u];
   const MeshDev M = a.meshes[U.mesh];
   const int64_t tb = U.task_base;
@@ -610,7 +623,7 @@ __global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
   const int li = lane & 15;
   const int g = lane >> 4;
   const int32_t* inv = a.inv + tb;
-  const int kw = (blockIdx.x - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
+  const int kw = (blk - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
   if (kw >= U.n_cells) return;
   // lane L: the task of slot kw + L (slots past the scheduled tasks of a cyclic
   // graph, reported after the build, get no row)

@@ -250,8 +250,8 @@ struct sweep_dag_s {
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
-  Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, cden,
-      csrc, out_s;
+  Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, cds,
+      out_s;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
   struct GraphEntry {
     std::vector<uint64_t> key;
@@ -411,8 +411,7 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
                         const float* gsrc, const float* jsum_prev, float albedo, hipStream_t s) {
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cden.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->csrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
   sweep::PrepArgs q{};
   q.units = d->units_d.as<Unit>();
   q.n_units = (int32_t)d->units.size();
@@ -429,8 +428,7 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.G = G;
   q.tden = d->tden.as<float>();
   q.tsrc = d->tsrc.as<float>();
-  q.cden = d->cden.as<float>();
-  q.csrc = d->csrc.as<float>();
+  q.cds = d->cds.as<float2>();
   ProfScope ps("prep", s);
   HIP_TRY(sweep::launch_prep(q, d->n_blocks, s));
   return SWEEP_OK;
@@ -1039,8 +1037,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   }
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cden.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->csrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   sweep::ReduceArgs r{};
   r.units = d->units_d.as<Unit>();
@@ -1100,7 +1097,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
                                pkey(totals), pkey(saved), (uint64_t)saved_bytes};
   opts_key(key, p);
   for (const Buf* b : {&d->phi_a, &d->phi_b, &d->pin, &d->pin_prev, &d->jsum_a, &d->jsum_b,
-                       &d->partial, &d->tden, &d->tsrc, &d->cden, &d->csrc, &d->out_s,
+                       &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
                        &d->mesh_blk_base})
     key.push_back(pkey(b->p));
   return run_graph(d, key, s, body);
@@ -1133,8 +1130,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cden.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->csrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   const float* phi_final = (const float*)saved;
   auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
@@ -1180,7 +1176,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                pkey(dL_dkappa), pkey(dL_demission)};
   opts_key(key, p);
   for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->tden, &d->tsrc,
-                       &d->cden, &d->csrc, &d->out_s})
+                       &d->cds, &d->out_s})
     key.push_back(pkey(b->p));
   return run_graph(d, key, s, body);
 }
@@ -1200,8 +1196,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   HIP_TRY(d->phi_a.alloc(4 * DCG));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cden.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->csrc.alloc(4 * (size_t)d->T * G));
+  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   ST_TRY(run_prep(d, G, kappa, emission, nullptr, nullptr, p.albedo, s));
   hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -124,8 +124,7 @@ struct PrepArgs {
   float albedo;
   float inv_D;
   int32_t G;
-  float* cden;             // [T][G] cell order (scratch)
-  float* csrc;             // [T][G] cell order (scratch)
+  float2* cds;             // [T][G] cell order (scratch): (denominator, source)
   float* tden;             // [T][G] schedule order
   float* tsrc;             // [T][G] schedule order
 };

@@ -534,7 +534,7 @@ hipError_t launch_sweep_t(const SweepArgs& a, int32_t gn, int32_t grid, int32_t 
 }
 
 // Per-task denominators Aperp + kappa V and sources, first in cell order within
-// each unit (every access coalesced).
+// each unit (every access coalesced), as (denominator, source) pairs.
 __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_units, int b) {
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -556,7 +556,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   for (int g = 0; g < a.G; ++g) {
     const int64_t cg = ci * a.G + g;
     const double kap = (double)a.kappa[cg];
-    a.cden[t * a.G + g] = (float)(ap + kap * V);
     double s;
     if (a.emission != nullptr) {
       s = (double)a.emission[cg];
@@ -565,7 +564,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     } else {
       s = (double)a.gsrc[cg];
     }
-    a.csrc[t * a.G + g] = (float)s;
+    a.cds[t * a.G + g] = make_float2((float)(ap + kap * V), (float)s);
   }
 }
 
@@ -579,8 +578,9 @@ __global__ __launch_bounds__(256) void k_prep_order(PrepArgs a) {
   const int64_t t = U.task_base + k;
   const int64_t tc = U.task_base + a.sched[t];
   for (int g = 0; g < a.G; ++g) {
-    a.tden[t * a.G + g] = a.cden[tc * a.G + g];
-    a.tsrc[t * a.G + g] = a.csrc[tc * a.G + g];
+    const float2 v = a.cds[tc * a.G + g];  // one gathered access per task and group
+    a.tden[t * a.G + g] = v.x;
+    a.tsrc[t * a.G + g] = v.y;
   }
 }
 

@@ -372,8 +372,13 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
       }
     }
     __syncthreads();
-    const int32_t* lpg = a.lp + U.lp_base;
-    const int64_t* levg = a.lev + U.lp_base;
+    // level tables outside LDS are read through the scalar cache (constant
+    // address space: the sweep never writes them), so reading them never waits
+    // for the vector loads in flight
+    using cint = const __attribute__((address_space(4))) int32_t;
+    using clong = const __attribute__((address_space(4))) int64_t;
+    cint* lpg = (cint*)(a.lp + U.lp_base);
+    clong* levg = (clong*)(a.lev + U.lp_base);
     auto LP = [&](int l) -> int { return LVL_LDS ? lps[l] : lpg[l]; };
     auto LEV = [&](int l) -> int64_t { return LVL_LDS ? levs[l] : levg[l]; };
     const int64_t obase = ((int64_t)U.dir * a.C_total + U.cell_off) * a.G + a.g0;

@@ -676,18 +676,24 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   constexpr int kRowNarrow = 16;
   constexpr int kRowCap = 32;
   int64_t ovf_cap = 2;
-  std::vector<int64_t> fp;
+  {
+    // face statistics on the device (one small copy back)
+    Buf fstat;
+    HIP_TRY(fstat.alloc(16));
+    HIP_TRY(hipMemsetAsync(fstat.p, 0, 16, s));
+    for (int m = 0; m < n_meshes; ++m)
+      HIP_TRY(sweep::launch_face_stats(meshes[m].face_ptr, meshes[m].n_cells, kRowCap, n_dirs,
+                                       fstat.as<unsigned long long>(), s));
+    unsigned long long fs[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(fs, fstat.p, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    max_faces = std::max<int>(max_faces, (int)fs[0]);
+    ovf_cap += (int64_t)fs[1];
+  }
   for (int m = 0; m < n_meshes; ++m) {
     for (int32_t c = 0; c < D->mesh_cells[m]; c += sweep::kTileCellsHost) {
       cbm.push_back(m);
       cbc.push_back(c);
-    }
-    fp.resize(meshes[m].n_cells + 1);
-    HIP_TRY(hipMemcpy(fp.data(), meshes[m].face_ptr, 8 * fp.size(), hipMemcpyDeviceToHost));
-    for (int32_t c = 0; c < meshes[m].n_cells; ++c) {
-      const int nf = (int)(fp[c + 1] - fp[c]);
-      max_faces = std::max(max_faces, nf);
-      if (nf > kRowCap) ovf_cap += (int64_t)(nf + 2) * n_dirs;
     }
     max_cells = std::max(max_cells, meshes[m].n_cells);
   }

@@ -586,6 +586,28 @@ __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
   a.len_dn[t] = c >= 0 ? a.rowlen_dn[U.task_base + c] : 0;
 }
 
+// Per mesh: the largest face count of a cell, and the overflow room the wide
+// rows need ((faces + 2) ints per direction for every cell with more than
+// row_cap faces), accumulated into out[0] (max) and out[1] (sum).
+__global__ void k_face_stats(const int64_t* face_ptr, int n_cells, int row_cap, int n_dirs,
+                             unsigned long long* out) {
+  unsigned long long mx = 0, sum = 0;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += gridDim.x * blockDim.x) {
+    const unsigned long long nf = (unsigned long long)(face_ptr[c + 1] - face_ptr[c]);
+    mx = nf > mx ? nf : mx;
+    if (nf > (unsigned long long)row_cap) sum += (nf + 2) * (unsigned long long)n_dirs;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long m2 = __shfl_xor(mx, o);
+    mx = m2 > mx ? m2 : mx;
+    sum += __shfl_xor(sum, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, mx);
+    atomicAdd(out + 1, sum);
+  }
+}
+
 // Per face: the neighbour code (>= 0: interior neighbour, -1: vacuum wall,
 // -(nb + 2): periodic image of cell nb) and A n rounded to FP32, 16 bytes that
 // the row fill reads instead of the FP64 geometry.
@@ -806,6 +828,14 @@ hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_stats(const int64_t* face_ptr, int32_t n_cells, int32_t row_cap, int32_t n_dirs,
+                             unsigned long long* out, hipStream_t s) {
+  if (n_cells <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, grid1d(n_cells, 256));
+  hipLaunchKernelGGL(k_face_stats, dim3(grid), dim3(256), 0, s, face_ptr, n_cells, row_cap, n_dirs, out);
   return hipGetLastError();
 }
 

@@ -176,6 +176,9 @@ constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build ke
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s);
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
+// out[0] = max faces of a cell, out[1] += overflow ints for rows of row_cap entries
+hipError_t launch_face_stats(const int64_t* face_ptr, int32_t n_cells, int32_t row_cap, int32_t n_dirs,
+                             unsigned long long* out, hipStream_t s);
 hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s);
 hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s);

@@ -7,7 +7,8 @@ of ``synth``.
 
 What is computed is documented in ``sweep_oracle.c`` (orientation of appendix A
 and sec. 2.5, algorithm 2's FIFO schedule, transport scheme (a) of sec. 2.6
-with a first-order upwind cell balance, periodic passes of sec. 2.7, source
+with a first-order upwind cell balance or an exponential (e^{-tau}) cell law,
+periodic passes of sec. 2.7, source
 iteration of algorithm 1, and the adjoint).  This module only marshals numpy
 arrays; every function loops over the independent meshes of a workload.
 """
@@ -62,10 +63,11 @@ def _load():
         lib.orc_forward.restype = ctypes.c_int
         lib.orc_forward.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
-                                    P, P, P, P, P, P]
+                                    ctypes.c_int32, P, P, P, P, P, P]
         lib.orc_adjoint.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
-                                    ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, P, P, P]
+                                    ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                    P, P, P, P]
         _lib = lib
     return _lib
 
@@ -97,6 +99,16 @@ def _check(st, what):
         raise OracleError("%s: %s (%d)" % (what, names.get(st, "error"), st))
 
 
+LAWS = {"upwind": 0, "exp": 1}
+
+
+def _law(w):
+    law = w.get("law", "upwind")
+    if law not in LAWS:
+        raise OracleError("unknown cell law %r" % (law,))
+    return LAWS[law]
+
+
 def _offsets(meshes):
     off = [0]
     for m in meshes:
@@ -123,9 +135,10 @@ def build_dag(mesh: dict, dirs: np.ndarray, eps: float = EPS_TIE):
 
 
 def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: float = EPS_TIE):
-    """Sweep workload `w` (see synth.workloads).  Returns dict with
-    J [C,G], absorbed [C,G], totals [n_meshes,G,8] and, on request, phi (list of [D,C,G]
-    per mesh), jsum_ckpt (list of [n_scat,C,G]) and the FIFO order (list of [D,C])."""
+    """Sweep workload `w` (see synth.workloads; w["law"] is "upwind" (default) or "exp").
+    Returns dict with J [C,G], absorbed [C,G], totals [n_meshes,G,8] and, on request, phi
+    (list of [D,C,G] per mesh: the exit flux density), jsum_ckpt (list of [n_scat,C,G]) and
+    the FIFO order (list of [D,C])."""
     lib = _load()
     dirs = _c(w["dirs"], np.float64)
     D, G = len(dirs), int(w["G"])
@@ -134,6 +147,7 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
     off = _offsets(w["meshes"])
     periodic = w.get("boundary", "vacuum") == "periodic"
     n_pbc, albedo, n_scat = int(w.get("n_pbc", 1)), float(w.get("albedo", 0.0)), int(w.get("n_scat", 1))
+    law = _law(w)
     J = np.zeros((off[-1], G))
     Ab = np.zeros((off[-1], G))
     totals = np.zeros((len(w["meshes"]), G, N_TOTALS))
@@ -151,7 +165,8 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
         ck = np.zeros((n_scat, C, G)) if want_phi else None
         qo = np.zeros((D, C), np.int32) if want_order else None
         _check(lib.orc_forward(ctypes.byref(s), D, _p(dirs), eps, G, _p(k), _p(e), int(periodic),
-                               n_pbc, albedo, n_scat, _p(j), _p(a), _p(t), _p(phi), _p(ck), _p(qo)),
+                               n_pbc, albedo, n_scat, law, _p(j), _p(a), _p(t), _p(phi), _p(ck),
+                               _p(qo)),
                "forward")
         J[sl], Ab[sl], totals[mi] = j, a, t
         phis.append(phi)
@@ -178,6 +193,7 @@ def adjoint(w: dict, gJ: np.ndarray, gA: np.ndarray, eps: float = EPS_TIE):
     off = _offsets(w["meshes"])
     periodic = w.get("boundary", "vacuum") == "periodic"
     albedo, n_scat = float(w.get("albedo", 0.0)), int(w.get("n_scat", 1))
+    law = _law(w)
     dk = np.zeros((off[-1], G))
     de = np.zeros((off[-1], G))
     for mi, mesh in enumerate(w["meshes"]):
@@ -187,7 +203,7 @@ def adjoint(w: dict, gJ: np.ndarray, gA: np.ndarray, eps: float = EPS_TIE):
         a = np.zeros((C, G))
         b = np.zeros((C, G))
         _check(lib.orc_adjoint(ctypes.byref(s), D, _p(dirs), eps, G, _p(_c(kap[sl], np.float64)),
-                               _p(_c(em[sl], np.float64)), int(periodic), albedo, n_scat,
+                               _p(_c(em[sl], np.float64)), int(periodic), albedo, n_scat, law,
                                _p(_c(gJ[sl], np.float64)), _p(_c(gA[sl], np.float64)), _p(a), _p(b)),
                "adjoint")
         dk[sl], de[sl] = a, b

@@ -30,6 +30,22 @@
  *  threads; results do not depend on it).  A task's level is 0 without
  *  upwind tasks, else 1 + max level of its upwind tasks.
  *
+ *  Exponential cell law (the attenuation form 1 - e^{-dn sigma} of the
+ *  scattering test, sec. 3.3,
+ *  with the mean distance travelled in the cell read as the mean chord
+ *  V / Aperp of a parallel beam, so the optical depth is tau = kappa V / Aperp):
+ *  the total power entering the task, T = inflow + S, leaves it attenuated by
+ *  e^{-tau}, split over the outflow faces in proportion to w, and the rest,
+ *  T (1 - e^{-tau}), is absorbed.  The exit flux density (what the downwind
+ *  cells and the walls see, per unit w) is T e^{-tau} / Aperp and the cell
+ *  average, absorbed / (kappa V), is T (1 - e^{-tau}) / (kappa V) (T / Aperp for
+ *  kappa = 0).  tau is capped at TAU_CAP = 40 for the transmission: a thicker
+ *  cell passes on e^{-40} = 4.2e-18 of its power, which keeps the exit flux
+ *  density of single precision implementations in the normal range; the cap
+ *  changes no result by more than that fraction of T and conservation stays
+ *  exact.  J and absorbed use the cell average; escape and periodic outflow
+ *  use the exit flux density.  Under the first-order upwind law both are phi.
+ *
  *  Periodic boundaries (sec. 2.7): faces with a non-zero image shift are cut
  *  from the dependency graph; radiation leaving through them enters the
  *  partner cell in the next pass (pass 0 starts from zero inflow).
@@ -37,9 +53,10 @@
  *  Source iteration (sec. 2.3, algorithm 1) with isotropic scattering
  *  (eq. radiativeTransfer): kappa is the extinction, kappa_s = a kappa,
  *  kappa_a = (1-a) kappa; iteration i uses the source
- *  S = L/D + kappa_s V sum_d' phi^{i-1}_{d'} / D, phi^{-1} = 0.
+ *  S = L/D + kappa_s V sum_d' avg^{i-1}_{d'} / D, avg^{-1} = 0.
  *
- *  Outputs: J = (1/4pi) sum_d phi, absorbed = kappa_a V sum_d phi; totals per
+ *  Outputs: J = (1/4pi) sum_d avg, absorbed = kappa_a V sum_d avg (avg: the
+ *  cell average, phi itself under the upwind law); totals per
  *  group: [emitted, absorbed, escaped, periodic inflow, periodic outflow,
  *  net scattering source, max E, L1 E] where E is the relative change of the
  *  periodic inflow per cell between the last two passes (eq. relativeErrorPbc).
@@ -79,6 +96,19 @@ static double orient(const double* om, const double* n) {
 }
 
 /* face classes */
+#define LAW_UPWIND 0
+#define LAW_EXP 1
+#define TAU_CAP 40.0
+
+/* Exponential law of one task: exit flux density and cell average of the
+ * total entering power T (see the header). */
+static void exp_law(double T, double aperp, double kV, double* out, double* avg) {
+  const double tau = kV / aperp;
+  const double tc = tau < TAU_CAP ? tau : TAU_CAP;
+  *out = T * exp(-tc) / aperp;
+  *avg = kV > 0.0 ? T * (-expm1(-tc)) / kV : T / aperp;
+}
+
 #define F_NONE 0
 #define F_OUT 1
 #define F_IN 2
@@ -168,14 +198,16 @@ int orc_build_dag(const orc_mesh* m, int32_t D, const double* dirs, double eps, 
 /* One sweep of one direction over all groups.
  *   src:  [C][G] source per task of this direction (already divided by D)
  *   prev: [C][G] phi of this direction in the previous periodic pass (NULL: zero)
- *   phi:  [C][G] output
+ *   phi:  [C][G] output: exit flux density (what downwind cells and walls see)
+ *   avg:  [C][G] output: cell average (equal to phi under the upwind law)
  *   acc:  [G][4] += escaped, periodic inflow, periodic outflow (FP64)
  *   jin:  [C][G] += periodic inflow into each cell (may be NULL)
  *   qorder: [C] processing order (output, may be NULL) */
 static int sweep_direction(const orc_mesh* m, const double* om, double eps, int32_t G,
-                           const double* kappa, const double* src, const double* prev,
-                           double* phi, double* acc, double* jin, int32_t* cnt, int32_t* queue,
-                           int32_t* lvl, int32_t* qorder) {
+                           int32_t law, const double* kappa, const double* src,
+                           const double* prev, double* phi, double* avg, double* acc,
+                           double* jin, int32_t* cnt, int32_t* queue, int32_t* lvl,
+                           int32_t* qorder) {
   const int32_t C = m->n_cells;
   double* nin = (double*)malloc(sizeof(double) * (size_t)G);
   int32_t head = 0, tail = 0;
@@ -212,12 +244,23 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
       }
     }
     for (int32_t g = 0; g < G; ++g) {
-      const double den = aperp + kappa[(int64_t)c * G + g] * m->cell_volume[c];
+      const int64_t i = (int64_t)c * G + g;
+      const double kV = kappa[i] * m->cell_volume[c];
+      if (law == LAW_EXP) {
+        if (!(aperp > 0.0)) {
+          free(nin);
+          return ORC_ERR_ARG;
+        }
+        exp_law(nin[g] + src[i], aperp, kV, &phi[i], &avg[i]);
+        continue;
+      }
+      const double den = aperp + kV;
       if (!(den > 0.0)) {
         free(nin);
         return ORC_ERR_ARG;
       }
-      phi[(int64_t)c * G + g] = (nin[g] + src[(int64_t)c * G + g]) / den;
+      phi[i] = (nin[g] + src[i]) / den;
+      avg[i] = phi[i];
     }
     /* outflow: boundaries and downwind neighbours */
     for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
@@ -241,18 +284,22 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
 /* Forward sweep with periodic passes and source iteration.
  *   kappa, emission, J, absorbed: [C][G]
  *   totals: [G][8]
- *   phi_out: [D][C][G] phi of the final pass (may be NULL)
- *   jsum_ckpt: [n_scat][C][G] sum_d phi of every iteration's final pass (may be NULL)
+ *   law: LAW_UPWIND or LAW_EXP
+ *   phi_out: [D][C][G] exit flux density of the final pass (may be NULL)
+ *   jsum_ckpt: [n_scat][C][G] sum_d of the cell averages of every iteration's
+ *              final pass (may be NULL)
  *   qorder: [D][C] FIFO processing order of every direction (may be NULL) */
 int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
-                double albedo, int32_t n_scat, double* J, double* absorbed, double* totals,
-                double* phi_out, double* jsum_ckpt, int32_t* qorder) {
+                double albedo, int32_t n_scat, int32_t law, double* J, double* absorbed,
+                double* totals, double* phi_out, double* jsum_ckpt, int32_t* qorder) {
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
   if (D < 1 || G < 1 || n_pbc < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
+  if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
   if (!periodic) n_pbc = 1;
   double* phi = (double*)calloc((size_t)(D * CG), sizeof(double));
+  double* avg = (double*)calloc((size_t)(D * CG), sizeof(double));
   double* phiprev = (double*)calloc((size_t)(D * CG), sizeof(double));
   double* jsum = (double*)calloc((size_t)CG, sizeof(double));     /* sum_d phi, current */
   double* jsum_old = (double*)calloc((size_t)CG, sizeof(double)); /* previous iteration */
@@ -260,7 +307,8 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   double* jin = (double*)calloc((size_t)(D * CG), sizeof(double));
   double* jin_old = (double*)calloc((size_t)CG, sizeof(double));
   double* accd = (double*)calloc((size_t)D * 4 * G, sizeof(double));
-  if (!phi || !phiprev || !jsum || !jsum_old || !src || !jin || !jin_old || !accd) return ORC_ERR_OOM;
+  if (!phi || !avg || !phiprev || !jsum || !jsum_old || !src || !jin || !jin_old || !accd)
+    return ORC_ERR_OOM;
   int status = ORC_OK;
   for (int32_t it = 0; it < n_scat && status == ORC_OK; ++it) {
     /* source of this iteration */
@@ -286,9 +334,10 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
       for (int32_t d = 0; d < D; ++d) {
         int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
         int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
-        int st = sweep_direction(m, dirs + 3 * d, eps, G, kappa, src,
+        int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src,
                                  (periodic && p > 0) ? phiprev + (int64_t)d * CG : NULL,
-                                 phi + (int64_t)d * CG, accd + (int64_t)d * 4 * G,
+                                 phi + (int64_t)d * CG, avg + (int64_t)d * CG,
+                                 accd + (int64_t)d * 4 * G,
                                  jin + (int64_t)d * CG, cnt, q, NULL,
                                  qorder ? qorder + (int64_t)d * C : NULL);
         if (st != ORC_OK) {
@@ -302,10 +351,10 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
       if (p + 1 < n_pbc) memcpy(phiprev, phi, sizeof(double) * (size_t)(D * CG));
     }
     if (status != ORC_OK) break;
-    /* direction sum in ascending d */
+    /* direction sum of the cell averages in ascending d */
     for (int64_t i = 0; i < CG; ++i) {
       double s = 0.0;
-      for (int32_t d = 0; d < D; ++d) s += phi[(int64_t)d * CG + i];
+      for (int32_t d = 0; d < D; ++d) s += avg[(int64_t)d * CG + i];
       jsum[i] = s;
     }
     if (jsum_ckpt) memcpy(jsum_ckpt + (int64_t)it * CG, jsum, sizeof(double) * (size_t)CG);
@@ -350,6 +399,7 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
     if (phi_out) memcpy(phi_out, phi, sizeof(double) * (size_t)(D * CG));
   }
   free(phi);
+  free(avg);
   free(phiprev);
   free(jsum);
   free(jsum_old);
@@ -361,55 +411,99 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
 }
 
 /* ------------------------------------------------------------------ adjoint */
-/* Reverse sweep of one direction: solves M^T lambda = g with
- * M = diag(Aperp + kappa V) - W (W[c][u] = w of the inflow face of c from u):
- *   lambda_c = (g_c + sum_{outflow faces to interior e} w lambda_e) / (Aperp_c + kappa_c V_c),
+/* Derivative of h(tau) = (e^tau - 1) / tau: a Taylor series below 1e-2
+ * (truncation below 1.3e-13 relative), the closed form above. */
+static double dh_dtau(double tau) {
+  if (tau < 1e-2) return 0.5 + tau * (1.0 / 3.0 + tau * (1.0 / 8.0 + tau * (1.0 / 30.0 + tau / 144.0)));
+  return ((tau - 1.0) * exp(tau) + 1.0) / (tau * tau);
+}
+
+/* Reverse sweep of one direction.  Written with x the stored per-task value
+ * (phi under the upwind law, the exit flux density under the exponential law),
+ * the forward sweep solves M x = S with M = diag(den) - W (W[c][u] = w of the
+ * inflow face of c from u):
+ *   upwind:      den = Aperp + kappa V, and the cell average is x;
+ *   exponential: den = Aperp e^{tau_c} (T = den x), and the cell average is
+ *                r x with r = Aperp (e^{tau_c} - 1) / (kappa V) (1 at kappa = 0),
+ *                tau_c = min(tau, TAU_CAP).
+ * For g = dL/d(cell average), dL/dx = r g, so lambda = M^{-T} (r g):
+ *   lambda_c = (r_c g_c + sum_{outflow faces to interior e} w lambda_e) / den_c,
  * visiting the cells in the reverse of the forward queue order, so every
- * downwind lambda is final before it is read. */
+ * downwind lambda is final before it is read.  It also writes, per task,
+ *   dk_c = -lambda_c x_c d(den_c)/dkappa_c + g_c x_c dr_c/dkappa_c
+ * (the part of dL/dkappa_c this direction contributes through M and r):
+ *   upwind: d(den)/dkappa = V, dr/dkappa = 0;
+ *   exponential, tau < TAU_CAP: d(den)/dkappa = V e^tau, r = h(tau) with
+ *     h(t) = (e^t - 1)/t, dr/dkappa = h'(tau) V / Aperp;
+ *   exponential, tau >= TAU_CAP: d(den)/dkappa = 0, dr/dkappa = -r / kappa. */
 static void adjoint_direction(const orc_mesh* m, const double* om, double eps, int32_t G,
-                              const double* kappa, const double* g, const int32_t* qorder,
-                              double* lam) {
+                              int32_t law, const double* kappa, const double* g,
+                              const double* x, const int32_t* qorder, double* lam, double* dk) {
   const int32_t C = m->n_cells;
   for (int32_t k = C - 1; k >= 0; --k) {
     const int32_t c = qorder[k];
+    const double V = m->cell_volume[c];
     double aperp = 0.0;
     for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
       const double s = orient(om, m->face_normal + 3 * f);
       if (face_class(s, eps) == F_OUT) aperp += m->face_area[f] * fabs(s);
     }
     for (int32_t gg = 0; gg < G; ++gg) {
-      double acc = g[(int64_t)c * G + gg];
+      const int64_t i = (int64_t)c * G + gg;
+      const double kap = kappa[i];
+      double den, r = 1.0, dden = V, dr = 0.0;
+      if (law == LAW_EXP) {
+        const double tau = kap * V / aperp;
+        if (tau < TAU_CAP) {
+          den = aperp * exp(tau);
+          r = kap > 0.0 ? aperp * expm1(tau) / (kap * V) : 1.0;
+          dden = V * exp(tau);
+          dr = dh_dtau(tau) * V / aperp;
+        } else {
+          den = aperp * exp(TAU_CAP);
+          r = aperp * expm1(TAU_CAP) / (kap * V);
+          dden = 0.0;
+          dr = -r / kap;
+        }
+      } else {
+        den = aperp + kap * V;
+      }
+      double acc = r * g[i];
       for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
         const double s = orient(om, m->face_normal + 3 * f);
         const int32_t nb = m->face_nbr[f];
         if (face_class(s, eps) != F_OUT || nb < 0 || is_periodic_face(m, f)) continue;
         acc += m->face_area[f] * fabs(s) * lam[(int64_t)nb * G + gg];
       }
-      lam[(int64_t)c * G + gg] = acc / (aperp + kappa[(int64_t)c * G + gg] * m->cell_volume[c]);
+      lam[i] = acc / den;
+      dk[i] = -lam[i] * x[i] * dden + g[i] * x[i] * dr;
     }
   }
 }
 
 /* Gradients of a loss L(J, absorbed) given gJ = dL/dJ and gA = dL/dabsorbed ([C][G]).
+ * avg denotes the cell average and x the stored value of adjoint_direction.
  *
- * Without scattering (one iteration): dL/dphi_{c,d} = gJ_c/(4pi) + gA_c kappa_a,c V_c =: g_c,
- *   lambda_d = M_d^{-T} g, dL/dL_c = sum_d lambda_{c,d}/D,
- *   dL/dkappa_c = gA_c (1-a) V_c sum_d phi_{c,d} - V_c sum_d lambda_{c,d} phi_{c,d}.
+ * Without scattering (one iteration): dL/d avg_{c,d} = gJ_c/(4pi) + gA_c kappa_a,c V_c =: g_c,
+ *   lambda_d = M_d^{-T} (r_d g), dL/dL_c = sum_d lambda_{c,d}/D,
+ *   dL/dkappa_c = gA_c (1-a) V_c sum_d avg_{c,d} + sum_d dk_{c,d}
+ *   (dk from adjoint_direction; under the upwind law sum_d dk = -V_c sum_d lambda phi).
  * With source iteration (iterations i = 0..n-1, outputs from the last):
- *   lambda^{n-1} from g as above; lambda^{i-1}_d = M_d^{-T} g^{i-1} with
+ *   lambda^{n-1} from g as above; lambda^{i-1}_d = M_d^{-T} (r_d g^{i-1}) with
  *   g^{i-1}_c = a kappa_c V_c (sum_d lambda^i_{c,d}) / D;
  *   dL/dL_c = sum_i sum_d lambda^i_{c,d} / D;
- *   dL/dkappa_c = gA_c (1-a) V_c sum_d phi^{n-1}_{c,d}
- *     + sum_i [ -V_c sum_d lambda^i_{c,d} phi^i_{c,d}
- *               + a V_c (sum_d lambda^i_{c,d}) (sum_d' phi^{i-1}_{c,d'}) / D ],  phi^{-1} = 0.
- * phi^i is recomputed from the stored direction sums of iteration i-1.
+ *   dL/dkappa_c = gA_c (1-a) V_c sum_d avg^{n-1}_{c,d}
+ *     + sum_i [ sum_d dk^i_{c,d} + a V_c (sum_d lambda^i_{c,d}) (sum_d' avg^{i-1}_{c,d'}) / D ],
+ *   avg^{-1} = 0.
+ * x^i is recomputed from the stored direction sums of iteration i-1.
  * Periodic boundaries are not supported (returns ORC_ERR_UNSUPPORTED). */
 int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, double albedo,
-                int32_t n_scat, const double* gJ, const double* gA, double* dkappa,
+                int32_t n_scat, int32_t law, const double* gJ, const double* gA, double* dkappa,
                 double* demission) {
   if (periodic) return ORC_ERR_UNSUPPORTED;
   if (D < 1 || G < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
+  if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
   double* J = (double*)malloc(sizeof(double) * (size_t)CG);
@@ -418,14 +512,18 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   double* tots = G <= 64 ? tot : (double*)malloc(sizeof(double) * 8 * (size_t)G);
   double* jsum = (double*)malloc(sizeof(double) * (size_t)(n_scat * CG));
   double* phi = (double*)malloc(sizeof(double) * (size_t)(D * CG));
+  double* avg = (double*)malloc(sizeof(double) * (size_t)(D * CG));
   double* lam = (double*)malloc(sizeof(double) * (size_t)(D * CG));
+  double* dkd = (double*)malloc(sizeof(double) * (size_t)(D * CG));
   double* gsrc = (double*)malloc(sizeof(double) * (size_t)CG);
   double* src = (double*)malloc(sizeof(double) * (size_t)CG);
   double* lsum = (double*)malloc(sizeof(double) * (size_t)CG);
   int32_t* qorder = (int32_t*)malloc(sizeof(int32_t) * (size_t)D * C);
-  if (!J || !Ab || !tots || !jsum || !phi || !lam || !gsrc || !src || !lsum || !qorder) return ORC_ERR_OOM;
-  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, J, Ab, tots,
-                           NULL, jsum, NULL);
+  if (!J || !Ab || !tots || !jsum || !phi || !avg || !lam || !dkd || !gsrc || !src || !lsum ||
+      !qorder)
+    return ORC_ERR_OOM;
+  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, law, J, Ab,
+                           tots, NULL, jsum, NULL);
   if (status == ORC_OK) {
     memset(dkappa, 0, sizeof(double) * (size_t)CG);
     memset(demission, 0, sizeof(double) * (size_t)CG);
@@ -437,7 +535,7 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         dkappa[i] += gA[i] * (1.0 - albedo) * V * jsum[(int64_t)(n_scat - 1) * CG + i];
       }
     for (int32_t it = n_scat - 1; it >= 0 && status == ORC_OK; --it) {
-      /* recompute phi^it from the direction sums of iteration it-1 */
+      /* recompute x^it from the direction sums of iteration it-1 */
       for (int32_t c = 0; c < C; ++c)
         for (int32_t g = 0; g < G; ++g) {
           const int64_t i = (int64_t)c * G + g;
@@ -451,11 +549,12 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         double acc[4 * 64];
         double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
         memset(a4, 0, sizeof(double) * 4 * (size_t)G);
-        int st = sweep_direction(m, dirs + 3 * d, eps, G, kappa, src, NULL, phi + (int64_t)d * CG,
-                                 a4, NULL, cnt, q, NULL, qorder + (int64_t)d * C);
+        int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, NULL,
+                                 phi + (int64_t)d * CG, avg + (int64_t)d * CG, a4, NULL, cnt, q,
+                                 NULL, qorder + (int64_t)d * C);
         if (st == ORC_OK)
-          adjoint_direction(m, dirs + 3 * d, eps, G, kappa, gsrc, qorder + (int64_t)d * C,
-                            lam + (int64_t)d * CG);
+          adjoint_direction(m, dirs + 3 * d, eps, G, law, kappa, gsrc, phi + (int64_t)d * CG,
+                            qorder + (int64_t)d * C, lam + (int64_t)d * CG, dkd + (int64_t)d * CG);
         else {
 #pragma omp critical
           status = st;
@@ -469,14 +568,14 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         for (int32_t g = 0; g < G; ++g) {
           const int64_t i = (int64_t)c * G + g;
           const double V = m->cell_volume[c];
-          double ls = 0.0, lp = 0.0;
+          double ls = 0.0, dks = 0.0;
           for (int32_t d = 0; d < D; ++d) {
             ls += lam[(int64_t)d * CG + i];
-            lp += lam[(int64_t)d * CG + i] * phi[(int64_t)d * CG + i];
+            dks += dkd[(int64_t)d * CG + i];
           }
           const double prev = it > 0 ? jsum[(int64_t)(it - 1) * CG + i] : 0.0;
           demission[i] += ls / D;
-          dkappa[i] += -V * lp + albedo * V * ls * prev / D;
+          dkappa[i] += dks + albedo * V * ls * prev / D;
           lsum[i] = ls;
         }
       /* adjoint source of the previous iteration */
@@ -492,7 +591,9 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   if (tots != tot) free(tots);
   free(jsum);
   free(phi);
+  free(avg);
   free(lam);
+  free(dkd);
   free(gsrc);
   free(src);
   free(lsum);

@@ -6,6 +6,11 @@ dependency graph, ordering or queue.  For direction Omega (sec. 2.5/2.6):
 
     (Aperp_c + kappa_c V_c) phi_c - sum_{inflow faces f of c} A_f |n_f . Omega| phi_nbr(f) = S_c
 
+With the exponential cell law (transmission e^{-tau} over the mean chord
+V/Aperp, tau = kappa V / Aperp, capped at 40) the unknown is the exit flux
+density x and the diagonal becomes Aperp e^{tau}; the cell average is r x with
+r = Aperp (e^{tau} - 1) / (kappa V) (1 at kappa = 0).
+
 cyclic=True also couples the periodic faces, giving the fixed point of the
 periodic-boundary passes (sec. 2.7).  `dense_scatter_system` couples all
 directions through the isotropic scattering term of eq. radiativeTransfer, giving
@@ -26,8 +31,12 @@ def _faces(mesh):
     return owner, mesh["face_nbr"], shift, mesh["face_area"], mesh["face_normal"]
 
 
-def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS):
-    """M (C x C) and the outflow weights of walls / periodic faces for one direction."""
+TAU_CAP = 40.0
+
+
+def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS, law="upwind"):
+    """M (C x C), the outflow weights of walls / periodic faces for one direction and
+    r, the factor from the unknown to the cell average."""
     owner, nbr, shift, area, normal = _faces(mesh)
     C = len(mesh["cell_volume"])
     s = normal @ np.asarray(omega, np.float64)
@@ -35,14 +44,22 @@ def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS):
     out = s > eps
     inn = s < -eps
     aperp = np.bincount(owner[out], weights=w[out], minlength=C)
-    M = np.diag(aperp + kappa * mesh["cell_volume"])
+    kV = kappa * mesh["cell_volume"]
+    if law == "exp":
+        tau = np.minimum(kV / aperp, TAU_CAP)
+        M = np.diag(aperp * np.exp(tau))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(kV > 0, aperp * np.expm1(tau) / kV, 1.0)
+    else:
+        M = np.diag(aperp + kV)
+        r = np.ones(C)
     interior = nbr >= 0
     per = shift != 0
     use = inn & interior & ((~per) | cyclic)
     np.add.at(M, (owner[use], nbr[use]), -w[use])
     wall_out = np.bincount(owner[out & ~interior], weights=w[out & ~interior], minlength=C)
     per_out = np.bincount(owner[out & interior & per], weights=w[out & interior & per], minlength=C)
-    return M, wall_out, per_out
+    return M, wall_out, per_out, r
 
 
 def dense_forward(w, cyclic=False):
@@ -52,6 +69,7 @@ def dense_forward(w, cyclic=False):
     kap = np.asarray(w["kappa"], np.float64)
     em = np.asarray(w["emission"], np.float64)
     D = len(dirs)
+    law = w.get("law", "upwind")
     off = 0
     Js, As, tots, phis = [], [], [], []
     for mesh in w["meshes"]:
@@ -59,13 +77,15 @@ def dense_forward(w, cyclic=False):
         k = kap[off:off + C]
         e = em[off:off + C]
         phi = np.zeros((D, C, G))
+        avg = np.zeros((D, C, G))
         esc = np.zeros(G)
         for d in range(D):
             for g in range(G):
-                M, wall, _ = direction_matrix(mesh, dirs[d], k[:, g], cyclic)
+                M, wall, _, r = direction_matrix(mesh, dirs[d], k[:, g], cyclic, law=law)
                 phi[d, :, g] = np.linalg.solve(M, e[:, g] / D)
+                avg[d, :, g] = r * phi[d, :, g]
                 esc[g] += wall @ phi[d, :, g]
-        js = phi.sum(axis=0)
+        js = avg.sum(axis=0)
         J = js / (4 * np.pi)
         A = k * mesh["cell_volume"][:, None] * js
         Js.append(J)
@@ -79,7 +99,8 @@ def dense_forward(w, cyclic=False):
 def dense_scatter_system(w):
     """Fixed point of source iteration: all D directions solved together for one mesh, one group.
 
-    Unknowns phi[d,c]; equations M_d phi_d - (a kappa V / D) sum_d' phi_d' = L / D."""
+    Unknowns x[d,c]; equations M_d x_d - (a kappa V / D) sum_d' r_d' x_d' = L / D; returns
+    the cell averages r_d x_d."""
     (mesh,) = w["meshes"]
     dirs = w["dirs"]
     D = len(dirs)
@@ -88,14 +109,18 @@ def dense_scatter_system(w):
     L = np.asarray(w["emission"], np.float64)[:, 0]
     a = w["albedo"]
     V = mesh["cell_volume"]
+    law = w.get("law", "upwind")
     big = np.zeros((D * C, D * C))
+    rs = []
     for d in range(D):
-        M, _, _ = direction_matrix(mesh, dirs[d], k)
+        M, _, _, r = direction_matrix(mesh, dirs[d], k, law=law)
+        rs.append(r)
         big[d * C:(d + 1) * C, d * C:(d + 1) * C] += M
+    for d in range(D):
         for d2 in range(D):
-            big[d * C:(d + 1) * C, d2 * C:(d2 + 1) * C] -= np.diag(a * k * V / D)
-    phi = np.linalg.solve(big, np.tile(L / D, D)).reshape(D, C)
-    return phi
+            big[d * C:(d + 1) * C, d2 * C:(d2 + 1) * C] -= np.diag(a * k * V / D * rs[d2])
+    x = np.linalg.solve(big, np.tile(L / D, D)).reshape(D, C)
+    return x * np.stack(rs)
 
 
 def dense_adjoint(w, gJ, gA):
@@ -120,7 +145,7 @@ def dense_adjoint(w, gJ, gA):
             gphi = gj / (4 * np.pi) + ga * k * V
             jsum = np.zeros(C)
             for d in range(D):
-                M, _, _ = direction_matrix(mesh, dirs[d], k)
+                M, _, _, _ = direction_matrix(mesh, dirs[d], k)
                 phi = np.linalg.solve(M, e / D)
                 lam = np.linalg.solve(M.T, gphi)
                 jsum += phi

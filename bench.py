@@ -112,7 +112,7 @@ def make_workload(name: str) -> dict:
 def fwd_opts(w: dict, form: str = "batched", block: int = 0, ring: int = 0) -> dict:
     return dict(boundary=w.get("boundary", "vacuum"), n_pbc=int(w.get("n_pbc", 1)),
                 albedo=float(w.get("albedo", 0.0)), n_scat=int(w.get("n_scat", 1)), form=form,
-                block=block, ring=ring)
+                block=block, ring=ring, law=w.get("law", "upwind"))
 
 
 def updates_per_pass(w: dict) -> int:
@@ -206,6 +206,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_plain_scale", choices=WORKLOADS)
     ap.add_argument("--block", type=int, default=0, help="sweep workgroup size (0 = tuned)")
     ap.add_argument("--ring", type=int, default=0, help="LDS ring capacity (0 = tuned)")
+    ap.add_argument("--law", default="upwind", choices=("upwind", "exp"),
+                    help="cell law: first-order upwind balance or exponential attenuation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tune", action="store_true",
@@ -235,6 +237,7 @@ def main() -> int:
 
     t0 = time.perf_counter()
     w = make_workload(args.workload)
+    w["law"] = args.law
     log("workload %s built in %.1f s" % (args.workload, time.perf_counter() - t0))
     G = int(w["G"])
     C = sum(len(m["cell_volume"]) for m in w["meshes"])
@@ -362,6 +365,7 @@ def main() -> int:
         "config": {"workload": args.workload, "cells": C, "directions": D, "groups": G,
                    "meshes": len(w["meshes"]), "boundary": w.get("boundary", "vacuum"),
                    "n_pbc": fo["n_pbc"], "n_scat": fo["n_scat"], "albedo": fo["albedo"],
+                   "law": fo["law"],
                    "adjoint": do_adj, "updates_per_step": n_updates, "form": "batched",
                    "block": fo["block"] or "default", "ring": fo["ring"] or "default"},
         "roofline": roof,

@@ -27,6 +27,19 @@
  *   J = (1/4pi) sum_d phi          absorbed = kappa_a V sum_d phi
  * with kappa_a = (1 - albedo) kappa, kappa being the extinction coefficient.
  *
+ * Exponential cell law (opts->law = SWEEP_LAW_EXP): the attenuation form
+ * 1 - e^{-dn sigma} of the paper's scattering test (sec. 3.3), with the mean
+ * distance travelled in the cell taken as the mean chord V / Aperp, so the
+ * optical depth of a task is tau = kappa V / Aperp.  The power entering the
+ * task, T = sum_{inflow f} w_f x_upwind(f) + S, leaves with the factor e^{-tau}
+ * through the outflow faces (exit flux density x = T e^{-tau} / Aperp, what the
+ * downwind cells, the walls and the periodic partners receive per unit w) and
+ * T (1 - e^{-tau}) is absorbed; the cell average that enters J, absorbed and
+ * the scattering source is phi = T (1 - e^{-tau}) / (kappa V) (T / Aperp at
+ * kappa = 0).  tau is capped at 40 for the transmission (a thicker cell passes
+ * on e^{-40} = 4.2e-18 of T), which keeps x in the normal FP32 range so that
+ * phi can be recovered from it.  Requires Aperp > 0 (every closed cell).
+ *
  * Conventions for every call:
  *   - every function returns sweep_status_t; on failure sweep_last_error()
  *     returns a thread-local message; no exception or abort crosses the ABI;
@@ -104,6 +117,7 @@ typedef struct {
 
 enum { SWEEP_BOUNDARY_VACUUM = 0, SWEEP_BOUNDARY_PERIODIC = 1 };
 enum { SWEEP_FORM_BATCHED = 0, SWEEP_FORM_PLAIN = 1 };
+enum { SWEEP_LAW_UPWIND = 0, SWEEP_LAW_EXP = 1 };
 
 typedef struct {
   int32_t boundary;  /* SWEEP_BOUNDARY_*; PERIODIC requires the meshes' face_shift */
@@ -117,7 +131,9 @@ typedef struct {
   int32_t use_graph; /* 1: run the pass sequence as a captured hipGraph; the first call with
                         a given set of arguments captures and instantiates it (kept with the
                         DAG, at most 8), later calls replay it on `stream` */
-  int32_t reserved[5];
+  int32_t law;       /* SWEEP_LAW_UPWIND (first-order upwind balance, default) or
+                        SWEEP_LAW_EXP (exponential attenuation, see above) */
+  int32_t reserved[4];
 } sweep_fwd_opts_t;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -149,8 +165,9 @@ sweep_status_t sweep_dag_export(sweep_dag_t dag, int32_t* level, int32_t* order,
                                 void* stream);
 
 /* Bytes of the `saved` workspace sweep_forward fills for sweep_adjoint:
- * phi of the final pass ([n_dirs][C_total][G] FP32) followed by the direction
- * sums sum_d phi of every source iteration ([n_scat][C_total][G] FP32). */
+ * phi of the final pass ([n_dirs][C_total][G] FP32; the exit flux density x
+ * under SWEEP_LAW_EXP) followed by the direction sums sum_d phi of every source
+ * iteration ([n_scat][C_total][G] FP32). */
 size_t sweep_saved_bytes(sweep_dag_t dag, int32_t G, const sweep_fwd_opts_t* opts);
 
 /* Forward sweep: n_scat source iterations, each made of n_pbc passes (vacuum:

@@ -52,7 +52,7 @@ def upload_mesh(mesh: dict, device="cuda") -> dict:
 
 
 def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
-              use_graph=False) -> B.sweep_fwd_opts_t:
+              use_graph=False, law="upwind") -> B.sweep_fwd_opts_t:
     o = B.sweep_fwd_opts_t()
     o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
     o.n_pbc = int(n_pbc)
@@ -62,6 +62,7 @@ def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", 
     o.block = int(block)
     o.ring = int(ring)
     o.use_graph = int(bool(use_graph))
+    o.law = {"upwind": B.SWEEP_LAW_UPWIND, "exp": B.SWEEP_LAW_EXP}[law]
     return o
 
 

@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "SWEEP_OK", -1: "SWEEP_ERR_INVALID_ARG", -2: "SWEEP_ERR_CYCLE
 SWEEP_N_TOTALS = 8
 SWEEP_BOUNDARY_VACUUM, SWEEP_BOUNDARY_PERIODIC = 0, 1
 SWEEP_FORM_BATCHED, SWEEP_FORM_PLAIN = 0, 1
+SWEEP_LAW_UPWIND, SWEEP_LAW_EXP = 0, 1
 
 EXPORTED = ("sweep_last_error", "sweep_build_dag", "sweep_destroy_dag", "sweep_dag_info",
             "sweep_dag_export", "sweep_saved_bytes", "sweep_forward", "sweep_adjoint",
@@ -59,7 +60,8 @@ class sweep_fwd_opts_t(ctypes.Structure):
     _fields_ = [("boundary", ctypes.c_int32), ("n_pbc", ctypes.c_int32),
                 ("albedo", ctypes.c_double), ("n_scat", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("block", ctypes.c_int32), ("ring", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("use_graph", ctypes.c_int32), ("law", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 _lib = None

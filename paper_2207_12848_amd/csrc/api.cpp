@@ -330,6 +330,16 @@ sweep_status_t validate_mesh_host(const sweep_mesh_t& m, int idx) {
   return SWEEP_OK;
 }
 
+// Per-mesh first cell and cell count on the device (for the reductions).
+sweep_status_t ensure_mesh_tables(sweep_dag_t d) {
+  if (d->mesh_off_d.p) return SWEEP_OK;
+  HIP_TRY(d->mesh_off_d.alloc(4 * d->mesh_off.size()));
+  HIP_TRY(d->mesh_cells_d.alloc(4 * d->mesh_cells.size()));
+  HIP_TRY(hipMemcpy(d->mesh_off_d.p, d->mesh_off.data(), 4 * d->mesh_off.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(d->mesh_cells_d.p, d->mesh_cells.data(), 4 * d->mesh_cells.size(), hipMemcpyHostToDevice));
+  return SWEEP_OK;
+}
+
 // Reduction block tables for G groups: blocks never straddle meshes.
 sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
   if (d->red_G == G) return SWEEP_OK;
@@ -357,7 +367,7 @@ sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
 }
 
 struct FwdPlan {
-  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph;
+  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law;
   float albedo;
 };
 
@@ -370,6 +380,9 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   p->block = o ? o->block : 0;
   p->ring = o ? o->ring : 0;
   p->use_graph = o ? o->use_graph : 0;
+  p->law = o ? o->law : SWEEP_LAW_UPWIND;
+  if (p->law != SWEEP_LAW_UPWIND && p->law != SWEEP_LAW_EXP)
+    return fail(SWEEP_ERR_INVALID_ARG, "unknown cell law %d", p->law);
   if (p->boundary != SWEEP_BOUNDARY_VACUUM && p->boundary != SWEEP_BOUNDARY_PERIODIC)
     return fail(SWEEP_ERR_INVALID_ARG, "unknown boundary %d", p->boundary);
   if (p->n_pbc < 1 || p->n_scat < 1) return fail(SWEEP_ERR_INVALID_ARG, "n_pbc and n_scat must be >= 1");
@@ -408,7 +421,8 @@ int default_ring(int gn, int ring) {
 
 // Per-task denominators and sources for one sweep (schedule order).
 sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
-                        const float* gsrc, const float* jsum_prev, float albedo, hipStream_t s) {
+                        const float* gsrc, const float* jsum_prev, float albedo, int32_t law,
+                        hipStream_t s) {
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
@@ -426,6 +440,7 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.albedo = albedo;
   q.inv_D = 1.0f / (float)d->D;
   q.G = G;
+  q.law = law;
   q.tden = d->tden.as<float>();
   q.tsrc = d->tsrc.as<float>();
   q.cds = d->cds.as<float2>();
@@ -549,7 +564,7 @@ void opts_key(std::vector<uint64_t>& k, const FwdPlan& p) {
   uint32_t ab;
   std::memcpy(&ab, &p.albedo, 4);
   k.insert(k.end(), {(uint64_t)p.boundary, (uint64_t)p.n_pbc, (uint64_t)p.n_scat, (uint64_t)p.form,
-                     (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab});
+                     (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab, (uint64_t)p.law});
 }
 
 sweep_status_t check_common(sweep_dag_t d, int32_t G) {
@@ -1035,12 +1050,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     if (saved) return (float*)saved + DCG + (int64_t)it * CG;
     return (it % 2 == 0) ? d->jsum_a.as<float>() : d->jsum_b.as<float>();
   };
-  if (!d->mesh_off_d.p) {
-    HIP_TRY(d->mesh_off_d.alloc(4 * d->mesh_off.size()));
-    HIP_TRY(d->mesh_cells_d.alloc(4 * d->mesh_cells.size()));
-    HIP_TRY(hipMemcpy(d->mesh_off_d.p, d->mesh_off.data(), 4 * d->mesh_off.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(d->mesh_cells_d.p, d->mesh_cells.data(), 4 * d->mesh_cells.size(), hipMemcpyHostToDevice));
-  }
+  ST_TRY(ensure_mesh_tables(d));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
@@ -1055,6 +1065,8 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   r.mesh_off = d->mesh_off_d.as<int32_t>();
   r.mesh_cells = d->mesh_cells_d.as<int32_t>();
   r.bnd = d->bnd.as<float2>();
+  r.aperp = d->aperp.as<float>();
+  r.law = p.law;
   r.kappa = kappa;
   r.emission = emission;
   r.vol = d->vol.as<float>();
@@ -1070,7 +1082,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
       float* prev = nullptr;
       for (int ps = 0; ps < p.n_pbc; ++ps) {
         float* dst = ((p.n_pbc - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
-        if (ps == 0) ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, st));
+        if (ps == 0) ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
         ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, st));
         if (periodic && ps + 1 < p.n_pbc) {
           sweep::ReduceArgs q = r;
@@ -1129,6 +1141,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   StreamScope stream_scope(s);
   const int64_t CG = d->C_total * G;
   const int64_t DCG = CG * d->D;
+  ST_TRY(ensure_mesh_tables(d));
   HIP_TRY(d->lam.alloc(4 * DCG));
   HIP_TRY(d->gsrc.alloc(4 * CG));
   HIP_TRY(d->dk64.alloc(8 * CG));
@@ -1152,16 +1165,22 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
       const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
       const float* phi_it = phi_final;
       if (it != p.n_scat - 1) {
-        ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, st));
+        ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
         ST_TRY(run_sweep(d, false, p, G, nullptr, d->phi_a.as<float>(), nullptr, st));
         phi_it = d->phi_a.as<float>();
       }
-      ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, st));
+      ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
       ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, st));
       sweep::AdjReduceArgs q{};
       q.D = d->D;
       q.G = G;
       q.C_total = d->C_total;
+      q.law = p.law;
+      q.n_meshes = d->n_meshes;
+      q.units = d->units_d.as<Unit>();
+      q.mesh_off = d->mesh_off_d.as<int32_t>();
+      q.aperp = d->aperp.as<float>();
+      q.gsrc = d->gsrc.as<float>();
       q.lam = d->lam.as<float>();
       q.phi = phi_it;
       q.kappa = kappa;
@@ -1204,7 +1223,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
-  ST_TRY(run_prep(d, G, kappa, emission, nullptr, nullptr, p.albedo, s));
+  ST_TRY(run_prep(d, G, kappa, emission, nullptr, nullptr, p.albedo, p.law, s));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {

@@ -589,7 +589,7 @@ __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
 // Per mesh: the largest face count of a cell, and the overflow room the wide
 // rows need ((faces + 2) ints per direction for every cell with more than
 // row_cap faces), accumulated into out[0] (max) and out[1] (sum).
-__global__ void k_face_stats(const int64_t* face_ptr, int n_cells, int row_cap, int n_dirs,
+__global__ __launch_bounds__(256) void k_face_stats(const int64_t* face_ptr, int n_cells, int row_cap, int n_dirs,
                              unsigned long long* out) {
   unsigned long long mx = 0, sum = 0;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cells; c += gridDim.x * blockDim.x) {
@@ -602,7 +602,19 @@ __global__ void k_face_stats(const int64_t* face_ptr, int n_cells, int row_cap, 
     mx = m2 > mx ? m2 : mx;
     sum += __shfl_xor(sum, o);
   }
+  // one atomic pair per block: same-address atomics from every wave serialise
+  __shared__ unsigned long long part[2][4];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    part[0][w] = mx;
+    part[1][w] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      mx = part[0][i] > mx ? part[0][i] : mx;
+      sum += part[1][i];
+    }
     atomicMax(out, mx);
     atomicAdd(out + 1, sum);
   }
@@ -834,7 +846,7 @@ hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
 hipError_t launch_face_stats(const int64_t* face_ptr, int32_t n_cells, int32_t row_cap, int32_t n_dirs,
                              unsigned long long* out, hipStream_t s) {
   if (n_cells <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)std::min<int64_t>(1024, grid1d(n_cells, 256));
+  const unsigned grid = (unsigned)std::min<int64_t>(256, grid1d(n_cells, 256));
   hipLaunchKernelGGL(k_face_stats, dim3(grid), dim3(256), 0, s, face_ptr, n_cells, row_cap, n_dirs, out);
   return hipGetLastError();
 }

@@ -124,6 +124,7 @@ struct PrepArgs {
   float albedo;
   float inv_D;
   int32_t G;
+  int32_t law;             // SWEEP_LAW_UPWIND / SWEEP_LAW_EXP
   float2* cds;             // [T][G] cell order (scratch): (denominator, source)
   float* tden;             // [T][G] schedule order
   float* tsrc;             // [T][G] schedule order
@@ -143,6 +144,8 @@ struct ReduceArgs {
   const float* pin;          // [D][C][G] or nullptr
   const double* pin_prev;    // [C][G] or nullptr
   const float2* bnd;         // per task, cell order
+  const float* aperp;        // per task, cell order
+  int32_t law;
   const float* kappa;
   const float* emission;
   const float* vol;
@@ -161,6 +164,12 @@ struct AdjReduceArgs {
   int32_t D;
   int32_t G;
   int64_t C_total;
+  int32_t law;
+  int32_t n_meshes;
+  const Unit* units;       // [n_meshes * D]
+  const int32_t* mesh_off; // [n_meshes + 1] first global cell of each mesh
+  const float* aperp;      // per task, cell order
+  const float* gsrc;       // [C][G] adjoint source of this iteration (dL/d cell average)
   const float* lam;        // [D][C][G]
   const float* phi;        // [D][C][G]
   const float* kappa;

@@ -14,6 +14,7 @@
 // reads; an older upwind result is prefetched from global memory a step ahead
 // (it was stored at least two barriers earlier by the same workgroup).
 #include "internal.h"
+#include "sweep.h"
 
 namespace sweep {
 
@@ -538,8 +539,43 @@ hipError_t launch_sweep_t(const SweepArgs& a, int32_t gn, int32_t grid, int32_t 
   }
 }
 
-// Per-task denominators Aperp + kappa V and sources, first in cell order within
-// each unit (every access coalesced), as (denominator, source) pairs.
+// Exponential cell law: with the optical depth tau = kappa V / Aperp (capped at
+// 40 for the transmission), the entering power T of a task becomes the exit
+// flux density x = T / den, den = Aperp e^{min(tau, 40)}, and the cell average
+// is r x, r = Aperp (e^{min(tau, 40)} - 1) / (kappa V) (1 at kappa = 0).
+constexpr double kTauCap = 40.0;
+
+struct ExpTask {
+  double den, r;
+};
+
+__device__ __forceinline__ ExpTask exp_task(double ap, double kV) {
+  const double tc = fmin(kV / ap, kTauCap);
+  ExpTask e;
+  e.den = ap * exp(tc);
+  e.r = kV > 0.0 ? ap * expm1(tc) / kV : 1.0;
+  return e;
+}
+
+// h'(t) for h(t) = (e^t - 1) / t: below 0.5 the power series
+// sum_{k>=1} k t^{k-1} / (k+1)! to 18 terms (remainder below 1e-18), above it
+// ((t - 1)(e^t - 1) + t) / t^2.
+__device__ __forceinline__ double dh_dt(double t) {
+  if (t < 0.5) {
+    double p = 0.5, s = 0.0;  // p = t^{k-1} / (k+1)!
+    for (int k = 1; k <= 18; ++k) {
+      s += (double)k * p;
+      p *= t / (double)(k + 2);
+    }
+    return s;
+  }
+  return ((t - 1.0) * expm1(t) + t) / (t * t);
+}
+
+// Per-task denominators (Aperp + kappa V, or the exponential law's den) and
+// sources, first in cell order within each unit (every access coalesced), as
+// (denominator, source) pairs.  The adjoint source of the exponential law is
+// r g, g being the derivative with respect to the cell average.
 __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_units, int b) {
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -561,15 +597,21 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   for (int g = 0; g < a.G; ++g) {
     const int64_t cg = ci * a.G + g;
     const double kap = (double)a.kappa[cg];
+    double den = ap + kap * V, r = 1.0;
+    if (a.law == SWEEP_LAW_EXP) {
+      const ExpTask e = exp_task(ap, kap * V);
+      den = e.den;
+      r = e.r;
+    }
     double s;
     if (a.emission != nullptr) {
       s = (double)a.emission[cg];
       if (a.jsum_prev != nullptr) s += (double)a.albedo * kap * V * (double)a.jsum_prev[cg];
       s *= (double)a.inv_D;
     } else {
-      s = (double)a.gsrc[cg];
+      s = (double)a.gsrc[cg] * r;
     }
-    a.cds[t * a.G + g] = make_float2((float)(ap + kap * V), (float)s);
+    a.cds[t * a.G + g] = make_float2((float)den, (float)s);
   }
 }
 
@@ -610,21 +652,24 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(ReduceArgs a) {
     const int64_t cg = (int64_t)c * G + g;
     const int64_t stride = a.C_total * G;
     const int lc = c - a.mesh_off[m];
+    const double V = (double)a.vol[c];
+    const double kap = (double)a.kappa[cg];
+    const bool exp_law = a.law == SWEEP_LAW_EXP;
     double js = 0.0, pn = 0.0, esc = 0.0, pout = 0.0;
     for (int d = 0; d < a.D; ++d) {
+      // phi holds the exit flux density x (phi itself under the upwind law)
       const double ph = (double)a.phi[d * stride + cg];
-      js += ph;
       if (a.pin != nullptr) pn += (double)a.pin[d * stride + cg];
       if (a.last) {
-        const float2 b = a.bnd[a.units[m * a.D + d].task_base + lc];
+        const int64_t t = a.units[m * a.D + d].task_base + lc;
+        const float2 b = a.bnd[t];
         esc += (double)b.x * ph;
         pout += (double)b.y * ph;
+        js += exp_law ? ph * exp_task((double)a.aperp[t], kap * V).r : ph;
       }
     }
     if (a.pin_sum != nullptr) a.pin_sum[cg] = pn;
     if (a.last) {
-      const double V = (double)a.vol[c];
-      const double kap = (double)a.kappa[cg];
       const double ka = (1.0 - (double)a.albedo) * kap;
       const double ks = (double)a.albedo * kap;
       const double ab = ka * V * js;
@@ -715,17 +760,52 @@ __global__ void k_adj_reduce(AdjReduceArgs a, double* dk, double* de) {
   const int64_t n = a.C_total * a.G;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double ls = 0.0, lph = 0.0;
-  for (int d = 0; d < a.D; ++d) {
-    const double l = (double)a.lam[d * n + i];
-    ls += l;
-    lph += l * (double)a.phi[d * n + i];
-  }
   const double V = (double)a.vol[i / a.G];
+  double ls = 0.0, dks;
+  if (a.law == SWEEP_LAW_EXP) {
+    // per direction: -lambda x d(den)/dkappa + g x dr/dkappa, with
+    // tau < 40: d(den)/dkappa = V e^tau, dr/dkappa = h'(tau) V / Aperp;
+    // tau >= 40: d(den)/dkappa = 0, dr/dkappa = -r / kappa
+    const int c = (int)(i / a.G);
+    int lo = 0, hi = a.n_meshes - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.mesh_off[mid] <= c) lo = mid; else hi = mid - 1;
+    }
+    const int lc = c - a.mesh_off[lo];
+    const double kap = (double)a.kappa[i];
+    const double kV = kap * V;
+    const double g = (double)a.gsrc[i];
+    dks = 0.0;
+    for (int d = 0; d < a.D; ++d) {
+      const double l = (double)a.lam[d * n + i];
+      const double x = (double)a.phi[d * n + i];
+      const double ap = (double)a.aperp[a.units[lo * a.D + d].task_base + lc];
+      const double tau = kV / ap;
+      double dden, dr;
+      if (tau < kTauCap) {
+        dden = V * exp(tau);
+        dr = dh_dt(tau) * V / ap;
+      } else {
+        dden = 0.0;
+        dr = -(ap * expm1(kTauCap) / kV) / kap;
+      }
+      ls += l;
+      dks += -l * x * dden + g * x * dr;
+    }
+  } else {
+    double lph = 0.0;
+    for (int d = 0; d < a.D; ++d) {
+      const double l = (double)a.lam[d * n + i];
+      ls += l;
+      lph += l * (double)a.phi[d * n + i];
+    }
+    dks = -V * lph;
+  }
   const double prev = a.jsum_prev != nullptr ? (double)a.jsum_prev[i] : 0.0;
   const double alb = (double)a.albedo;
   const double invD = (double)a.inv_D;
-  dk[i] += -V * lph + alb * V * ls * prev * invD;
+  dk[i] += dks + alb * V * ls * prev * invD;
   de[i] += ls * invD;
   a.gsrc_next[i] = (float)(alb * (double)a.kappa[i] * V * ls * invD);
 }

@@ -34,7 +34,8 @@ def _sw():
 
 
 def _opts(w):
-    return dict(boundary=w["boundary"], n_pbc=w["n_pbc"], albedo=w["albedo"], n_scat=w["n_scat"])
+    return dict(boundary=w["boundary"], n_pbc=w["n_pbc"], albedo=w["albedo"], n_scat=w["n_scat"],
+                law=w.get("law", "upwind"))
 
 
 def _dev(w):
@@ -98,6 +99,23 @@ def gpu_forward_adjoint(w, adjoint=True):
 
 def test_c2_full_forward_and_adjoint():
     w = W.c2_plain_scale()
+    g = gpu_forward_adjoint(w)
+    ref = oracle.forward(w)
+    field_close(g["J"], ref["J"], name="J")
+    field_close(g["A"], ref["absorbed"], name="absorbed")
+    assert np.all(np.abs(g["tot"][..., :3] - ref["totals"][..., :3]) <=
+                  REL * np.abs(ref["totals"][..., :3]))
+    assert balance(g["tot"]).max() <= 1e-6
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    grad_close(g["dk"], dk, "dL/dkappa")
+    grad_close(g["de"], de, "dL/demission")
+
+
+def test_c2_full_exp_law_forward_and_adjoint():
+    """The c2 workload under the exponential cell law: its optical depths per
+    task reach ~10, so the attenuation factors span e^0 .. e^-10."""
+    w = dict(W.c2_plain_scale(), law="exp")
     g = gpu_forward_adjoint(w)
     ref = oracle.forward(w)
     field_close(g["J"], ref["J"], name="J")

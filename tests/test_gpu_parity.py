@@ -34,7 +34,8 @@ def _dev(w):
 
 
 def _opts(w):
-    return dict(boundary=w["boundary"], n_pbc=w["n_pbc"], albedo=w["albedo"], n_scat=w["n_scat"])
+    return dict(boundary=w["boundary"], n_pbc=w["n_pbc"], albedo=w["albedo"], n_scat=w["n_scat"],
+                law=w.get("law", "upwind"))
 
 
 def assert_field_close(gpu, ref, rel=REL, floor=1e-20, name="field"):

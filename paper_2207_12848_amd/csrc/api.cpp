@@ -664,7 +664,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   D->T = off * n_dirs;
   const int64_t T = D->T;
   const int n_units = n_meshes * n_dirs;
-  // units: u = mesh * D + dir
+  // units: u = mesh * D + dir; the tasks of unit (m, d) start at D * (first cell
+  // of m) + d * cells(m) (k_adj_reduce indexes per-task arrays with this formula)
   std::vector<int32_t> blk_base(n_units + 1, 0);
   for (int m = 0; m < n_meshes; ++m)
     for (int d = 0; d < n_dirs; ++d) {
@@ -1177,7 +1178,6 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
       q.C_total = d->C_total;
       q.law = p.law;
       q.n_meshes = d->n_meshes;
-      q.units = d->units_d.as<Unit>();
       q.mesh_off = d->mesh_off_d.as<int32_t>();
       q.aperp = d->aperp.as<float>();
       q.gsrc = d->gsrc.as<float>();

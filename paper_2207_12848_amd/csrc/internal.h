@@ -166,9 +166,8 @@ struct AdjReduceArgs {
   int64_t C_total;
   int32_t law;
   int32_t n_meshes;
-  const Unit* units;       // [n_meshes * D]
   const int32_t* mesh_off; // [n_meshes + 1] first global cell of each mesh
-  const float* aperp;      // per task, cell order
+  const float* aperp;      // per task: unit (m, d) starts at D * mesh_off[m] + d * cells(m)
   const float* gsrc;       // [C][G] adjoint source of this iteration (dL/d cell average)
   const float* lam;        // [D][C][G]
   const float* phi;        // [D][C][G]

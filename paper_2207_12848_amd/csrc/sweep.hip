@@ -545,28 +545,38 @@ hipError_t launch_sweep_t(const SweepArgs& a, int32_t gn, int32_t grid, int32_t 
 // is r x, r = Aperp (e^{min(tau, 40)} - 1) / (kappa V) (1 at kappa = 0).
 constexpr double kTauCap = 40.0;
 
-struct ExpTask {
-  double den, r;
-};
+__device__ __forceinline__ double exp_den(double ap, double kV) {
+  return ap * exp(fmin(kV / ap, kTauCap));
+}
 
-__device__ __forceinline__ ExpTask exp_task(double ap, double kV) {
-  const double tc = fmin(kV / ap, kTauCap);
-  ExpTask e;
-  e.den = ap * exp(tc);
-  e.r = kV > 0.0 ? ap * expm1(tc) / kV : 1.0;
-  return e;
+__device__ __forceinline__ double exp_r(double ap, double kV) {
+  return kV > 0.0 ? ap * expm1(fmin(kV / ap, kTauCap)) / kV : 1.0;
 }
 
 // h'(t) for h(t) = (e^t - 1) / t: below 0.5 the power series
-// sum_{k>=1} k t^{k-1} / (k+1)! to 18 terms (remainder below 1e-18), above it
+// sum_{k>=1} k t^{k-1} / (k+1)! to 18 terms (remainder below 1e-18, Horner
+// with the coefficients folded at compile time), above it
 // ((t - 1)(e^t - 1) + t) / t^2.
+struct DhSeries {
+  double c[18];
+};
+
+constexpr DhSeries dh_series() {
+  DhSeries r{};
+  double f = 2.0;  // (k+1)!
+  for (int k = 1; k <= 18; ++k) {
+    r.c[k - 1] = (double)k / f;
+    f *= (double)(k + 2);
+  }
+  return r;
+}
+
 __device__ __forceinline__ double dh_dt(double t) {
   if (t < 0.5) {
-    double p = 0.5, s = 0.0;  // p = t^{k-1} / (k+1)!
-    for (int k = 1; k <= 18; ++k) {
-      s += (double)k * p;
-      p *= t / (double)(k + 2);
-    }
+    constexpr DhSeries S = dh_series();
+    double s = S.c[17];
+#pragma unroll
+    for (int k = 16; k >= 0; --k) s = s * t + S.c[k];
     return s;
   }
   return ((t - 1.0) * expm1(t) + t) / (t * t);
@@ -597,19 +607,16 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   for (int g = 0; g < a.G; ++g) {
     const int64_t cg = ci * a.G + g;
     const double kap = (double)a.kappa[cg];
-    double den = ap + kap * V, r = 1.0;
-    if (a.law == SWEEP_LAW_EXP) {
-      const ExpTask e = exp_task(ap, kap * V);
-      den = e.den;
-      r = e.r;
-    }
+    const bool exp_law = a.law == SWEEP_LAW_EXP;
+    const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
     double s;
     if (a.emission != nullptr) {
       s = (double)a.emission[cg];
       if (a.jsum_prev != nullptr) s += (double)a.albedo * kap * V * (double)a.jsum_prev[cg];
       s *= (double)a.inv_D;
     } else {
-      s = (double)a.gsrc[cg] * r;
+      s = (double)a.gsrc[cg];
+      if (exp_law) s *= exp_r(ap, kap * V);
     }
     a.cds[t * a.G + g] = make_float2((float)den, (float)s);
   }
@@ -665,7 +672,7 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(ReduceArgs a) {
         const float2 b = a.bnd[t];
         esc += (double)b.x * ph;
         pout += (double)b.y * ph;
-        js += exp_law ? ph * exp_task((double)a.aperp[t], kap * V).r : ph;
+        js += exp_law ? ph * exp_r((double)a.aperp[t], kap * V) : ph;
       }
     }
     if (a.pin_sum != nullptr) a.pin_sum[cg] = pn;
@@ -772,15 +779,18 @@ __global__ void k_adj_reduce(AdjReduceArgs a, double* dk, double* de) {
       const int mid = (lo + hi + 1) >> 1;
       if (a.mesh_off[mid] <= c) lo = mid; else hi = mid - 1;
     }
-    const int lc = c - a.mesh_off[lo];
+    // tasks of mesh m: [direction][local cell] from D * (first cell of m)
+    const int64_t Cm = a.mesh_off[lo + 1] - a.mesh_off[lo];
+    const float* apc = a.aperp + (int64_t)a.D * a.mesh_off[lo] + (c - a.mesh_off[lo]);
     const double kap = (double)a.kappa[i];
     const double kV = kap * V;
     const double g = (double)a.gsrc[i];
     dks = 0.0;
+#pragma unroll 4
     for (int d = 0; d < a.D; ++d) {
       const double l = (double)a.lam[d * n + i];
       const double x = (double)a.phi[d * n + i];
-      const double ap = (double)a.aperp[a.units[lo * a.D + d].task_base + lc];
+      const double ap = (double)apc[d * Cm];
       const double tau = kV / ap;
       double dden, dr;
       if (tau < kTauCap) {

@@ -195,6 +195,29 @@ def lattice_workload(n: int, dirs: np.ndarray, kappa: float, src_cells, lum, per
     return w
 
 
+KPC_CM = 3.0856775814913673e21
+
+
+def hii_rtype(n_side: int = 32, D: int = 84) -> dict:
+    """R-type HII region (sec. 3.1.1): an n_side^3 lattice of a cube of side
+    12.8 kpc, uniform neutral hydrogen n_H = 1e-3 cm^-3, one source of 1e49
+    ionising photons/s in the central cell (emission in units of that rate),
+    sigma_H = 5.38e-18 cm^2 and alpha_B = 2.59e-13 cm^3/s (tests section).
+    kappa is the fully neutral extinction per mesh length unit; `hii` holds the
+    parameters of the time stepping (step cap and end time in recombination
+    times, the step-limit factor)."""
+    c = n_side // 2
+    hii = dict(n_H=1e-3, sigma_H=5.38e-18, alpha_B=2.59e-13, photon_rate=1e49,
+               length_unit=12.8 * KPC_CM, dt_max_trec=0.05, t_end_trec=1.5, courant=1.0)
+    w = lattice_workload(n_side, direction_set(D), hii["n_H"] * hii["sigma_H"] * hii["length_unit"],
+                         [c + n_side * (c + n_side * c)], [1.0])
+    w["name"] = "hii_rtype"
+    w["law"] = "exp"
+    w["hii"] = hii
+    w["source_pos"] = np.full(3, (c + 0.5) / n_side)
+    return w
+
+
 def small_random(n_cells: int, D: int, G: int = 1, seed: int = 0, periodic: bool = False,
                  n_src: int = 3, tau: float = 3.0, sigma: float = 1.0, n_meshes: int = 1,
                  **opts) -> dict:

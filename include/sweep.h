@@ -216,6 +216,39 @@ sweep_status_t sweep_tune(sweep_dag_t dag, int32_t G, const float* kappa, const 
                           const sweep_fwd_opts_t* opts, int32_t reps, sweep_fwd_opts_t* best,
                           double* best_ms, void* stream);
 
+/* Hydrogen photoionisation chemistry for time-dependent runs such as the R-type
+ * expansion of an HII region (sec. 3.1.1): one frequency bin, constant cross
+ * section and case B recombination coefficient (tests section), uniform n_H. */
+typedef struct {
+  double n_H;         /* hydrogen number density (cm^-3) */
+  double sigma_H;     /* photoionisation cross section (cm^2) */
+  double alpha_B;     /* case B recombination coefficient (cm^3 s^-1) */
+  double photon_rate; /* photons/s per unit of the emission (and absorbed) arrays */
+  double length_unit; /* cm per mesh length unit (volumes scale with its cube) */
+  double dt_max;      /* largest step (s) */
+  double courant;     /* step-limit factor f in (0, 1] */
+  double reserved[5];
+} sweep_ion_params_t;
+
+/* One chemistry step after a forward sweep with G = 1 (use SWEEP_LAW_EXP and
+ * kappa = n_H y sigma_H length_unit, which this call writes for the next sweep):
+ *   absorbed: DEVICE [C_total] FP32, the `absorbed` output of sweep_forward
+ *             (photons/s in units of photon_rate; albedo 0)
+ *   neutral:  DEVICE [C_total] FP64 neutral fraction y in [0, 1], updated in place
+ *   kappa:    DEVICE [C_total] FP32 output, n_H y' sigma_H length_unit
+ *   t_left:   the step is at most t_left seconds
+ *   dt:       HOST output, the step taken (s)
+ * With u = 1 - y, V the cell volume in cm^3 and P = photon_rate * absorbed:
+ *   dt = min(dt_max, t_left, courant * min_c n_H V y / (P - alpha_B n_H^2 u^2 V))
+ * over the cells with a positive denominator, so no cell gains more ionised
+ * atoms than it has neutral ones; then every absorbed photon ionises one atom
+ * and recombination is implicit:
+ *   n_H V (u' - u) = P dt - alpha_B n_H^2 u'^2 V dt   (photon conserving).
+ * Synchronises `stream` once (to read the step).  Errors: INVALID_ARG, HIP. */
+sweep_status_t sweep_ion_step(sweep_dag_t dag, const float* absorbed, const sweep_ion_params_t* p,
+                              double t_left, double* neutral, float* kappa, double* dt,
+                              void* stream);
+
 /* Kernel timing with HIP events (for measurement tools).  While enabled, every
  * launch of the library's main kernels is bracketed by two hipEvents recorded
  * on the launch stream.  Kernel names: "count", "kahn", "fill", "prep",

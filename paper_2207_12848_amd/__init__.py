@@ -20,12 +20,13 @@ from . import _binding as B
 from ._binding import (SweepError, SweepLibraryError, sweep_adjoint, sweep_build_dag,  # noqa: F401
                        sweep_dag_export, sweep_dag_info, sweep_destroy_dag, sweep_forward,
                        sweep_last_error, sweep_profile_enable, sweep_profile_read,
-                       sweep_profile_reset, sweep_saved_bytes, sweep_tune)
+                       sweep_ion_step, sweep_profile_reset, sweep_saved_bytes, sweep_tune)
 
 TOTAL_NAMES = ("emitted", "absorbed", "escaped", "pbc_in", "pbc_out", "scat_net", "pbc_err_max",
                "pbc_err_l1")
 
-__all__ = ["Dag", "build_dag", "forward", "adjoint", "tune", "SweepFunction", "upload_mesh",
+__all__ = ["Dag", "build_dag", "forward", "adjoint", "tune", "ion_step", "evolve_ionisation",
+           "SweepFunction", "upload_mesh",
            "SweepError", "SweepLibraryError", "TOTAL_NAMES"] + list(B.EXPORTED)
 
 
@@ -208,6 +209,49 @@ def tune(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, reps: int = 3, s
     B.check(sweep_tune(dag.handle, G, _ptr(kappa), _ptr(emission), ctypes.byref(o), int(reps),
                        ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
     return {"block": int(best.block), "ring": int(best.ring), "ms": float(ms.value)}
+
+
+def ion_step(dag: Dag, absorbed: torch.Tensor, neutral: torch.Tensor, kappa: torch.Tensor,
+             params: dict, t_left: float, stream=None) -> float:
+    """One photoionisation chemistry step (sweep_ion_step): updates `neutral` (float64
+    CUDA [C]) and writes `kappa` (float32 CUDA [C, 1]) in place; returns the step (s).
+    params: n_H, sigma_H, alpha_B, photon_rate, length_unit, dt_max (s), courant."""
+    C = dag.n_cells
+    if not (neutral.is_cuda and neutral.dtype == torch.float64 and neutral.numel() == C
+            and neutral.is_contiguous()):
+        raise ValueError("neutral must be a contiguous float64 CUDA tensor with %d elements" % C)
+    _check_field(absorbed, C, 1, "absorbed")
+    _check_field(kappa, C, 1, "kappa")
+    p = B.sweep_ion_params_t()
+    for k in ("n_H", "sigma_H", "alpha_B", "photon_rate", "length_unit", "dt_max", "courant"):
+        setattr(p, k, float(params[k]))
+    dt = ctypes.c_double()
+    B.check(sweep_ion_step(dag.handle, _ptr(absorbed), ctypes.byref(p), float(t_left), _ptr(neutral),
+                           _ptr(kappa), ctypes.byref(dt), _stream(stream)))
+    return float(dt.value)
+
+
+def evolve_ionisation(dag: Dag, emission: torch.Tensor, params: dict, t_end: float,
+                      neutral: torch.Tensor = None, record=None, max_steps: int = 10_000_000,
+                      **opts):
+    """Time-step a photoionisation run (sweep under the exponential law, then
+    ion_step) from `neutral` (default: fully neutral) until t_end seconds.
+    Returns (t, neutral, steps); calls record(step, t, neutral, absorbed, dt) after
+    every step when given."""
+    C = dag.n_cells
+    dev = emission.device
+    y = torch.ones(C, dtype=torch.float64, device=dev) if neutral is None else neutral
+    kappa = (y * (params["n_H"] * params["sigma_H"] * params["length_unit"])).float().reshape(C, 1)
+    o = dict(opts, law="exp")
+    t, step = 0.0, 0
+    while t < t_end and step < max_steps:
+        _, A, _ = forward(dag, kappa, emission, **o)
+        dt = ion_step(dag, A, y, kappa, params, t_end - t)
+        t += dt
+        step += 1
+        if record is not None:
+            record(step - 1, t, y, A, dt)
+    return t, y, step
 
 
 KERNELS = ("count", "kahn", "fill", "prep", "sweep_fwd", "sweep_adj", "reduce")

@@ -22,7 +22,8 @@ SWEEP_LAW_UPWIND, SWEEP_LAW_EXP = 0, 1
 
 EXPORTED = ("sweep_last_error", "sweep_build_dag", "sweep_destroy_dag", "sweep_dag_info",
             "sweep_dag_export", "sweep_saved_bytes", "sweep_forward", "sweep_adjoint",
-            "sweep_tune", "sweep_profile_enable", "sweep_profile_reset", "sweep_profile_read")
+            "sweep_tune", "sweep_ion_step", "sweep_profile_enable", "sweep_profile_reset",
+            "sweep_profile_read")
 
 
 class SweepLibraryError(RuntimeError):
@@ -54,6 +55,13 @@ class sweep_dag_info_t(ctypes.Structure):
                 ("n_up_entries", ctypes.c_int64), ("n_down_entries", ctypes.c_int64),
                 ("max_depth", ctypes.c_int32), ("min_depth", ctypes.c_int32),
                 ("mean_depth", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class sweep_ion_params_t(ctypes.Structure):
+    _fields_ = [("n_H", ctypes.c_double), ("sigma_H", ctypes.c_double), ("alpha_B", ctypes.c_double),
+                ("photon_rate", ctypes.c_double), ("length_unit", ctypes.c_double),
+                ("dt_max", ctypes.c_double), ("courant", ctypes.c_double),
+                ("reserved", ctypes.c_double * 5)]
 
 
 class sweep_fwd_opts_t(ctypes.Structure):
@@ -89,6 +97,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sweep_forward": (ctypes.c_int, [P, I32, P, P, P, P, P, P, P, SZ, P]),
         "sweep_adjoint": (ctypes.c_int, [P, I32, P, P, P, P, SZ, P, P, P, P, P]),
         "sweep_tune": (ctypes.c_int, [P, I32, P, P, P, I32, P, P, P]),
+        "sweep_ion_step": (ctypes.c_int, [P, P, P, ctypes.c_double, P, P, P, P]),
         "sweep_profile_enable": (ctypes.c_int, [I32]),
         "sweep_profile_reset": (ctypes.c_int, []),
         "sweep_profile_read": (ctypes.c_int, [ctypes.c_char_p, P, P]),
@@ -145,6 +154,10 @@ def sweep_adjoint(dag, G, kappa, emission, opts, saved, saved_bytes, dL_dJ, dL_d
 
 def sweep_tune(dag, G, kappa, emission, opts, reps, best, best_ms, stream) -> int:
     return load().sweep_tune(dag, G, kappa, emission, opts, reps, best, best_ms, stream)
+
+
+def sweep_ion_step(dag, absorbed, params, t_left, neutral, kappa, dt, stream) -> int:
+    return load().sweep_ion_step(dag, absorbed, params, t_left, neutral, kappa, dt, stream)
 
 
 def sweep_profile_enable(on: int) -> int:

@@ -24,6 +24,7 @@ SOURCES = [
     # classifies faces exactly as written; the sweep rounds every product and sum)
     ("dag.hip", DEVICE + ["-ffp-contract=off"]),
     ("sweep.hip", DEVICE + ["-ffp-contract=off"]),
+    ("chem.hip", DEVICE + ["-ffp-contract=off"]),
     ("api.cpp", []),
 ]
 

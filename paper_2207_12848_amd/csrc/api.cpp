@@ -251,7 +251,7 @@ struct sweep_dag_s {
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
   Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, cds,
-      out_s;
+      out_s, ion_min;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
   struct GraphEntry {
     std::vector<uint64_t> key;
@@ -1275,6 +1275,46 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   best->block = bp.block;
   best->ring = bp.ring;
   *best_ms = best_t;
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_ion_params_t* p,
+                              double t_left, double* neutral, float* kappa, double* dt,
+                              void* stream) {
+  g_err.clear();
+  ST_TRY(check_common(d, 1));
+  if (!absorbed || !p || !neutral || !kappa || !dt)
+    return fail(SWEEP_ERR_INVALID_ARG, "missing argument");
+  if (!(p->n_H > 0.0) || !(p->sigma_H > 0.0) || !(p->alpha_B > 0.0) || !(p->photon_rate > 0.0) ||
+      !(p->length_unit > 0.0) || !(p->dt_max > 0.0) || !(t_left > 0.0))
+    return fail(SWEEP_ERR_INVALID_ARG, "n_H, sigma_H, alpha_B, photon_rate, length_unit, dt_max "
+                                       "and t_left must be positive");
+  if (!(p->courant > 0.0) || !(p->courant <= 1.0))
+    return fail(SWEEP_ERR_INVALID_ARG, "courant must be in (0, 1]");
+  hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
+  HIP_TRY(d->ion_min.alloc(8));
+  sweep::IonArgs a{};
+  a.n = d->C_total;
+  a.vol = d->vol.as<float>();
+  a.absorbed = absorbed;
+  a.neutral = neutral;
+  a.kappa = kappa;
+  a.n_H = p->n_H;
+  a.sigma_H = p->sigma_H;
+  a.alpha_B = p->alpha_B;
+  a.photon_rate = p->photon_rate;
+  a.length_unit = p->length_unit;
+  a.l3 = p->length_unit * p->length_unit * p->length_unit;
+  HIP_TRY(sweep::launch_ion_limit(a, d->ion_min.as<unsigned long long>(), s));
+  uint64_t bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, d->ion_min.p, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double lim;
+  std::memcpy(&lim, &bits, 8);
+  const double step = std::min(std::min(p->dt_max, t_left), p->courant * lim);
+  HIP_TRY(sweep::launch_ion_update(a, step, s));
+  *dt = step;
   return SWEEP_OK;
 }
 

@@ -179,7 +179,20 @@ struct AdjReduceArgs {
   float* gsrc_next;        // adjoint source of the previous iteration
 };
 
-// launchers (kernels in dag.hip / sweep.hip)
+// Photoionisation chemistry step (chem.hip).
+struct IonArgs {
+  int64_t n;               // cells
+  const float* vol;        // [n] mesh units
+  const float* absorbed;   // [n] photons/s in units of photon_rate
+  double* neutral;         // [n] neutral fraction y
+  float* kappa;            // [n] out: n_H y sigma_H length_unit
+  double n_H, sigma_H, alpha_B, photon_rate, length_unit;
+  double l3;               // length_unit^3
+};
+
+// launchers (kernels in dag.hip / sweep.hip / chem.hip)
+hipError_t launch_ion_limit(const IonArgs& a, unsigned long long* out, hipStream_t s);
+hipError_t launch_ion_update(const IonArgs& a, double dt, hipStream_t s);
 constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build kernels
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s);
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);

@@ -36,7 +36,7 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 WORKLOADS = ("c1_plain_small", "c2_plain_scale", "c3_batched_groups", "c4_differentiation",
-             "c5_uneven_scatter")
+             "c5_uneven_scatter", "hii_rtype")
 # kernels whose counters a PMC summary under profiles/ may cover, and their source
 KERNEL_SOURCE = {"count": "dag.hip", "kahn": "dag.hip", "fill": "dag.hip", "prep": "sweep.hip",
                  "sweep_fwd": "sweep.hip", "sweep_adj": "sweep.hip", "reduce": "sweep.hip"}
@@ -197,6 +197,78 @@ def copy_calibration(nbytes: int, reps: int) -> None:
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}))
 
 
+# ------------------------------------------------------------------ photoionisation workload
+def hii_bench(args) -> int:
+    """R-type HII region (hii_rtype lattice, 84 directions): one step is one time step,
+    a forward sweep under the exponential law plus one chemistry step on the graphs
+    built once.  Timed from the state after `warmup` steps of a neutral start."""
+    import torch
+
+    import paper_2207_12848_amd as sw
+    from synth import workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.hii_rtype(args.hii_side, 84)
+    p = dict(w["hii"])
+    trec = 1.0 / (p["alpha_B"] * p["n_H"])
+    p["dt_max"] = p["dt_max_trec"] * trec
+    C = args.hii_side ** 3
+    D = len(w["dirs"])
+    meshes = [sw.upload_mesh(m, dev) for m in w["meshes"]]
+    dag = sw.build_dag(meshes, w["dirs"])
+    info = dag.info()
+    e = torch.as_tensor(w["emission"]).to(dev).contiguous()
+    t_w, y, _ = sw.evolve_ionisation(dag, e, p, 1e30, max_steps=max(args.warmup, 1))
+    torch.cuda.synchronize()
+    sw.profile_reset()
+    sw.profile_enable(True)
+    t0 = time.perf_counter()
+    t_s, y, n = sw.evolve_ionisation(dag, e, p, 1e30, neutral=y, max_steps=args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sw.profile_enable(False)
+    kt = sw.kernel_times()
+    sw.profile_reset()
+    ms = (t1 - t0) * 1e3 / max(n, 1)
+    n_updates = C * D * n
+    sizes = dict(C=C, H=6 * C, T=C * D, Eu=int(info["n_up_entries"]), Ed=int(info["n_down_entries"]),
+                 G=1)
+    per_kernel = {}
+    for k, (cnt, tms) in kt.items():
+        if cnt:
+            b = byte_model(k, sizes)
+            per_kernel[k] = dict(launches=cnt, ms_per_step=round(tms / n, 5),
+                                 avg_launch_ms=round(tms / cnt, 5), alg_bytes_per_launch=b,
+                                 alg_gbs=round(b / (tms / cnt * 1e-3) / 1e9, 2))
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["ms_per_step"])
+    pk = per_kernel[dom]
+    roof = {"bound": "hbm", "achieved": pk["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(pk["alg_gbs"] / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom,
+            "bytes_per_launch": pk["alg_bytes_per_launch"], "avg_launch_ms": pk["avg_launch_ms"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import hii as OH
+        k = 2
+        c0 = time.perf_counter()
+        OH.evolve(w, 1e30, max_steps=k)
+        dt_cpu = time.perf_counter() - c0
+        import oracle
+        cpu = {"value": C * D * k / dt_cpu, "unit": "cell-direction updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": "the first %d time steps of the same run (FP64 sweep + numpy chemistry), "
+                         "%.1f s" % (k, dt_cpu)}
+    line = {"metric": "cell-direction updates/s, photoionisation time steps (sweep + chemistry)",
+            "value": n_updates / ((t1 - t0) if n else float("inf")), "unit": "cell-direction updates/s",
+            "n_gpus": 1, "steps": n, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "hii_rtype", "cells": C, "directions": D, "groups": 1,
+                       "law": "exp", "boundary": "vacuum", "simulated_time_trec": round(t_s / trec, 5)},
+            "roofline": roof, "cpu_baseline": cpu, "kernels": per_kernel}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 # ------------------------------------------------------------------ main
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
@@ -206,6 +278,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c2_plain_scale", choices=WORKLOADS)
     ap.add_argument("--block", type=int, default=0, help="sweep workgroup size (0 = tuned)")
     ap.add_argument("--ring", type=int, default=0, help="LDS ring capacity (0 = tuned)")
+    ap.add_argument("--hii-side", type=int, default=32,
+                    help="lattice side of the hii_rtype workload")
     ap.add_argument("--law", default="upwind", choices=("upwind", "exp"),
                     help="cell law: first-order upwind balance or exponential attenuation")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -224,6 +298,8 @@ def main() -> int:
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, 5)
         return 0
+    if args.workload == "hii_rtype":
+        return hii_bench(args)
 
     import numpy as np
     import torch

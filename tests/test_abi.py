@@ -56,3 +56,33 @@ def test_binding_fails_loudly_without_library(tmp_path):
             B.load(str(tmp_path / "missing.so"))
         finally:
             B._lib = B._lib_saved
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes struct of the binding has the C struct's size and field offsets
+    (a small C program compiled with gcc against include/sweep.h prints them)."""
+    import subprocess
+    from paper_2207_12848_amd import _binding as B
+    structs = [B.sweep_mesh_t, B.sweep_build_opts_t, B.sweep_dag_info_t, B.sweep_fwd_opts_t,
+               B.sweep_ion_params_t]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "sweep.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (n, n))
+        for f in st._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (n, f[0], n, f[0]))
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)]).decode().split("\n"):
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for st in structs:
+        n = st.__name__
+        assert got[(n, "size")] == ctypes.sizeof(st), n
+        for f in st._fields_:
+            assert got[(n, f[0])] == getattr(st, f[0]).offset, (n, f[0])

@@ -63,7 +63,7 @@ def _load():
         lib.orc_forward.restype = ctypes.c_int
         lib.orc_forward.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
-                                    ctypes.c_int32, P, P, P, P, P, P]
+                                    ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P]
         lib.orc_adjoint.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
@@ -134,11 +134,14 @@ def build_dag(mesh: dict, dirs: np.ndarray, eps: float = EPS_TIE):
     return level, order, indeg, depth
 
 
-def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: float = EPS_TIE):
+def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: float = EPS_TIE,
+            phi_init=None):
     """Sweep workload `w` (see synth.workloads; w["law"] is "upwind" (default) or "exp").
     Returns dict with J [C,G], absorbed [C,G], totals [n_meshes,G,8] and, on request, phi
     (list of [D,C,G] per mesh: the exit flux density), jsum_ckpt (list of [n_scat,C,G]) and
-    the FIFO order (list of [D,C])."""
+    the FIFO order (list of [D,C]).  w["merge"]: periodic passes and source iterations
+    advance together (max(n_pbc, n_scat) passes).  phi_init: list of [D,C,G] exit flux
+    densities per mesh whose periodic outflow feeds the first pass (warm start)."""
     lib = _load()
     dirs = _c(w["dirs"], np.float64)
     D, G = len(dirs), int(w["G"])
@@ -148,6 +151,7 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
     periodic = w.get("boundary", "vacuum") == "periodic"
     n_pbc, albedo, n_scat = int(w.get("n_pbc", 1)), float(w.get("albedo", 0.0)), int(w.get("n_scat", 1))
     law = _law(w)
+    merged = int(bool(w.get("merge", False)))
     J = np.zeros((off[-1], G))
     Ab = np.zeros((off[-1], G))
     totals = np.zeros((len(w["meshes"]), G, N_TOTALS))
@@ -164,9 +168,10 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
         phi = np.zeros((D, C, G)) if want_phi else None
         ck = np.zeros((n_scat, C, G)) if want_phi else None
         qo = np.zeros((D, C), np.int32) if want_order else None
+        pin = None if phi_init is None else _c(phi_init[mi], np.float64)
         _check(lib.orc_forward(ctypes.byref(s), D, _p(dirs), eps, G, _p(k), _p(e), int(periodic),
-                               n_pbc, albedo, n_scat, law, _p(j), _p(a), _p(t), _p(phi), _p(ck),
-                               _p(qo)),
+                               n_pbc, albedo, n_scat, law, merged, _p(pin), _p(j), _p(a), _p(t),
+                               _p(phi), _p(ck), _p(qo)),
                "forward")
         J[sl], Ab[sl], totals[mi] = j, a, t
         phis.append(phi)

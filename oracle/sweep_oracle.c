@@ -285,14 +285,18 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
  *   kappa, emission, J, absorbed: [C][G]
  *   totals: [G][8]
  *   law: LAW_UPWIND or LAW_EXP
+ *   merged: 1 = periodic passes and source iterations advance together (see below)
+ *   phi_init: [D][C][G] exit flux densities whose periodic outflow feeds the first
+ *             pass (a warm start from an earlier solution), or NULL (zero inflow)
  *   phi_out: [D][C][G] exit flux density of the final pass (may be NULL)
  *   jsum_ckpt: [n_scat][C][G] sum_d of the cell averages of every iteration's
  *              final pass (may be NULL)
  *   qorder: [D][C] FIFO processing order of every direction (may be NULL) */
 int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
-                double albedo, int32_t n_scat, int32_t law, double* J, double* absorbed,
-                double* totals, double* phi_out, double* jsum_ckpt, int32_t* qorder) {
+                double albedo, int32_t n_scat, int32_t law, int32_t merged,
+                const double* phi_init, double* J, double* absorbed, double* totals,
+                double* phi_out, double* jsum_ckpt, int32_t* qorder) {
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
   if (D < 1 || G < 1 || n_pbc < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
@@ -310,16 +314,28 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   if (!phi || !avg || !phiprev || !jsum || !jsum_old || !src || !jin || !jin_old || !accd)
     return ORC_ERR_OOM;
   int status = ORC_OK;
-  for (int32_t it = 0; it < n_scat && status == ORC_OK; ++it) {
-    /* source of this iteration */
-    for (int32_t c = 0; c < C; ++c)
-      for (int32_t g = 0; g < G; ++g) {
-        const int64_t i = (int64_t)c * G + g;
-        const double ks = albedo * kappa[i];
-        src[i] = emission[i] / D + ks * m->cell_volume[c] * jsum_old[i] / D;
-      }
-    memset(phiprev, 0, sizeof(double) * (size_t)(D * CG));
-    for (int32_t p = 0; p < n_pbc && status == ORC_OK; ++p) {
+  /* merged: one sequence of max(n_pbc, n_scat) passes, each taking its scattering
+   * source from the previous pass's direction sums and its periodic inflow from
+   * the previous pass (only differs from the nested order with periodic
+   * boundaries and several source iterations) */
+  const int32_t merge = merged && periodic && n_scat > 1;
+  const int32_t n_outer = merge ? 1 : n_scat;
+  const int32_t n_inner = merge ? (n_pbc > n_scat ? n_pbc : n_scat) : n_pbc;
+  const int32_t warm = periodic && phi_init != NULL;
+  for (int32_t it = 0; it < n_outer && status == ORC_OK; ++it) {
+    if (warm && it == 0)
+      memcpy(phiprev, phi_init, sizeof(double) * (size_t)(D * CG));
+    else
+      memset(phiprev, 0, sizeof(double) * (size_t)(D * CG));
+    for (int32_t p = 0; p < n_inner && status == ORC_OK; ++p) {
+      /* source of this iteration (nested: once per iteration; merged: every pass) */
+      if (p == 0 || merge)
+        for (int32_t c = 0; c < C; ++c)
+          for (int32_t g = 0; g < G; ++g) {
+            const int64_t i = (int64_t)c * G + g;
+            const double ks = albedo * kappa[i];
+            src[i] = emission[i] / D + ks * m->cell_volume[c] * jsum_old[i] / D;
+          }
       /* keep the previous pass's per-cell periodic inflow for E */
       if (p > 0) {
         for (int64_t i = 0; i < CG; ++i) {
@@ -335,7 +351,9 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
         int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
         int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src,
-                                 (periodic && p > 0) ? phiprev + (int64_t)d * CG : NULL,
+                                 (periodic && (p > 0 || (warm && it == 0)))
+                                     ? phiprev + (int64_t)d * CG
+                                     : NULL,
                                  phi + (int64_t)d * CG, avg + (int64_t)d * CG,
                                  accd + (int64_t)d * 4 * G,
                                  jin + (int64_t)d * CG, cnt, q, NULL,
@@ -348,17 +366,22 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         free(q);
       }
       if (status != ORC_OK) break;
-      if (p + 1 < n_pbc) memcpy(phiprev, phi, sizeof(double) * (size_t)(D * CG));
+      if (p + 1 < n_inner) memcpy(phiprev, phi, sizeof(double) * (size_t)(D * CG));
+      if (merge || p + 1 == n_inner) {
+        /* direction sum of the cell averages in ascending d */
+        for (int64_t i = 0; i < CG; ++i) {
+          double s = 0.0;
+          for (int32_t d = 0; d < D; ++d) s += avg[(int64_t)d * CG + i];
+          jsum[i] = s;
+        }
+      }
+      if (merge && p + 1 < n_inner) memcpy(jsum_old, jsum, sizeof(double) * (size_t)CG);
     }
     if (status != ORC_OK) break;
-    /* direction sum of the cell averages in ascending d */
-    for (int64_t i = 0; i < CG; ++i) {
-      double s = 0.0;
-      for (int32_t d = 0; d < D; ++d) s += avg[(int64_t)d * CG + i];
-      jsum[i] = s;
-    }
-    if (jsum_ckpt) memcpy(jsum_ckpt + (int64_t)it * CG, jsum, sizeof(double) * (size_t)CG);
-    if (it + 1 < n_scat) memcpy(jsum_old, jsum, sizeof(double) * (size_t)CG);
+    /* merged: the sums of the final pass go to the last checkpoint */
+    const int32_t slot = merge ? n_scat - 1 : it;
+    if (jsum_ckpt) memcpy(jsum_ckpt + (int64_t)slot * CG, jsum, sizeof(double) * (size_t)CG);
+    if (!merge && it + 1 < n_scat) memcpy(jsum_old, jsum, sizeof(double) * (size_t)CG);
   }
   if (status == ORC_OK) {
     for (int32_t g = 0; g < G; ++g)
@@ -379,7 +402,7 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         double jn = 0.0;
         for (int32_t d = 0; d < D; ++d) jn += jin[(int64_t)d * CG + i];
         const double jo = jin_old[i];
-        if (periodic && n_pbc > 1 && jn + jo > 0.0) {
+        if (periodic && n_inner > 1 && jn + jo > 0.0) {
           const double e = fabs(jn - jo) / (jn + jo);
           if (e > totals[8 * g + 6]) totals[8 * g + 6] = e;
         }
@@ -389,7 +412,7 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
     for (int32_t g = 0; g < G; ++g) {
       double den = 0.0;
       for (int32_t c = 0; c < C; ++c) den += jin_old[(int64_t)c * G + g];
-      totals[8 * g + 7] = (periodic && n_pbc > 1 && den > 0.0) ? totals[8 * g + 7] / den : 0.0;
+      totals[8 * g + 7] = (periodic && n_inner > 1 && den > 0.0) ? totals[8 * g + 7] / den : 0.0;
       for (int32_t d = 0; d < D; ++d) {
         totals[8 * g + 2] += accd[(int64_t)d * 4 * G + 4 * g + 0];
         totals[8 * g + 3] += accd[(int64_t)d * 4 * G + 4 * g + 1];
@@ -522,8 +545,8 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   if (!J || !Ab || !tots || !jsum || !phi || !avg || !lam || !dkd || !gsrc || !src || !lsum ||
       !qorder)
     return ORC_ERR_OOM;
-  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, law, J, Ab,
-                           tots, NULL, jsum, NULL);
+  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, law, 0,
+                           NULL, J, Ab, tots, NULL, jsum, NULL);
   if (status == ORC_OK) {
     memset(dkappa, 0, sizeof(double) * (size_t)CG);
     memset(demission, 0, sizeof(double) * (size_t)CG);

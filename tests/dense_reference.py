@@ -96,11 +96,12 @@ def dense_forward(w, cyclic=False):
     return dict(J=np.concatenate(Js), absorbed=np.concatenate(As), totals=np.stack(tots), phi=phis)
 
 
-def dense_scatter_system(w):
+def dense_scatter_system(w, cyclic=False):
     """Fixed point of source iteration: all D directions solved together for one mesh, one group.
 
     Unknowns x[d,c]; equations M_d x_d - (a kappa V / D) sum_d' r_d' x_d' = L / D; returns
-    the cell averages r_d x_d."""
+    the cell averages r_d x_d.  cyclic=True couples the periodic faces as well (the
+    fixed point of periodic passes and source iteration together)."""
     (mesh,) = w["meshes"]
     dirs = w["dirs"]
     D = len(dirs)
@@ -113,7 +114,7 @@ def dense_scatter_system(w):
     big = np.zeros((D * C, D * C))
     rs = []
     for d in range(D):
-        M, _, _, r = direction_matrix(mesh, dirs[d], k, law=law)
+        M, _, _, r = direction_matrix(mesh, dirs[d], k, cyclic=cyclic, law=law)
         rs.append(r)
         big[d * C:(d + 1) * C, d * C:(d + 1) * C] += M
     for d in range(D):

@@ -133,7 +133,17 @@ typedef struct {
                         DAG, at most 8), later calls replay it on `stream` */
   int32_t law;       /* SWEEP_LAW_UPWIND (first-order upwind balance, default) or
                         SWEEP_LAW_EXP (exponential attenuation, see above) */
-  int32_t reserved[4];
+  int32_t merge;     /* 1: with periodic boundaries and n_scat > 1, run the combined
+                        scheme of sec. 2.7: max(n_pbc, n_scat) passes, each taking its
+                        scattering source from the previous pass's direction sums and
+                        its periodic inflow from the previous pass; 0: n_scat source
+                        iterations of n_pbc passes each (every iteration's first pass
+                        from zero inflow) */
+  int32_t warm_start; /* 1 (periodic only): the first pass takes its periodic inflow
+                        from the phi that `saved` holds (the final pass of an earlier
+                        call with this DAG and G) instead of zero (sec. 2.7's warm start);
+                        requires `saved` */
+  int32_t reserved[2];
 } sweep_fwd_opts_t;
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -53,7 +53,7 @@ def upload_mesh(mesh: dict, device="cuda") -> dict:
 
 
 def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
-              use_graph=False, law="upwind") -> B.sweep_fwd_opts_t:
+              use_graph=False, law="upwind", merge=False, warm_start=False) -> B.sweep_fwd_opts_t:
     o = B.sweep_fwd_opts_t()
     o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
     o.n_pbc = int(n_pbc)
@@ -64,6 +64,8 @@ def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", 
     o.ring = int(ring)
     o.use_graph = int(bool(use_graph))
     o.law = {"upwind": B.SWEEP_LAW_UPWIND, "exp": B.SWEEP_LAW_EXP}[law]
+    o.merge = int(bool(merge))
+    o.warm_start = int(bool(warm_start))
     return o
 
 
@@ -155,9 +157,11 @@ def _check_field(t, C, G, name):
 
 
 def forward(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, save_for_adjoint: bool = False,
-            stream=None, **opts):
+            stream=None, saved: torch.Tensor = None, **opts):
     """Forward sweep.  kappa/emission: float32 CUDA [C_total, G].  Returns
-    (J [C,G], absorbed [C,G], totals [n_meshes, G, 8] float64[, saved workspace])."""
+    (J [C,G], absorbed [C,G], totals [n_meshes, G, 8] float64[, saved workspace]).
+    `saved`: an existing workspace to fill (and, with warm_start=True, to take the
+    first pass's periodic inflow from); it is returned as the fourth element."""
     C = dag.n_cells
     G = kappa.numel() // max(C, 1)
     _check_field(kappa, C, G, "kappa")
@@ -167,9 +171,11 @@ def forward(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, save_for_adjo
     A = torch.empty_like(J)
     tot = torch.empty((len(dag.mesh_cells), G, B.SWEEP_N_TOTALS), dtype=torch.float64,
                       device=kappa.device)
-    saved = None
     nbytes = 0
-    if save_for_adjoint:
+    if saved is not None:
+        nbytes = saved.numel() * saved.element_size()
+        save_for_adjoint = True
+    elif save_for_adjoint:
         nbytes = int(sweep_saved_bytes(dag.handle, G, ctypes.byref(o)))
         saved = torch.empty(nbytes // 4, dtype=torch.float32, device=kappa.device)
     B.check(sweep_forward(dag.handle, G, _ptr(kappa), _ptr(emission), ctypes.byref(o), _ptr(J),

@@ -250,8 +250,8 @@ struct sweep_dag_s {
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
-  Buf phi_a, phi_b, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, cds,
-      out_s, ion_min;
+  Buf phi_a, phi_b, phi_w, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
+      tsrc, cds, out_s, ion_min;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
   struct GraphEntry {
     std::vector<uint64_t> key;
@@ -367,7 +367,7 @@ sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
 }
 
 struct FwdPlan {
-  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law;
+  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm;
   float albedo;
 };
 
@@ -381,6 +381,8 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   p->ring = o ? o->ring : 0;
   p->use_graph = o ? o->use_graph : 0;
   p->law = o ? o->law : SWEEP_LAW_UPWIND;
+  p->merge = o ? (o->merge != 0) : 0;
+  p->warm = o ? (o->warm_start != 0) : 0;
   if (p->law != SWEEP_LAW_UPWIND && p->law != SWEEP_LAW_EXP)
     return fail(SWEEP_ERR_INVALID_ARG, "unknown cell law %d", p->law);
   if (p->boundary != SWEEP_BOUNDARY_VACUUM && p->boundary != SWEEP_BOUNDARY_PERIODIC)
@@ -564,7 +566,8 @@ void opts_key(std::vector<uint64_t>& k, const FwdPlan& p) {
   uint32_t ab;
   std::memcpy(&ab, &p.albedo, 4);
   k.insert(k.end(), {(uint64_t)p.boundary, (uint64_t)p.n_pbc, (uint64_t)p.n_scat, (uint64_t)p.form,
-                     (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab, (uint64_t)p.law});
+                     (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab, (uint64_t)p.law,
+                     (uint64_t)p.merge, (uint64_t)p.warm});
 }
 
 sweep_status_t check_common(sweep_dag_t d, int32_t G) {
@@ -1031,18 +1034,28 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   const size_t need = sweep_saved_bytes(d, G, opts);
   if (saved && saved_bytes < need)
     return fail(SWEEP_ERR_INVALID_ARG, "saved workspace has %zu bytes, %zu needed", saved_bytes, need);
+  // merged: periodic passes and source iterations advance together, max(n_pbc, n_scat)
+  // passes, each taking its scattering source and its periodic inflow from the one
+  // before (the same as the nested order unless both are iterated)
+  const bool merge = p.merge && periodic && p.n_scat > 1;
+  const int n_outer = merge ? 1 : p.n_scat;
+  const int n_inner = merge ? std::max(p.n_pbc, p.n_scat) : p.n_pbc;
+  const bool warm = p.warm && periodic;
+  if (warm && !saved)
+    return fail(SWEEP_ERR_INVALID_ARG, "warm_start takes the periodic inflow from `saved`, which is NULL");
   hipStream_t s = (hipStream_t)stream;
   StreamScope stream_scope(s);
   const int64_t CG = d->C_total * G;
   const int64_t DCG = CG * d->D;
   ST_TRY(ensure_reduce_tables(d, G));
   if (!saved) HIP_TRY(d->phi_a.alloc(4 * DCG));
-  if (periodic && p.n_pbc > 1) HIP_TRY(d->phi_b.alloc(4 * DCG));
+  if (periodic && n_inner > 1) HIP_TRY(d->phi_b.alloc(4 * DCG));
+  if (warm) HIP_TRY(d->phi_w.alloc(4 * DCG));
   if (periodic) {
     HIP_TRY(d->pin.alloc(4 * DCG));
     HIP_TRY(d->pin_prev.alloc(8 * CG));
   }
-  if (!saved) {
+  if (!saved || merge) {
     HIP_TRY(d->jsum_a.alloc(4 * CG));
     HIP_TRY(d->jsum_b.alloc(4 * CG));
   }
@@ -1051,6 +1064,8 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     if (saved) return (float*)saved + DCG + (int64_t)it * CG;
     return (it % 2 == 0) ? d->jsum_a.as<float>() : d->jsum_b.as<float>();
   };
+  // direction sums of merged pass k (alternating buffers)
+  auto jm = [&](int k) -> float* { return (k % 2 == 0) ? d->jsum_a.as<float>() : d->jsum_b.as<float>(); };
   ST_TRY(ensure_mesh_tables(d));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
@@ -1076,22 +1091,32 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   r.absorbed = absorbed;
   r.partial = d->partial.as<double>();
   r.cells_per_block = d->red_cpb;
-  // source iterations, each made of the periodic passes, then the totals
+  // source iterations, each made of the periodic passes (or the merged sequence),
+  // then the totals
   auto body = [&](hipStream_t st) -> sweep_status_t {
-    for (int it = 0; it < p.n_scat; ++it) {
-      const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
-      float* prev = nullptr;
-      for (int ps = 0; ps < p.n_pbc; ++ps) {
-        float* dst = ((p.n_pbc - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
-        if (ps == 0) ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
+    if (warm)  // the previous call's final phi, before this call overwrites `saved`
+      HIP_TRY(hipMemcpyAsync(d->phi_w.p, saved, 4 * DCG, hipMemcpyDeviceToDevice, st));
+    for (int it = 0; it < n_outer; ++it) {
+      const float* jprev_it = it > 0 ? ckpt(it - 1) : nullptr;
+      float* prev = (warm && it == 0) ? d->phi_w.as<float>() : nullptr;
+      for (int ps = 0; ps < n_inner; ++ps) {
+        float* dst = ((n_inner - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
+        const float* jprev = merge ? (ps > 0 ? jm(ps - 1) : nullptr) : jprev_it;
+        const bool final_pass = ps + 1 == n_inner;
+        if (ps == 0 || merge)
+          ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
         ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, st));
-        if (periodic && ps + 1 < p.n_pbc) {
+        if (!final_pass && (merge || periodic)) {
+          // bookkeeping of a pass before the last: the per-cell periodic inflow (for E)
+          // and, merged, the direction sums that feed the next pass's source
           sweep::ReduceArgs q = r;
           q.phi = dst;
-          q.pin = d->pin.as<float>();
+          q.pin = periodic ? d->pin.as<float>() : nullptr;
           q.pin_prev = nullptr;
-          q.pin_sum = d->pin_prev.as<double>();
-          q.last = 0;
+          q.pin_sum = periodic ? d->pin_prev.as<double>() : nullptr;
+          q.jsum_prev = jprev;
+          q.jsum = merge ? jm(ps) : nullptr;
+          q.last = merge ? 1 : 0;
           HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
         }
         prev = dst;
@@ -1099,13 +1124,18 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
       sweep::ReduceArgs q = r;
       q.phi = phi_final;
       q.pin = periodic ? d->pin.as<float>() : nullptr;
-      q.pin_prev = (periodic && p.n_pbc > 1) ? d->pin_prev.as<double>() : nullptr;
+      q.pin_prev = (periodic && n_inner > 1) ? d->pin_prev.as<double>() : nullptr;
       q.pin_sum = nullptr;
-      q.jsum_prev = jprev;
-      q.jsum = ckpt(it);
+      q.jsum_prev = merge ? (n_inner > 1 ? jm(n_inner - 2) : nullptr) : jprev_it;
+      q.jsum = merge ? jm(n_inner - 1) : ckpt(it);
       q.last = 1;
-      ProfScope ps("reduce", st);
-      HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
+      {
+        ProfScope ps("reduce", st);
+        HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
+      }
+      // merged: the final pass's sums are the last iteration's checkpoint
+      if (merge && saved)
+        HIP_TRY(hipMemcpyAsync(ckpt(p.n_scat - 1), jm(n_inner - 1), 4 * CG, hipMemcpyDeviceToDevice, st));
     }
     HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
                                  d->n_meshes, G, totals, st));
@@ -1115,8 +1145,8 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
                                pkey(totals), pkey(saved), (uint64_t)saved_bytes};
   opts_key(key, p);
-  for (const Buf* b : {&d->phi_a, &d->phi_b, &d->pin, &d->pin_prev, &d->jsum_a, &d->jsum_b,
-                       &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
+  for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->jsum_a,
+                       &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
                        &d->mesh_blk_base})
     key.push_back(pkey(b->p));
   return run_graph(d, key, s, body);

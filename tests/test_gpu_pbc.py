@@ -1,0 +1,74 @@
+"""GPU parity of the merged periodic/scattering iterations and the warm-started
+periodic inflow (sec. 2.7) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from synth import workloads as W  # noqa: E402
+from tests.test_gpu_parity import _dev, _opts, _sw, assert_field_close, check_forward  # noqa: E402
+
+
+@pytest.mark.parametrize("law,n_pbc,n_scat", [("upwind", 3, 5), ("exp", 6, 2), ("upwind", 4, 4)])
+def test_merged_iterations_match_oracle(law, n_pbc, n_scat):
+    w = W.small_random(2500, 24, G=2, seed=90 + n_pbc, periodic=True, n_pbc=n_pbc, albedo=0.5,
+                       n_scat=n_scat, n_src=5)
+    w = dict(w, law=law, merge=True)
+    dag, J, A, tot, ref = check_forward(w, merge=True)
+    assert np.allclose(tot[..., 6], ref["totals"][..., 6], rtol=1e-4, atol=1e-6)
+    assert np.allclose(tot[..., 5], ref["totals"][..., 5], rtol=1e-4, atol=1e-8 * tot[..., 0].max())
+
+
+def test_merged_equals_nested_without_scattering():
+    sw = _sw()
+    w = W.small_random(1500, 8, G=1, seed=95, periodic=True, n_pbc=4)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    a = sw.forward(dag, k, e, **_opts(w))
+    b = sw.forward(dag, k, e, merge=True, **_opts(w))
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_warm_start_matches_oracle_and_continues_the_passes():
+    sw = _sw()
+    w = W.small_random(3000, 24, G=2, seed=96, periodic=True, n_src=6, tau=2.0)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    _, _, _, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic", n_pbc=3)
+    J, A, tot, _ = sw.forward(dag, k, e, saved=saved, boundary="periodic", n_pbc=4, warm_start=True)
+    torch.cuda.synchronize()
+    ra = oracle.forward(dict(w, n_pbc=3), want_phi=True)
+    rb = oracle.forward(dict(w, n_pbc=4), phi_init=ra["phi"])
+    assert_field_close(J.cpu().numpy(), rb["J"], name="J warm")
+    assert_field_close(A.cpu().numpy(), rb["absorbed"], name="absorbed warm")
+    # 3 passes then 4 warm-started passes = 7 passes from zero inflow
+    J7, _, _ = sw.forward(dag, k, e, boundary="periodic", n_pbc=7)
+    assert_field_close(J.cpu().numpy(), J7.cpu().numpy().astype(np.float64), name="J 3+4 vs 7")
+
+
+def test_warm_start_needs_saved():
+    sw = _sw()
+    w = W.small_random(500, 8, G=1, seed=97, periodic=True)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    with pytest.raises(sw.SweepError, match="INVALID_ARG"):
+        sw.forward(dag, k, e, boundary="periodic", warm_start=True)
+
+
+def test_merged_graph_replays_match_eager():
+    sw = _sw()
+    w = W.small_random(2000, 24, G=1, seed=98, periodic=True, n_pbc=3, albedo=0.4, n_scat=4)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    J0, A0, t0 = sw.forward(dag, k, e, merge=True, **_opts(w))
+    J = torch.empty_like(J0)
+    for _ in range(3):
+        Jg, Ag, tg = sw.forward(dag, k, e, merge=True, use_graph=True, **_opts(w))
+        torch.cuda.synchronize()
+        assert torch.equal(Jg, J0) and torch.equal(Ag, A0) and torch.equal(tg, t0)
+        J.copy_(Jg)

@@ -20,6 +20,9 @@ namespace sweep {
 namespace {
 
 constexpr int kCountBlock = 256;
+// k_count: 512 threads (16 directions of a 32-cell tile at a time) so that two
+// workgroups with their face tiles and staged rows keep 16 wavefronts per CU
+constexpr int kCountThreads = 512;
 constexpr int kTileCells = 32;  // cells per tile of the cell-order kernels
 constexpr int kKahnBlock = 576;  // 8 worker wavefronts and one that stores the schedule
 
@@ -119,7 +122,7 @@ __device__ __forceinline__ FaceTile stage_tile(const MeshDev& M, int c0, unsigne
 // are assembled in LDS and written out as contiguous blocks (STAGE), or
 // written straight to global memory.
 template <bool STAGE>
-__global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
+__global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_max[2];
   __shared__ unsigned long long s_ent[2];
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
   __syncthreads();
   const int ci = threadIdx.x % kTileCells;
   const int dj = threadIdx.x / kTileCells;
-  constexpr int kDirs = kCountBlock / kTileCells;
+  constexpr int kDirs = kCountThreads / kTileCells;
   const int c = T.c0 + ci;
   const int nc = T.cend - T.c0;
   const bool cell = c < T.cend;
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(kCountBlock) void k_count(DagBuildArgs a) {
         __syncthreads();
         // the tile's rows of direction d0 + j are nc * W consecutive ints of dnw
         const int per4 = nc * W / 4;
-        for (int i = threadIdx.x; i < kDirs * per4; i += kCountBlock) {
+        for (int i = threadIdx.x; i < kDirs * per4; i += kCountThreads) {
           const int j = i / per4, r = i - j * per4;
           if (d0 + j < a.D) {
             const int64_t tb = a.units[m * a.D + d0 + j].task_base;
@@ -790,14 +793,14 @@ size_t count_lds_bytes(int max_faces, int dn_width) {
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s) {
   if (n_cblocks <= 0) return hipSuccess;
   const size_t tile = tile_lds_bytes();
-  const size_t staged = tile + (size_t)kCountBlock * a.dn_width * 4;
+  const size_t staged = tile + (size_t)kCountThreads * a.dn_width * 4;
   const bool stage = staged <= (size_t)lds_limit - 64;
   const size_t lds = stage ? staged : tile;
   const void* fn = stage ? (const void*)k_count<true> : (const void*)k_count<false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (stage) hipLaunchKernelGGL(k_count<true>, dim3(n_cblocks), dim3(kCountBlock), lds, s, a);
-  else hipLaunchKernelGGL(k_count<false>, dim3(n_cblocks), dim3(kCountBlock), lds, s, a);
+  if (stage) hipLaunchKernelGGL(k_count<true>, dim3(n_cblocks), dim3(kCountThreads), lds, s, a);
+  else hipLaunchKernelGGL(k_count<false>, dim3(n_cblocks), dim3(kCountThreads), lds, s, a);
   return hipGetLastError();
 }
 

@@ -68,11 +68,12 @@ __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_unit
 }
 
 // The cell-order kernel stages a tile of kTileCells consecutive cells' faces
-// in LDS with coalesced loads (room for kTileFaces faces per cell on average;
+// in LDS with coalesced loads (room for kTileFaces faces per cell on average,
+// above the ~15.5 of a Voronoi cell and small enough for three workgroups per CU;
 // a tile with more faces is read from global memory instead); the workgroup
 // then covers every direction, 32 consecutive lanes handling the tile's cells
 // for one direction.
-constexpr int kTileFaces = 32;
+constexpr int kTileFaces = 17;
 
 struct FaceTile {
   int c0, cend;       // cells [c0, cend) of mesh m

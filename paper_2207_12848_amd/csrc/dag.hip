@@ -649,7 +649,9 @@ __global__ void k_face_records(MeshDev M, int4* frec) {
 // schedule positions come from the unit's inverse schedule.
 constexpr int kFillBlock = 256;
 
-__global__ __launch_bounds__(kFillBlock) void k_fill(DagBuildArgs a) {
+// Five wavefronts per SIMD: the register budget (at most 102 VGPRs) still
+// compiles without spills; six would spill and run slower.
+__global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_fill(DagBuildArgs a) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int u = unit_of_block(a.blk_base, a.n_units, blk);
   const Unit U = a.units[u];

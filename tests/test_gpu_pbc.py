@@ -66,9 +66,30 @@ def test_merged_graph_replays_match_eager():
     dag = sw.build_dag(w["meshes"], w["dirs"])
     k, e = _dev(w)
     J0, A0, t0 = sw.forward(dag, k, e, merge=True, **_opts(w))
-    J = torch.empty_like(J0)
     for _ in range(3):
         Jg, Ag, tg = sw.forward(dag, k, e, merge=True, use_graph=True, **_opts(w))
         torch.cuda.synchronize()
         assert torch.equal(Jg, J0) and torch.equal(Ag, A0) and torch.equal(tg, t0)
-        J.copy_(Jg)
+
+
+def test_periodic_error_curve_matches_oracle():
+    """E = |j_n - j_{n-1}| / (j_n + j_{n-1}) of the last two passes (eq. relativeErrorPbc),
+    max over cells and L1 form, for 2..8 passes: the GPU's curve follows the oracle's
+    and falls with every pass after the third."""
+    sw = _sw()
+    w = W.small_random(3000, 24, G=2, seed=99, periodic=True, n_src=6, tau=2.0)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    curve = []
+    for n in range(2, 9):
+        _, _, tot = sw.forward(dag, k, e, boundary="periodic", n_pbc=n)
+        g = tot.cpu().numpy()[0]
+        r = oracle.forward(dict(w, n_pbc=n))["totals"][0]
+        assert np.allclose(g[:, 6], r[:, 6], rtol=1e-3, atol=1e-6), n
+        assert np.allclose(g[:, 7], r[:, 7], rtol=1e-4, atol=1e-7), n
+        curve.append(g[:, 7])
+        print("passes %d: E max %s  E L1 %s" % (n, np.array2string(g[:, 6], precision=4),
+                                                np.array2string(g[:, 7], precision=4)))
+    curve = np.array(curve)
+    assert np.all(curve[0] == 1.0)  # the first pass starts from zero inflow
+    assert np.all(np.diff(curve[1:], axis=0) < 0)

@@ -63,7 +63,8 @@ def _load():
         lib.orc_forward.restype = ctypes.c_int
         lib.orc_forward.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
-                                    ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, P, P]
+                                    ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double, P, P, P, P, P,
+                                    P]
         lib.orc_adjoint.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
@@ -140,7 +141,9 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
     Returns dict with J [C,G], absorbed [C,G], totals [n_meshes,G,8] and, on request, phi
     (list of [D,C,G] per mesh: the exit flux density), jsum_ckpt (list of [n_scat,C,G]) and
     the FIFO order (list of [D,C]).  w["merge"]: periodic passes and source iterations
-    advance together (max(n_pbc, n_scat) passes).  phi_init: list of [D,C,G] exit flux
+    advance together (max(n_pbc, n_scat) passes).  w["pbc_tol"]: stop the periodic passes
+    of an iteration once E < pbc_tol everywhere (n_pbc is then the maximum).
+    phi_init: list of [D,C,G] exit flux
     densities per mesh whose periodic outflow feeds the first pass (warm start)."""
     lib = _load()
     dirs = _c(w["dirs"], np.float64)
@@ -170,7 +173,8 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
         qo = np.zeros((D, C), np.int32) if want_order else None
         pin = None if phi_init is None else _c(phi_init[mi], np.float64)
         _check(lib.orc_forward(ctypes.byref(s), D, _p(dirs), eps, G, _p(k), _p(e), int(periodic),
-                               n_pbc, albedo, n_scat, law, merged, _p(pin), _p(j), _p(a), _p(t),
+                               n_pbc, albedo, n_scat, law, merged, _p(pin),
+                               float(w.get("pbc_tol", 0.0)), _p(j), _p(a), _p(t),
                                _p(phi), _p(ck), _p(qo)),
                "forward")
         J[sl], Ab[sl], totals[mi] = j, a, t

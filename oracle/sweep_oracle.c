@@ -288,6 +288,9 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
  *   merged: 1 = periodic passes and source iterations advance together (see below)
  *   phi_init: [D][C][G] exit flux densities whose periodic outflow feeds the first
  *             pass (a warm start from an earlier solution), or NULL (zero inflow)
+ *   pbc_tol: > 0 (nested order only): the periodic passes of an iteration stop after
+ *            the first pass (from the second on) whose E is below pbc_tol in every
+ *            cell and group; n_pbc is then the maximum (sec. 2.7)
  *   phi_out: [D][C][G] exit flux density of the final pass (may be NULL)
  *   jsum_ckpt: [n_scat][C][G] sum_d of the cell averages of every iteration's
  *              final pass (may be NULL)
@@ -295,12 +298,13 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
 int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
                 double albedo, int32_t n_scat, int32_t law, int32_t merged,
-                const double* phi_init, double* J, double* absorbed, double* totals,
-                double* phi_out, double* jsum_ckpt, int32_t* qorder) {
+                const double* phi_init, double pbc_tol, double* J, double* absorbed,
+                double* totals, double* phi_out, double* jsum_ckpt, int32_t* qorder) {
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
   if (D < 1 || G < 1 || n_pbc < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
   if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
+  if (!(pbc_tol >= 0.0) || (merged && pbc_tol > 0.0)) return ORC_ERR_ARG;
   if (!periodic) n_pbc = 1;
   double* phi = (double*)calloc((size_t)(D * CG), sizeof(double));
   double* avg = (double*)calloc((size_t)(D * CG), sizeof(double));
@@ -322,7 +326,9 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   const int32_t n_outer = merge ? 1 : n_scat;
   const int32_t n_inner = merge ? (n_pbc > n_scat ? n_pbc : n_scat) : n_pbc;
   const int32_t warm = periodic && phi_init != NULL;
+  int32_t n_done = n_inner; /* passes of the last iteration (fewer if pbc_tol stopped them) */
   for (int32_t it = 0; it < n_outer && status == ORC_OK; ++it) {
+    n_done = n_inner;
     if (warm && it == 0)
       memcpy(phiprev, phi_init, sizeof(double) * (size_t)(D * CG));
     else
@@ -366,8 +372,21 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         free(q);
       }
       if (status != ORC_OK) break;
-      if (p + 1 < n_inner) memcpy(phiprev, phi, sizeof(double) * (size_t)(D * CG));
-      if (merge || p + 1 == n_inner) {
+      /* convergence test of sec. 2.7: stop once E < pbc_tol in every cell and group */
+      int stop = 0;
+      if (periodic && pbc_tol > 0.0 && p > 0) {
+        double emax = 0.0;
+        for (int64_t i = 0; i < CG; ++i) {
+          double jn = 0.0;
+          for (int32_t d = 0; d < D; ++d) jn += jin[(int64_t)d * CG + i];
+          const double jo = jin_old[i];
+          const double e = jn + jo > 0.0 ? fabs(jn - jo) / (jn + jo) : 0.0;
+          if (e > emax) emax = e;
+        }
+        stop = emax < pbc_tol;
+      }
+      if (p + 1 < n_inner && !stop) memcpy(phiprev, phi, sizeof(double) * (size_t)(D * CG));
+      if (merge || p + 1 == n_inner || stop) {
         /* direction sum of the cell averages in ascending d */
         for (int64_t i = 0; i < CG; ++i) {
           double s = 0.0;
@@ -376,6 +395,10 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         }
       }
       if (merge && p + 1 < n_inner) memcpy(jsum_old, jsum, sizeof(double) * (size_t)CG);
+      if (stop) {
+        n_done = p + 1;
+        break;
+      }
     }
     if (status != ORC_OK) break;
     /* merged: the sums of the final pass go to the last checkpoint */
@@ -402,7 +425,7 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         double jn = 0.0;
         for (int32_t d = 0; d < D; ++d) jn += jin[(int64_t)d * CG + i];
         const double jo = jin_old[i];
-        if (periodic && n_inner > 1 && jn + jo > 0.0) {
+        if (periodic && n_done > 1 && jn + jo > 0.0) {
           const double e = fabs(jn - jo) / (jn + jo);
           if (e > totals[8 * g + 6]) totals[8 * g + 6] = e;
         }
@@ -412,7 +435,7 @@ int orc_forward(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
     for (int32_t g = 0; g < G; ++g) {
       double den = 0.0;
       for (int32_t c = 0; c < C; ++c) den += jin_old[(int64_t)c * G + g];
-      totals[8 * g + 7] = (periodic && n_inner > 1 && den > 0.0) ? totals[8 * g + 7] / den : 0.0;
+      totals[8 * g + 7] = (periodic && n_done > 1 && den > 0.0) ? totals[8 * g + 7] / den : 0.0;
       for (int32_t d = 0; d < D; ++d) {
         totals[8 * g + 2] += accd[(int64_t)d * 4 * G + 4 * g + 0];
         totals[8 * g + 3] += accd[(int64_t)d * 4 * G + 4 * g + 1];
@@ -546,7 +569,7 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
       !qorder)
     return ORC_ERR_OOM;
   int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, law, 0,
-                           NULL, J, Ab, tots, NULL, jsum, NULL);
+                           NULL, 0.0, J, Ab, tots, NULL, jsum, NULL);
   if (status == ORC_OK) {
     memset(dkappa, 0, sizeof(double) * (size_t)CG);
     memset(demission, 0, sizeof(double) * (size_t)CG);

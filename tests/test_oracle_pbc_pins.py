@@ -73,3 +73,21 @@ def test_warm_start_continues_the_passes():
     c = oracle.forward(dict(w, n_pbc=7), want_phi=True)
     assert np.allclose(b["J"], c["J"], rtol=1e-13, atol=0)
     assert np.allclose(b["phi"][0], c["phi"][0], rtol=1e-13, atol=1e-300)
+
+
+def test_convergence_threshold_stops_the_passes():
+    """pbc_tol (sec. 2.7): the passes stop at the first pass k >= 2 whose E is below the
+    threshold in every cell; the result is then exactly that of k passes."""
+    w = _w(n_scat=1)
+    emax = [oracle.forward(dict(w, n_pbc=n))["totals"][0, :, 6].max() for n in range(2, 12)]
+    tol = 0.5 * (emax[4] + emax[5])  # between the E of 6 and of 7 passes
+    k = 2 + next(i for i, e in enumerate(emax) if e < tol)
+    assert k == 7
+    r = oracle.forward(dict(w, n_pbc=40, pbc_tol=tol), want_phi=True)
+    ref = oracle.forward(dict(w, n_pbc=k), want_phi=True)
+    assert np.array_equal(r["J"], ref["J"]) and np.array_equal(r["phi"][0], ref["phi"][0])
+    assert np.array_equal(r["totals"], ref["totals"])
+    assert r["totals"][0, :, 6].max() < tol
+    # a threshold no pass reaches runs all n_pbc passes
+    r = oracle.forward(dict(w, n_pbc=5, pbc_tol=1e-30))
+    assert np.array_equal(r["J"], oracle.forward(dict(w, n_pbc=5))["J"])

@@ -49,8 +49,9 @@
  *     ([C_total][G], row-major), cells of all meshes concatenated in mesh
  *     order (global cell id = mesh offset + local id);
  *   - work is enqueued on the caller's `stream` (a hipStream_t, NULL = null
- *     stream); only sweep_build_dag, sweep_dag_info and sweep_dag_export
- *     synchronise that stream;
+ *     stream); only sweep_build_dag, sweep_dag_info, sweep_dag_export,
+ *     sweep_tune, sweep_ion_step and sweep_forward with pbc_tol synchronise
+ *     that stream;
  *   - the caller owns every array argument and output; outputs are fully
  *     overwritten; the library owns the DAG object and its internal buffers.
  */
@@ -143,7 +144,12 @@ typedef struct {
                         from the phi that `saved` holds (the final pass of an earlier
                         call with this DAG and G) instead of zero (sec. 2.7's warm start);
                         requires `saved` */
-  int32_t reserved[2];
+  double pbc_tol;    /* > 0 (periodic, nested order): the passes of a source iteration
+                        stop after the first pass from the second on whose E (below) is
+                        below pbc_tol in every cell, group and mesh; n_pbc is then the
+                        maximum (sec. 2.7).  Reads E back after every pass, so it
+                        synchronises `stream` per pass and cannot be combined with
+                        use_graph or merge.  0 = always n_pbc passes */
 } sweep_fwd_opts_t;
 
 /* Message of the last failed call on this thread ("" if none). */

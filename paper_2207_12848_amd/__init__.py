@@ -53,7 +53,8 @@ def upload_mesh(mesh: dict, device="cuda") -> dict:
 
 
 def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
-              use_graph=False, law="upwind", merge=False, warm_start=False) -> B.sweep_fwd_opts_t:
+              use_graph=False, law="upwind", merge=False, warm_start=False,
+              pbc_tol=0.0) -> B.sweep_fwd_opts_t:
     o = B.sweep_fwd_opts_t()
     o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
     o.n_pbc = int(n_pbc)
@@ -66,6 +67,7 @@ def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", 
     o.law = {"upwind": B.SWEEP_LAW_UPWIND, "exp": B.SWEEP_LAW_EXP}[law]
     o.merge = int(bool(merge))
     o.warm_start = int(bool(warm_start))
+    o.pbc_tol = float(pbc_tol)
     return o
 
 

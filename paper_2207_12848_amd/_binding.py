@@ -69,7 +69,7 @@ class sweep_fwd_opts_t(ctypes.Structure):
                 ("albedo", ctypes.c_double), ("n_scat", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("block", ctypes.c_int32), ("ring", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("law", ctypes.c_int32), ("merge", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("warm_start", ctypes.c_int32), ("pbc_tol", ctypes.c_double)]
 
 
 _lib = None

@@ -250,7 +250,7 @@ struct sweep_dag_s {
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
-  Buf phi_a, phi_b, phi_w, pin, pin_prev, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
+  Buf phi_a, phi_b, phi_w, pin, pin_prev, pin_prev2, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
       tsrc, cds, out_s, ion_min;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
   struct GraphEntry {
@@ -369,6 +369,7 @@ sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
 struct FwdPlan {
   int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm;
   float albedo;
+  double pbc_tol;
 };
 
 sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
@@ -383,6 +384,9 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   p->law = o ? o->law : SWEEP_LAW_UPWIND;
   p->merge = o ? (o->merge != 0) : 0;
   p->warm = o ? (o->warm_start != 0) : 0;
+  p->pbc_tol = o ? o->pbc_tol : 0.0;
+  if (!(p->pbc_tol >= 0.0) || !std::isfinite(p->pbc_tol))
+    return fail(SWEEP_ERR_INVALID_ARG, "pbc_tol must be finite and >= 0");
   if (p->law != SWEEP_LAW_UPWIND && p->law != SWEEP_LAW_EXP)
     return fail(SWEEP_ERR_INVALID_ARG, "unknown cell law %d", p->law);
   if (p->boundary != SWEEP_BOUNDARY_VACUUM && p->boundary != SWEEP_BOUNDARY_PERIODIC)
@@ -568,6 +572,9 @@ void opts_key(std::vector<uint64_t>& k, const FwdPlan& p) {
   k.insert(k.end(), {(uint64_t)p.boundary, (uint64_t)p.n_pbc, (uint64_t)p.n_scat, (uint64_t)p.form,
                      (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab, (uint64_t)p.law,
                      (uint64_t)p.merge, (uint64_t)p.warm});
+  uint64_t tb;
+  std::memcpy(&tb, &p.pbc_tol, 8);
+  k.push_back(tb);
 }
 
 sweep_status_t check_common(sweep_dag_t d, int32_t G) {
@@ -1043,6 +1050,14 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   const bool warm = p.warm && periodic;
   if (warm && !saved)
     return fail(SWEEP_ERR_INVALID_ARG, "warm_start takes the periodic inflow from `saved`, which is NULL");
+  // convergence threshold (sec. 2.7): after every pass from the second on, E is read
+  // back and the passes of the iteration stop once it is below pbc_tol everywhere
+  const bool tol = periodic && p.pbc_tol > 0.0 && n_inner > 1;
+  if (tol && merge)
+    return fail(SWEEP_ERR_INVALID_ARG, "pbc_tol applies to the nested order, not to merge");
+  if (tol && p.use_graph)
+    return fail(SWEEP_ERR_INVALID_ARG, "pbc_tol stops on values read back each pass; it cannot be "
+                                       "captured in a graph (use_graph)");
   hipStream_t s = (hipStream_t)stream;
   StreamScope stream_scope(s);
   const int64_t CG = d->C_total * G;
@@ -1055,6 +1070,9 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     HIP_TRY(d->pin.alloc(4 * DCG));
     HIP_TRY(d->pin_prev.alloc(8 * CG));
   }
+  if (tol) HIP_TRY(d->pin_prev2.alloc(8 * CG));
+  const int64_t n_tot = (int64_t)d->n_meshes * G * 8;
+  std::vector<double> tot_host(tol ? n_tot : 0);
   if (!saved || merge) {
     HIP_TRY(d->jsum_a.alloc(4 * CG));
     HIP_TRY(d->jsum_b.alloc(4 * CG));
@@ -1106,6 +1124,40 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
         if (ps == 0 || merge)
           ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
         ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, st));
+        if (tol) {
+          // the full reduction after every pass: E against the previous pass's
+          // per-cell inflow (double-buffered sums), then the totals read back
+          double* sums[2] = {d->pin_prev.as<double>(), d->pin_prev2.as<double>()};
+          sweep::ReduceArgs q = r;
+          q.phi = dst;
+          q.pin = d->pin.as<float>();
+          q.pin_prev = ps > 0 ? sums[(ps + 1) % 2] : nullptr;
+          q.pin_sum = sums[ps % 2];
+          q.jsum_prev = jprev;
+          q.jsum = ckpt(it);
+          q.last = 1;
+          {
+            ProfScope pr("reduce", st);
+            HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
+          }
+          bool stop = final_pass;
+          if (ps > 0 && !final_pass) {
+            HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
+                                         d->n_meshes, G, totals, st));
+            HIP_TRY(hipMemcpyAsync(tot_host.data(), totals, 8 * n_tot, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            double emax = 0.0;
+            for (int64_t i = 6; i < n_tot; i += 8) emax = std::max(emax, tot_host[i]);
+            stop = emax < p.pbc_tol;
+          }
+          if (stop) {
+            if (dst != phi_final)
+              HIP_TRY(hipMemcpyAsync(phi_final, dst, 4 * DCG, hipMemcpyDeviceToDevice, st));
+            break;
+          }
+          prev = dst;
+          continue;
+        }
         if (!final_pass && (merge || periodic)) {
           // bookkeeping of a pass before the last: the per-cell periodic inflow (for E)
           // and, merged, the direction sums that feed the next pass's source
@@ -1121,6 +1173,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
         }
         prev = dst;
       }
+      if (tol) continue;  // the last pass's reduction is done
       sweep::ReduceArgs q = r;
       q.phi = phi_final;
       q.pin = periodic ? d->pin.as<float>() : nullptr;
@@ -1145,7 +1198,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
                                pkey(totals), pkey(saved), (uint64_t)saved_bytes};
   opts_key(key, p);
-  for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->jsum_a,
+  for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->pin_prev2, &d->jsum_a,
                        &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
                        &d->mesh_blk_base})
     key.push_back(pkey(b->p));

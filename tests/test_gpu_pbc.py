@@ -93,3 +93,24 @@ def test_periodic_error_curve_matches_oracle():
     curve = np.array(curve)
     assert np.all(curve[0] == 1.0)  # the first pass starts from zero inflow
     assert np.all(np.diff(curve[1:], axis=0) < 0)
+
+
+def test_convergence_threshold_matches_oracle():
+    sw = _sw()
+    w = W.small_random(3000, 24, G=2, seed=99, periodic=True, n_src=6, tau=2.0)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    # a threshold between the E of 6 and of 7 passes (0.1253 and 0.0707 for group 0,
+    # 0.1624 and 0.1135 for group 1): the passes stop after the 7th
+    tol = 0.14
+    J, A, tot = sw.forward(dag, k, e, boundary="periodic", n_pbc=40, pbc_tol=tol)
+    J7, A7, tot7 = sw.forward(dag, k, e, boundary="periodic", n_pbc=7)
+    torch.cuda.synchronize()
+    assert torch.equal(J, J7) and torch.equal(A, A7)
+    assert np.allclose(tot.cpu().numpy(), tot7.cpu().numpy(), rtol=1e-12, atol=0)
+    ref = oracle.forward(dict(w, n_pbc=40, pbc_tol=tol))
+    assert_field_close(J.cpu().numpy(), ref["J"], name="J")
+    assert tot.cpu().numpy()[..., 6].max() < tol
+    for bad in (dict(merge=True, n_scat=2, albedo=0.3), dict(use_graph=True)):
+        with pytest.raises(sw.SweepError, match="INVALID_ARG"):
+            sw.forward(dag, k, e, boundary="periodic", n_pbc=5, pbc_tol=tol, **bad)

@@ -69,10 +69,12 @@ def ion_update(absorbed: np.ndarray, y: np.ndarray, V: np.ndarray, dt: float, p:
     return 1.0 - np.minimum(un, 1.0)
 
 
-def evolve(w: dict, t_end: float, max_steps: int = 1_000_000, record=None):
+def evolve(w: dict, t_end: float, max_steps: int = 1_000_000, record=None, dir_sets=None):
     """Time-step workload `w` (one mesh, G = 1, no scattering, exponential law; w["hii"]
     holds the physical parameters) from a neutral start to t_end seconds.  Returns (t, y) and
-    calls record(step, t, y, absorbed, dt) after every step when given."""
+    calls record(step, t, y, absorbed, dt) after every step when given.  dir_sets: a list
+    of direction sets used in turn, one per step (the rotated directions of sec. 2.6
+    that smear out the preferred directions); default w["dirs"] for every step."""
     p = w["hii"]
     (mesh,) = w["meshes"]
     V = np.asarray(mesh["cell_volume"], np.float64) * p["length_unit"] ** 3
@@ -83,6 +85,8 @@ def evolve(w: dict, t_end: float, max_steps: int = 1_000_000, record=None):
         if t >= t_end:
             break
         ww["kappa"] = kappa_of(y, p)[:, None]
+        if dir_sets is not None:
+            ww["dirs"] = dir_sets[step % len(dir_sets)]
         absorbed = forward(ww)["absorbed"][:, 0]
         dt_max = p["dt_max_trec"] * recombination_time(p)
         dt = min(dt_max, t_end - t, p["courant"] * ion_limit(absorbed, y, V, p))

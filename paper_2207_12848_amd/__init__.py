@@ -245,7 +245,12 @@ def evolve_ionisation(dag: Dag, emission: torch.Tensor, params: dict, t_end: flo
     """Time-step a photoionisation run (sweep under the exponential law, then
     ion_step) from `neutral` (default: fully neutral) until t_end seconds.
     Returns (t, neutral, steps); calls record(step, t, neutral, absorbed, dt) after
-    every step when given."""
+    every step when given.  `dag` may be a list of DAGs of the same meshes built for
+    rotated direction sets: step k sweeps dag[(k0 + k) % len(dag)], k0 = opts
+    "step0" (default 0)."""
+    dags = list(dag) if isinstance(dag, (list, tuple)) else [dag]
+    step0 = int(opts.pop("step0", 0))
+    dag = dags[0]
     C = dag.n_cells
     dev = emission.device
     y = torch.ones(C, dtype=torch.float64, device=dev) if neutral is None else neutral
@@ -253,8 +258,9 @@ def evolve_ionisation(dag: Dag, emission: torch.Tensor, params: dict, t_end: flo
     o = dict(opts, law="exp")
     t, step = 0.0, 0
     while t < t_end and step < max_steps:
-        _, A, _ = forward(dag, kappa, emission, **o)
-        dt = ion_step(dag, A, y, kappa, params, t_end - t)
+        dg = dags[(step0 + step) % len(dags)]
+        _, A, _ = forward(dg, kappa, emission, **o)
+        dt = ion_step(dg, A, y, kappa, params, t_end - t)
         t += dt
         step += 1
         if record is not None:

@@ -32,3 +32,24 @@ def fibonacci(D: int) -> np.ndarray:
 
 def direction_set(D: int) -> np.ndarray:
     return octant_diagonals() if D == 8 else fibonacci(D)
+
+
+def rotation(theta: float, phi: float) -> np.ndarray:
+    """Rotation by theta about y followed by phi about z."""
+    ct, st, cp, sp = np.cos(theta), np.sin(theta), np.cos(phi), np.sin(phi)
+    ry = np.array([[ct, 0.0, st], [0.0, 1.0, 0.0], [-st, 0.0, ct]])
+    rz = np.array([[cp, -sp, 0.0], [sp, cp, 0.0], [0.0, 0.0, 1.0]])
+    return rz @ ry
+
+
+def rotated_sets(D: int, n_rot: int, seed: int = 0) -> list:
+    """n_rot copies of direction_set(D), each rotated by seeded random angles
+    theta in [0, pi], phi in [0, 2 pi] (the first copy unrotated), renormalised."""
+    rng = np.random.default_rng(np.random.SeedSequence([2207, 12848, 7, seed]))
+    base = direction_set(D)
+    out = [base]
+    for _ in range(n_rot - 1):
+        r = rotation(rng.uniform(0.0, np.pi), rng.uniform(0.0, 2.0 * np.pi))
+        d = base @ r.T
+        out.append(d / np.linalg.norm(d, axis=1, keepdims=True))
+    return out

@@ -138,3 +138,49 @@ def test_rtype_expansion_against_analytic(n_side):
     # within 8 % at every checkpoint and 4 % from one recombination time on
     assert np.all(np.abs(err_h) < 0.08)
     assert np.all(np.abs(err_h[np.array([x[0] for x in rows]) >= 1.0]) < 0.04)
+
+
+def test_rotated_direction_sets_match_oracle():
+    """Five rotated direction sets used in turn (one DAG each, built once)."""
+    from synth.directions import rotated_sets
+    sw = _sw()
+    w = W.hii_rtype(16, 24)
+    p = _params(w)
+    sets = rotated_sets(24, 5)
+    t_end = 0.1 * H.recombination_time(p)
+    t_o, y_o = H.evolve(w, t_end, dir_sets=sets)
+    dags = [sw.build_dag(w["meshes"], d) for d in sets]
+    e = torch.tensor(np.asarray(w["emission"], np.float32), device="cuda")
+    t_g, y_g, n = sw.evolve_ionisation(dags, e, p, t_end)
+    y_g = y_g.cpu().numpy()
+    V = w["meshes"][0]["cell_volume"]
+    rv_o, rv_g = HA.volume_radius(y_o, V), HA.volume_radius(y_g, V)
+    print("%d steps, volume radius rel diff %.3e, max |dy| %.3e" % (n, abs(rv_g / rv_o - 1),
+                                                                 np.abs(y_g - y_o).max()))
+    assert abs(rv_g / rv_o - 1) <= 1e-4
+    assert np.abs(y_g - y_o).max() <= 1e-3
+
+
+def test_rtype_expansion_with_rotations_32():
+    """The 32^3 run of the R-type test with N_rot = 5 rotated sets of 84 directions."""
+    from synth.directions import rotated_sets
+    sw = _sw()
+    w = W.hii_rtype(32, 84)
+    p = _params(w)
+    trec = H.recombination_time(p)
+    dags = [sw.build_dag(w["meshes"], d) for d in rotated_sets(84, 5)]
+    V = torch.tensor(w["meshes"][0]["cell_volume"] * p["length_unit"] ** 3, device="cuda")
+    e = torch.tensor(np.asarray(w["emission"], np.float32), device="cuda")
+    y = torch.ones(32 ** 3, dtype=torch.float64, device="cuda")
+    t, step = 0.0, 0
+    errs = []
+    t0 = time.perf_counter()
+    for c in (0.05, 0.25, 0.5, 1.0, 1.5):
+        dt, y, n = sw.evolve_ionisation(dags, e, dict(p), c * trec - t, neutral=y, step0=step)
+        t += dt
+        step += n
+        rv = float((3.0 * torch.sum((1.0 - y) * V) / (4.0 * np.pi)) ** (1.0 / 3.0))
+        errs.append(rv / float(H.rtype_radius(t, p)) - 1)
+        print("  t/t_rec %.2f  step %6d  R_V/R_r - 1 = %+.4f" % (t / trec, step, errs[-1]))
+    print("%d steps in %.2f s" % (step, time.perf_counter() - t0))
+    assert np.all(np.abs(errs) < 0.03)

@@ -100,3 +100,41 @@ def test_stromgren_sphere_is_reached():
     assert abs(rows[-1, 2] / rs - 1) < 0.03
     assert 1.0 < rows[-1, 1] / rs < 1.1
     assert abs(rows[-1, 3] / p["photon_rate"] - 1) < 0.05
+
+
+def test_direction_sets_in_turn():
+    """Cycling identical direction sets changes nothing; a set turned by 90 degrees
+    about z through the source's cell turns the ionisation field with it (before the
+    front reaches the box walls, which sit half a cell off-centre)."""
+    from synth.directions import rotation
+    w = W.hii_rtype(16, 24)
+    p = w["hii"]
+    t_end = 0.05 * H.recombination_time(p)
+    _, y1 = H.evolve(w, t_end)
+    _, y2 = H.evolve(w, t_end, dir_sets=[w["dirs"], w["dirs"].copy()])
+    assert np.array_equal(y1, y2)
+    rz = rotation(0.0, 0.5 * np.pi)
+    _, yr = H.evolve(w, t_end, dir_sets=[w["dirs"] @ rz.T])
+    n, c = 16, 8
+    i, j, k = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    # the cell at offset (x, y) from the source's cell maps to offset (-y, x)
+    ii, jj = c - (j - c), c + (i - c)
+    ok = (ii >= 0) & (ii < n) & (jj >= 0) & (jj < n)
+    src = (i + n * (j + n * k))[ok]
+    dst = (ii + n * (jj + n * k))[ok]
+    assert np.max(np.abs(yr[dst] - y1[src])) < 1e-9
+
+
+def test_rotated_sets_reduce_the_radius_error():
+    """Five rotated sets in turn (sec. 2.6's N_rot = 5) against one fixed set."""
+    from synth.directions import rotated_sets
+    w = W.hii_rtype(16, 24)
+    p = w["hii"]
+    t_end = 0.5 * H.recombination_time(p)
+    V = w["meshes"][0]["cell_volume"] * p["length_unit"] ** 3
+    ra = H.rtype_radius(t_end, p)
+    errs = []
+    for n_rot in (1, 5):
+        _, y = H.evolve(w, t_end, dir_sets=rotated_sets(24, n_rot))
+        errs.append(abs(HA.volume_radius(y, V) / ra - 1))
+    assert errs[1] < errs[0] < 0.02

@@ -160,7 +160,8 @@ const char* sweep_last_error(void);
  *   meshes: HOST array of n_meshes descriptors (their arrays on the device)
  *   dirs:   HOST [n_dirs*3] unit vectors (FP64); every direction owns 4pi/n_dirs
  *   opts:   may be NULL for defaults
- * Synchronises `stream` once.  Errors: INVALID_ARG (validation), CYCLE, OOM, HIP. */
+ * Synchronises `stream` once.  Errors: INVALID_ARG (validation), CYCLE, OOM, HIP,
+ * UNSUPPORTED (more than 2^31 - 2 tasks, cells x directions, in one DAG). */
 sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, const double* dirs,
                                int32_t n_dirs, const sweep_build_opts_t* opts, void* stream,
                                sweep_dag_t* out);

@@ -673,6 +673,10 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   D->C_total = off;
   D->T = off * n_dirs;
   const int64_t T = D->T;
+  // the row-pointer scans index tasks with 32-bit counts
+  if (T + 1 > INT32_MAX)
+    return fail(SWEEP_ERR_UNSUPPORTED, "%lld tasks (cells x directions) in one DAG; at most %d: "
+                "split the directions over several DAGs", (long long)T, INT32_MAX - 1);
   const int n_units = n_meshes * n_dirs;
   // units: u = mesh * D + dir; the tasks of unit (m, d) start at D * (first cell
   // of m) + d * cells(m) (k_adj_reduce indexes per-task arrays with this formula)
@@ -860,12 +864,12 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   // the longest downwind list sets how much of every row Kahn's algorithm loads
   a.dn_chunks = std::max(1, std::min(dn_width / 4, (stats[1] + 3) / 4));
   // row lengths in schedule order (the input of the row-pointer scan)
-  HIP_TRY(len_up.alloc(8 * (T + 1)));
-  HIP_TRY(len_dn.alloc(8 * (T + 1)));
-  a.len_up = len_up.as<int64_t>();
-  a.len_dn = len_dn.as<int64_t>();
-  HIP_TRY(hipMemsetAsync(a.len_up + T, 0, 8, s));
-  HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 8, s));
+  HIP_TRY(len_up.alloc(4 * (T + 1)));
+  HIP_TRY(len_dn.alloc(4 * (T + 1)));
+  a.len_up = len_up.as<int32_t>();
+  a.len_dn = len_dn.as<int32_t>();
+  HIP_TRY(hipMemsetAsync(a.len_up + T, 0, 4, s));
+  HIP_TRY(hipMemsetAsync(a.len_dn + T, 0, 4, s));
   // Kahn counters in LDS as 4-bit fields when the mesh fits the LDS
   // (the kernel's static LDS holds two frontier copies of 2048 cells); the
   // rows' entries of cells with larger counts are flagged first
@@ -883,10 +887,10 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.up_ptr = D->up_ptr.as<int64_t>();
   a.dn_ptr = D->dn_ptr.as<int64_t>();
   size_t tmp_bytes = 0;
-  HIP_TRY(sweep::launch_scan_i64(a.len_up, a.up_ptr, T + 1, nullptr, &tmp_bytes, s));
+  HIP_TRY(sweep::launch_scan_len(a.len_up, a.up_ptr, T + 1, nullptr, &tmp_bytes, s));
   HIP_TRY(scan_tmp.alloc(tmp_bytes));
-  HIP_TRY(sweep::launch_scan_i64(a.len_up, a.up_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
-  HIP_TRY(sweep::launch_scan_i64(a.len_dn, a.dn_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
+  HIP_TRY(sweep::launch_scan_len(a.len_up, a.up_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
+  HIP_TRY(sweep::launch_scan_len(a.len_dn, a.dn_ptr, T + 1, scan_tmp.p, &tmp_bytes, s));
   HIP_TRY(D->up.alloc(8 * std::max<int64_t>(D->n_up, 1)));
   HIP_TRY(D->dn.alloc(8 * std::max<int64_t>(D->n_dn, 1)));
   a.up = D->up.as<int2>();

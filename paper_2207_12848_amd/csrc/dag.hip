@@ -868,10 +868,17 @@ hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,
+struct WidenToI64 {
+  __host__ __device__ int64_t operator()(int32_t v) const { return (int64_t)v; }
+};
+
+hipError_t launch_scan_len(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,
                            hipStream_t s) {
-  // exclusive prefix sum; tmp == nullptr queries the temporary storage size
-  return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, in, out, (int)n, s);
+  // exclusive prefix sum of int32 row lengths into int64 row pointers (the
+  // lengths are widened as they are read, so the sums never overflow);
+  // tmp == nullptr queries the temporary storage size
+  hipcub::TransformInputIterator<int64_t, WidenToI64, const int32_t*> it(in, WidenToI64());
+  return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, it, out, (int)n, s);
 }
 
 hipError_t launch_d2f(const double* in, float* out, int64_t n, hipStream_t s) {

@@ -70,8 +70,8 @@ struct DagBuildArgs {
   int32_t* err;    // set to 1 if a unit could not be fully ordered
   int64_t* lev_up;  // per unit level table: first upwind-row entry of each level
   int64_t* lev_dn;
-  int64_t* len_up;  // [T+1] row lengths in schedule order (scan input)
-  int64_t* len_dn;  // [T+1]
+  int32_t* len_up;  // [T+1] row lengths in schedule order (scan input)
+  int32_t* len_dn;  // [T+1]
   int64_t* up_ptr;  // [T+1]
   int64_t* dn_ptr;  // [T+1]
   int2* up;         // (position of the upwind task | -(partner cell + 1) for periodic inflow, w)
@@ -206,7 +206,7 @@ hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s);
 size_t count_lds_bytes(int max_faces, int dn_width);
 hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s);
-hipError_t launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,
+hipError_t launch_scan_len(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,
                            hipStream_t s);
 hipError_t launch_d2f(const double* in, float* out, int64_t n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -475,7 +475,11 @@ static double dh_dtau(double tau) {
  * For g = dL/d(cell average), dL/dx = r g, so lambda = M^{-T} (r g):
  *   lambda_c = (r_c g_c + sum_{outflow faces to interior e} w lambda_e) / den_c,
  * visiting the cells in the reverse of the forward queue order, so every
- * downwind lambda is final before it is read.  It also writes, per task,
+ * downwind lambda is final before it is read.  With periodic passes the
+ * forward pass p also takes w x^{p-1}(partner) through every periodic inflow
+ * face, so lambda^p gets w lambda^{p+1}(partner) through every periodic outflow
+ * face (lam_next; NULL for the last pass), and only the last pass carries the
+ * loss (g = NULL before it).  It also writes, per task,
  *   dk_c = -lambda_c x_c d(den_c)/dkappa_c + g_c x_c dr_c/dkappa_c
  * (the part of dL/dkappa_c this direction contributes through M and r):
  *   upwind: d(den)/dkappa = V, dr/dkappa = 0;
@@ -484,7 +488,8 @@ static double dh_dtau(double tau) {
  *   exponential, tau >= TAU_CAP: d(den)/dkappa = 0, dr/dkappa = -r / kappa. */
 static void adjoint_direction(const orc_mesh* m, const double* om, double eps, int32_t G,
                               int32_t law, const double* kappa, const double* g,
-                              const double* x, const int32_t* qorder, double* lam, double* dk) {
+                              const double* lam_next, const double* x, const int32_t* qorder,
+                              double* lam, double* dk) {
   const int32_t C = m->n_cells;
   for (int32_t k = C - 1; k >= 0; --k) {
     const int32_t c = qorder[k];
@@ -514,15 +519,18 @@ static void adjoint_direction(const orc_mesh* m, const double* om, double eps, i
       } else {
         den = aperp + kap * V;
       }
-      double acc = r * g[i];
+      double acc = g ? r * g[i] : 0.0;
       for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
         const double s = orient(om, m->face_normal + 3 * f);
         const int32_t nb = m->face_nbr[f];
-        if (face_class(s, eps) != F_OUT || nb < 0 || is_periodic_face(m, f)) continue;
-        acc += m->face_area[f] * fabs(s) * lam[(int64_t)nb * G + gg];
+        if (face_class(s, eps) != F_OUT || nb < 0) continue;
+        if (!is_periodic_face(m, f))
+          acc += m->face_area[f] * fabs(s) * lam[(int64_t)nb * G + gg];
+        else if (lam_next)  /* what leaves here enters nb in the next pass */
+          acc += m->face_area[f] * fabs(s) * lam_next[(int64_t)nb * G + gg];
       }
       lam[i] = acc / den;
-      dk[i] = -lam[i] * x[i] * dden + g[i] * x[i] * dr;
+      dk[i] = -lam[i] * x[i] * dden + (g ? g[i] * x[i] * dr : 0.0);
     }
   }
 }
@@ -541,35 +549,43 @@ static void adjoint_direction(const orc_mesh* m, const double* om, double eps, i
  *   dL/dkappa_c = gA_c (1-a) V_c sum_d avg^{n-1}_{c,d}
  *     + sum_i [ sum_d dk^i_{c,d} + a V_c (sum_d lambda^i_{c,d}) (sum_d' avg^{i-1}_{c,d'}) / D ],
  *   avg^{-1} = 0.
- * x^i is recomputed from the stored direction sums of iteration i-1.
- * Periodic boundaries are not supported (returns ORC_ERR_UNSUPPORTED). */
+ * With periodic boundaries every iteration is n_pbc passes x^0..x^{P-1} (pass 0
+ * from zero inflow, the scattering source the same in every pass, the loss and
+ * the next iteration's source on the last pass only).  The reverse passes run
+ * p = P-1..0 with lambda^{P-1} from the iteration's adjoint source and lambda^p
+ * fed by lambda^{p+1} through the periodic faces (adjoint_direction); the sums
+ * over d above become sums over passes and d, each pass's dk using its own x^p.
+ * x^p is recomputed from the stored direction sums of iteration i-1. */
 int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
-                const double* kappa, const double* emission, int32_t periodic, double albedo,
-                int32_t n_scat, int32_t law, const double* gJ, const double* gA, double* dkappa,
-                double* demission) {
-  if (periodic) return ORC_ERR_UNSUPPORTED;
-  if (D < 1 || G < 1 || n_scat < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
+                const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
+                double albedo, int32_t n_scat, int32_t law, const double* gJ, const double* gA,
+                double* dkappa, double* demission) {
+  if (D < 1 || G < 1 || n_scat < 1 || n_pbc < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
   if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
+  const int32_t P = periodic ? n_pbc : 1;
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
+  const int64_t DCG = (int64_t)D * CG;
   double* J = (double*)malloc(sizeof(double) * (size_t)CG);
   double* Ab = (double*)malloc(sizeof(double) * (size_t)CG);
   double tot[8 * 64];
   double* tots = G <= 64 ? tot : (double*)malloc(sizeof(double) * 8 * (size_t)G);
   double* jsum = (double*)malloc(sizeof(double) * (size_t)(n_scat * CG));
-  double* phi = (double*)malloc(sizeof(double) * (size_t)(D * CG));
-  double* avg = (double*)malloc(sizeof(double) * (size_t)(D * CG));
-  double* lam = (double*)malloc(sizeof(double) * (size_t)(D * CG));
-  double* dkd = (double*)malloc(sizeof(double) * (size_t)(D * CG));
+  double* xs = (double*)malloc(sizeof(double) * (size_t)(P * DCG)); /* x of every pass */
+  double* avg = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* lam = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* lam_next = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* dkd = (double*)malloc(sizeof(double) * (size_t)DCG);
   double* gsrc = (double*)malloc(sizeof(double) * (size_t)CG);
   double* src = (double*)malloc(sizeof(double) * (size_t)CG);
   double* lsum = (double*)malloc(sizeof(double) * (size_t)CG);
+  double* dksum = (double*)malloc(sizeof(double) * (size_t)CG);
   int32_t* qorder = (int32_t*)malloc(sizeof(int32_t) * (size_t)D * C);
-  if (!J || !Ab || !tots || !jsum || !phi || !avg || !lam || !dkd || !gsrc || !src || !lsum ||
-      !qorder)
+  if (!J || !Ab || !tots || !jsum || !xs || !avg || !lam || !lam_next || !dkd || !gsrc || !src ||
+      !lsum || !dksum || !qorder)
     return ORC_ERR_OOM;
-  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, 0, 1, albedo, n_scat, law, 0,
-                           NULL, 0.0, J, Ab, tots, NULL, jsum, NULL);
+  int status = orc_forward(m, D, dirs, eps, G, kappa, emission, periodic, P, albedo, n_scat, law,
+                           0, NULL, 0.0, J, Ab, tots, NULL, jsum, NULL);
   if (status == ORC_OK) {
     memset(dkappa, 0, sizeof(double) * (size_t)CG);
     memset(demission, 0, sizeof(double) * (size_t)CG);
@@ -581,48 +597,65 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
         dkappa[i] += gA[i] * (1.0 - albedo) * V * jsum[(int64_t)(n_scat - 1) * CG + i];
       }
     for (int32_t it = n_scat - 1; it >= 0 && status == ORC_OK; --it) {
-      /* recompute x^it from the direction sums of iteration it-1 */
+      /* recompute the passes x^0..x^{P-1} of iteration it from the sums of it-1 */
       for (int32_t c = 0; c < C; ++c)
         for (int32_t g = 0; g < G; ++g) {
           const int64_t i = (int64_t)c * G + g;
           const double prev = it > 0 ? jsum[(int64_t)(it - 1) * CG + i] : 0.0;
           src[i] = emission[i] / D + albedo * kappa[i] * m->cell_volume[c] * prev / D;
         }
+      for (int32_t p = 0; p < P && status == ORC_OK; ++p) {
 #pragma omp parallel for schedule(dynamic, 1)
-      for (int32_t d = 0; d < D; ++d) {
-        int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
-        int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
-        double acc[4 * 64];
-        double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
-        memset(a4, 0, sizeof(double) * 4 * (size_t)G);
-        int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, NULL,
-                                 phi + (int64_t)d * CG, avg + (int64_t)d * CG, a4, NULL, cnt, q,
-                                 NULL, qorder + (int64_t)d * C);
-        if (st == ORC_OK)
-          adjoint_direction(m, dirs + 3 * d, eps, G, law, kappa, gsrc, phi + (int64_t)d * CG,
-                            qorder + (int64_t)d * C, lam + (int64_t)d * CG, dkd + (int64_t)d * CG);
-        else {
+        for (int32_t d = 0; d < D; ++d) {
+          int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+          int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+          double acc[4 * 64];
+          double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
+          memset(a4, 0, sizeof(double) * 4 * (size_t)G);
+          const double* prev = p > 0 ? xs + (int64_t)(p - 1) * DCG + (int64_t)d * CG : NULL;
+          int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, prev,
+                                   xs + (int64_t)p * DCG + (int64_t)d * CG, avg + (int64_t)d * CG,
+                                   a4, NULL, cnt, q, NULL, qorder + (int64_t)d * C);
+          if (st != ORC_OK) {
 #pragma omp critical
-          status = st;
+            status = st;
+          }
+          if (a4 != acc) free(a4);
+          free(cnt);
+          free(q);
         }
-        if (a4 != acc) free(a4);
-        free(cnt);
-        free(q);
       }
       if (status != ORC_OK) break;
-      for (int32_t c = 0; c < C; ++c)
-        for (int32_t g = 0; g < G; ++g) {
-          const int64_t i = (int64_t)c * G + g;
-          const double V = m->cell_volume[c];
+      /* reverse passes */
+      memset(lsum, 0, sizeof(double) * (size_t)CG);
+      memset(dksum, 0, sizeof(double) * (size_t)CG);
+      for (int32_t p = P - 1; p >= 0; --p) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int32_t d = 0; d < D; ++d)
+          adjoint_direction(m, dirs + 3 * d, eps, G, law, kappa, p == P - 1 ? gsrc : NULL,
+                            p < P - 1 ? lam_next + (int64_t)d * CG : NULL,
+                            xs + (int64_t)p * DCG + (int64_t)d * CG, qorder + (int64_t)d * C,
+                            lam + (int64_t)d * CG, dkd + (int64_t)d * CG);
+        for (int64_t i = 0; i < CG; ++i) {
           double ls = 0.0, dks = 0.0;
           for (int32_t d = 0; d < D; ++d) {
             ls += lam[(int64_t)d * CG + i];
             dks += dkd[(int64_t)d * CG + i];
           }
+          lsum[i] += ls;
+          dksum[i] += dks;
+        }
+        double* t = lam_next;
+        lam_next = lam;
+        lam = t;
+      }
+      for (int32_t c = 0; c < C; ++c)
+        for (int32_t g = 0; g < G; ++g) {
+          const int64_t i = (int64_t)c * G + g;
+          const double V = m->cell_volume[c];
           const double prev = it > 0 ? jsum[(int64_t)(it - 1) * CG + i] : 0.0;
-          demission[i] += ls / D;
-          dkappa[i] += dks + albedo * V * ls * prev / D;
-          lsum[i] = ls;
+          demission[i] += lsum[i] / D;
+          dkappa[i] += dksum[i] + albedo * V * lsum[i] * prev / D;
         }
       /* adjoint source of the previous iteration */
       for (int32_t c = 0; c < C; ++c)
@@ -636,13 +669,15 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   free(Ab);
   if (tots != tot) free(tots);
   free(jsum);
-  free(phi);
+  free(xs);
   free(avg);
   free(lam);
+  free(lam_next);
   free(dkd);
   free(gsrc);
   free(src);
   free(lsum);
+  free(dksum);
   free(qorder);
   return status;
 }

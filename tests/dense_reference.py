@@ -124,8 +124,9 @@ def dense_scatter_system(w, cyclic=False):
     return x * np.stack(rs)
 
 
-def dense_adjoint(w, gJ, gA):
-    """Gradients of L(J, absorbed) for one group, no scattering, vacuum: explicit matrices."""
+def dense_adjoint(w, gJ, gA, cyclic=False):
+    """Gradients of L(J, absorbed), no scattering, upwind law: explicit matrices (cyclic:
+    the periodic faces coupled, the fixed point of the periodic passes)."""
     dirs = w["dirs"]
     G = w["G"]
     kap = np.asarray(w["kappa"], np.float64)
@@ -146,7 +147,7 @@ def dense_adjoint(w, gJ, gA):
             gphi = gj / (4 * np.pi) + ga * k * V
             jsum = np.zeros(C)
             for d in range(D):
-                M, _, _, _ = direction_matrix(mesh, dirs[d], k)
+                M, _, _, _ = direction_matrix(mesh, dirs[d], k, cyclic=cyclic)
                 phi = np.linalg.solve(M, e / D)
                 lam = np.linalg.solve(M.T, gphi)
                 jsum += phi

@@ -286,7 +286,43 @@ def test_adjoint_sign_for_mean_intensity_loss():
     assert np.all(dk <= 0)
 
 
-def test_periodic_adjoint_unsupported():
-    w = W.small_random(200, 8, seed=14, periodic=True)
-    with pytest.raises(oracle.OracleError, match="unsupported"):
-        oracle.adjoint(w, np.ones((200, 1)), np.zeros((200, 1)))
+@pytest.mark.parametrize("law,albedo,n_scat", [("upwind", 0.0, 1), ("upwind", 0.4, 3), ("exp", 0.4, 2)])
+def test_periodic_adjoint_central_differences(law, albedo, n_scat):
+    """Adjoint through 3 periodic passes (and source iterations): central differences."""
+    w = W.small_random(200, 8, G=1, seed=14, periodic=True, n_pbc=3, n_src=3, albedo=albedo,
+                       n_scat=n_scat, tau=2.0)
+    w = dict(w, law=law, kappa=np.asarray(w["kappa"], np.float64),
+             emission=np.asarray(w["emission"], np.float64))
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    L = _loss(w)
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for c in rng.choice(200, 8, replace=False):
+        k0 = w["kappa"][c, 0]
+        wp = dict(w, kappa=w["kappa"].copy())
+        wm = dict(w, kappa=w["kappa"].copy())
+        wp["kappa"][c, 0] = k0 * (1 + h)
+        wm["kappa"][c, 0] = k0 * (1 - h)
+        fd = (_loss(wp) - _loss(wm)) / (2 * h * k0)
+        assert abs(fd - dk[c, 0]) <= 1e-6 * abs(dk[c, 0]) + 1e-10 * L / k0
+    for c in w["sources"]:
+        L0 = w["emission"][c, 0]
+        wp = dict(w, emission=w["emission"].copy())
+        wm = dict(w, emission=w["emission"].copy())
+        wp["emission"][c, 0] = L0 * (1 + h)
+        wm["emission"][c, 0] = L0 * (1 - h)
+        fd = (_loss(wp) - _loss(wm)) / (2 * h * L0)
+        assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
+
+
+def test_periodic_adjoint_converges_to_the_cyclic_adjoint():
+    """Many passes: the gradients of the passes approach those of the cyclic fixed point."""
+    w = W.small_random(180, 8, G=1, seed=3, periodic=True, n_src=3, tau=2.0)
+    rng = np.random.default_rng(6)
+    gJ = rng.random((180, 1))
+    gA = rng.random((180, 1))
+    rk, re_ = DR.dense_adjoint(w, gJ, gA, cyclic=True)
+    dk, de = oracle.adjoint(dict(w, n_pbc=200), gJ, gA)
+    assert _rel(dk, rk) < 1e-9
+    assert _rel(de, re_) < 1e-9

@@ -184,7 +184,9 @@ sweep_status_t sweep_dag_export(sweep_dag_t dag, int32_t* level, int32_t* order,
 /* Bytes of the `saved` workspace sweep_forward fills for sweep_adjoint:
  * phi of the final pass ([n_dirs][C_total][G] FP32; the exit flux density x
  * under SWEEP_LAW_EXP) followed by the direction sums sum_d phi of every source
- * iteration ([n_scat][C_total][G] FP32). */
+ * iteration ([n_scat][C_total][G] FP32) and, with periodic boundaries (nested
+ * order), phi of the passes before the last ([n_pbc - 1][n_dirs][C_total][G]
+ * FP32) of the last iteration. */
 size_t sweep_saved_bytes(sweep_dag_t dag, int32_t G, const sweep_fwd_opts_t* opts);
 
 /* Forward sweep: n_scat source iterations, each made of n_pbc passes (vacuum:
@@ -212,7 +214,12 @@ sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, con
  * writes dL_dkappa and dL_demission (DEVICE [C_total][G] FP32).  `saved` must
  * hold what sweep_forward wrote with the same kappa, emission and opts.
  * Source iterations are differentiated with per-iteration recomputation from
- * the saved direction sums.  Periodic boundaries: UNSUPPORTED. */
+ * the saved direction sums.  Periodic passes (nested order) are differentiated
+ * pass by pass in reverse: the adjoint of pass p gets w lambda^{p+1} of the
+ * partner cell through every periodic outflow face (summed with FP64 atomics,
+ * so the result varies by rounding between runs).  UNSUPPORTED: the merged
+ * order, pbc_tol and warm_start (a pass count or inflow that the forward
+ * decided at run time or took from outside). */
 sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const float* emission, const sweep_fwd_opts_t* opts,
                              const void* saved, size_t saved_bytes, const float* dL_dJ,

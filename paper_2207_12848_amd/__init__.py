@@ -110,8 +110,9 @@ class Dag:
             off += self.n_dirs * C
         return out
 
-    def saved_bytes(self, G: int, n_scat: int = 1) -> int:
-        return int(sweep_saved_bytes(self.handle, G, ctypes.byref(_fwd_opts(n_scat=n_scat))))
+    def saved_bytes(self, G: int, n_scat: int = 1, **opts) -> int:
+        """Bytes of the `saved` workspace for these forward options."""
+        return int(sweep_saved_bytes(self.handle, G, ctypes.byref(_fwd_opts(n_scat=n_scat, **opts))))
 
     def close(self):
         if self._h is not None:

@@ -250,6 +250,7 @@ struct sweep_dag_s {
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
+  Buf xpass, pbc_extra;  // periodic adjoint: recomputed passes, transposed coupling
   Buf phi_a, phi_b, phi_w, pin, pin_prev, pin_prev2, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
       tsrc, cds, out_s, ion_min;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
@@ -428,7 +429,7 @@ int default_ring(int gn, int ring) {
 // Per-task denominators and sources for one sweep (schedule order).
 sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
                         const float* gsrc, const float* jsum_prev, float albedo, int32_t law,
-                        hipStream_t s) {
+                        hipStream_t s, bool use_gsrc = true, const double* extra = nullptr) {
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
@@ -447,6 +448,9 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.inv_D = 1.0f / (float)d->D;
   q.G = G;
   q.law = law;
+  q.use_gsrc = use_gsrc ? 1 : 0;
+  q.C_total = d->C_total;
+  q.extra = extra;
   q.tden = d->tden.as<float>();
   q.tsrc = d->tsrc.as<float>();
   q.cds = d->cds.as<float2>();
@@ -1027,7 +1031,10 @@ sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, i
 size_t sweep_saved_bytes(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
   if (!dag_ok(d) || G < 1) return 0;
   const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
-  return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat);
+  // periodic (nested order): phi of the passes before the last, for the adjoint
+  const bool periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC && !opts->merge;
+  const size_t extra = periodic ? (size_t)std::max(0, opts->n_pbc - 1) * d->D : 0;
+  return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat + extra);
 }
 
 sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
@@ -1088,6 +1095,12 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   };
   // direction sums of merged pass k (alternating buffers)
   auto jm = [&](int k) -> float* { return (k % 2 == 0) ? d->jsum_a.as<float>() : d->jsum_b.as<float>(); };
+  // with `saved`, the periodic passes before the last keep their phi there (after the
+  // checkpoints) for the adjoint
+  const bool store_passes = saved && periodic && !merge;
+  auto pass_slot = [&](int ps) -> float* {
+    return (float*)saved + DCG + (int64_t)p.n_scat * CG + (int64_t)ps * DCG;
+  };
   ST_TRY(ensure_mesh_tables(d));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
@@ -1122,7 +1135,8 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
       const float* jprev_it = it > 0 ? ckpt(it - 1) : nullptr;
       float* prev = (warm && it == 0) ? d->phi_w.as<float>() : nullptr;
       for (int ps = 0; ps < n_inner; ++ps) {
-        float* dst = ((n_inner - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
+        float* dst = store_passes ? (ps == n_inner - 1 ? phi_final : pass_slot(ps))
+                     : ((n_inner - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
         const float* jprev = merge ? (ps > 0 ? jm(ps - 1) : nullptr) : jprev_it;
         const bool final_pass = ps + 1 == n_inner;
         if (ps == 0 || merge)
@@ -1218,8 +1232,14 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   ST_TRY(check_common(d, G));
   FwdPlan p;
   ST_TRY(read_opts(opts, &p));
-  if (p.boundary == SWEEP_BOUNDARY_PERIODIC)
-    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint of periodic passes is not implemented");
+  const bool periodic = p.boundary == SWEEP_BOUNDARY_PERIODIC;
+  if (periodic && (p.merge && p.n_scat > 1))
+    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint of the merged periodic/scattering order is not implemented");
+  if (periodic && (p.pbc_tol > 0.0 || p.warm))
+    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint needs a fixed number of passes from zero inflow "
+                                       "(no pbc_tol, no warm_start)");
+  if (periodic && !d->has_shift)
+    return fail(SWEEP_ERR_INVALID_ARG, "periodic boundaries need meshes built with face_shift");
   if (!kappa || !emission || !saved || !dL_dJ || !dL_dabsorbed || !dL_dkappa || !dL_demission)
     return fail(SWEEP_ERR_INVALID_ARG, "missing array argument");
   const size_t need = sweep_saved_bytes(d, G, opts);
@@ -1229,21 +1249,35 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   StreamScope stream_scope(s);
   const int64_t CG = d->C_total * G;
   const int64_t DCG = CG * d->D;
+  // P passes per iteration: x^0..x^{P-1}; the last iteration's are in `saved`
+  // (x^{P-1} first, the others after the checkpoints), earlier iterations'
+  // are recomputed into phi_a (x^{P-1}) and xpass (the others)
+  const int P = periodic ? p.n_pbc : 1;
   ST_TRY(ensure_mesh_tables(d));
   HIP_TRY(d->lam.alloc(4 * DCG));
   HIP_TRY(d->gsrc.alloc(4 * CG));
   HIP_TRY(d->dk64.alloc(8 * CG));
   HIP_TRY(d->de64.alloc(8 * CG));
   if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
+  if (p.n_scat > 1 && P > 1) HIP_TRY(d->xpass.alloc(4 * DCG * (P - 1)));
+  if (P > 1) HIP_TRY(d->pbc_extra.alloc(8 * DCG));
+  if (periodic) HIP_TRY(d->pin.alloc(4 * DCG));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   const float* phi_final = (const float*)saved;
   auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
-  // reverse iterations: recompute phi of iteration `it` (all but the last, which
-  // was saved), sweep the adjoint, accumulate the gradients and the adjoint
-  // source of iteration it - 1
+  auto xp = [&](int it, int ps) -> float* {
+    const bool last = it == p.n_scat - 1;
+    if (ps == P - 1) return last ? (float*)saved : d->phi_a.as<float>();
+    return last ? (float*)saved + DCG + (int64_t)p.n_scat * CG + (int64_t)ps * DCG
+                : d->xpass.as<float>() + (int64_t)ps * DCG;
+  };
+  // reverse iterations: recompute the passes of iteration `it` (all but the last,
+  // which were saved), run the reverse passes (the last with the loss source, the
+  // earlier ones fed through the periodic faces by the later pass's adjoint),
+  // accumulate the gradients and the adjoint source of iteration it - 1
   auto body = [&](hipStream_t st) -> sweep_status_t {
     HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(),
                                    ckpt(p.n_scat - 1), p.albedo, G, d->C_total,
@@ -1251,32 +1285,54 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                    d->de64.as<double>(), st));
     for (int it = p.n_scat - 1; it >= 0; --it) {
       const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
-      const float* phi_it = phi_final;
       if (it != p.n_scat - 1) {
         ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
-        ST_TRY(run_sweep(d, false, p, G, nullptr, d->phi_a.as<float>(), nullptr, st));
-        phi_it = d->phi_a.as<float>();
+        for (int ps = 0; ps < P; ++ps)
+          ST_TRY(run_sweep(d, false, p, G, ps > 0 ? xp(it, ps - 1) : nullptr, xp(it, ps),
+                           periodic ? d->pin.as<float>() : nullptr, st));
       }
-      ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
-      ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, st));
-      sweep::AdjReduceArgs q{};
-      q.D = d->D;
-      q.G = G;
-      q.C_total = d->C_total;
-      q.law = p.law;
-      q.n_meshes = d->n_meshes;
-      q.mesh_off = d->mesh_off_d.as<int32_t>();
-      q.aperp = d->aperp.as<float>();
-      q.gsrc = d->gsrc.as<float>();
-      q.lam = d->lam.as<float>();
-      q.phi = phi_it;
-      q.kappa = kappa;
-      q.vol = d->vol.as<float>();
-      q.jsum_prev = jprev;
-      q.albedo = p.albedo;
-      q.inv_D = 1.0f / (float)d->D;
-      q.gsrc_next = d->gsrc.as<float>();
-      HIP_TRY(sweep::launch_adj_reduce(q, d->dk64.as<double>(), d->de64.as<double>(), st));
+      for (int ps = P - 1; ps >= 0; --ps) {
+        const bool loss_pass = ps == P - 1;
+        if (!loss_pass) {
+          // the periodic coupling's adjoint: lam (of pass ps + 1) to the partners
+          HIP_TRY(sweep::launch_fill_f32(reinterpret_cast<float*>(d->pbc_extra.p), 2 * DCG, 0.0f, st));
+          sweep::PbcAdjArgs b{};
+          b.units = d->units_d.as<Unit>();
+          b.n_units = (int32_t)d->units.size();
+          b.blk_base = d->blk_base.as<int32_t>();
+          b.sched = d->sched.as<int32_t>();
+          b.up_ptr = d->up_ptr.as<int64_t>();
+          b.up = d->up.as<int2>();
+          b.lam = d->lam.as<float>();
+          b.extra = d->pbc_extra.as<double>();
+          b.C_total = d->C_total;
+          b.G = G;
+          HIP_TRY(sweep::launch_pbc_adj(b, d->n_blocks, st));
+        }
+        ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st,
+                        loss_pass, loss_pass ? nullptr : d->pbc_extra.as<double>()));
+        ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, st));
+        sweep::AdjReduceArgs q{};
+        q.D = d->D;
+        q.G = G;
+        q.C_total = d->C_total;
+        q.law = p.law;
+        q.n_meshes = d->n_meshes;
+        q.mesh_off = d->mesh_off_d.as<int32_t>();
+        q.aperp = d->aperp.as<float>();
+        q.gsrc = d->gsrc.as<float>();
+        q.use_g = loss_pass ? 1 : 0;
+        q.accumulate = loss_pass ? 0 : 1;
+        q.lam = d->lam.as<float>();
+        q.phi = xp(it, ps);
+        q.kappa = kappa;
+        q.vol = d->vol.as<float>();
+        q.jsum_prev = jprev;
+        q.albedo = p.albedo;
+        q.inv_D = 1.0f / (float)d->D;
+        q.gsrc_next = d->gsrc.as<float>();
+        HIP_TRY(sweep::launch_adj_reduce(q, d->dk64.as<double>(), d->de64.as<double>(), st));
+      }
     }
     HIP_TRY(sweep::launch_d2f_pair(d->dk64.as<double>(), d->de64.as<double>(), dL_dkappa,
                                    dL_demission, CG, st));
@@ -1287,8 +1343,8 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                (uint64_t)saved_bytes, pkey(dL_dJ), pkey(dL_dabsorbed),
                                pkey(dL_dkappa), pkey(dL_demission)};
   opts_key(key, p);
-  for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->tden, &d->tsrc,
-                       &d->cds, &d->out_s})
+  for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->pbc_extra,
+                       &d->pin, &d->tden, &d->tsrc, &d->cds, &d->out_s})
     key.push_back(pkey(b->p));
   return run_graph(d, key, s, body);
 }

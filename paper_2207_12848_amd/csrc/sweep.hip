@@ -615,8 +615,12 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
       if (a.jsum_prev != nullptr) s += (double)a.albedo * kap * V * (double)a.jsum_prev[cg];
       s *= (double)a.inv_D;
     } else {
-      s = (double)a.gsrc[cg];
-      if (exp_law) s *= exp_r(ap, kap * V);
+      s = 0.0;
+      if (a.use_gsrc) {
+        s = (double)a.gsrc[cg];
+        if (exp_law) s *= exp_r(ap, kap * V);
+      }
+      if (a.extra != nullptr) s += a.extra[((int64_t)U.dir * a.C_total + ci) * a.G + g];
     }
     a.cds[t * a.G + g] = make_float2((float)den, (float)s);
   }
@@ -784,7 +788,7 @@ __global__ void k_adj_reduce(AdjReduceArgs a, double* dk, double* de) {
     const float* apc = a.aperp + (int64_t)a.D * a.mesh_off[lo] + (c - a.mesh_off[lo]);
     const double kap = (double)a.kappa[i];
     const double kV = kap * V;
-    const double g = (double)a.gsrc[i];
+    const double g = a.use_g ? (double)a.gsrc[i] : 0.0;
     dks = 0.0;
 #pragma unroll 4
     for (int d = 0; d < a.D; ++d) {
@@ -817,7 +821,31 @@ __global__ void k_adj_reduce(AdjReduceArgs a, double* dk, double* de) {
   const double invD = (double)a.inv_D;
   dk[i] += dks + alb * V * ls * prev * invD;
   de[i] += ls * invD;
-  a.gsrc_next[i] = (float)(alb * (double)a.kappa[i] * V * ls * invD);
+  const double gn = alb * (double)a.kappa[i] * V * ls * invD;
+  a.gsrc_next[i] = (float)(a.accumulate ? (double)a.gsrc_next[i] + gn : gn);
+}
+
+// Adjoint of the periodic coupling, one thread per task in schedule order: the
+// forward pass takes w x(nb) of the previous pass through each periodic inflow
+// entry -(nb + 1) of the task's upwind row, so the previous pass's adjoint gets
+// w lambda(c) at the partner nb (FP64 atomics: partners receive from several
+// tasks; the sum order is not fixed, which moves results by rounding only).
+__global__ __launch_bounds__(256) void k_pbc_adj(PbcAdjArgs a) {
+  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
+  const Unit U = a.units[u];
+  const int k = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
+  if (k >= U.n_cells) return;
+  const int64_t t = U.task_base + k;
+  const int c = a.sched[t];
+  const int64_t obase = (int64_t)U.dir * a.C_total + U.cell_off;
+  for (int64_t e = a.up_ptr[t]; e < a.up_ptr[t + 1]; ++e) {
+    const int2 en = a.up[e];
+    if (en.x >= 0) continue;
+    const int nb = -en.x - 1;
+    const double w = (double)__int_as_float(en.y);
+    for (int g = 0; g < a.G; ++g)
+      atomicAdd(&a.extra[(obase + nb) * a.G + g], w * (double)a.lam[(obase + c) * a.G + g]);
+  }
 }
 
 __global__ void k_d2f_pair(const double* a, const double* b, float* oa, float* ob, int64_t n) {
@@ -913,6 +941,12 @@ hipError_t launch_adj_init(const float* dJ, const float* dA, const float* kappa,
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adj_init, dim3(grid1d(n, 256)), dim3(256), 0, s, dJ, dA, kappa, vol,
                      jsum_last, albedo, G, n, gsrc, dk, de);
+  return hipGetLastError();
+}
+
+hipError_t launch_pbc_adj(const PbcAdjArgs& a, int32_t n_blocks, hipStream_t s) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pbc_adj, dim3(n_blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

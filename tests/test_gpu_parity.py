@@ -271,11 +271,34 @@ def test_autograd_function():
     _grad_close(e.grad.cpu().numpy(), de_ref)
 
 
-def test_periodic_adjoint_unsupported():
+@pytest.mark.parametrize("law,n_pbc,albedo,n_scat,G", [("upwind", 3, 0.0, 1, 1), ("upwind", 2, 0.4, 3, 2),
+                                                      ("exp", 3, 0.3, 2, 1)])
+def test_periodic_adjoint_matches_oracle(law, n_pbc, albedo, n_scat, G):
     sw = _sw()
-    w = W.small_random(800, 8, seed=61, periodic=True)
+    w = W.small_random(2000, 24, G=G, seed=61 + n_pbc, periodic=True, n_pbc=n_pbc, n_src=4,
+                       albedo=albedo, n_scat=n_scat, tau=2.0)
+    w = dict(w, law=law)
+    rng = np.random.default_rng(12)
+    C = len(w["meshes"][0]["cell_volume"])
+    gJ = rng.random((C, G)).astype(np.float32)
+    gA = rng.random((C, G)).astype(np.float32)
+    dk_ref, de_ref = oracle.adjoint(w, gJ, gA)
     dag = sw.build_dag(w["meshes"], w["dirs"])
     k, e = _dev(w)
-    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic")
-    with pytest.raises(sw.SweepError, match="UNSUPPORTED"):
-        sw.adjoint(dag, k, e, saved, torch.ones_like(k), torch.ones_like(k), boundary="periodic")
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, **_opts(w))
+    dk, de = sw.adjoint(dag, k, e, saved, torch.tensor(gJ, device="cuda"),
+                        torch.tensor(gA, device="cuda"), **_opts(w))
+    _grad_close(dk.cpu().numpy(), dk_ref)
+    _grad_close(de.cpu().numpy(), de_ref)
+
+
+def test_periodic_adjoint_refuses_what_it_does_not_cover():
+    sw = _sw()
+    w = W.small_random(800, 8, seed=61, periodic=True, n_pbc=3)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic", n_pbc=3)
+    for extra in (dict(pbc_tol=0.1), dict(merge=True, n_scat=2, albedo=0.3)):
+        with pytest.raises(sw.SweepError, match="UNSUPPORTED"):
+            sw.adjoint(dag, k, e, saved, torch.ones_like(k), torch.ones_like(k),
+                       boundary="periodic", n_pbc=3, **extra)

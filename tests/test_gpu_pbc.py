@@ -39,7 +39,11 @@ def test_warm_start_matches_oracle_and_continues_the_passes():
     w = W.small_random(3000, 24, G=2, seed=96, periodic=True, n_src=6, tau=2.0)
     dag = sw.build_dag(w["meshes"], w["dirs"])
     k, e = _dev(w)
-    _, _, _, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic", n_pbc=3)
+    # one workspace for both calls, sized for the larger (it keeps every pass's phi)
+    import ctypes
+    nbytes = sw.sweep_saved_bytes(dag.handle, 2, ctypes.byref(sw._fwd_opts(boundary="periodic", n_pbc=4)))
+    saved = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    sw.forward(dag, k, e, saved=saved, boundary="periodic", n_pbc=3)
     J, A, tot, _ = sw.forward(dag, k, e, saved=saved, boundary="periodic", n_pbc=4, warm_start=True)
     torch.cuda.synchronize()
     ra = oracle.forward(dict(w, n_pbc=3), want_phi=True)

@@ -595,6 +595,7 @@ __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_unit
   return lo;
 }
 
+template <bool EXP_LAW>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
   const Unit U = a.units[u];
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   for (int g = 0; g < a.G; ++g) {
     const int64_t cg = ci * a.G + g;
     const double kap = (double)a.kappa[cg];
-    const bool exp_law = a.law == SWEEP_LAW_EXP;
+    const bool exp_law = EXP_LAW;
     const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
     double s;
     if (a.emission != nullptr) {
@@ -887,7 +888,8 @@ hipError_t launch_sweep_adj(const SweepArgs& a, int32_t gn, int32_t grid, int32_
 
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(n_blocks), dim3(256), 0, s, a);
+  if (a.law == SWEEP_LAW_EXP) hipLaunchKernelGGL(k_prep<true>, dim3(n_blocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_prep<false>, dim3(n_blocks), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_prep_order, dim3(n_blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -86,3 +86,13 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(n, "size")] == ctypes.sizeof(st), n
         for f in st._fields_:
             assert got[(n, f[0])] == getattr(st, f[0]).offset, (n, f[0])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus 2 exits with a message before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr

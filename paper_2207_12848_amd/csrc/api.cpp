@@ -1031,9 +1031,11 @@ sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, i
 size_t sweep_saved_bytes(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
   if (!dag_ok(d) || G < 1) return 0;
   const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
-  // periodic (nested order): phi of the passes before the last, for the adjoint
-  const bool periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC && !opts->merge;
-  const size_t extra = periodic ? (size_t)std::max(0, opts->n_pbc - 1) * d->D : 0;
+  // periodic (nested order; merge only takes effect with n_scat > 1): phi of the
+  // passes before the last, for the adjoint
+  const bool nested_periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC &&
+                               !(opts->merge && n_scat > 1);
+  const size_t extra = nested_periodic ? (size_t)std::max(0, opts->n_pbc - 1) * d->D : 0;
   return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat + extra);
 }
 

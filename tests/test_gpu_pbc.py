@@ -118,3 +118,23 @@ def test_convergence_threshold_matches_oracle():
     for bad in (dict(merge=True, n_scat=2, albedo=0.3), dict(use_graph=True)):
         with pytest.raises(sw.SweepError, match="INVALID_ARG"):
             sw.forward(dag, k, e, boundary="periodic", n_pbc=5, pbc_tol=tol, **bad)
+
+
+def test_merge_without_scattering_keeps_the_nested_workspace():
+    """merge only takes effect with several source iterations; with n_scat = 1 the
+    forward is the nested order and keeps every pass for the adjoint, so the
+    workspace size must include them (regression)."""
+    sw = _sw()
+    w = W.small_random(1500, 8, G=1, seed=100, periodic=True, n_pbc=3, n_src=4, tau=2.0)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    o = dict(boundary="periodic", n_pbc=3, merge=True)
+    assert dag.saved_bytes(1, **o) == dag.saved_bytes(1, boundary="periodic", n_pbc=3)
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, **o)
+    gJ = torch.ones_like(k)
+    gA = torch.zeros_like(k)
+    dk, de = sw.adjoint(dag, k, e, saved, gJ, gA, **o)
+    dk_ref, de_ref = oracle.adjoint(w, np.ones((1500, 1)), np.zeros((1500, 1)))
+    from tests.test_gpu_parity import _grad_close
+    _grad_close(dk.cpu().numpy(), dk_ref)
+    _grad_close(de.cpu().numpy(), de_ref)

@@ -22,13 +22,10 @@
  *  Aperp_c = sum of w over outflow faces, S_c = L_c / D (+ scattering source).
  *  Vacuum walls bring no inflow (sec. 2.5, fixed boundaries with I = 0).
  *
- *  Schedule (algorithm 2, single-core sweep): count the upwind dependencies of
- *  every task, queue the tasks with none, then repeatedly take the first task
- *  of the queue, solve it, decrement the counts of its downwind neighbours and
- *  queue those reaching zero.  Tasks of different directions never interact,
- *  so each direction gets its own FIFO (directions may run on separate
- *  threads; results do not depend on it).  A task's level is 0 without
- *  upwind tasks, else 1 + max level of its upwind tasks.
+ *  Schedule (algorithm 2): Kahn's topological traversal with a FIFO, one per
+ *  direction since tasks of different directions never interact (directions
+ *  may run on separate threads; results do not depend on it).  A task's level
+ *  is 0 without upwind tasks, else 1 + max level of its upwind tasks.
  *
  *  Exponential cell law (the attenuation form 1 - e^{-dn sigma} of the
  *  scattering test, sec. 3.3,

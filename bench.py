@@ -19,7 +19,7 @@ dominant kernel (HIP-event timing inside the timed region), the plain per-direct
 form of the same step, and the FP64 CPU oracle timed on the host with its parity
 check of the GPU outputs.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2_plain_scale]
+    python bench.py [--steps K] [--warmup W] [--workload c3_batched_groups]
 """
 from __future__ import annotations
 
@@ -122,44 +122,38 @@ def updates_per_pass(w: dict) -> int:
 
 # ------------------------------------------------------------------ CPU baseline
 CPU_SAMPLE_UPDATES = 3.0e8  # about 10-30 s of the oracle on a few dozen host threads
+PLAIN_SAMPLE_UPDATES = 1.5e8  # a few seconds of the plain form
 
 
-def cpu_baseline(w: dict, gpu: dict, n_updates: int) -> dict:
-    """The FP64 oracle on the host, timed over one full step (forward and adjoint) of
-    the same workload, and its element-wise comparison with the GPU outputs.  A step
-    larger than CPU_SAMPLE_UPDATES is sampled: the oracle then runs the same step
-    for the first k directions only (same meshes, fields and iterations), timed per
-    update, and no comparison is made."""
-    import numpy as np
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
 
-    import oracle
-    oracle.build()
-    do_adj = w.get("boundary", "vacuum") != "periodic"
+
+def sample_dirs(w: dict, n_updates: int) -> int:
+    """Directions of the oracle's bounded sample (all of them when the step is small)."""
     D = len(w["dirs"])
-    k = D
-    if n_updates > CPU_SAMPLE_UPDATES:
-        k = max(1, int(D * CPU_SAMPLE_UPDATES / n_updates))
-    ws = w if k == D else dict(w, dirs=np.ascontiguousarray(w["dirs"][:k]))
-    sample_updates = n_updates * k // D
-    t0 = time.perf_counter()
-    ref = oracle.forward(ws)
-    dk = de = None
-    if do_adj:
-        gJ, gA = oracle.absorbed_loss_grads(ws)
-        dk, de = oracle.adjoint(ws, gJ, gA)
-    dt = time.perf_counter() - t0
-    passes = n_updates // updates_per_pass(w)
-    cores = oracle.num_threads()
-    out = {"value": sample_updates / dt, "unit": "cell-direction updates/s", "cores": cores,
-           "kind": "oracle",
-           "sample": "%s of the same workload (%d updates: forward%s, %d pass(es)), FP64, "
-                     "%.1f s on %d OpenMP threads" % (
-                         "one full step" if k == D else "one step over the first %d of %d "
-                         "directions" % (k, D), sample_updates,
-                         " + adjoint" if do_adj else "", passes, dt, cores),
-           "parity_vs_gpu": None}
-    if k != D:
-        return out
+    if n_updates <= CPU_SAMPLE_UPDATES:
+        return D
+    return max(1, int(D * CPU_SAMPLE_UPDATES / n_updates))
+
+
+def parity(gpu: dict, ref: dict, dk, de) -> dict:
+    """Element-wise comparison of GPU outputs with the oracle's (the bars of the tests)."""
+    import numpy as np
 
     def rel(a, b, floor=1e-20):
         a = np.asarray(a, np.float64)
@@ -171,17 +165,51 @@ def cpu_baseline(w: dict, gpu: dict, n_updates: int) -> dict:
     par = dict(J=rel(gpu["J"], ref["J"]), absorbed=rel(gpu["absorbed"], ref["absorbed"]))
     tg = np.asarray(gpu["totals"], np.float64)
     tr = ref["totals"]
-    par["totals_max_rel"] = float(np.max(np.abs(tg[..., :6] - tr[..., :6]) /
-                                         np.maximum(np.abs(tr[..., :6]), 1e-300)))
-    if do_adj:
-        for key, a, b in (("dL_dkappa", gpu["dk"], dk), ("dL_demission", gpu["de"], de)):
-            a = np.asarray(a, np.float64)
-            par[key] = dict(l2_rel=float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
+    keep = np.abs(tr[..., :5]) > 0
+    par["totals_max_rel"] = float(np.max(np.where(keep, np.abs(tg[..., :5] - tr[..., :5]) /
+                                                  np.maximum(np.abs(tr[..., :5]), 1e-300), 0.0)))
+    for key, a, b in (("dL_dkappa", gpu["dk"], dk), ("dL_demission", gpu["de"], de)):
+        a = np.asarray(a, np.float64)
+        par[key] = dict(l2_rel=float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)))
     ok = (par["J"]["max_rel"] <= 1e-5 and par["absorbed"]["max_rel"] <= 1e-5 and
-          all(par[key]["l2_rel"] <= 1e-5 for key in ("dL_dkappa", "dL_demission") if key in par))
+          par["J"]["l1_rel"] <= 1e-5 and par["absorbed"]["l1_rel"] <= 1e-5 and
+          par["totals_max_rel"] <= 1e-5 and
+          all(par[key]["l2_rel"] <= 1e-5 for key in ("dL_dkappa", "dL_demission")))
     par["pass_1e-5"] = bool(ok)
-    out["parity_vs_gpu"] = par
-    return out
+    return par
+
+
+def cpu_baseline(w: dict, n_updates: int, gpu_full: dict, gpu_run) -> dict:
+    """The FP64 oracle on the host, timed over one step (forward and adjoint) of the
+    same workload, and its element-wise comparison with the GPU.  A step larger than
+    CPU_SAMPLE_UPDATES is sampled: the oracle then runs the same step for the first
+    k directions only (same meshes, fields, passes and iterations), timed per update,
+    and the GPU runs that sample too (untimed) for the comparison."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    D = len(w["dirs"])
+    k = sample_dirs(w, n_updates)
+    ws = w if k == D else dict(w, dirs=np.ascontiguousarray(w["dirs"][:k]))
+    sample_updates = n_updates * k // D
+    t0 = time.perf_counter()
+    ref = oracle.forward(ws)
+    gJ, gA = oracle.absorbed_loss_grads(ws)
+    dk, de = oracle.adjoint(ws, gJ, gA)
+    dt = time.perf_counter() - t0
+    passes = n_updates // updates_per_pass(w)
+    cores = oracle.num_threads()
+    gpu = gpu_full if k == D else gpu_run(ws)
+    return {"value": sample_updates / dt, "unit": "cell-direction updates/s", "cores": cores,
+            "kind": "oracle", "host": host_cpu(),
+            "sample": "%s of the same workload (%d updates: forward + adjoint, %d pass(es)), "
+                      "FP64, %.1f s on %d OpenMP threads" % (
+                          "one full step" if k == D else "one step over the first %d of %d "
+                          "directions" % (k, D), sample_updates, passes, dt, cores),
+            "parity_vs_gpu": dict(parity(gpu, ref, dk, de),
+                                  sample="all directions of the timed step" if k == D else
+                                  "the GPU on the oracle's %d-direction sample" % k)}
 
 
 # ------------------------------------------------------------------ copy calibration
@@ -275,7 +303,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2_plain_scale", choices=WORKLOADS)
+    ap.add_argument("--workload", default="c3_batched_groups", choices=WORKLOADS)
     ap.add_argument("--block", type=int, default=0, help="sweep workgroup size (0 = tuned)")
     ap.add_argument("--ring", type=int, default=0, help="LDS ring capacity (0 = tuned)")
     ap.add_argument("--hii-side", type=int, default=32,
@@ -324,8 +352,6 @@ def main() -> int:
     emission = torch.as_tensor(w["emission"]).to(dev).contiguous()
     gJ = torch.zeros((C, G), dtype=torch.float32, device=dev)
     gA = torch.full((C, G), 1.0 / (4.0 * math.pi), dtype=torch.float32, device=dev)
-    periodic = w.get("boundary", "vacuum") == "periodic"
-    do_adj = not periodic  # the adjoint of periodic passes is not implemented
     fo = fwd_opts(w, "batched", args.block, args.ring)
 
     # validate the mesh once; the timed steps rebuild the graphs without re-checking it
@@ -338,18 +364,18 @@ def main() -> int:
         log("tuned launch shape: %s" % tuned)
     dag0.close()
 
-    def step(form="batched"):
+    def step(form="batched", dirs=None):
+        """build + forward (saving for the adjoint) + adjoint of the absorbed-photon loss"""
         o = dict(fo, form=form)
-        dag = sw.build_dag(meshes, w["dirs"], validate=False)
-        J, A, tot, saved = sw.forward(dag, kappa, emission, save_for_adjoint=do_adj, **o) \
-            if do_adj else (*sw.forward(dag, kappa, emission, **o), None)
-        dk = de = None
-        if do_adj:
-            dk, de = sw.adjoint(dag, kappa, emission, saved, gJ, gA, **o)
+        dag = sw.build_dag(meshes, w["dirs"] if dirs is None else dirs, validate=False)
+        J, A, tot, saved = sw.forward(dag, kappa, emission, save_for_adjoint=True, **o)
+        dk, de = sw.adjoint(dag, kappa, emission, saved, gJ, gA, **o)
         return dag, J, A, tot, dk, de
 
+    # every pass of the forward is a sweep of all C * D * G updates; the adjoint
+    # sweeps every pass again in reverse (its recomputed passes are not counted)
     passes_fwd = int(fo["n_pbc"]) * int(fo["n_scat"])
-    passes_adj = int(fo["n_scat"]) if do_adj else 0
+    passes_adj = passes_fwd
     n_updates = C * D * G * (passes_fwd + passes_adj)
 
     for i in range(args.warmup):
@@ -400,26 +426,41 @@ def main() -> int:
             "kernel": dom, "bytes_per_launch": pk["alg_bytes_per_launch"],
             "avg_launch_ms": round(pk["avg_launch_ms"], 4)}
 
-    # plain per-direction form of the same step, for comparison
+    def run_sample(ws):
+        """The batched GPU step on a direction sample (untimed), as numpy outputs."""
+        dag, J, A, tot, dk, de = step(dirs=ws["dirs"])
+        torch.cuda.synchronize()
+        r = dict(J=J.cpu().numpy(), absorbed=A.cpu().numpy(), totals=tot.cpu().numpy(),
+                 dk=dk.cpu().numpy(), de=de.cpu().numpy())
+        dag.close()
+        return r
+
+    # plain per-(mesh, direction, group) form of the same step, for comparison: on the
+    # first few directions when the whole step would take long in this form (its
+    # launches run one after another, so its time per update does not depend on D)
     plain = None
     if not args.no_plain:
-        out = step("plain")
+        kp = D if n_updates <= PLAIN_SAMPLE_UPDATES else max(1, int(D * PLAIN_SAMPLE_UPDATES / n_updates))
+        pdirs = np.ascontiguousarray(w["dirs"][:kp])
+        out = step("plain", dirs=pdirs)
         out[0].close()
         torch.cuda.synchronize()
-        reps = 1
         t0 = time.perf_counter()
-        for _ in range(reps):
-            out = step("plain")
-            out[0].close()
+        out = step("plain", dirs=pdirs)
         torch.cuda.synchronize()
-        pms = (time.perf_counter() - t0) * 1e3 / reps
-        plain = {"value": n_updates / (pms * 1e-3), "ms_per_step": round(pms, 3),
-                 "batched_speedup": round(pms / ms, 2)}
-        log("plain form: %.3f ms/step" % pms)
+        pms = (time.perf_counter() - t0) * 1e3
+        out[0].close()
+        pupd = n_updates * kp // D
+        pv = pupd / (pms * 1e-3)
+        plain = {"value": pv, "ms_per_step": round(pms, 3), "directions": kp,
+                 "updates_per_step": pupd, "batched_speedup": round(value / pv, 2),
+                 "sample": "one step over all directions" if kp == D else
+                           "one step over the first %d of %d directions" % (kp, D)}
+        log("plain form: %.3f ms/step over %d directions" % (pms, kp))
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, gpu, n_updates)
+        cpu = cpu_baseline(w, n_updates, gpu, run_sample)
         log("cpu baseline: %.3g updates/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     depth_max = int(info["max_depth"])
@@ -442,7 +483,7 @@ def main() -> int:
                    "meshes": len(w["meshes"]), "boundary": w.get("boundary", "vacuum"),
                    "n_pbc": fo["n_pbc"], "n_scat": fo["n_scat"], "albedo": fo["albedo"],
                    "law": fo["law"],
-                   "adjoint": do_adj, "updates_per_step": n_updates, "form": "batched",
+                   "adjoint": True, "updates_per_step": n_updates, "form": "batched",
                    "block": fo["block"] or "default", "ring": fo["ring"] or "default"},
         "roofline": roof,
         "cpu_baseline": cpu,

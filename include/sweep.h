@@ -49,9 +49,16 @@
  *     ([C_total][G], row-major), cells of all meshes concatenated in mesh
  *     order (global cell id = mesh offset + local id);
  *   - work is enqueued on the caller's `stream` (a hipStream_t, NULL = null
- *     stream); only sweep_build_dag, sweep_dag_info, sweep_dag_export,
- *     sweep_tune, sweep_ion_step and sweep_forward with pbc_tol synchronise
- *     that stream;
+ *     stream); only sweep_build_dag, sweep_dag_export, sweep_dag_level_widths,
+ *     sweep_tune, sweep_ion_step, sweep_sync, and sweep_forward /
+ *     sweep_adjoint with pbc_tol or check set synchronise that stream;
+ *   - inputs that only the kernels see (kappa and emission negative or not
+ *     finite, a task whose denominator Aperp + kappa V is not positive, loss
+ *     gradients that are not finite) raise an error flag kept with the DAG;
+ *     the next call on that DAG that synchronises (sweep_sync, sweep_dag_export,
+ *     sweep_tune, sweep_ion_step, pbc_tol or check) returns
+ *     SWEEP_ERR_INVALID_ARG for it and clears it.  The outputs of the call that
+ *     saw such input are not meaningful;
  *   - the caller owns every array argument and output; outputs are fully
  *     overwritten; the library owns the DAG object and its internal buffers.
  */
@@ -150,6 +157,9 @@ typedef struct {
                         maximum (sec. 2.7).  Reads E back after every pass, so it
                         synchronises `stream` per pass and cannot be combined with
                         use_graph or merge.  0 = always n_pbc passes */
+  int32_t check;     /* 1: synchronise `stream` at the end of the call and return
+                        SWEEP_ERR_INVALID_ARG if the kernels met invalid input (see the
+                        conventions above); 0: leave it to the next synchronising call */
 } sweep_fwd_opts_t;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -204,7 +214,9 @@ size_t sweep_saved_bytes(sweep_dag_t dag, int32_t G, const sweep_fwd_opts_t* opt
  *                    emitted + pbc_in + scat_net = absorbed + escaped + pbc_out
  *   saved:           DEVICE workspace of sweep_saved_bytes() bytes, or NULL
  *   opts:            may be NULL for defaults (vacuum, one pass, no scattering)
- * Errors: INVALID_ARG, UNSUPPORTED, OOM, HIP. */
+ * Errors: INVALID_ARG (with check: also invalid kappa or emission),
+ * UNSUPPORTED (a mesh whose cells x G x 4 bytes exceed the kernels' 32-bit
+ * buffer range), OOM, HIP. */
 sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, const float* emission,
                              const sweep_fwd_opts_t* opts, float* J, float* absorbed,
                              double* totals, void* saved, size_t saved_bytes, void* stream);
@@ -225,6 +237,24 @@ sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const void* saved, size_t saved_bytes, const float* dL_dJ,
                              const float* dL_dabsorbed, float* dL_dkappa, float* dL_demission,
                              void* stream);
+
+/* Synchronise `stream` and report the invalid input that the kernels of
+ * earlier calls on `dag` met (see the conventions above); clears the report.
+ * Errors: INVALID_ARG (there was such input), NOT_BUILT, HIP. */
+sweep_status_t sweep_sync(sweep_dag_t dag, void* stream);
+
+/* Critical-path length of every (mesh, direction) graph: depth[m * n_dirs + d]
+ * (HOST, n_meshes * n_dirs int32), the number of levels, i.e. of steps of a
+ * level-synchronous sweep (sec. 2.5's pipe length).  Host data, no sync. */
+sweep_status_t sweep_dag_depths(sweep_dag_t dag, int32_t* depth);
+
+/* Tasks per level, summed over the directions of mesh `mesh` (every mesh if
+ * mesh = -1): width[l] for l < n_levels (HOST int64; levels past a graph's
+ * depth count nothing).  This is how many tasks a level-synchronous sweep has
+ * in flight at each step, the GPU analogue of the paper's pipe fill (sec. 2.5).
+ * Synchronises `stream`.  Errors: INVALID_ARG, NOT_BUILT, OOM, HIP. */
+sweep_status_t sweep_dag_level_widths(sweep_dag_t dag, int32_t mesh, int64_t* width,
+                                      int32_t n_levels, void* stream);
 
 /* Autotuner of the sweep's launch shape: times `reps` forward sweeps (after
  * one untimed sweep) of the batched form for every candidate number of threads
@@ -272,6 +302,14 @@ typedef struct {
 sweep_status_t sweep_ion_step(sweep_dag_t dag, const float* absorbed, const sweep_ion_params_t* p,
                               double t_left, double* neutral, float* kappa, double* dt,
                               void* stream);
+
+/* The absorption coefficient of the neutral hydrogen for the next sweep of a
+ * photoionisation run: kappa[c] = n_H y[c] sigma_H length_unit (DEVICE
+ * neutral [C_total] FP64 in, kappa [C_total] FP32 out), the value sweep_ion_step
+ * writes after each step; for the first sweep of a run.  Uses n_H, sigma_H and
+ * length_unit of `p`.  Errors: INVALID_ARG, NOT_BUILT, HIP. */
+sweep_status_t sweep_ion_kappa(sweep_dag_t dag, const sweep_ion_params_t* p, const double* neutral,
+                               float* kappa, void* stream);
 
 /* Kernel timing with HIP events (for measurement tools).  While enabled, every
  * launch of the library's main kernels is bracketed by two hipEvents recorded

@@ -20,7 +20,8 @@ from . import _binding as B
 from ._binding import (SweepError, SweepLibraryError, sweep_adjoint, sweep_build_dag,  # noqa: F401
                        sweep_dag_export, sweep_dag_info, sweep_destroy_dag, sweep_forward,
                        sweep_last_error, sweep_profile_enable, sweep_profile_read,
-                       sweep_ion_step, sweep_profile_reset, sweep_saved_bytes, sweep_tune)
+                       sweep_ion_step, sweep_profile_reset, sweep_saved_bytes, sweep_tune,
+                       sweep_sync, sweep_dag_depths, sweep_dag_level_widths, sweep_ion_kappa)
 
 TOTAL_NAMES = ("emitted", "absorbed", "escaped", "pbc_in", "pbc_out", "scat_net", "pbc_err_max",
                "pbc_err_l1")
@@ -54,7 +55,7 @@ def upload_mesh(mesh: dict, device="cuda") -> dict:
 
 def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
               use_graph=False, law="upwind", merge=False, warm_start=False,
-              pbc_tol=0.0) -> B.sweep_fwd_opts_t:
+              pbc_tol=0.0, check=False) -> B.sweep_fwd_opts_t:
     o = B.sweep_fwd_opts_t()
     o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
     o.n_pbc = int(n_pbc)
@@ -68,6 +69,7 @@ def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", 
     o.merge = int(bool(merge))
     o.warm_start = int(bool(warm_start))
     o.pbc_tol = float(pbc_tol)
+    o.check = int(bool(check))
     return o
 
 
@@ -91,6 +93,23 @@ class Dag:
         i = B.sweep_dag_info_t()
         B.check(sweep_dag_info(self.handle, ctypes.byref(i)))
         return {k: getattr(i, k) for k, _ in B.sweep_dag_info_t._fields_}
+
+    def depths(self) -> np.ndarray:
+        """Critical-path length of every (mesh, direction) graph, int32 [n_meshes, n_dirs]."""
+        d = np.empty(len(self.mesh_cells) * self.n_dirs, np.int32)
+        B.check(sweep_dag_depths(self.handle, d.ctypes.data))
+        return d.reshape(len(self.mesh_cells), self.n_dirs)
+
+    def level_widths(self, mesh: int = -1, stream=None) -> np.ndarray:
+        """Tasks per level summed over the directions of `mesh` (-1: every mesh), int64."""
+        n = int(self.info()["max_depth"])
+        w = np.zeros(n, np.int64)
+        B.check(sweep_dag_level_widths(self.handle, int(mesh), w.ctypes.data, n, _stream(stream)))
+        return w
+
+    def sync(self, stream=None) -> None:
+        """Synchronise the stream; raises SweepError if earlier calls met invalid input."""
+        B.check(sweep_sync(self.handle, _stream(stream)))
 
     def export(self, stream=None):
         """(level, order, indeg) as int32 numpy arrays laid out [mesh][direction][cell]."""
@@ -255,7 +274,11 @@ def evolve_ionisation(dag: Dag, emission: torch.Tensor, params: dict, t_end: flo
     C = dag.n_cells
     dev = emission.device
     y = torch.ones(C, dtype=torch.float64, device=dev) if neutral is None else neutral
-    kappa = (y * (params["n_H"] * params["sigma_H"] * params["length_unit"])).float().reshape(C, 1)
+    kappa = torch.empty((C, 1), dtype=torch.float32, device=dev)
+    p = B.sweep_ion_params_t()
+    for k in ("n_H", "sigma_H", "length_unit"):
+        setattr(p, k, float(params[k]))
+    B.check(sweep_ion_kappa(dag.handle, ctypes.byref(p), _ptr(y), _ptr(kappa), _stream(None)))
     o = dict(opts, law="exp")
     t, step = 0.0, 0
     while t < t_end and step < max_steps:

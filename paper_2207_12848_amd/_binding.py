@@ -23,7 +23,8 @@ SWEEP_LAW_UPWIND, SWEEP_LAW_EXP = 0, 1
 EXPORTED = ("sweep_last_error", "sweep_build_dag", "sweep_destroy_dag", "sweep_dag_info",
             "sweep_dag_export", "sweep_saved_bytes", "sweep_forward", "sweep_adjoint",
             "sweep_tune", "sweep_ion_step", "sweep_profile_enable", "sweep_profile_reset",
-            "sweep_profile_read")
+            "sweep_profile_read", "sweep_sync", "sweep_dag_depths", "sweep_dag_level_widths",
+            "sweep_ion_kappa")
 
 
 class SweepLibraryError(RuntimeError):
@@ -69,7 +70,8 @@ class sweep_fwd_opts_t(ctypes.Structure):
                 ("albedo", ctypes.c_double), ("n_scat", ctypes.c_int32),
                 ("form", ctypes.c_int32), ("block", ctypes.c_int32), ("ring", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("law", ctypes.c_int32), ("merge", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("pbc_tol", ctypes.c_double)]
+                ("warm_start", ctypes.c_int32), ("pbc_tol", ctypes.c_double),
+                ("check", ctypes.c_int32)]
 
 
 _lib = None
@@ -101,6 +103,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sweep_profile_enable": (ctypes.c_int, [I32]),
         "sweep_profile_reset": (ctypes.c_int, []),
         "sweep_profile_read": (ctypes.c_int, [ctypes.c_char_p, P, P]),
+        "sweep_sync": (ctypes.c_int, [P, P]),
+        "sweep_dag_depths": (ctypes.c_int, [P, P]),
+        "sweep_dag_level_widths": (ctypes.c_int, [P, I32, P, I32, P]),
+        "sweep_ion_kappa": (ctypes.c_int, [P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -170,3 +176,19 @@ def sweep_profile_reset() -> int:
 
 def sweep_profile_read(kernel, launches, total_ms) -> int:
     return load().sweep_profile_read(kernel, launches, total_ms)
+
+
+def sweep_sync(dag, stream) -> int:
+    return load().sweep_sync(dag, stream)
+
+
+def sweep_dag_depths(dag, depth) -> int:
+    return load().sweep_dag_depths(dag, depth)
+
+
+def sweep_dag_level_widths(dag, mesh, width, n_levels, stream) -> int:
+    return load().sweep_dag_level_widths(dag, mesh, width, n_levels, stream)
+
+
+def sweep_ion_kappa(dag, params, neutral, kappa, stream) -> int:
+    return load().sweep_ion_kappa(dag, params, neutral, kappa, stream)

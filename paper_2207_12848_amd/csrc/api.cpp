@@ -246,6 +246,8 @@ struct sweep_dag_s {
       aperp, bnd, vol, counter, blk_base;
   int32_t n_blocks = 0;  // 256-task blocks over all units (prep kernel)
   int32_t max_depth = 0;
+  int32_t max_cells = 0;  // cells of the largest mesh
+  Buf flag;               // device error bits (see internal.h) raised by asynchronous calls
   // reduction tables (depend on G)
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
@@ -368,7 +370,7 @@ sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
 }
 
 struct FwdPlan {
-  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm;
+  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm, check;
   float albedo;
   double pbc_tol;
 };
@@ -386,6 +388,7 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   p->merge = o ? (o->merge != 0) : 0;
   p->warm = o ? (o->warm_start != 0) : 0;
   p->pbc_tol = o ? o->pbc_tol : 0.0;
+  p->check = o ? (o->check != 0) : 0;
   if (!(p->pbc_tol >= 0.0) || !std::isfinite(p->pbc_tol))
     return fail(SWEEP_ERR_INVALID_ARG, "pbc_tol must be finite and >= 0");
   if (p->law != SWEEP_LAW_UPWIND && p->law != SWEEP_LAW_EXP)
@@ -454,6 +457,7 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.tden = d->tden.as<float>();
   q.tsrc = d->tsrc.as<float>();
   q.cds = d->cds.as<float2>();
+  q.flag = d->flag.as<int32_t>();
   ProfScope ps("prep", s);
   HIP_TRY(sweep::launch_prep(q, d->n_blocks, s));
   return SWEEP_OK;
@@ -587,6 +591,34 @@ sweep_status_t check_common(sweep_dag_t d, int32_t G) {
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != d->device) return fail(SWEEP_ERR_INVALID_ARG, "DAG was built on device %d, current is %d", d->device, dev);
+  return SWEEP_OK;
+}
+
+// Reports (and clears) the invalid inputs the kernels of earlier asynchronous
+// calls on `d` flagged; synchronises `s`.
+sweep_status_t take_device_error(sweep_dag_t d, hipStream_t s) {
+  int32_t bits = 0;
+  HIP_TRY(hipMemcpyAsync(&bits, d->flag.p, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bits == 0) return SWEEP_OK;
+  HIP_TRY(sweep::launch_fill_i32(d->flag.as<int32_t>(), 1, 0, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::string what;
+  if (bits & sweep::kErrKappa) what += " kappa negative or not finite;";
+  if (bits & sweep::kErrEmission) what += " emission negative or not finite;";
+  if (bits & sweep::kErrCell) what += " a cell with Aperp + kappa V not positive and finite;";
+  if (bits & sweep::kErrGrad) what += " dL/dJ or dL/dabsorbed not finite;";
+  return fail(SWEEP_ERR_INVALID_ARG, "invalid input to an earlier sweep call on this DAG:%s its "
+                                     "outputs are not meaningful", what.c_str());
+}
+
+// Every array a sweep launch with G groups addresses through a buffer resource
+// stays within kMaxBufBytes.
+sweep_status_t check_buffer_range(sweep_dag_t d, int32_t G) {
+  if ((int64_t)d->max_cells * G * 4 > sweep::kMaxBufBytes)
+    return fail(SWEEP_ERR_UNSUPPORTED, "a mesh of %d cells with %d groups exceeds the sweep's "
+                "32-bit buffer range (%lld bytes per direction); use fewer groups per call",
+                d->max_cells, G, (long long)sweep::kMaxBufBytes);
   return SWEEP_OK;
 }
 
@@ -748,16 +780,18 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     md[m].n_cells = meshes[m].n_cells;
     md[m].cell_off = D->mesh_off[m];
   }
-  // compact FP32 face records for the row fill
+  // per-face neighbour codes and per-(direction, face) signed weights for the row fill
   int64_t n_faces_total = 0;
   for (int m = 0; m < n_meshes; ++m) n_faces_total += meshes[m].n_half_faces;
-  Buf frec;
-  HIP_TRY(frec.alloc(16 * n_faces_total));
+  Buf fcode, wface;
+  HIP_TRY(fcode.alloc(4 * n_faces_total));
+  HIP_TRY(wface.alloc(4 * (size_t)n_faces_total * n_dirs));
   {
     int64_t fo = 0;
     for (int m = 0; m < n_meshes; ++m) {
-      md[m].frec = frec.as<int4>() + fo;
-      HIP_TRY(sweep::launch_face_records(md[m], frec.as<int4>() + fo, s));
+      md[m].fcode = fcode.as<int32_t>() + fo;
+      md[m].face_off = fo;
+      HIP_TRY(sweep::launch_face_codes(md[m], fcode.as<int32_t>() + fo, s));
       fo += meshes[m].n_half_faces;
     }
   }
@@ -779,8 +813,6 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_up.alloc(4 * T));
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
-  Buf fmask;  // face bits per task (first 32 faces of the cell)
-  HIP_TRY(fmask.alloc(8 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
   HIP_TRY(cnt.alloc(4 * T));  // overflow counters of Kahn's algorithm
   HIP_TRY(inv.alloc(4 * T));
@@ -819,7 +851,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.rowlen_up = rowlen_up.as<int32_t>();
   a.rowlen_dn = rowlen_dn.as<int32_t>();
   a.aperp = D->aperp.as<float>();
-  a.fmask = fmask.as<uint2>();
+  a.wface = wface.as<float>();
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
   a.inv = inv.as<int32_t>();
@@ -914,10 +946,24 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
                               meshes[m].n_cells, s));
   std::vector<int32_t> depth(n_units);
   int32_t err = 0;
+  Buf ue_d;  // row entries per unit (the sweep addresses a unit's rows with 32-bit offsets)
+  HIP_TRY(ue_d.alloc(16 * (size_t)n_units));
+  HIP_TRY(sweep::launch_unit_entries(D->units_d.as<Unit>(), n_units, D->up_ptr.as<int64_t>(),
+                                     D->dn_ptr.as<int64_t>(), ue_d.as<int64_t>(), s));
+  std::vector<int64_t> ue(2 * (size_t)n_units);
+  HIP_TRY(hipMemcpyAsync(ue.data(), ue_d.p, 16 * (size_t)n_units, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(depth.data(), depth_d.p, 4 * n_units, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(&err, err_d.p, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (err) return fail(SWEEP_ERR_CYCLE, "a dependency graph is cyclic: some tasks never become ready");
+  for (int u = 0; u < n_units; ++u)
+    if (8 * std::max(ue[2 * u], ue[2 * u + 1]) > sweep::kMaxBufBytes)
+      return fail(SWEEP_ERR_UNSUPPORTED, "mesh %d, direction %d: %lld row entries exceed the sweep's "
+                  "32-bit buffer range", D->units[u].mesh, D->units[u].dir,
+                  (long long)std::max(ue[2 * u], ue[2 * u + 1]));
+  D->max_cells = max_cells;
+  HIP_TRY(D->flag.alloc(4));
+  HIP_TRY(sweep::launch_fill_i32(D->flag.as<int32_t>(), 1, 0, s));
   for (int u = 0; u < n_units; ++u) {
     D->units[u].depth = depth[u];
     D->max_depth = std::max(D->max_depth, depth[u]);
@@ -1008,7 +1054,7 @@ sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, i
     HIP_TRY(hipMemcpyAsync(sched.data(), d->sched.p, 4 * T, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(lp.data(), d->lp.p, 4 * lp.size(), hipMemcpyDeviceToHost, s));
   }
-  HIP_TRY(hipStreamSynchronize(s));
+  ST_TRY(take_device_error(d, s));
   // the schedule groups every unit's cells by level (level k = slots [lp[k], lp[k+1]));
   // the canonical order sorts each level by cell id
   for (const Unit& U : d->units) {
@@ -1044,6 +1090,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
                              double* totals, void* saved, size_t saved_bytes, void* stream) {
   g_err.clear();
   ST_TRY(check_common(d, G));
+  ST_TRY(check_buffer_range(d, G));
   FwdPlan p;
   ST_TRY(read_opts(opts, &p));
   if (!kappa || !emission || !J || !absorbed || !totals)
@@ -1165,7 +1212,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
             HIP_TRY(sweep::launch_totals(d->partial.as<double>(), d->mesh_blk_base.as<int32_t>(),
                                          d->n_meshes, G, totals, st));
             HIP_TRY(hipMemcpyAsync(tot_host.data(), totals, 8 * n_tot, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
+            ST_TRY(take_device_error(d, st));
             double emax = 0.0;
             for (int64_t i = 6; i < n_tot; i += 8) emax = std::max(emax, tot_host[i]);
             stop = emax < p.pbc_tol;
@@ -1214,15 +1261,19 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
                                  d->n_meshes, G, totals, st));
     return SWEEP_OK;
   };
-  if (!p.use_graph) return body(s);
-  std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
-                               pkey(totals), pkey(saved), (uint64_t)saved_bytes};
-  opts_key(key, p);
-  for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->pin_prev2, &d->jsum_a,
-                       &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
-                       &d->mesh_blk_base})
-    key.push_back(pkey(b->p));
-  return run_graph(d, key, s, body);
+  if (!p.use_graph) {
+    ST_TRY(body(s));
+  } else {
+    std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
+                                 pkey(totals), pkey(saved), (uint64_t)saved_bytes};
+    opts_key(key, p);
+    for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->pin_prev2,
+                         &d->jsum_a, &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
+                         &d->mesh_blk_base, &d->blk_mesh, &d->blk_cell0})
+      key.push_back(pkey(b->p));
+    ST_TRY(run_graph(d, key, s, body));
+  }
+  return p.check ? take_device_error(d, s) : SWEEP_OK;
 }
 
 sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
@@ -1232,6 +1283,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                              void* stream) {
   g_err.clear();
   ST_TRY(check_common(d, G));
+  ST_TRY(check_buffer_range(d, G));
   FwdPlan p;
   ST_TRY(read_opts(opts, &p));
   const bool periodic = p.boundary == SWEEP_BOUNDARY_PERIODIC;
@@ -1284,7 +1336,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
     HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(),
                                    ckpt(p.n_scat - 1), p.albedo, G, d->C_total,
                                    d->gsrc.as<float>(), d->dk64.as<double>(),
-                                   d->de64.as<double>(), st));
+                                   d->de64.as<double>(), d->flag.as<int32_t>(), st));
     for (int it = p.n_scat - 1; it >= 0; --it) {
       const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
       if (it != p.n_scat - 1) {
@@ -1340,15 +1392,19 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                    dL_demission, CG, st));
     return SWEEP_OK;
   };
-  if (!p.use_graph) return body(s);
-  std::vector<uint64_t> key = {2, (uint64_t)G, pkey(kappa), pkey(emission), pkey(saved),
-                               (uint64_t)saved_bytes, pkey(dL_dJ), pkey(dL_dabsorbed),
-                               pkey(dL_dkappa), pkey(dL_demission)};
-  opts_key(key, p);
-  for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->pbc_extra,
-                       &d->pin, &d->tden, &d->tsrc, &d->cds, &d->out_s})
-    key.push_back(pkey(b->p));
-  return run_graph(d, key, s, body);
+  if (!p.use_graph) {
+    ST_TRY(body(s));
+  } else {
+    std::vector<uint64_t> key = {2, (uint64_t)G, pkey(kappa), pkey(emission), pkey(saved),
+                                 (uint64_t)saved_bytes, pkey(dL_dJ), pkey(dL_dabsorbed),
+                                 pkey(dL_dkappa), pkey(dL_demission)};
+    opts_key(key, p);
+    for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->pbc_extra,
+                         &d->pin, &d->tden, &d->tsrc, &d->cds, &d->out_s})
+      key.push_back(pkey(b->p));
+    ST_TRY(run_graph(d, key, s, body));
+  }
+  return p.check ? take_device_error(d, s) : SWEEP_OK;
 }
 
 sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
@@ -1356,6 +1412,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
                           double* best_ms, void* stream) {
   g_err.clear();
   ST_TRY(check_common(d, G));
+  ST_TRY(check_buffer_range(d, G));
   FwdPlan p;
   ST_TRY(read_opts(opts, &p));
   if (!kappa || !emission || !best || !best_ms) return fail(SWEEP_ERR_INVALID_ARG, "missing argument");
@@ -1414,6 +1471,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != SWEEP_OK) return st;
+  ST_TRY(take_device_error(d, s));
   if (best_t < 0.0) return fail(SWEEP_ERR_UNSUPPORTED, "no launch shape fits the LDS");
   if (opts) *best = *opts;
   else std::memset(best, 0, sizeof(*best));
@@ -1454,12 +1512,63 @@ sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_
   HIP_TRY(sweep::launch_ion_limit(a, d->ion_min.as<unsigned long long>(), s));
   uint64_t bits = 0;
   HIP_TRY(hipMemcpyAsync(&bits, d->ion_min.p, 8, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
+  ST_TRY(take_device_error(d, s));
   double lim;
   std::memcpy(&lim, &bits, 8);
   const double step = std::min(std::min(p->dt_max, t_left), p->courant * lim);
   HIP_TRY(sweep::launch_ion_update(a, step, s));
   *dt = step;
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_sync(sweep_dag_t d, void* stream) {
+  g_err.clear();
+  if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
+  return take_device_error(d, (hipStream_t)stream);
+}
+
+sweep_status_t sweep_dag_depths(sweep_dag_t d, int32_t* depth) {
+  g_err.clear();
+  if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
+  if (!depth) return fail(SWEEP_ERR_INVALID_ARG, "depth is NULL");
+  for (size_t u = 0; u < d->units.size(); ++u) depth[u] = d->units[u].depth;
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_dag_level_widths(sweep_dag_t d, int32_t mesh, int64_t* width, int32_t n_levels,
+                                      void* stream) {
+  g_err.clear();
+  if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");
+  if (!width || n_levels < 0) return fail(SWEEP_ERR_INVALID_ARG, "width is NULL or n_levels < 0");
+  if (mesh < -1 || mesh >= d->n_meshes) return fail(SWEEP_ERR_INVALID_ARG, "mesh %d out of range", mesh);
+  if (n_levels == 0) return SWEEP_OK;
+  hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
+  Buf w;
+  HIP_TRY(w.alloc(8 * (size_t)n_levels));
+  HIP_TRY(hipMemsetAsync(w.p, 0, 8 * (size_t)n_levels, s));
+  HIP_TRY(sweep::launch_level_widths(d->units_d.as<Unit>(), (int32_t)d->units.size(),
+                                     d->lp.as<int32_t>(), mesh, w.as<int64_t>(), n_levels, s));
+  HIP_TRY(hipMemcpyAsync(width, w.p, 8 * (size_t)n_levels, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return SWEEP_OK;
+}
+
+sweep_status_t sweep_ion_kappa(sweep_dag_t d, const sweep_ion_params_t* p, const double* neutral,
+                               float* kappa, void* stream) {
+  g_err.clear();
+  ST_TRY(check_common(d, 1));
+  if (!p || !neutral || !kappa) return fail(SWEEP_ERR_INVALID_ARG, "missing argument");
+  if (!(p->n_H > 0.0) || !(p->sigma_H > 0.0) || !(p->length_unit > 0.0))
+    return fail(SWEEP_ERR_INVALID_ARG, "n_H, sigma_H and length_unit must be positive");
+  sweep::IonArgs a{};
+  a.n = d->C_total;
+  a.neutral = const_cast<double*>(neutral);
+  a.kappa = kappa;
+  a.n_H = p->n_H;
+  a.sigma_H = p->sigma_H;
+  a.length_unit = p->length_unit;
+  HIP_TRY(sweep::launch_ion_kappa(a, (hipStream_t)stream));
   return SWEEP_OK;
 }
 

@@ -60,6 +60,20 @@ __global__ __launch_bounds__(256) void k_ion_update(IonArgs a, double dt) {
   a.kappa[c] = (float)(a.n_H * yn * a.sigma_H * a.length_unit);
 }
 
+// The absorption coefficient of the neutral hydrogen in length units:
+// kappa = n_H y sigma_H length_unit.
+__global__ __launch_bounds__(256) void k_ion_kappa(IonArgs a) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n) return;
+  a.kappa[c] = (float)(a.n_H * a.neutral[c] * a.sigma_H * a.length_unit);
+}
+
+hipError_t launch_ion_kappa(const IonArgs& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ion_kappa, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_ion_limit(const IonArgs& a, unsigned long long* out, hipStream_t s) {
   hipLaunchKernelGGL(k_ion_init, dim3(1), dim3(64), 0, s, out);
   if (a.n <= 0) return hipGetLastError();

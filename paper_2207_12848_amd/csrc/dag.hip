@@ -33,18 +33,14 @@ __device__ __forceinline__ double orient(double ox, double oy, double oz, const 
   return (a + b) + c;
 }
 
-// Face weight w = A |Omega . n| in FP32 from the face's FP32 vector A n; the
-// same expression on both sides of a face (whose A n differ only in sign)
-// gives the same weight, so what a cell sends through a face is exactly what
-// its neighbour receives.  The face's class (inflow, outflow, none) is decided
-// by the FP64 orientation above, never by this value.
-__device__ __forceinline__ float face_w32(float ox, float oy, float oz, float ax, float ay,
-                                          float az) {
-  const float p = ox * ax;
-  const float q = oy * ay;
-  const float r = oz * az;
-  return fabsf((p + q) + r);
-}
+// Face weight w = A |Omega . n| from the FP64 orientation s, rounded once to
+// FP32: within one rounding of the FP64 weight however grazing the face is (a
+// weight formed from FP32 normals would carry an absolute error of ~1e-7 A,
+// large against A |s| for nearly parallel faces).  Twin half-faces have equal
+// areas and exactly negated normals, so their s differ only in sign and both
+// sides of a face get the same weight: what a cell sends through a face is
+// exactly what its neighbour receives.
+__device__ __forceinline__ float face_w(double A, double s) { return (float)(A * fabs(s)); }
 
 // Unit of block b (units own consecutive block ranges).
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2
@@ -115,7 +111,8 @@ __device__ __forceinline__ FaceTile stage_tile(const MeshDev& M, int c0, unsigne
 }
 
 // Per task: upwind/downwind counts, Aperp = sum of outflow w, boundary outflow
-// weights, face bits and the fixed-width row of downwind cells.  A row holds
+// weights, the signed weight of every face and the fixed-width row of downwind
+// cells.  A row holds
 // dn_width entries padded with -1; a task with more downwind cells keeps
 // dn_width - 1 of them and stores -(o + 2) in the last slot, o being the
 // offset in dn_ovf of [count, rest of the list].  A thread handles one cell of
@@ -151,22 +148,22 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
       const int d = d0 + dj;
       if (cell && d < a.D) {
         const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
-        const float fx = (float)ox, fy = (float)oy, fz = (float)oz;
         const int64_t t = a.units[m * a.D + d].task_base + c;
+        // this direction's signed weights of the tile's faces
+        float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces + T.f0;
         int32_t* row = STAGE ? srow + threadIdx.x * W : a.dnw + t * W;  // LDS: [dj][ci][W]
         int32_t* ovf = nullptr;
         int nup = 0, npin = 0, ndn = 0;
-        uint32_t um = 0, dm = 0;
         double ap = 0.0, wall = 0.0, per = 0.0;
         for (int f = fb; f < fe; ++f) {
           const double* n = nrm + 3 * f;
           const double sv = orient(ox, oy, oz, n);
           const int nb = nbr[f];
           const bool periodic = shift != nullptr && shift[f] != 0;
-          const uint32_t bit = f - fb < 32 ? 1u << (f - fb) : 0u;  // face bits: first 32 faces
+          const float w = face_w(area[f], sv);
+          float ws = __int_as_float(0x7fc00000);  // neither inflow nor outflow
           if (sv > a.eps) {
-            const double A = area[f];
-            const double w = face_w32(fx, fy, fz, (float)(A * n[0]), (float)(A * n[1]), (float)(A * n[2]));
+            ws = w;
             ap += w;
             if (nb < 0) wall += w;
             else if (periodic) per += w;
@@ -186,17 +183,18 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
                 ovf[1 + ndn - (W - 1)] = nb;
               }
               ++ndn;
-              dm |= bit;
             }
-          } else if (sv < -a.eps && nb >= 0) {
-            if (periodic) ++npin; else ++nup;
-            um |= bit;
+          } else if (sv < -a.eps) {
+            ws = -w;
+            if (nb >= 0) {
+              if (periodic) ++npin; else ++nup;
+            }
           }
+          wf[f] = ws;
         }
         if (ovf != nullptr) ovf[0] = ndn - (W - 1);
         if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
         for (int q = ndn; q < W; ++q) row[q] = -1;
-        a.fmask[t] = make_uint2(um, dm);
         a.indeg[t] = nup;
         a.rowlen_up[t] = nup + npin;
         a.rowlen_dn[t] = ndn;
@@ -625,44 +623,39 @@ __global__ __launch_bounds__(256) void k_face_stats(const int64_t* face_ptr, int
 }
 
 // Per face: the neighbour code (>= 0: interior neighbour, -1: vacuum wall,
-// -(nb + 2): periodic image of cell nb) and A n rounded to FP32, 16 bytes that
-// the row fill reads instead of the FP64 geometry.
-__global__ void k_face_records(MeshDev M, int4* frec) {
+// -(nb + 2): periodic image of cell nb), which the row fill reads next to the
+// face's signed weight instead of the FP64 geometry.
+__global__ void k_face_codes(MeshDev M, int32_t* fcode) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= M.n_faces) return;
   const int nb = M.face_nbr[f];
   const bool periodic = M.face_shift != nullptr && M.face_shift[f] != 0;
-  const double A = M.face_area[f];
-  const int code = nb < 0 ? -1 : (periodic ? -(nb + 2) : nb);
-  frec[f] = make_int4(code, __float_as_int((float)(A * M.face_normal[3 * f])),
-                      __float_as_int((float)(A * M.face_normal[3 * f + 1])),
-                      __float_as_int((float)(A * M.face_normal[3 * f + 2])));
+  fcode[f] = nb < 0 ? -1 : (periodic ? -(nb + 2) : nb);
 }
 
 // Rows of the upwind and downwind lists, in schedule order: each wavefront
 // takes 64 consecutive schedule slots of one unit.  Every lane first loads one
-// slot's task (cell, row pointers, face range, face bits of the first 32 faces
-// from k_count); then,
-// 16 slots per round, 16 lanes share one task, one face record per lane.  The
-// face bits give every entry its place in the row (rows keep the cell's face
-// order); consecutive slots write consecutive rows, and the neighbours'
-// schedule positions come from the unit's inverse schedule.
+// slot's task (cell, row pointers, face range); then, 16 slots per round, 16
+// lanes share one task, one face per lane, 16 faces at a time.  Each face's
+// neighbour code and signed weight (from k_count) give its class; a ballot
+// over the 16 lanes gives every entry its place in the row (rows keep the
+// cell's face order).  Consecutive slots write consecutive rows, and the
+// neighbours' schedule positions come from the unit's inverse schedule.
 constexpr int kFillBlock = 256;
 
 // Five wavefronts per SIMD: the register budget (at most 102 VGPRs) still
-// compiles without spills; six would spill and run slower.
+// compiles without spills.
 __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_fill(DagBuildArgs a) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int u = unit_of_block(a.blk_base, a.n_units, blk);
   const Unit U = a.units[u];
   const MeshDev M = a.meshes[U.mesh];
   const int64_t tb = U.task_base;
-  const float fx = (float)a.dirs[3 * U.dir], fy = (float)a.dirs[3 * U.dir + 1],
-              fz = (float)a.dirs[3 * U.dir + 2];
   const int lane = threadIdx.x & 63;
   const int li = lane & 15;
   const int g = lane >> 4;
   const int32_t* inv = a.inv + tb;
+  const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)U.dir * M.n_faces;
   const int kw = (blk - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
   if (kw >= U.n_cells) return;
   // lane L: the task of slot kw + L (slots past the scheduled tasks of a cyclic
@@ -675,13 +668,11 @@ __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5)))
   const int64_t ed0 = a.dn_ptr[tb + kc];
   const int64_t f0 = M.face_ptr[c];
   const int nf = kv ? (int)(M.face_ptr[c + 1] - f0) : 0;
-  const uint2 bits = a.fmask[tb + c];
   const int rounds = min(4, (U.n_cells - kw + 15) >> 4);
   const uint32_t below = (1u << li) - 1u;
   for (int r = 0; r < rounds; ++r) {
     // group g handles slots kw + 16 r + 4 g + j, j = 0..3
     int64_t eu[4], ed[4], fb[4];
-    uint32_t um[4], dm[4];
     int nfj[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -690,68 +681,36 @@ __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5)))
       ed[j] = __shfl(ed0, src);
       fb[j] = __shfl(f0, src);
       nfj[j] = __shfl(nf, src);
-      um[j] = (uint32_t)__shfl((int)bits.x, src);
-      dm[j] = (uint32_t)__shfl((int)bits.y, src);
     }
     int mx = max(max(nfj[0], nfj[1]), max(nfj[2], nfj[3]));
     mx = max(mx, __shfl_xor(mx, 16));
     mx = max(mx, __shfl_xor(mx, 32));
-    for (int h = 0; h < 2 && h * 16 < mx; ++h) {
+    for (int h = 0; h * 16 < mx; ++h) {
       const int fo = h * 16 + li;
-      int4 rec[4];
+      int code[4];
+      float ws[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) rec[j] = M.frec[fo < nfj[j] ? fb[j] + fo : 0];  // face 0 exists
+      for (int j = 0; j < 4; ++j) {
+        const int64_t f = fo < nfj[j] ? fb[j] + fo : 0;  // face 0 exists
+        code[j] = M.fcode[f];
+        ws[j] = wf[f];
+      }
       int pos[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pos[j] = inv[rec[j].x >= 0 ? rec[j].x : 0];
+      for (int j = 0; j < 4; ++j) pos[j] = inv[code[j] >= 0 ? code[j] : 0];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t bit = 1u << fo;
-        const bool has = fo < nfj[j];
-        const bool up = has && (um[j] & bit) != 0u;
-        const bool dn = has && (dm[j] & bit) != 0u;
-        const float w = face_w32(fx, fy, fz, __int_as_float(rec[j].y), __int_as_float(rec[j].z),
-                                 __int_as_float(rec[j].w));
-        const uint32_t pre = h == 0 ? below : (0xffffu | (below << 16));  // faces before fo
-        if (up) {
-          const int code = rec[j].x;
-          a.up[eu[j] + __popc(um[j] & pre)] = make_int2(code >= 0 ? pos[j] : code + 1, __float_as_int(w));
-        }
-        if (dn) a.dn[ed[j] + __popc(dm[j] & pre)] = make_int2(pos[j], __float_as_int(w));
-      }
-    }
-    // faces past the 32 face bits (rare): classified here in FP64 exactly as in
-    // k_count, placed after the first 32 faces' entries with a ballot per chunk
-    if (mx > 32) {
-      const double ox = a.dirs[3 * U.dir], oy = a.dirs[3 * U.dir + 1], oz = a.dirs[3 * U.dir + 2];
-      int64_t ru[4], rd[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        ru[j] = eu[j] + __popc(um[j]);
-        rd[j] = ed[j] + __popc(dm[j]);
-      }
-      for (int h = 2; h * 16 < mx; ++h) {
-        const int fo = h * 16 + li;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool has = fo < nfj[j];
-          const int64_t f = has ? fb[j] + fo : 0;
-          const int4 rec = M.frec[f];
-          const double* n3 = M.face_normal + 3 * f;
-          const double sv = orient(ox, oy, oz, n3);
-          const int code = rec.x;
-          const bool up = has && code != -1 && sv < -a.eps;
-          const bool dn = has && code >= 0 && sv > a.eps;
-          const int pos = inv[code >= 0 ? code : 0];
-          const float w = face_w32(fx, fy, fz, __int_as_float(rec.y), __int_as_float(rec.z),
-                                   __int_as_float(rec.w));
-          const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
-          const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
-          if (up) a.up[ru[j] + __popc(mu & below)] = make_int2(code >= 0 ? pos : code + 1, __float_as_int(w));
-          if (dn) a.dn[rd[j] + __popc(md & below)] = make_int2(pos, __float_as_int(w));
-          ru[j] += __popc(mu);
-          rd[j] += __popc(md);
-        }
+        const bool has = fo < nfj[j] && !isnan(ws[j]);
+        const bool in = has && signbit(ws[j]);
+        const bool up = in && code[j] != -1;           // interior or periodic inflow
+        const bool dn = has && !in && code[j] >= 0;    // interior outflow
+        const float w = fabsf(ws[j]);
+        const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
+        const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
+        if (up) a.up[eu[j] + __popc(mu & below)] = make_int2(code[j] >= 0 ? pos[j] : code[j] + 1, __float_as_int(w));
+        if (dn) a.dn[ed[j] + __popc(md & below)] = make_int2(pos[j], __float_as_int(w));
+        eu[j] += __popc(mu);
+        ed[j] += __popc(md);
       }
     }
   }
@@ -766,6 +725,25 @@ __global__ void k_level_entries(DagBuildArgs a) {
     a.lev_up[U.lp_base + l] = a.up_ptr[k];
     a.lev_dn[U.lp_base + l] = a.dn_ptr[k];
   }
+}
+
+__global__ void k_unit_entries(const Unit* units, int32_t n_units, const int64_t* up_ptr,
+                               const int64_t* dn_ptr, int64_t* out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n_units) return;
+  const int64_t t0 = units[u].task_base, t1 = t0 + units[u].n_cells;
+  out[2 * u] = up_ptr[t1] - up_ptr[t0];
+  out[2 * u + 1] = dn_ptr[t1] - dn_ptr[t0];
+}
+
+// Tasks per level, one workgroup per unit.
+__global__ void k_level_widths(const Unit* units, const int32_t* lp, int32_t mesh,
+                               unsigned long long* width, int32_t n_levels) {
+  const Unit U = units[blockIdx.x];
+  if (mesh >= 0 && U.mesh != mesh) return;
+  const int32_t* l = lp + U.lp_base;
+  for (int k = threadIdx.x; k < min(U.depth, n_levels); k += blockDim.x)
+    atomicAdd(width + k, (unsigned long long)(l[k + 1] - l[k]));
 }
 
 __global__ void k_d2f(const double* in, float* out, int64_t n) {
@@ -857,9 +835,9 @@ hipError_t launch_face_stats(const int64_t* face_ptr, int32_t n_cells, int32_t r
   return hipGetLastError();
 }
 
-hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s) {
+hipError_t launch_face_codes(const MeshDev& m, int32_t* fcode, hipStream_t s) {
   if (m.n_faces <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_face_records, dim3(grid1d(m.n_faces, 256)), dim3(256), 0, s, m, frec);
+  hipLaunchKernelGGL(k_face_codes, dim3(grid1d(m.n_faces, 256)), dim3(256), 0, s, m, fcode);
   return hipGetLastError();
 }
 
@@ -879,6 +857,22 @@ hipError_t launch_scan_len(const int32_t* in, int64_t* out, int64_t n, void* tmp
   // tmp == nullptr queries the temporary storage size
   hipcub::TransformInputIterator<int64_t, WidenToI64, const int32_t*> it(in, WidenToI64());
   return hipcub::DeviceScan::ExclusiveSum(tmp, *tmp_bytes, it, out, (int)n, s);
+}
+
+hipError_t launch_unit_entries(const Unit* units, int32_t n_units, const int64_t* up_ptr,
+                               const int64_t* dn_ptr, int64_t* out, hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_entries, dim3(grid1d(n_units, 256)), dim3(256), 0, s, units, n_units,
+                     up_ptr, dn_ptr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_widths(const Unit* units, int32_t n_units, const int32_t* lp, int32_t mesh,
+                               int64_t* width, int32_t n_levels, hipStream_t s) {
+  if (n_units <= 0 || n_levels <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_widths, dim3(n_units), dim3(256), 0, s, units, lp, mesh,
+                     reinterpret_cast<unsigned long long*>(width), n_levels);
+  return hipGetLastError();
 }
 
 hipError_t launch_d2f(const double* in, float* out, int64_t n, hipStream_t s) {

@@ -5,6 +5,17 @@
 
 namespace sweep {
 
+// Bits of the device error flag a DAG keeps: invalid inputs seen by the kernels
+// of an asynchronous call, reported by the next call that synchronises.
+constexpr int32_t kErrKappa = 1;     // kappa negative or not finite
+constexpr int32_t kErrEmission = 2;  // emission negative or not finite
+constexpr int32_t kErrCell = 4;      // a task's denominator (Aperp + kappa V) not positive and finite
+constexpr int32_t kErrGrad = 8;      // dL/dJ or dL/dabsorbed not finite
+
+// Largest byte size of any array the sweep kernels address through a buffer
+// resource (32-bit offsets; offsets from kOob up stay past the end).
+constexpr int64_t kMaxBufBytes = 0x7fffffe0;
+
 // One (mesh, direction) sweep.  Task arrays of unit u occupy
 // [task_base, task_base + n_cells); its level pointers [lp_base, lp_base + depth + 2).
 struct Unit {
@@ -26,7 +37,8 @@ struct MeshDev {
   const double* face_area;
   const double* face_normal;
   const double* cell_volume;
-  const int4* frec;  // per face: neighbour code, then A n as three FP32 (see k_face_records)
+  const int32_t* fcode;  // per face: neighbour code (see k_face_codes)
+  int64_t face_off;      // first face of the mesh in the concatenated per-face arrays
   int64_t n_faces;
   int32_t n_cells;
   int32_t cell_off;
@@ -59,7 +71,10 @@ struct DagBuildArgs {
   int32_t* rowlen_up;
   int32_t* rowlen_dn;
   float* aperp;
-  uint2* fmask;  // per task (cell order): inflow-entry and outflow-entry bits of the first 32 faces
+  // per (direction, face) of every mesh, at D * face_off + d * n_faces + f: the face
+  // weight w = A |Omega . n| rounded once to FP32 from FP64, with the face's class
+  // in its sign: outflow +w, inflow -w, neither NaN
+  float* wface;
   float2* bnd;  // (sum of w over wall outflow faces, over periodic outflow faces)
   int32_t* cnt;
   int32_t* inv;    // cell -> position in the unit's schedule
@@ -129,6 +144,7 @@ struct PrepArgs {
   int64_t C_total;
   const double* extra;     // adjoint: per-task source [D][C_total][G] or nullptr
   float2* cds;             // [T][G] cell order (scratch): (denominator, source)
+  int32_t* flag;           // device error bits (atomicOr): kErrKappa, kErrEmission, kErrCell
   float* tden;             // [T][G] schedule order
   float* tsrc;             // [T][G] schedule order
 };
@@ -221,11 +237,18 @@ hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 // out[0] = max faces of a cell, out[1] += overflow ints for rows of row_cap entries
 hipError_t launch_face_stats(const int64_t* face_ptr, int32_t n_cells, int32_t row_cap, int32_t n_dirs,
                              unsigned long long* out, hipStream_t s);
-hipError_t launch_face_records(const MeshDev& m, int4* frec, hipStream_t s);
+hipError_t launch_face_codes(const MeshDev& m, int32_t* fcode, hipStream_t s);
 hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s);
 size_t count_lds_bytes(int max_faces, int dn_width);
 hipError_t launch_level_entries(const DagBuildArgs& a, hipStream_t s);
+// out[2u], out[2u + 1]: upwind and downwind row entries of unit u
+hipError_t launch_unit_entries(const Unit* units, int32_t n_units, const int64_t* up_ptr,
+                               const int64_t* dn_ptr, int64_t* out, hipStream_t s);
+// width[l] += tasks at level l of every unit of `mesh` (all meshes if mesh < 0), l < n_levels
+hipError_t launch_level_widths(const Unit* units, int32_t n_units, const int32_t* lp, int32_t mesh,
+                               int64_t* width, int32_t n_levels, hipStream_t s);
+hipError_t launch_ion_kappa(const IonArgs& a, hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_scan_len(const int32_t* in, int64_t* out, int64_t n, void* tmp, size_t* tmp_bytes,
                            hipStream_t s);
@@ -242,7 +265,7 @@ hipError_t launch_totals(const double* partial, const int32_t* mesh_blk_base, in
                          int32_t G, double* totals, hipStream_t s);
 hipError_t launch_adj_init(const float* dJ, const float* dA, const float* kappa, const float* vol,
                            const float* jsum_last, float albedo, int32_t G, int64_t C,
-                           float* gsrc, double* dk, double* de, hipStream_t s);
+                           float* gsrc, double* dk, double* de, int32_t* flag, hipStream_t s);
 hipError_t launch_adj_reduce(const AdjReduceArgs& a, double* dk, double* de, hipStream_t s);
 hipError_t launch_d2f_pair(const double* a, const double* b, float* oa, float* ob, int64_t n,
                            hipStream_t s);

@@ -13,6 +13,8 @@
 // LDS, indexed by schedule position modulo `ring`, so most upwind reads are LDS
 // reads; an older upwind result is prefetched from global memory a step ahead
 // (it was stored at least two barriers earlier by the same workgroup).
+#include <float.h>
+
 #include "internal.h"
 #include "sweep.h"
 
@@ -215,106 +217,73 @@ __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& 
   }
 }
 
-// Inflow of one task from its staged row (raw entries in LDS), in batches of 8:
-// one LDS read per entry and one of the ring slot it names, then a multiply and
-// an add per entry in row order (explicit rounding, no contraction).  `far`
-// collects the largest offset from the window's start of the batch entries
-// read (the row's and up to 7 after it, which are entries of the same level or
-// the padding that follows the level's block, inside the window): the result
-// holds when far < w.n; otherwise the task is recomputed by gather_mixed.
+// GN consecutive groups of one task from a [slot][G] array (one load; offsets
+// past the buffer's end read zeros without memory traffic).
 template <int GN>
-__device__ __forceinline__ Inflow<GN> gather_staged(const SweepArgs& a, const TaskRec<GN>& t,
-                                                    const int2* stg, const float* ring, Window w,
-                                                    uint32_t& far) {
+__device__ __forceinline__ void ld_groups(__amdgpu_buffer_rsrc_t r, uint32_t off, float* v) {
+  if constexpr (GN == 4) {
+    const int4 x = ld_b128(r, off, 0);
+    v[0] = __int_as_float(x.x);
+    v[1] = __int_as_float(x.y);
+    v[2] = __int_as_float(x.z);
+    v[3] = __int_as_float(x.w);
+  } else if constexpr (GN == 2) {
+    const int2 x = ld_b64(r, off, 0);
+    v[0] = __int_as_float(x.x);
+    v[1] = __int_as_float(x.y);
+  } else {
+#pragma unroll
+    for (int g = 0; g < GN; ++g) v[g] = ld_f32(r, off + 4u * g, 0);
+  }
+}
+
+// Inflow of one task in row order, in batches of 8 entries (the row's entries
+// from the LDS staging buffer, or from global memory for levels that were not
+// staged).  An entry inside the window reads its ring slot; an older result is
+// loaded from out_s (stored at least one barrier earlier by this workgroup) and
+// a periodic inflow -(partner + 1) from the previous pass (PER; zero without
+// one).  Every load of a batch is issued before the first is used, so a batch
+// costs one memory round trip whatever its mix.  The sum is the same sequence
+// of rounded products and additions in row order on every path; entries past
+// the row's end (the rest of the batch) are skipped by a select.
+template <int GN, bool PER, bool STAGED>
+__device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs& B,
+                                             const TaskRec<GN>& t, const int2* stg, uint32_t eoff,
+                                             const float* ring, Window w) {
   Inflow<GN> in;
 #pragma unroll
   for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
   for (int rb = t.r0; rb < t.r1; rb += 8) {
     int2 en[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) en[q] = stg[rb + q];
-    float rv[8][GN];
+    for (int q = 0; q < 8; ++q)
+      en[q] = STAGED ? stg[rb + q] : ld_b64(B.ent, 8u * (uint32_t)(rb + q), eoff);
+    const int nr = t.r1 - rb;  // entries of the row in this batch
+    float gv[8][GN], pv[8][GN], rv[8][GN];
+    bool inw[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const float* v = ring + (en[q].x & a.ring_mask) * GN;
+      const int p = en[q].x;
+      const bool val = q < nr;
+      inw[q] = w.has(p);  // never for p < 0 (the window starts at lo >= 0)
+      const bool glob = val && !inw[q] && p >= 0;
+      ld_groups<GN>(B.outs, glob ? 4u * (uint32_t)(p * a.G) : kOob, gv[q]);
+      if (PER) ld_groups<GN>(B.prev, val && p < 0 ? 4u * (uint32_t)((-p - 1) * a.G) : kOob, pv[q]);
+      const float* v = ring + (p & a.ring_mask) * GN;
 #pragma unroll
       for (int g = 0; g < GN; ++g) rv[q][g] = v[g];
     }
-    const int nr = t.r1 - rb;  // entries of the row in this batch
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      far = max(far, (uint32_t)(en[q].x - w.lo));
-      const float y = q < nr ? __int_as_float(en[q].y) : 0.0f;
-#pragma unroll
-      for (int g = 0; g < GN; ++g) in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(y, rv[q][g]));
-    }
-  }
-  return in;
-}
-
-// Inflow of one task from its staged row when some entries lie outside the
-// window, in row order: in-window entries from the ring, older results from
-// out_s (written at least one barrier earlier by this workgroup) and periodic
-// inflows from the previous pass (zero without one).
-template <int GN>
-__device__ __forceinline__ Inflow<GN> gather_mixed(const SweepArgs& a, const UnitBufs& B,
-                                                   const TaskRec<GN>& t, const int2* stg, Window w,
-                                                   const float* ring) {
-  Inflow<GN> in;
-#pragma unroll
-  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
-  for (int r = t.r0; r < t.r1; ++r) {
-    const int2 en = stg[r];
-    const int p = en.x;
-    const float y = __int_as_float(en.y);
-    if (p >= 0) {
-      const bool inw = w.has(p);
+      const bool val = q < nr;
+      const bool per = PER && en[q].x < 0;
+      const float y = __int_as_float(en[q].y);
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
-        const float v = inw ? ring[(p & a.ring_mask) * GN + g]
-                            : ld_f32(B.outs, 4u * (uint32_t)(p * a.G + g), 0);
-        in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(y, v));
-      }
-    } else {
-#pragma unroll
-      for (int g = 0; g < GN; ++g) {
-        const float v = __fmul_rn(y, ld_f32(B.prev, 4u * (uint32_t)((-p - 1) * a.G + g), 0));
-        in.acc[g] = __fadd_rn(in.acc[g], v);
-        in.pin[g] = __fadd_rn(in.pin[g], v);
-      }
-    }
-  }
-  return in;
-}
-
-// Inflow of one task straight from global memory (levels with more entries
-// than the staging buffer holds), in row order.
-template <int GN>
-__device__ __forceinline__ Inflow<GN> gather_global(const SweepArgs& a, const UnitBufs& B,
-                                                    const TaskRec<GN>& t, int64_t e0, Window w,
-                                                    const float* ring) {
-  Inflow<GN> in;
-#pragma unroll
-  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
-  const uint32_t eoff = 8u * (uint32_t)(e0 - B.ue0);
-  for (int r = t.r0; r < t.r1; ++r) {
-    const int2 en = ld_b64(B.ent, 8u * (uint32_t)r, eoff);
-    const int p = en.x;
-    const float w8 = __int_as_float(en.y);
-    if (p >= 0) {
-      const bool inw = w.has(p);
-#pragma unroll
-      for (int g = 0; g < GN; ++g) {
-        const float v = inw ? ring[(p & a.ring_mask) * GN + g]
-                            : ld_f32(B.outs, 4u * (uint32_t)(p * a.G + g), 0);
-        in.acc[g] = __fadd_rn(in.acc[g], __fmul_rn(w8, v));
-      }
-    } else {
-#pragma unroll
-      for (int g = 0; g < GN; ++g) {
-        const float v = __fmul_rn(w8, ld_f32(B.prev, 4u * (uint32_t)((-p - 1) * a.G + g), 0));
-        in.acc[g] = __fadd_rn(in.acc[g], v);
-        in.pin[g] = __fadd_rn(in.pin[g], v);
+        const float x = inw[q] ? rv[q][g] : (per ? pv[q][g] : gv[q][g]);
+        const float pr = __fmul_rn(y, x);
+        in.acc[g] = val ? __fadd_rn(in.acc[g], pr) : in.acc[g];
+        if (PER) in.pin[g] = (val && per) ? __fadd_rn(in.pin[g], pr) : in.pin[g];
       }
     }
   }
@@ -457,23 +426,16 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
       const Window w = window<REVERSE>(k0, k1, R);
       const bool staged = curL.nst == curL.ne;
       if (staged && k1 - k0 <= nthr) {
-        uint32_t far = 0;
-        Inflow<GN> in = gather_staged<GN>(a, cur, stg, ring, w, far);
-        if (far >= w.n) in = gather_mixed<GN>(a, B, cur, stg, w, ring);
+        const Inflow<GN> in = gather<GN, PIN, true>(a, B, cur, stg, 0u, ring, w);
         finish_fast<GN, PIN>(a, B, cur, k0 + tid, in, ring, sink);
         return;
       }
+      const uint32_t eoff = 8u * (uint32_t)(e0 - B.ue0);
       for (int k = k0 + tid; k < k1; k += nthr) {
         TaskRec<GN> t;
         if (k == k0 + tid) t = cur; else load_rec<GN>(a, B, k, e0, t);
-        Inflow<GN> in;
-        if (staged) {
-          uint32_t far = 0;
-          in = gather_staged<GN>(a, t, stg, ring, w, far);
-          if (far >= w.n) in = gather_mixed<GN>(a, B, t, stg, w, ring);
-        } else {
-          in = gather_global<GN>(a, B, t, e0, w, ring);
-        }
+        const Inflow<GN> in = staged ? gather<GN, PIN, true>(a, B, t, stg, 0u, ring, w)
+                                     : gather<GN, PIN, false>(a, B, t, nullptr, eoff, ring, w);
         finish_task<GN, PIN>(a, B, t, k, in, ring);
       }
       // the uncommon steps leave no memory operation of theirs in flight, so the
@@ -623,6 +585,14 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
       }
       if (a.extra != nullptr) s += a.extra[((int64_t)U.dir * a.C_total + ci) * a.G + g];
     }
+    // invalid inputs raise the DAG's error flag (reported by the next call that
+    // synchronises); the kernels run on regardless
+    int32_t bad = 0;
+    if (!(kap >= 0.0 && kap <= DBL_MAX)) bad |= kErrKappa;
+    if (a.emission != nullptr && !((double)a.emission[cg] >= 0.0 && (double)a.emission[cg] <= DBL_MAX))
+      bad |= kErrEmission;
+    if (!(den > 0.0 && den <= DBL_MAX)) bad |= kErrCell;
+    if (bad != 0) atomicOr(a.flag, bad);
     a.cds[t * a.G + g] = make_float2((float)den, (float)s);
   }
 }
@@ -757,11 +727,12 @@ __global__ __launch_bounds__(256) void k_totals(const double* partial, const int
 
 __global__ void k_adj_init(const float* dJ, const float* dA, const float* kappa, const float* vol,
                            const float* jsum_last, float albedo, int32_t G, int64_t n,
-                           float* gsrc, double* dk, double* de) {
+                           float* gsrc, double* dk, double* de, int32_t* flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double V = (double)vol[i / G];
   const double ga = (double)dA[i];
+  if (!(fabs(ga) <= DBL_MAX && fabs((double)dJ[i]) <= DBL_MAX)) atomicOr(flag, kErrGrad);
   const double ka = (1.0 - (double)albedo) * (double)kappa[i];
   gsrc[i] = (float)((double)dJ[i] * (double)kInv4Pi + ga * ka * V);
   dk[i] = ga * (1.0 - (double)albedo) * V * (double)jsum_last[i];
@@ -938,11 +909,11 @@ hipError_t launch_totals(const double* partial, const int32_t* mesh_blk_base, in
 
 hipError_t launch_adj_init(const float* dJ, const float* dA, const float* kappa, const float* vol,
                            const float* jsum_last, float albedo, int32_t G, int64_t C,
-                           float* gsrc, double* dk, double* de, hipStream_t s) {
+                           float* gsrc, double* dk, double* de, int32_t* flag, hipStream_t s) {
   const int64_t n = C * G;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adj_init, dim3(grid1d(n, 256)), dim3(256), 0, s, dJ, dA, kappa, vol,
-                     jsum_last, albedo, G, n, gsrc, dk, de);
+                     jsum_last, albedo, G, n, gsrc, dk, de, flag);
   return hipGetLastError();
 }
 

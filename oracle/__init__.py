@@ -6,8 +6,9 @@ Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 of ``synth``.
 
 What is computed is documented in ``sweep_oracle.c`` (orientation of appendix A
-and sec. 2.5, algorithm 2's FIFO schedule, transport scheme (a) of sec. 2.6
-with a first-order upwind cell balance or an exponential (e^{-tau}) cell law,
+and sec. 2.5, algorithm 2's FIFO schedule, transport schemes (a) and (b) of
+sec. 2.6 (w["scheme"] = "area" or "aligned", w["n_aligned"] = 3) with a
+first-order upwind cell balance or an exponential (e^{-tau}) cell law,
 periodic passes of sec. 2.7, source
 iteration of algorithm 1, and the adjoint).  This module only marshals numpy
 arrays; every function loops over the independent meshes of a workload.
@@ -39,7 +40,11 @@ class _Mesh(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int32), ("face_ptr", ctypes.c_void_p),
                 ("face_nbr", ctypes.c_void_p), ("face_shift", ctypes.c_void_p),
                 ("face_area", ctypes.c_void_p), ("face_normal", ctypes.c_void_p),
-                ("cell_volume", ctypes.c_void_p)]
+                ("cell_volume", ctypes.c_void_p), ("face_twin", ctypes.c_void_p),
+                ("scheme", ctypes.c_int32), ("n_aligned", ctypes.c_int32)]
+
+
+SCHEMES = {"area": 0, "aligned": 1}
 
 
 def build(force: bool = False) -> str:
@@ -81,16 +86,28 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
-def _mesh_struct(mesh):
+def _mesh_struct(mesh, scheme="area", n_aligned=3):
+    """The C view of a mesh; scheme "area" (transport scheme (a)) or "aligned"
+    (scheme (b): the outflow shared by the n_aligned most aligned faces)."""
+    if scheme not in SCHEMES:
+        raise OracleError("unknown transport scheme %r" % (scheme,))
+    if scheme == "aligned" and mesh.get("face_twin") is None:
+        raise OracleError("the aligned scheme needs the meshes' face_twin")
     keep = dict(face_ptr=_c(mesh["face_ptr"], np.int64), face_nbr=_c(mesh["face_nbr"], np.int32),
                 face_shift=_c(mesh["face_shift"], np.int8) if mesh.get("periodic") else None,
                 face_area=_c(mesh["face_area"], np.float64),
                 face_normal=_c(mesh["face_normal"], np.float64),
-                cell_volume=_c(mesh["cell_volume"], np.float64))
+                cell_volume=_c(mesh["cell_volume"], np.float64),
+                face_twin=_c(mesh["face_twin"], np.int32) if mesh.get("face_twin") is not None
+                else None)
     s = _Mesh(len(keep["cell_volume"]), _p(keep["face_ptr"]), _p(keep["face_nbr"]),
               _p(keep["face_shift"]), _p(keep["face_area"]), _p(keep["face_normal"]),
-              _p(keep["cell_volume"]))
+              _p(keep["cell_volume"]), _p(keep["face_twin"]), SCHEMES[scheme], int(n_aligned))
     return s, keep
+
+
+def _scheme(w):
+    return w.get("scheme", "area"), int(w.get("n_aligned", 3))
 
 
 def _check(st, what):
@@ -117,13 +134,14 @@ def _offsets(meshes):
     return off
 
 
-def build_dag(mesh: dict, dirs: np.ndarray, eps: float = EPS_TIE):
+def build_dag(mesh: dict, dirs: np.ndarray, eps: float = EPS_TIE, scheme: str = "area",
+              n_aligned: int = 3):
     """Levels, canonical order and upwind counts of every task of one mesh.
 
     Returns level [D,C], order [D,C] (cells of each direction sorted by (level, cell)),
     indeg [D,C] and depth [D]."""
     lib = _load()
-    s, keep = _mesh_struct(mesh)
+    s, keep = _mesh_struct(mesh, scheme, n_aligned)
     dirs = _c(dirs, np.float64)
     D, C = len(dirs), s.n_cells
     level = np.zeros((D, C), np.int32)
@@ -160,7 +178,7 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
     totals = np.zeros((len(w["meshes"]), G, N_TOTALS))
     phis, ckpts, orders = [], [], []
     for mi, mesh in enumerate(w["meshes"]):
-        s, keep = _mesh_struct(mesh)
+        s, keep = _mesh_struct(mesh, *_scheme(w))
         C = s.n_cells
         sl = slice(off[mi], off[mi + 1])
         k = _c(kap[sl], np.float64)
@@ -207,7 +225,7 @@ def adjoint(w: dict, gJ: np.ndarray, gA: np.ndarray, eps: float = EPS_TIE):
     dk = np.zeros((off[-1], G))
     de = np.zeros((off[-1], G))
     for mi, mesh in enumerate(w["meshes"]):
-        s, keep = _mesh_struct(mesh)
+        s, keep = _mesh_struct(mesh, *_scheme(w))
         C = s.n_cells
         sl = slice(off[mi], off[mi + 1])
         a = np.zeros((C, G))

@@ -20,6 +20,11 @@
  *  w_i phi_c, and
  *      (Aperp_c + kappa_c V_c) phi_c = sum_{inflow faces} w_f phi_upwind + S_c,
  *  Aperp_c = sum of w over outflow faces, S_c = L_c / D (+ scattering source).
+ *  Scheme (b) of sec. 2.6 (direction-conserving transport): the same total
+ *  outflow Aperp_c phi_c is shared equally by the n outflow faces whose normals
+ *  are the most aligned with Omega (n = 3 = the number of dimensions, the
+ *  paper's choice), so only those faces carry radiation (see carries()); the
+ *  dependency graph keeps only their edges.
  *  Vacuum walls bring no inflow (sec. 2.5, fixed boundaries with I = 0).
  *
  *  Schedule (algorithm 2): Kahn's topological traversal with a FIFO, one per
@@ -75,6 +80,12 @@
 #define ORC_ERR_OOM -3
 #define ORC_ERR_UNSUPPORTED -6
 
+/* Transport schemes of sec. 2.6 (how a cell's outflow is shared among its
+ * downwind faces). */
+#define SCHEME_AREA 0    /* (a): in proportion to A_i (n_i . Omega) over every outflow face */
+#define SCHEME_ALIGNED 1 /* (b): equally over the n outflow faces whose normals are the most
+                            aligned with Omega (direction-conserving transport) */
+
 typedef struct {
   int32_t n_cells;
   const int64_t* face_ptr;
@@ -83,6 +94,9 @@ typedef struct {
   const double* face_area;
   const double* face_normal; /* 3 per face */
   const double* cell_volume;
+  const int32_t* face_twin;  /* matching half-face of the neighbour (needed by scheme (b)) */
+  int32_t scheme;            /* SCHEME_AREA or SCHEME_ALIGNED */
+  int32_t n_aligned;         /* scheme (b): faces that share the outflow (n_dim = 3 in the paper) */
 } orc_mesh;
 
 static double orient(const double* om, const double* n) {
@@ -120,12 +134,62 @@ static int is_periodic_face(const orc_mesh* m, int64_t f) {
   return m->face_shift != NULL && m->face_shift[f] != 0;
 }
 
-/* in-graph upwind dependency: interior (non-periodic) inflow face */
+/* Does radiation of cell c leave through its face f in direction om, and with
+ * which weight w (what leaves is w times the cell's value)?
+ *   scheme (a): every outflow face (s > eps), w = A_f |s_f|;
+ *   scheme (b): the n outflow faces with the largest s (ties: the lower face
+ *     index first), n = min(n_aligned, number of outflow faces), each with
+ *     w = Aperp_c / n, Aperp_c = sum over all outflow faces of A |s| (the same
+ *     total outflow as scheme (a), shared equally). */
+static int carries(const orc_mesh* m, const double* om, double eps, int32_t c, int64_t f,
+                   double* w) {
+  const double sf = orient(om, m->face_normal + 3 * f);
+  if (face_class(sf, eps) != F_OUT) return 0;
+  if (m->scheme == SCHEME_AREA) {
+    *w = m->face_area[f] * fabs(sf);
+    return 1;
+  }
+  int32_t n_out = 0, rank = 0;
+  double aperp = 0.0;
+  for (int64_t g = m->face_ptr[c]; g < m->face_ptr[c + 1]; ++g) {
+    const double sg = orient(om, m->face_normal + 3 * g);
+    if (face_class(sg, eps) != F_OUT) continue;
+    ++n_out;
+    aperp += m->face_area[g] * fabs(sg);
+    if (sg > sf || (sg == sf && g < f)) ++rank;
+  }
+  const int32_t n = n_out < m->n_aligned ? n_out : m->n_aligned;
+  if (rank >= n) return 0;
+  *w = aperp / n;
+  return 1;
+}
+
+/* Does radiation enter cell c through its face f (from the neighbour, interior
+ * or periodic), and with which weight?  Scheme (a): f is an inflow face, w the
+ * face's own A |s| (equal to its twin's); scheme (b): the neighbour sends
+ * through the twin face. */
+static int receives(const orc_mesh* m, const double* om, double eps, int32_t c, int64_t f,
+                    double* w) {
+  const int32_t nb = m->face_nbr[f];
+  if (nb < 0) return 0;
+  if (m->scheme == SCHEME_AREA) {
+    const double s = orient(om, m->face_normal + 3 * f);
+    if (face_class(s, eps) != F_IN) return 0;
+    *w = m->face_area[f] * fabs(s);
+    return 1;
+  }
+  (void)c;
+  return carries(m, om, eps, nb, m->face_twin[f], w);
+}
+
+/* in-graph upwind dependency: radiation received through an interior
+ * (non-periodic) face */
 static int upwind_count(const orc_mesh* m, const double* om, double eps, int32_t c) {
   int n = 0;
+  double w;
   for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
     if (m->face_nbr[f] < 0 || is_periodic_face(m, f)) continue;
-    if (face_class(orient(om, m->face_normal + 3 * f), eps) == F_IN) ++n;
+    if (receives(m, om, eps, c, f, &w)) ++n;
   }
   return n;
 }
@@ -143,10 +207,11 @@ static int32_t fifo_order(const orc_mesh* m, const double* om, double eps, int32
   }
   while (head < tail) {
     const int32_t c = queue[head++];
+    double w;
     for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
       const int32_t nb = m->face_nbr[f];
       if (nb < 0 || is_periodic_face(m, f)) continue;
-      if (face_class(orient(om, m->face_normal + 3 * f), eps) != F_OUT) continue;
+      if (!carries(m, om, eps, c, f, &w)) continue;
       if (level[nb] < level[c] + 1) level[nb] = level[c] + 1;
       if (--cnt[nb] == 0) queue[tail++] = nb;
     }
@@ -221,11 +286,10 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
     for (int32_t g = 0; g < G; ++g) nin[g] = 0.0;
     for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
       const double s = orient(om, m->face_normal + 3 * f);
-      const int k = face_class(s, eps);
-      const double w = m->face_area[f] * fabs(s);
-      if (k == F_OUT) {
-        aperp += w;
-      } else if (k == F_IN && m->face_nbr[f] >= 0) {
+      double w;
+      if (face_class(s, eps) == F_OUT) {
+        aperp += m->face_area[f] * fabs(s);
+      } else if (receives(m, om, eps, c, f, &w)) {
         const int32_t nb = m->face_nbr[f];
         if (is_periodic_face(m, f)) {
           if (prev)
@@ -261,9 +325,8 @@ static int sweep_direction(const orc_mesh* m, const double* om, double eps, int3
     }
     /* outflow: boundaries and downwind neighbours */
     for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
-      const double s = orient(om, m->face_normal + 3 * f);
-      if (face_class(s, eps) != F_OUT) continue;
-      const double w = m->face_area[f] * fabs(s);
+      double w;
+      if (!carries(m, om, eps, c, f, &w)) continue;
       const int32_t nb = m->face_nbr[f];
       if (nb < 0) {
         for (int32_t g = 0; g < G; ++g) acc[4 * g + 0] += w * phi[(int64_t)c * G + g];
@@ -518,13 +581,13 @@ static void adjoint_direction(const orc_mesh* m, const double* om, double eps, i
       }
       double acc = g ? r * g[i] : 0.0;
       for (int64_t f = m->face_ptr[c]; f < m->face_ptr[c + 1]; ++f) {
-        const double s = orient(om, m->face_normal + 3 * f);
         const int32_t nb = m->face_nbr[f];
-        if (face_class(s, eps) != F_OUT || nb < 0) continue;
+        double w;
+        if (nb < 0 || !carries(m, om, eps, c, f, &w)) continue;
         if (!is_periodic_face(m, f))
-          acc += m->face_area[f] * fabs(s) * lam[(int64_t)nb * G + gg];
+          acc += w * lam[(int64_t)nb * G + gg];
         else if (lam_next)  /* what leaves here enters nb in the next pass */
-          acc += m->face_area[f] * fabs(s) * lam_next[(int64_t)nb * G + gg];
+          acc += w * lam_next[(int64_t)nb * G + gg];
       }
       lam[i] = acc / den;
       dk[i] = -lam[i] * x[i] * dden + (g ? g[i] * x[i] * dr : 0.0);

@@ -11,6 +11,11 @@ V/Aperp, tau = kappa V / Aperp, capped at 40) the unknown is the exit flux
 density x and the diagonal becomes Aperp e^{tau}; the cell average is r x with
 r = Aperp (e^{tau} - 1) / (kappa V) (1 at kappa = 0).
 
+Transport scheme (b) of sec. 2.6 (scheme="aligned"): a cell's outflow Aperp phi
+is shared equally by its n outflow faces with the largest Omega . n (ties: the
+lower face index), so the coupling is assembled from the sending side:
+M[i, c] -= Aperp_c / n for every such face of c towards i.
+
 cyclic=True also couples the periodic faces, giving the fixed point of the
 periodic-boundary passes (sec. 2.7).  `dense_scatter_system` couples all
 directions through the isotropic scattering term of eq. radiativeTransfer, giving
@@ -34,12 +39,40 @@ def _faces(mesh):
 TAU_CAP = 40.0
 
 
-def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS, law="upwind"):
+def _orient(normal, omega):
+    """Omega . n per face, as (ox nx + oy ny) + oz nz in FP64 (elementwise, no FMA)."""
+    o = np.asarray(omega, np.float64)
+    return (normal[:, 0] * o[0] + normal[:, 1] * o[1]) + normal[:, 2] * o[2]
+
+
+def aligned_choice(mesh, omega, eps=EPS, n_aligned=3):
+    """Scheme (b): per face, the weight with which its owner's intensity leaves
+    through it (Aperp / n on the owner's n most aligned outflow faces, else 0),
+    and whether it carries radiation."""
+    owner, nbr, shift, area, normal = _faces(mesh)
+    C = len(mesh["cell_volume"])
+    s = _orient(normal, omega)
+    out = s > eps
+    aperp = np.bincount(owner[out], weights=(area * np.abs(s))[out], minlength=C)
+    fp = mesh["face_ptr"]
+    wb = np.zeros(len(s))
+    chosen = np.zeros(len(s), bool)
+    for c in range(C):
+        fs = [f for f in range(fp[c], fp[c + 1]) if out[f]]
+        fs.sort(key=lambda f: (-s[f], f))
+        n = min(n_aligned, len(fs))
+        for f in fs[:n]:
+            chosen[f] = True
+            wb[f] = aperp[c] / n
+    return wb, chosen
+
+
+def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS, law="upwind", scheme="area"):
     """M (C x C), the outflow weights of walls / periodic faces for one direction and
     r, the factor from the unknown to the cell average."""
     owner, nbr, shift, area, normal = _faces(mesh)
     C = len(mesh["cell_volume"])
-    s = normal @ np.asarray(omega, np.float64)
+    s = _orient(normal, omega) if scheme == "aligned" else normal @ np.asarray(omega, np.float64)
     w = area * np.abs(s)
     out = s > eps
     inn = s < -eps
@@ -55,6 +88,14 @@ def direction_matrix(mesh, omega, kappa, cyclic=False, eps=EPS, law="upwind"):
         r = np.ones(C)
     interior = nbr >= 0
     per = shift != 0
+    if scheme == "aligned":
+        wb, ch = aligned_choice(mesh, omega, eps)
+        use = ch & interior & ((~per) | cyclic)
+        np.add.at(M, (nbr[use], owner[use]), -wb[use])
+        wall_out = np.bincount(owner[ch & ~interior], weights=wb[ch & ~interior], minlength=C)
+        per_out = np.bincount(owner[ch & interior & per], weights=wb[ch & interior & per],
+                              minlength=C)
+        return M, wall_out, per_out, r
     use = inn & interior & ((~per) | cyclic)
     np.add.at(M, (owner[use], nbr[use]), -w[use])
     wall_out = np.bincount(owner[out & ~interior], weights=w[out & ~interior], minlength=C)
@@ -70,6 +111,7 @@ def dense_forward(w, cyclic=False):
     em = np.asarray(w["emission"], np.float64)
     D = len(dirs)
     law = w.get("law", "upwind")
+    scheme = w.get("scheme", "area")
     off = 0
     Js, As, tots, phis = [], [], [], []
     for mesh in w["meshes"]:
@@ -81,7 +123,8 @@ def dense_forward(w, cyclic=False):
         esc = np.zeros(G)
         for d in range(D):
             for g in range(G):
-                M, wall, _, r = direction_matrix(mesh, dirs[d], k[:, g], cyclic, law=law)
+                M, wall, _, r = direction_matrix(mesh, dirs[d], k[:, g], cyclic, law=law,
+                                                 scheme=scheme)
                 phi[d, :, g] = np.linalg.solve(M, e[:, g] / D)
                 avg[d, :, g] = r * phi[d, :, g]
                 esc[g] += wall @ phi[d, :, g]
@@ -132,6 +175,7 @@ def dense_adjoint(w, gJ, gA, cyclic=False):
     kap = np.asarray(w["kappa"], np.float64)
     em = np.asarray(w["emission"], np.float64)
     D = len(dirs)
+    scheme = w.get("scheme", "area")
     off = 0
     dk_all, de_all = [], []
     for mesh in w["meshes"]:
@@ -147,7 +191,7 @@ def dense_adjoint(w, gJ, gA, cyclic=False):
             gphi = gj / (4 * np.pi) + ga * k * V
             jsum = np.zeros(C)
             for d in range(D):
-                M, _, _, _ = direction_matrix(mesh, dirs[d], k, cyclic=cyclic)
+                M, _, _, _ = direction_matrix(mesh, dirs[d], k, cyclic=cyclic, scheme=scheme)
                 phi = np.linalg.solve(M, e / D)
                 lam = np.linalg.solve(M.T, gphi)
                 jsum += phi
@@ -160,12 +204,14 @@ def dense_adjoint(w, gJ, gA, cyclic=False):
     return np.concatenate(dk_all), np.concatenate(de_all)
 
 
-def brute_levels(mesh, omega, eps=EPS):
+def brute_levels(mesh, omega, eps=EPS, scheme="area"):
     """Longest-path levels by repeated relaxation over the edge list (no queue)."""
     owner, nbr, shift, area, normal = _faces(mesh)
     C = len(mesh["cell_volume"])
     s = normal @ np.asarray(omega, np.float64)
     e = (s > eps) & (nbr >= 0) & (shift == 0)
+    if scheme == "aligned":
+        e = aligned_choice(mesh, omega, eps)[1] & (nbr >= 0) & (shift == 0)
     src, dst = owner[e], nbr[e]
     level = np.zeros(C, np.int64)
     for _ in range(C + 1):

@@ -310,6 +310,9 @@ def main() -> int:
                     help="lattice side of the hii_rtype workload")
     ap.add_argument("--law", default="upwind", choices=("upwind", "exp"),
                     help="cell law: first-order upwind balance or exponential attenuation")
+    ap.add_argument("--scheme", default="area", choices=("area", "aligned"),
+                    help="transport scheme: (a) area-weighted outflow or (b) the three most "
+                         "aligned outflow faces")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tune", action="store_true",
@@ -342,6 +345,7 @@ def main() -> int:
     t0 = time.perf_counter()
     w = make_workload(args.workload)
     w["law"] = args.law
+    w["scheme"] = args.scheme
     log("workload %s built in %.1f s" % (args.workload, time.perf_counter() - t0))
     G = int(w["G"])
     C = sum(len(m["cell_volume"]) for m in w["meshes"])
@@ -355,7 +359,7 @@ def main() -> int:
     fo = fwd_opts(w, "batched", args.block, args.ring)
 
     # validate the mesh once; the timed steps rebuild the graphs without re-checking it
-    dag0 = sw.build_dag(meshes, w["dirs"], validate=True)
+    dag0 = sw.build_dag(meshes, w["dirs"], validate=True, scheme=args.scheme)
     info = dag0.info()
     tuned = None
     if args.tune:
@@ -367,7 +371,8 @@ def main() -> int:
     def step(form="batched", dirs=None):
         """build + forward (saving for the adjoint) + adjoint of the absorbed-photon loss"""
         o = dict(fo, form=form)
-        dag = sw.build_dag(meshes, w["dirs"] if dirs is None else dirs, validate=False)
+        dag = sw.build_dag(meshes, w["dirs"] if dirs is None else dirs, validate=False,
+                           scheme=args.scheme)
         J, A, tot, saved = sw.forward(dag, kappa, emission, save_for_adjoint=True, **o)
         dk, de = sw.adjoint(dag, kappa, emission, saved, gJ, gA, **o)
         return dag, J, A, tot, dk, de
@@ -482,7 +487,7 @@ def main() -> int:
         "config": {"workload": args.workload, "cells": C, "directions": D, "groups": G,
                    "meshes": len(w["meshes"]), "boundary": w.get("boundary", "vacuum"),
                    "n_pbc": fo["n_pbc"], "n_scat": fo["n_scat"], "albedo": fo["albedo"],
-                   "law": fo["law"],
+                   "law": fo["law"], "scheme": args.scheme,
                    "adjoint": True, "updates_per_step": n_updates, "form": "batched",
                    "block": fo["block"] or "default", "ring": fo["ring"] or "default"},
         "roofline": roof,

@@ -101,10 +101,28 @@ typedef struct {
   const double* cell_volume;  /* [n_cells] */
 } sweep_mesh_t;
 
+/* Transport schemes of sec. 2.6: how a cell's outflow Aperp phi is shared among
+ * its outflow faces (see sweep_build_opts_t.scheme). */
+enum { SWEEP_SCHEME_AREA = 0, SWEEP_SCHEME_ALIGNED = 1 };
+
 typedef struct {
   double eps_tie;   /* |Omega.n| <= eps_tie: the face carries nothing (default 1e-12) */
   int32_t validate; /* 1: check the mesh and directions on the host first (default 1) */
-  int32_t reserved[7];
+  int32_t kahn_counters; /* where the level computation keeps its per-cell dependency
+                            counters: 0 = LDS when the largest mesh fits (4 bits per
+                            cell), else global memory; 1 = LDS (UNSUPPORTED if the mesh
+                            does not fit); 2 = global memory.  The levels do not depend
+                            on it */
+  int32_t scheme;   /* SWEEP_SCHEME_AREA (default): scheme (a), each outflow face i gets
+                       the share A_i (n_i . Omega) / Aperp (weight w = A |s|).
+                       SWEEP_SCHEME_ALIGNED: scheme (b), direction-conserving transport:
+                       the n outflow faces with the largest Omega . n (ties: the lower
+                       face index) each carry Aperp / n and the others nothing, so a
+                       task has at most n downwind dependencies; needs every mesh's
+                       face_twin.  The graph, the sweeps, the periodic passes and the
+                       adjoint all follow the chosen scheme */
+  int32_t n_aligned; /* scheme (b): n, 1..4 (0 = 3, the number of dimensions) */
+  int32_t reserved[4];
 } sweep_build_opts_t;
 
 /* Opaque handle of a built set of per-direction dependency graphs. */
@@ -121,6 +139,8 @@ typedef struct {
   int32_t min_depth;
   double mean_depth;
   int64_t device_bytes;   /* bytes held by the DAG */
+  int32_t kahn_lds_counters; /* 1: the levels were computed with counters in LDS */
+  int32_t scheme;            /* SWEEP_SCHEME_* the DAG was built with */
 } sweep_dag_info_t;
 
 enum { SWEEP_BOUNDARY_VACUUM = 0, SWEEP_BOUNDARY_PERIODIC = 1 };
@@ -160,6 +180,10 @@ typedef struct {
   int32_t check;     /* 1: synchronise `stream` at the end of the call and return
                         SWEEP_ERR_INVALID_ARG if the kernels met invalid input (see the
                         conventions above); 0: leave it to the next synchronising call */
+  int32_t grid;      /* batched form: at most this many persistent workgroups (each takes
+                        (mesh, direction) units from a shared counter until none is
+                        left); 0 = as many as the GPU holds at once.  Results do not
+                        depend on it */
 } sweep_fwd_opts_t;
 
 /* Message of the last failed call on this thread ("" if none). */

@@ -55,7 +55,7 @@ def upload_mesh(mesh: dict, device="cuda") -> dict:
 
 def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
               use_graph=False, law="upwind", merge=False, warm_start=False,
-              pbc_tol=0.0, check=False) -> B.sweep_fwd_opts_t:
+              pbc_tol=0.0, check=False, grid=0) -> B.sweep_fwd_opts_t:
     o = B.sweep_fwd_opts_t()
     o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
     o.n_pbc = int(n_pbc)
@@ -70,6 +70,7 @@ def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", 
     o.warm_start = int(bool(warm_start))
     o.pbc_tol = float(pbc_tol)
     o.check = int(bool(check))
+    o.grid = int(grid)
     return o
 
 
@@ -146,8 +147,12 @@ class Dag:
 
 
 def build_dag(meshes, dirs, eps: float = 1e-12, validate: bool = True, device="cuda",
-              stream=None) -> Dag:
-    """Build the dependency graphs of `meshes` (numpy dicts or upload_mesh() results)."""
+              stream=None, kahn_counters: str = "auto", scheme: str = "area",
+              n_aligned: int = 3) -> Dag:
+    """Build the dependency graphs of `meshes` (numpy dicts or upload_mesh() results).
+    kahn_counters: "auto", "lds" or "global" (where the level computation counts).
+    scheme: transport scheme "area" (a) or "aligned" (b, the outflow shared by the
+    n_aligned most aligned outflow faces; needs face_twin)."""
     B.load()
     dev = [m if isinstance(m.get("face_ptr"), torch.Tensor) else upload_mesh(m, device)
            for m in meshes]
@@ -166,6 +171,9 @@ def build_dag(meshes, dirs, eps: float = 1e-12, validate: bool = True, device="c
     opts = B.sweep_build_opts_t()
     opts.eps_tie = float(eps)
     opts.validate = int(bool(validate))
+    opts.kahn_counters = {"auto": 0, "lds": 1, "global": 2}[kahn_counters]
+    opts.scheme = {"area": B.SWEEP_SCHEME_AREA, "aligned": B.SWEEP_SCHEME_ALIGNED}[scheme]
+    opts.n_aligned = int(n_aligned)
     h = ctypes.c_void_p()
     B.check(sweep_build_dag(arr, len(dev), d.ctypes.data, len(d), ctypes.byref(opts),
                             _stream(stream), ctypes.byref(h)))

@@ -19,6 +19,7 @@ SWEEP_N_TOTALS = 8
 SWEEP_BOUNDARY_VACUUM, SWEEP_BOUNDARY_PERIODIC = 0, 1
 SWEEP_FORM_BATCHED, SWEEP_FORM_PLAIN = 0, 1
 SWEEP_LAW_UPWIND, SWEEP_LAW_EXP = 0, 1
+SWEEP_SCHEME_AREA, SWEEP_SCHEME_ALIGNED = 0, 1
 
 EXPORTED = ("sweep_last_error", "sweep_build_dag", "sweep_destroy_dag", "sweep_dag_info",
             "sweep_dag_export", "sweep_saved_bytes", "sweep_forward", "sweep_adjoint",
@@ -47,7 +48,8 @@ class sweep_mesh_t(ctypes.Structure):
 
 class sweep_build_opts_t(ctypes.Structure):
     _fields_ = [("eps_tie", ctypes.c_double), ("validate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("kahn_counters", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("n_aligned", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class sweep_dag_info_t(ctypes.Structure):
@@ -55,7 +57,8 @@ class sweep_dag_info_t(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("n_tasks", ctypes.c_int64),
                 ("n_up_entries", ctypes.c_int64), ("n_down_entries", ctypes.c_int64),
                 ("max_depth", ctypes.c_int32), ("min_depth", ctypes.c_int32),
-                ("mean_depth", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("mean_depth", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("kahn_lds_counters", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 class sweep_ion_params_t(ctypes.Structure):
@@ -71,7 +74,7 @@ class sweep_fwd_opts_t(ctypes.Structure):
                 ("form", ctypes.c_int32), ("block", ctypes.c_int32), ("ring", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("law", ctypes.c_int32), ("merge", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("pbc_tol", ctypes.c_double),
-                ("check", ctypes.c_int32)]
+                ("check", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
 
 _lib = None

@@ -247,7 +247,16 @@ struct sweep_dag_s {
   int32_t n_blocks = 0;  // 256-task blocks over all units (prep kernel)
   int32_t max_depth = 0;
   int32_t max_cells = 0;  // cells of the largest mesh
+  int32_t kahn_lds = 0;   // the levels were computed with counters in LDS
+  int32_t scheme = SWEEP_SCHEME_AREA;
   Buf flag;               // device error bits (see internal.h) raised by asynchronous calls
+  std::vector<int64_t> unit_up, unit_dn;  // row entries of every unit
+  // step tables of the level-synchronous sweep, one per workgroup size
+  struct StepTable {
+    int32_t block = 0;
+    Buf k, eu, ed, base, n;
+  };
+  std::vector<std::unique_ptr<StepTable>> steps;
   // reduction tables (depend on G)
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
@@ -370,7 +379,7 @@ sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
 }
 
 struct FwdPlan {
-  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm, check;
+  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm, check, grid;
   float albedo;
   double pbc_tol;
 };
@@ -389,6 +398,8 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   p->warm = o ? (o->warm_start != 0) : 0;
   p->pbc_tol = o ? o->pbc_tol : 0.0;
   p->check = o ? (o->check != 0) : 0;
+  p->grid = o ? o->grid : 0;
+  if (p->grid < 0) return fail(SWEEP_ERR_INVALID_ARG, "grid must be >= 0");
   if (!(p->pbc_tol >= 0.0) || !std::isfinite(p->pbc_tol))
     return fail(SWEEP_ERR_INVALID_ARG, "pbc_tol must be finite and >= 0");
   if (p->law != SWEEP_LAW_UPWIND && p->law != SWEEP_LAW_EXP)
@@ -422,11 +433,69 @@ std::vector<std::pair<int, int>> group_chunks(int G, bool plain) {
   return ch;
 }
 
-int default_ring(int gn, int ring) {
-  if (ring > 0) return ring;
-  int r = 1;
-  while ((size_t)(r * 2) * gn * sizeof(float) <= 64 * 1024) r *= 2;
-  return r;
+// The largest ring (a power of two) whose LDS layout fits next to the staging
+// buffers and prefetched slots of `block` threads; 0 if none does.
+int default_ring(sweep_dag_t d, int gn, int block) {
+  int best = 0;
+  for (int r = 64; r <= (1 << 20); r *= 2)
+    if (sweep::sweep_lds_layout(gn, r, block).bytes <= (size_t)d->lds_max) best = r;
+  return best;
+}
+
+// The step table of `block`-thread sweeps (built on first use, kept with the DAG).
+sweep_status_t ensure_steps(sweep_dag_t d, int block, hipStream_t s, sweep_dag_s::StepTable** out) {
+  for (auto& t : d->steps)
+    if (t->block == block) {
+      *out = t.get();
+      return SWEEP_OK;
+    }
+  if (g_capturing)  // prepare_steps builds every table a captured sequence needs beforehand
+    return fail(SWEEP_ERR_HIP, "step table of %d threads missing during graph capture", block);
+  const int n_units = (int)d->units.size();
+  const int cap_t = block, cap_e = sweep::kStageCh * block - 8;
+  // capacity per unit: a level of w tasks and e entries gives at most
+  // w / cap_t + 1.15 e / cap_e + 2 steps, and the levels' e sum to at most the
+  // unit's upwind plus downwind entries
+  std::vector<int64_t> base(n_units + 1, 0);
+  for (int u = 0; u < n_units; ++u) {
+    const Unit& U = d->units[u];
+    const int64_t e = d->unit_up[u] + d->unit_dn[u];
+    base[u + 1] = base[u] + 2 * (int64_t)U.depth + U.n_cells / cap_t + (e * 115) / (100LL * cap_e) + 3;
+  }
+  std::unique_ptr<sweep_dag_s::StepTable> t(new sweep_dag_s::StepTable());
+  t->block = block;
+  const int64_t total = base[n_units];
+  HIP_TRY(t->k.alloc(4 * total));
+  HIP_TRY(t->eu.alloc(8 * total));
+  HIP_TRY(t->ed.alloc(8 * total));
+  HIP_TRY(t->base.alloc(8 * (size_t)(n_units + 1)));
+  HIP_TRY(t->n.alloc(4 * (size_t)n_units));
+  HIP_TRY(hipMemcpyAsync(t->base.p, base.data(), 8 * (size_t)(n_units + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(sweep::launch_steps(d->units_d.as<Unit>(), n_units, d->lp.as<int32_t>(),
+                              d->lev_up.as<int64_t>(), d->lev_dn.as<int64_t>(),
+                              d->up_ptr.as<int64_t>(), d->dn_ptr.as<int64_t>(),
+                              t->base.as<int64_t>(), cap_t, cap_e, t->k.as<int32_t>(),
+                              t->eu.as<int64_t>(), t->ed.as<int64_t>(), t->n.as<int32_t>(), s));
+  std::vector<int32_t> ns(n_units);
+  HIP_TRY(hipMemcpyAsync(ns.data(), t->n.p, 4 * (size_t)n_units, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int u = 0; u < n_units; ++u)
+    if (ns[u] < 0) return fail(SWEEP_ERR_HIP, "step table of unit %d overflowed its capacity", u);
+  *out = t.get();
+  d->steps.push_back(std::move(t));
+  return SWEEP_OK;
+}
+
+// Builds the step tables the sweeps of a call with these options use (before
+// any capture: building one synchronises the stream).
+sweep_status_t prepare_steps(sweep_dag_t d, const FwdPlan& p, int32_t G, hipStream_t s) {
+  for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
+    (void)g0;
+    const int block = p.block > 0 ? p.block : sweep::kSweepMaxBlock(gn);
+    sweep_dag_s::StepTable* t = nullptr;
+    ST_TRY(ensure_steps(d, block, s, &t));
+  }
+  return SWEEP_OK;
 }
 
 // Per-task denominators and sources for one sweep (schedule order).
@@ -469,8 +538,6 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
   sweep::SweepArgs a{};
   a.units = d->units_d.as<Unit>();
   a.sched = d->sched.as<int32_t>();
-  a.lp = d->lp.as<int32_t>();
-  a.lev = reverse ? d->lev_dn.as<int64_t>() : d->lev_up.as<int64_t>();
   a.row_ptr = reverse ? d->dn_ptr.as<int64_t>() : d->up_ptr.as<int64_t>();
   a.ent = reverse ? d->dn.as<int2>() : d->up.as<int2>();
   a.n_ent = reverse ? d->n_dn : d->n_up;
@@ -486,29 +553,25 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
   a.D = d->D;
   const int n_units = (int)d->units.size();
   for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
-    int block = p.block > 0 ? p.block : (gn == 1 ? 1024 : 512);
-    const int ring = default_ring(gn, p.ring);
-    const int stage = sweep::kStageEntries;
-    // level tables in LDS when they fit next to the ring and the staging
-    // buffers, else read from global memory (512 threads per workgroup)
-    int lp_cap = d->max_depth + 2;
-    sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, stage, lp_cap);
-    if (L.bytes > (size_t)d->lds_max) {
-      lp_cap = 0;
-      block = 512;
-      L = sweep::sweep_lds_layout(gn, ring, stage, lp_cap);
-    }
-    if (L.bytes > (size_t)d->lds_max)
+    const int block = p.block > 0 ? p.block : sweep::kSweepMaxBlock(gn);
+    if (block > sweep::kSweepMaxBlock(gn))
+      return fail(SWEEP_ERR_INVALID_ARG, "block %d: at most %d threads with %d packed groups", block,
+                  sweep::kSweepMaxBlock(gn), gn);
+    const int ring = p.ring > 0 ? p.ring : default_ring(d, gn, block);
+    const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, std::max(ring, 64), block);
+    if (ring == 0 || L.bytes > (size_t)d->lds_max)
       return fail(p.ring > 0 ? SWEEP_ERR_INVALID_ARG : SWEEP_ERR_UNSUPPORTED,
-                  "ring %d x %d groups needs %zu bytes of LDS, %d available", ring, gn, L.bytes,
-                  d->lds_max);
+                  "ring %d x %d groups with %d threads needs %zu bytes of LDS, %d available", ring,
+                  gn, block, L.bytes, d->lds_max);
+    sweep_dag_s::StepTable* stp = nullptr;
+    ST_TRY(ensure_steps(d, block, s, &stp));
+    a.step_k = stp->k.as<int32_t>();
+    a.step_e = reverse ? stp->ed.as<int64_t>() : stp->eu.as<int64_t>();
+    a.step_base = stp->base.as<int64_t>();
+    a.n_steps = stp->n.as<int32_t>();
     a.g0 = g0;
     a.ring_mask = ring - 1;
-    a.stage_entries = stage;
-    a.lp_cap = lp_cap;
     a.stage_off = L.stage_off;
-    a.lp_off = L.lp_off;
-    a.lev_off = L.lev_off;
     if (p.form == SWEEP_FORM_PLAIN) {
       a.work_counter = nullptr;
       a.n_units = 1;
@@ -522,7 +585,8 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
     } else {
       int per_cu = std::max(1, (int)((size_t)kMaxLds / (L.bytes + 256)));
       per_cu = std::min(per_cu, std::max(1, 2048 / block));
-      const int grid = std::min(n_units, d->cu_count * per_cu);
+      int grid = std::min(n_units, d->cu_count * per_cu);
+      if (p.grid > 0) grid = std::min(grid, p.grid);
       a.work_counter = d->counter.as<int32_t>();
       a.unit_order = d->order_d.as<int32_t>();
       a.n_units = n_units;
@@ -579,7 +643,7 @@ void opts_key(std::vector<uint64_t>& k, const FwdPlan& p) {
   std::memcpy(&ab, &p.albedo, 4);
   k.insert(k.end(), {(uint64_t)p.boundary, (uint64_t)p.n_pbc, (uint64_t)p.n_scat, (uint64_t)p.form,
                      (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab, (uint64_t)p.law,
-                     (uint64_t)p.merge, (uint64_t)p.warm});
+                     (uint64_t)p.merge, (uint64_t)p.warm, (uint64_t)p.grid});
   uint64_t tb;
   std::memcpy(&tb, &p.pbc_tol, 8);
   k.push_back(tb);
@@ -677,6 +741,15 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   if (dirs == nullptr || n_dirs < 1) return fail(SWEEP_ERR_INVALID_ARG, "need at least one direction");
   const double eps = opts ? opts->eps_tie : 1e-12;
   const int validate = opts ? opts->validate : 1;
+  const int kahn_counters = opts ? opts->kahn_counters : 0;
+  if (kahn_counters < 0 || kahn_counters > 2)
+    return fail(SWEEP_ERR_INVALID_ARG, "kahn_counters must be 0, 1 or 2");
+  const int scheme = opts ? opts->scheme : SWEEP_SCHEME_AREA;
+  const int n_aligned = opts && opts->n_aligned > 0 ? opts->n_aligned : 3;
+  if (scheme != SWEEP_SCHEME_AREA && scheme != SWEEP_SCHEME_ALIGNED)
+    return fail(SWEEP_ERR_INVALID_ARG, "unknown transport scheme %d", scheme);
+  if (scheme == SWEEP_SCHEME_ALIGNED && (n_aligned < 1 || n_aligned > sweep::kMaxAligned))
+    return fail(SWEEP_ERR_INVALID_ARG, "n_aligned must be in [1, %d]", sweep::kMaxAligned);
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(SWEEP_ERR_INVALID_ARG, "eps_tie must be >= 0");
   for (int d = 0; d < n_dirs; ++d) {
     const double n = std::sqrt(dirs[3 * d] * dirs[3 * d] + dirs[3 * d + 1] * dirs[3 * d + 1] +
@@ -691,6 +764,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(hipDeviceGetAttribute(&D->cu_count, hipDeviceAttributeMultiprocessorCount, D->device));
   D->n_meshes = n_meshes;
   D->D = n_dirs;
+  D->scheme = scheme;
   D->eps = eps;
   int64_t off = 0;
   for (int m = 0; m < n_meshes; ++m) {
@@ -698,6 +772,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     if (M.n_cells < 1 || M.n_half_faces < 1 || !M.face_ptr || !M.cell_volume || !M.face_nbr ||
         !M.face_area || !M.face_normal)
       return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: missing arrays, no cells or no faces", m);
+    if (scheme == SWEEP_SCHEME_ALIGNED && !M.face_twin)
+      return fail(SWEEP_ERR_INVALID_ARG, "mesh %d: the aligned transport scheme needs face_twin", m);
     if (validate) ST_TRY(validate_mesh_host(M, m));
     D->mesh_off.push_back((int32_t)off);
     D->mesh_cells.push_back(M.n_cells);
@@ -764,13 +840,16 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     max_cells = std::max(max_cells, meshes[m].n_cells);
   }
   const int n_cblocks = (int)cbm.size();
-  int dn_width = std::min(kRowNarrow, (max_faces + 3) / 4 * 4);
+  // scheme (b) rows hold at most n_aligned <= 4 entries: never any overflow
+  int dn_width = scheme == SWEEP_SCHEME_ALIGNED ? sweep::kMaxAligned
+                                                : std::min(kRowNarrow, (max_faces + 3) / 4 * 4);
   const int64_t ovf_cap_narrow = std::max<int64_t>(1 << 20, T / 4);
   if (ovf_cap > INT32_MAX / 2)
     return fail(SWEEP_ERR_UNSUPPORTED, "too many cells with more than %d faces", kRowCap);
   std::vector<sweep::MeshDev> md(n_meshes);
   for (int m = 0; m < n_meshes; ++m) {
     md[m].face_ptr = meshes[m].face_ptr;
+    md[m].face_twin = meshes[m].face_twin;
     md[m].face_nbr = meshes[m].face_nbr;
     md[m].face_shift = meshes[m].face_shift;
     md[m].face_area = meshes[m].face_area;
@@ -814,7 +893,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
-  HIP_TRY(cnt.alloc(4 * T));  // overflow counters of Kahn's algorithm
+  HIP_TRY(cnt.alloc(4 * (T + 64 * (int64_t)n_units)));  // Kahn's counters in global memory
   HIP_TRY(inv.alloc(4 * T));
   HIP_TRY(D->sched.alloc(4 * T));
   HIP_TRY(D->lp.alloc(4 * (T + 2 * (int64_t)n_units)));
@@ -846,6 +925,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.meshes = meshes_d.as<sweep::MeshDev>();
   a.dirs = dirs_d.as<double>();
   a.eps = eps;
+  a.scheme = scheme;
+  a.n_aligned = n_aligned;
   a.blk_base = D->blk_base.as<int32_t>();
   a.indeg = D->indeg.as<int32_t>();
   a.rowlen_up = rowlen_up.as<int32_t>();
@@ -854,6 +935,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.wface = wface.as<float>();
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
+  a.n_tasks = T;
   a.inv = inv.as<int32_t>();
   a.sched = D->sched.as<int32_t>();
   a.lp = D->lp.as<int32_t>();
@@ -909,7 +991,15 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   // Kahn counters in LDS as 4-bit fields when the mesh fits the LDS
   // (the kernel's static LDS holds two frontier copies of 2048 cells); the
   // rows' entries of cells with larger counts are flagged first
-  const bool lds_cnt = (size_t)4 * ((max_cells + 7) / 8 + 64) + 17 * 1024 <= (size_t)lds_limit;
+  const bool lds_fits = (size_t)4 * ((max_cells + 7) / 8 + 64) + 17 * 1024 <= (size_t)lds_limit;
+  if (kahn_counters == 1 && !lds_fits)
+    return fail(SWEEP_ERR_UNSUPPORTED, "the counters of a %d-cell mesh do not fit in LDS", max_cells);
+  const bool lds_cnt = kahn_counters == 2 ? false : lds_fits;
+  // counters in global memory are bytes
+  if (!lds_cnt && stats[0] > 254)
+    return fail(SWEEP_ERR_UNSUPPORTED, "a cell with %d upwind dependencies in one direction "
+                "(at most 254 when the mesh's counters do not fit in LDS)", stats[0]);
+  D->kahn_lds = lds_cnt ? 1 : 0;
   if (lds_cnt) HIP_TRY(sweep::launch_mark(a, n_big, s));
   {
     ProfScope ps("kahn", s);
@@ -962,6 +1052,12 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
                   "32-bit buffer range", D->units[u].mesh, D->units[u].dir,
                   (long long)std::max(ue[2 * u], ue[2 * u + 1]));
   D->max_cells = max_cells;
+  D->unit_up.resize(n_units);
+  D->unit_dn.resize(n_units);
+  for (int u = 0; u < n_units; ++u) {
+    D->unit_up[u] = ue[2 * u];
+    D->unit_dn[u] = ue[2 * u + 1];
+  }
   HIP_TRY(D->flag.alloc(4));
   HIP_TRY(sweep::launch_fill_i32(D->flag.as<int32_t>(), 1, 0, s));
   for (int u = 0; u < n_units; ++u) {
@@ -1037,6 +1133,8 @@ sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
   int64_t b = 0;
   for (const Buf* x : bufs) b += (int64_t)x->bytes;
   info->device_bytes = b;
+  info->kahn_lds_counters = d->kahn_lds;
+  info->scheme = d->scheme;
   return SWEEP_OK;
 }
 
@@ -1123,6 +1221,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   const int64_t CG = d->C_total * G;
   const int64_t DCG = CG * d->D;
   ST_TRY(ensure_reduce_tables(d, G));
+  ST_TRY(prepare_steps(d, p, G, s));
   if (!saved) HIP_TRY(d->phi_a.alloc(4 * DCG));
   if (periodic && n_inner > 1) HIP_TRY(d->phi_b.alloc(4 * DCG));
   if (warm) HIP_TRY(d->phi_w.alloc(4 * DCG));
@@ -1308,6 +1407,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   // are recomputed into phi_a (x^{P-1}) and xpass (the others)
   const int P = periodic ? p.n_pbc : 1;
   ST_TRY(ensure_mesh_tables(d));
+  ST_TRY(prepare_steps(d, p, G, s));
   HIP_TRY(d->lam.alloc(4 * DCG));
   HIP_TRY(d->gsrc.alloc(4 * CG));
   HIP_TRY(d->dk64.alloc(8 * CG));
@@ -1433,15 +1533,14 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
     return fail(SWEEP_ERR_HIP, "hipEventCreate failed");
   }
   const int gn = std::min(G, 4);
-  const int r0 = default_ring(gn, 0);
   double best_t = -1.0;
   FwdPlan bp = p;
   sweep_status_t st = SWEEP_OK;
   for (int block : {256, 512, 1024}) {
-    for (int ring : {r0 / 4, r0 / 2, r0, 2 * r0}) {
+    if (block > sweep::kSweepMaxBlock(gn)) continue;
+    const int r0 = default_ring(d, gn, block);
+    for (int ring : {r0 / 4, r0 / 2, r0}) {
       if (ring < 64) continue;
-      const sweep::LdsLayout L = sweep::sweep_lds_layout(gn, ring, sweep::kStageEntries, 0);
-      if (L.bytes > (size_t)d->lds_max) continue;
       FwdPlan q = p;
       q.form = SWEEP_FORM_BATCHED;
       q.block = block;
@@ -1481,22 +1580,14 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   return SWEEP_OK;
 }
 
-sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_ion_params_t* p,
-                              double t_left, double* neutral, float* kappa, double* dt,
-                              void* stream) {
-  g_err.clear();
-  ST_TRY(check_common(d, 1));
-  if (!absorbed || !p || !neutral || !kappa || !dt)
-    return fail(SWEEP_ERR_INVALID_ARG, "missing argument");
-  if (!(p->n_H > 0.0) || !(p->sigma_H > 0.0) || !(p->alpha_B > 0.0) || !(p->photon_rate > 0.0) ||
-      !(p->length_unit > 0.0) || !(p->dt_max > 0.0) || !(t_left > 0.0))
-    return fail(SWEEP_ERR_INVALID_ARG, "n_H, sigma_H, alpha_B, photon_rate, length_unit, dt_max "
-                                       "and t_left must be positive");
-  if (!(p->courant > 0.0) || !(p->courant <= 1.0))
-    return fail(SWEEP_ERR_INVALID_ARG, "courant must be in (0, 1]");
-  hipStream_t s = (hipStream_t)stream;
-  StreamScope stream_scope(s);
-  HIP_TRY(d->ion_min.alloc(8));
+}  // extern "C"
+
+namespace {
+
+// One photoionisation step; `minbuf` (device, 8 bytes) receives the step limit.
+sweep_status_t ion_step(sweep_dag_t d, const float* absorbed, const sweep_ion_params_t* p,
+                        double t_left, double* neutral, float* kappa, double* dt, hipStream_t s,
+                        unsigned long long* minbuf) {
   sweep::IonArgs a{};
   a.n = d->C_total;
   a.vol = d->vol.as<float>();
@@ -1509,9 +1600,9 @@ sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_
   a.photon_rate = p->photon_rate;
   a.length_unit = p->length_unit;
   a.l3 = p->length_unit * p->length_unit * p->length_unit;
-  HIP_TRY(sweep::launch_ion_limit(a, d->ion_min.as<unsigned long long>(), s));
+  HIP_TRY(sweep::launch_ion_limit(a, minbuf, s));  // writes +inf first, then the minimum
   uint64_t bits = 0;
-  HIP_TRY(hipMemcpyAsync(&bits, d->ion_min.p, 8, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&bits, minbuf, 8, hipMemcpyDeviceToHost, s));
   ST_TRY(take_device_error(d, s));
   double lim;
   std::memcpy(&lim, &bits, 8);
@@ -1519,6 +1610,46 @@ sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_
   HIP_TRY(sweep::launch_ion_update(a, step, s));
   *dt = step;
   return SWEEP_OK;
+}
+
+sweep_status_t check_ion_args(sweep_dag_t d, const float* absorbed, const sweep_ion_params_t* p,
+                              double t_left, double* neutral, float* kappa, double* dt) {
+  ST_TRY(check_common(d, 1));
+  if (!absorbed || !p || !neutral || !kappa || !dt)
+    return fail(SWEEP_ERR_INVALID_ARG, "missing argument");
+  if (!(p->n_H > 0.0) || !(p->sigma_H > 0.0) || !(p->alpha_B > 0.0) || !(p->photon_rate > 0.0) ||
+      !(p->length_unit > 0.0) || !(p->dt_max > 0.0) || !(t_left > 0.0))
+    return fail(SWEEP_ERR_INVALID_ARG, "n_H, sigma_H, alpha_B, photon_rate, length_unit, dt_max "
+                                       "and t_left must be positive");
+  if (!(p->courant > 0.0) || !(p->courant <= 1.0))
+    return fail(SWEEP_ERR_INVALID_ARG, "courant must be in (0, 1]");
+  return SWEEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_ion_params_t* p,
+                              double t_left, double* neutral, float* kappa, double* dt,
+                              void* stream) {
+  g_err.clear();
+  ST_TRY(check_ion_args(d, absorbed, p, t_left, neutral, kappa, dt));
+  hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
+  HIP_TRY(d->ion_min.alloc(8));
+  return ion_step(d, absorbed, p, t_left, neutral, kappa, dt, s,
+                  d->ion_min.as<unsigned long long>());
+}
+
+sweep_status_t sweep_ion_step_noalloc(sweep_dag_t d, const float* absorbed,
+                                      const sweep_ion_params_t* p, double t_left, double* neutral,
+                                      float* kappa, double* dt, void* stream) {
+  g_err.clear();
+  ST_TRY(check_ion_args(d, absorbed, p, t_left, neutral, kappa, dt));
+  unsigned long long* scratch = nullptr;  // the library's static scratch word on this device
+  HIP_TRY(sweep::ion_scratch(&scratch));
+  return ion_step(d, absorbed, p, t_left, neutral, kappa, dt, (hipStream_t)stream, scratch);
 }
 
 sweep_status_t sweep_sync(sweep_dag_t d, void* stream) {

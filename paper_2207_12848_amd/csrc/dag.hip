@@ -14,6 +14,7 @@
 #include <type_traits>
 
 #include "internal.h"
+#include "sweep.h"
 
 namespace sweep {
 
@@ -245,6 +246,163 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
   }
 }
 
+// Transport scheme (b) (direction-conserving transport, sec. 2.6), per task:
+// the cell's outflow Aperp phi is shared equally by its n = min(n_aligned,
+// outflow faces) outflow faces with the largest s (ties: the lower face
+// index), each carrying w_b = Aperp / n.  Those faces get the signed weight
+// +w_b, every other face NaN (nothing leaves through it); they are the task's
+// only downwind edges (rows of at most n entries), and the boundary sums count
+// only them.  Upwind counts depend on the neighbours' choices and are made by
+// k_count_in once every choice is written.
+__device__ __forceinline__ void top_insert(double (&bs)[kMaxAligned], int (&bf)[kMaxAligned],
+                                           double v, int f) {
+  // bs descending; an equal value already present stays first (lower face index)
+  const double os[kMaxAligned] = {bs[0], bs[1], bs[2], bs[3]};
+  const int of[kMaxAligned] = {bf[0], bf[1], bf[2], bf[3]};
+#pragma unroll
+  for (int k = 0; k < kMaxAligned; ++k) {
+    const bool keep = os[k] >= v;
+    const bool from_above = !keep && k > 0 && os[k > 0 ? k - 1 : 0] < v;
+    bs[k] = keep ? os[k] : (from_above ? os[k > 0 ? k - 1 : 0] : v);
+    bf[k] = keep ? of[k] : (from_above ? of[k > 0 ? k - 1 : 0] : f);
+  }
+}
+
+__global__ __launch_bounds__(kCountThreads) void k_count_aligned(DagBuildArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_max;
+  __shared__ unsigned long long s_ent;
+  if (threadIdx.x == 0) {
+    s_max = 0;
+    s_ent = 0ull;
+  }
+  const int m = a.cblk_mesh[blockIdx.x];
+  const MeshDev M = a.meshes[m];
+  const FaceTile T = stage_tile(M, a.cblk_c0[blockIdx.x], smem);
+  const int W = a.dn_width;
+  __syncthreads();
+  const int ci = threadIdx.x % kTileCells;
+  const int dj = threadIdx.x / kTileCells;
+  constexpr int kDirs = kCountThreads / kTileCells;
+  const int c = T.c0 + ci;
+  const bool cell = c < T.cend;
+  const int fb = cell ? (int)T.fp[ci] : 0, fe = cell ? (int)T.fp[ci + 1] : 0;
+  int mo = 0;
+  unsigned long long ed = 0;
+  auto run = [&](const double* nrm, const double* area, const int32_t* nbr, const int8_t* shift) {
+    for (int d0 = 0; d0 < a.D; d0 += kDirs) {
+      const int d = d0 + dj;
+      if (!(cell && d < a.D)) continue;
+      const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
+      const int64_t t = a.units[m * a.D + d].task_base + c;
+      float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces + T.f0;
+      double ap = 0.0;
+      int nout = 0;
+      double bs[kMaxAligned];
+      int bf[kMaxAligned];
+#pragma unroll
+      for (int k = 0; k < kMaxAligned; ++k) {
+        bs[k] = -__builtin_huge_val();
+        bf[k] = -1;
+      }
+      for (int f = fb; f < fe; ++f) {
+        const double sv = orient(ox, oy, oz, nrm + 3 * f);
+        if (sv > a.eps) {
+          ap += face_w(area[f], sv);
+          ++nout;
+          top_insert(bs, bf, sv, f);
+        }
+      }
+      const int n = min(nout, a.n_aligned);
+      const float wb = n > 0 ? (float)(ap / n) : 0.0f;
+      int32_t* row = a.dnw + t * W;
+      int ndn = 0;
+      double wall = 0.0, per = 0.0;
+      for (int f = fb; f < fe; ++f) {
+        bool chosen = false;
+#pragma unroll
+        for (int k = 0; k < kMaxAligned; ++k) chosen |= k < n && bf[k] == f;
+        wf[f] = chosen ? wb : __int_as_float(0x7fc00000);
+        if (!chosen) continue;
+        const int nb = nbr[f];
+        if (nb < 0) wall += wb;
+        else if (shift != nullptr && shift[f] != 0) per += wb;
+        else row[ndn++] = nb;
+      }
+      for (int q = ndn; q < W; ++q) row[q] = -1;
+      a.aperp[t] = (float)ap;
+      a.bnd[t] = make_float2((float)wall, (float)per);
+      a.rowlen_dn[t] = ndn;
+      mo = max(mo, ndn);
+      ed += (unsigned long long)ndn;
+    }
+  };
+  if (T.in_lds) {
+    constexpr int cap = kTileCells * kTileFaces;
+    const double* nrm = reinterpret_cast<const double*>(T.fp + kTileCells + 1);
+    const double* area = nrm + 3 * cap;
+    const int32_t* nbr = reinterpret_cast<const int32_t*>(area + cap);
+    const int8_t* shift = reinterpret_cast<const int8_t*>(nbr + cap);
+    run(nrm, area, nbr, shift);
+  } else {
+    run(M.face_normal + 3 * T.f0, M.face_area + T.f0, M.face_nbr + T.f0,
+        M.face_shift != nullptr ? M.face_shift + T.f0 : nullptr);
+  }
+  atomicMax(&s_max, mo);
+  atomicAdd(&s_ent, ed);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(a.stats + 1, s_max);
+    atomicAdd(a.ent_tot + 1, s_ent);
+  }
+}
+
+// Scheme (b), per task: the upwind dependencies are the faces whose twin the
+// neighbour chose (its signed weight is not NaN); counts, row lengths and the
+// tasks with 15 or more dependencies, as k_count does for scheme (a).
+__global__ __launch_bounds__(kCountThreads) void k_count_in(DagBuildArgs a) {
+  __shared__ int s_max;
+  __shared__ unsigned long long s_ent;
+  if (threadIdx.x == 0) {
+    s_max = 0;
+    s_ent = 0ull;
+  }
+  __syncthreads();
+  const int m = a.cblk_mesh[blockIdx.x];
+  const MeshDev M = a.meshes[m];
+  const int ci = threadIdx.x % kTileCells;
+  const int dj = threadIdx.x / kTileCells;
+  constexpr int kDirs = kCountThreads / kTileCells;
+  const int c = a.cblk_c0[blockIdx.x] + ci;
+  int mi = 0;
+  unsigned long long eu = 0;
+  if (c < M.n_cells) {
+    const int64_t fb = M.face_ptr[c], fe = M.face_ptr[c + 1];
+    for (int d = dj; d < a.D; d += kDirs) {
+      const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces;
+      int nup = 0, npin = 0;
+      for (int64_t f = fb; f < fe; ++f) {
+        if (M.face_nbr[f] < 0) continue;
+        if (isnan(wf[M.face_twin[f]])) continue;
+        if (M.face_shift != nullptr && M.face_shift[f] != 0) ++npin; else ++nup;
+      }
+      const int64_t t = a.units[m * a.D + d].task_base + c;
+      if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
+      a.indeg[t] = nup;
+      a.rowlen_up[t] = nup + npin;
+      mi = max(mi, nup);
+      eu += (unsigned long long)(nup + npin);
+    }
+  }
+  atomicMax(&s_max, mi);
+  atomicAdd(&s_ent, eu);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(a.stats, s_max);
+    atomicAdd(a.ent_tot, s_ent);
+  }
+}
+
 // Tasks with 15 or more upwind dependencies keep their counter in global
 // memory; the entries that point at them in their upwind cells' downwind rows
 // get bit 30 set, so that Kahn's algorithm sends those decrements there without
@@ -265,10 +423,13 @@ __global__ void k_mark(DagBuildArgs a, int32_t n_big) {
   const MeshDev M = a.meshes[U.mesh];
   const double ox = a.dirs[3 * U.dir], oy = a.dirs[3 * U.dir + 1], oz = a.dirs[3 * U.dir + 2];
   const int W = a.dn_width;
+  const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)U.dir * M.n_faces;
   for (int64_t f = M.face_ptr[c]; f < M.face_ptr[c + 1]; ++f) {
     const int nb = M.face_nbr[f];
     if (nb < 0 || (M.face_shift != nullptr && M.face_shift[f] != 0)) continue;
-    if (!(orient(ox, oy, oz, M.face_normal + 3 * f) < -a.eps)) continue;
+    const bool upwind = a.scheme == SWEEP_SCHEME_ALIGNED ? !isnan(wf[M.face_twin[f]])
+                                                         : orient(ox, oy, oz, M.face_normal + 3 * f) < -a.eps;
+    if (!upwind) continue;
     // nb is upwind of c: flag c in nb's row (or in its overflow list)
     int32_t* row = a.dnw + (U.task_base + nb) * W;
     for (int q = 0; q < W; ++q) {
@@ -320,6 +481,10 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63;
   int32_t* cnt = a.cnt + tb;
+  // counters in global memory: one byte per cell, four to a word, so that the
+  // counters of a whole unit (C bytes) stay in the last-level caches
+  uint8_t* cnt8 = reinterpret_cast<uint8_t*>(cnt);
+  uint32_t* cntw = reinterpret_cast<uint32_t*>(cnt);
   int32_t* sched = a.sched + tb;
   int32_t* spill = sched;  // frontier entries beyond the LDS copy (rewritten in place)
   int32_t* inv = a.inv + tb;
@@ -356,7 +521,7 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
         ready = ((nib[c >> 3] >> (4 * (c & 7))) & 15u) == 0u;
       } else {
         const int n = a.indeg[tb + c];
-        cnt[c] = n;
+        cnt8[c] = (uint8_t)n;  // below 256 (the host checks the largest in-degree)
         ready = n == 0;
       }
     }
@@ -436,10 +601,18 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
       int4 v[NCH];
 #pragma unroll
       for (int q = 0; q < NCH; ++q) v[q] = (q < Wr4 ? row4 : sent4)[q];
+      // a counter in global memory: 32-bit words of four byte counters (LDSCNT,
+      // the counters of cells with 15 or more dependencies: whole words)
       auto dec_global = [&](int nb) -> bool {
-        const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        return old == 1;
+        if (LDSCNT) {
+          const int old = __hip_atomic_fetch_add(cnt + nb, -1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+          return old == 1;
+        }
+        const uint32_t sh = (uint32_t)(nb & 3) * 8u;
+        const uint32_t old = __hip_atomic_fetch_add(cntw + (nb >> 2), 0u - (1u << sh), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        return ((old >> sh) & 255u) == 1u;
       };
       uint32_t wm = 0;  // bit 4q+i: cell i of chunk q became ready
       if (LDSCNT) {
@@ -492,12 +665,38 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           }
         }
       } else {
+        // counters in global memory: as above, every entry of the wavefront's
+        // non-empty chunks issues one atomic without a branch (padding entries
+        // subtract zero from a per-lane dummy word past the counters), so all
+        // of them are in flight before the first result is used
+        int nq = 0;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) nq += __ballot(v[q].x >= 0) != 0ull ? 1 : 0;
+        uint32_t* dummy = reinterpret_cast<uint32_t*>(a.cnt + a.n_tasks + 64 * (int64_t)blockIdx.x + lane);
+        uint32_t old[4 * NCH];
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
+          if (q >= nq) break;
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
-            if (xs[i] >= 0) wm |= (uint32_t)dec_global(xs[i] & ~kBigFlag) << (4 * q + i);
+          for (int i = 0; i < 4; ++i) {
+            const bool real = xs[i] >= 0;
+            const int nb = xs[i] & ~kBigFlag;
+            const uint32_t sh = (uint32_t)(nb & 3) * 8u;
+            old[4 * q + i] = __hip_atomic_fetch_add(real ? cntw + (nb >> 2) : dummy,
+                                                    real ? 0u - (1u << sh) : 0u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+          if (q >= nq) break;
+          const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t sh = (uint32_t)(xs[i] & 3) * 8u;
+            wm |= (uint32_t)(xs[i] >= 0 && ((old[4 * q + i] >> sh) & 255u) == 1u) << (4 * q + i);
+          }
         }
       }
       // a full row may end in a pointer to its overflow list (rare): one
@@ -645,6 +844,7 @@ constexpr int kFillBlock = 256;
 
 // Five wavefronts per SIMD: the register budget (at most 102 VGPRs) still
 // compiles without spills.
+template <bool ALIGNED>
 __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_fill(DagBuildArgs a) {
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int u = unit_of_block(a.blk_base, a.n_units, blk);
@@ -688,26 +888,38 @@ __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5)))
     for (int h = 0; h * 16 < mx; ++h) {
       const int fo = h * 16 + li;
       int code[4];
-      float ws[4];
+      float ws[4], wi[4];  // the face's own signed weight; scheme (b): its twin's
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t f = fo < nfj[j] ? fb[j] + fo : 0;  // face 0 exists
         code[j] = M.fcode[f];
         ws[j] = wf[f];
+        if (ALIGNED) wi[j] = wf[code[j] != -1 ? M.face_twin[f] : f];
       }
       int pos[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) pos[j] = inv[code[j] >= 0 ? code[j] : 0];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool has = fo < nfj[j] && !isnan(ws[j]);
-        const bool in = has && signbit(ws[j]);
-        const bool up = in && code[j] != -1;           // interior or periodic inflow
-        const bool dn = has && !in && code[j] >= 0;    // interior outflow
-        const float w = fabsf(ws[j]);
+        bool up, dn;
+        float w, wu;
+        if (ALIGNED) {
+          // radiation leaves through the faces the cell chose and enters through
+          // the faces whose twin the neighbour chose
+          up = fo < nfj[j] && code[j] != -1 && !isnan(wi[j]);
+          dn = fo < nfj[j] && code[j] >= 0 && !isnan(ws[j]);
+          w = ws[j];
+          wu = wi[j];
+        } else {
+          const bool has = fo < nfj[j] && !isnan(ws[j]);
+          const bool in = has && signbit(ws[j]);
+          up = in && code[j] != -1;           // interior or periodic inflow
+          dn = has && !in && code[j] >= 0;    // interior outflow
+          w = wu = fabsf(ws[j]);
+        }
         const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
         const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
-        if (up) a.up[eu[j] + __popc(mu & below)] = make_int2(code[j] >= 0 ? pos[j] : code[j] + 1, __float_as_int(w));
+        if (up) a.up[eu[j] + __popc(mu & below)] = make_int2(code[j] >= 0 ? pos[j] : code[j] + 1, __float_as_int(wu));
         if (dn) a.dn[ed[j] + __popc(md & below)] = make_int2(pos[j], __float_as_int(w));
         eu[j] += __popc(mu);
         ed[j] += __popc(md);
@@ -746,6 +958,76 @@ __global__ void k_level_widths(const Unit* units, const int32_t* lp, int32_t mes
     atomicAdd(width + k, (unsigned long long)(l[k + 1] - l[k]));
 }
 
+// Steps of the level-synchronous sweep, one workgroup per unit: every level l
+// (w tasks, e the larger of its upwind and downwind row entries) is cut into
+// n = max(1, ceil(w / cap_t), ceil(1.15 e / cap_e)) runs of consecutive
+// schedule positions with equal task counts (floor(c w / n) from the level's
+// start).  The tasks of a run are independent, so each run is one step of the
+// sweep; the 15 % margin keeps the runs' entry counts within cap_e for rows of
+// ordinary spread (a run above it is still correct, on the sweep's slower
+// path).  Writes the steps' first positions and entries (plus one closing
+// step) from step_base[u], and their number.
+constexpr int kStepsBlock = 256;
+__global__ __launch_bounds__(kStepsBlock) void k_steps(const Unit* units, const int32_t* lp,
+                                                       const int64_t* lev_up, const int64_t* lev_dn,
+                                                       const int64_t* up_ptr, const int64_t* dn_ptr,
+                                                       const int64_t* step_base, int32_t cap_t,
+                                                       int32_t cap_e, int32_t* sk, int64_t* seu,
+                                                       int64_t* sed, int32_t* n_steps) {
+  __shared__ int s_scan[kStepsBlock];
+  __shared__ int s_carry;
+  const Unit U = units[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int32_t* l = lp + U.lp_base;
+  const int64_t* lu = lev_up + U.lp_base;
+  const int64_t* ld = lev_dn + U.lp_base;
+  const int64_t base = step_base[blockIdx.x];
+  const int64_t cap = step_base[blockIdx.x + 1] - base;  // room for the steps and the closing one
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int l0 = 0; l0 < U.depth; l0 += kStepsBlock) {
+    const int lv = l0 + tid;
+    int n = 0, k0 = 0, w = 0;
+    if (lv < U.depth) {
+      k0 = l[lv];
+      w = l[lv + 1] - k0;
+      const int64_t e = max(lu[lv + 1] - lu[lv], ld[lv + 1] - ld[lv]);
+      const int64_t ne = (e * 115 + 100LL * cap_e - 1) / (100LL * cap_e);
+      n = max(1, max((w + cap_t - 1) / cap_t, (int)ne));
+    }
+    s_scan[tid] = n;
+    __syncthreads();
+    for (int o = 1; o < kStepsBlock; o <<= 1) {  // inclusive scan over the block
+      const int x = tid >= o ? s_scan[tid - o] : 0;
+      __syncthreads();
+      s_scan[tid] += x;
+      __syncthreads();
+    }
+    const int off = s_carry + s_scan[tid] - n;
+    // (the host sizes the table above every count; a count past it is reported)
+    for (int c = 0; c < n && off + c + 1 < cap; ++c) {
+      const int kk = k0 + (int)(((int64_t)c * w) / n);
+      sk[base + off + c] = kk;
+      seu[base + off + c] = up_ptr[U.task_base + kk];
+      sed[base + off + c] = dn_ptr[U.task_base + kk];
+    }
+    __syncthreads();
+    if (tid == kStepsBlock - 1) s_carry += s_scan[tid];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int ns = s_carry;
+    if (ns + 1 > cap) {
+      n_steps[blockIdx.x] = -1;
+      return;
+    }
+    sk[base + ns] = U.n_cells;
+    seu[base + ns] = up_ptr[U.task_base + U.n_cells];
+    sed[base + ns] = dn_ptr[U.task_base + U.n_cells];
+    n_steps[blockIdx.x] = ns;
+  }
+}
+
 __global__ void k_d2f(const double* in, float* out, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -773,6 +1055,17 @@ size_t count_lds_bytes(int max_faces, int dn_width) {
 
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s) {
   if (n_cblocks <= 0) return hipSuccess;
+  if (a.scheme == SWEEP_SCHEME_ALIGNED) {
+    const size_t tile = tile_lds_bytes();
+    hipError_t e = hipFuncSetAttribute((const void*)k_count_aligned,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)tile);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_aligned, dim3(n_cblocks), dim3(kCountThreads), tile, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // upwind counts once every cell's choice is written
+    hipLaunchKernelGGL(k_count_in, dim3(n_cblocks), dim3(kCountThreads), 0, s, a);
+    return hipGetLastError();
+  }
   const size_t tile = tile_lds_bytes();
   const size_t staged = tile + (size_t)kCountThreads * a.dn_width * 4;
   const bool stage = staged <= (size_t)lds_limit - 64;
@@ -794,6 +1087,12 @@ hipError_t launch_kahn_n(const DagBuildArgs& a, size_t lds, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NCH>
+hipError_t launch_kahn_g(const DagBuildArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_kahn<false, NCH>), dim3(a.n_units), dim3(kKahnBlock), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s) {
   if (lds_counters) {
     const size_t lds = sizeof(uint32_t) * (size_t)((max_cells + 7) / 8 + 64);
@@ -805,8 +1104,10 @@ hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cel
       default: return launch_kahn_n<8>(a, lds, s);
     }
   }
-  hipLaunchKernelGGL((k_kahn<false, 8>), dim3(a.n_units), dim3(kKahnBlock), 0, s, a);
-  return hipGetLastError();
+  switch (a.dn_chunks) {
+    case 0: case 1: case 2: case 3: case 4: return launch_kahn_g<4>(a, s);
+    default: return launch_kahn_g<8>(a, s);
+  }
 }
 
 hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s) {
@@ -823,7 +1124,10 @@ hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_
 
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  if (a.scheme == SWEEP_SCHEME_ALIGNED)
+    hipLaunchKernelGGL(k_fill<true>, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_fill<false>, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
   return hipGetLastError();
 }
 
@@ -872,6 +1176,16 @@ hipError_t launch_level_widths(const Unit* units, int32_t n_units, const int32_t
   if (n_units <= 0 || n_levels <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_level_widths, dim3(n_units), dim3(256), 0, s, units, lp, mesh,
                      reinterpret_cast<unsigned long long*>(width), n_levels);
+  return hipGetLastError();
+}
+
+hipError_t launch_steps(const Unit* units, int32_t n_units, const int32_t* lp, const int64_t* lev_up,
+                        const int64_t* lev_dn, const int64_t* up_ptr, const int64_t* dn_ptr,
+                        const int64_t* step_base, int32_t cap_t, int32_t cap_e, int32_t* step_k,
+                        int64_t* step_eu, int64_t* step_ed, int32_t* n_steps, hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_steps, dim3(n_units), dim3(kStepsBlock), 0, s, units, lp, lev_up, lev_dn,
+                     up_ptr, dn_ptr, step_base, cap_t, cap_e, step_k, step_eu, step_ed, n_steps);
   return hipGetLastError();
 }
 

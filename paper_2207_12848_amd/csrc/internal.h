@@ -37,6 +37,7 @@ struct MeshDev {
   const double* face_area;
   const double* face_normal;
   const double* cell_volume;
+  const int32_t* face_twin;  // matching half-face of the neighbour (scheme (b) only)
   const int32_t* fcode;  // per face: neighbour code (see k_face_codes)
   int64_t face_off;      // first face of the mesh in the concatenated per-face arrays
   int64_t n_faces;
@@ -51,6 +52,8 @@ struct DagBuildArgs {
   const MeshDev* meshes;
   const double* dirs;  // [D][3]
   double eps;
+  int32_t scheme;      // SWEEP_SCHEME_AREA (a) or SWEEP_SCHEME_ALIGNED (b)
+  int32_t n_aligned;   // scheme (b): outflow faces that share a cell's outflow (1..kMaxAligned)
   const int32_t* blk_base;  // [n_units+1] first block of each unit (cell-range kernels)
   const int32_t* cblk_mesh;  // cell-order kernels: mesh and first cell of every block
   const int32_t* cblk_c0;
@@ -76,7 +79,9 @@ struct DagBuildArgs {
   // in its sign: outflow +w, inflow -w, neither NaN
   float* wface;
   float2* bnd;  // (sum of w over wall outflow faces, over periodic outflow faces)
-  int32_t* cnt;
+  int32_t* cnt;     // [T] counters kept in global memory, then 64 per unit that take
+                    // the zero decrements of padding entries (see k_kahn)
+  int64_t n_tasks;  // T
   int32_t* inv;    // cell -> position in the unit's schedule
   // per task, schedule order within the unit
   int32_t* sched;  // position -> cell
@@ -100,8 +105,13 @@ struct SweepArgs {
   int32_t n_units;
   int32_t* work_counter;  // persistent form: next unit to take; nullptr: unit = blockIdx.x
   const int32_t* sched;
-  const int32_t* lp;
-  const int64_t* lev;      // per level: first row entry (lev_up forward, lev_dn adjoint)
+  // steps of the level-synchronous sweep (see k_steps): unit u's steps start at
+  // step_base[u]; step i covers schedule positions [step_k[i], step_k[i + 1]) and
+  // row entries [step_e[i], step_e[i + 1]) (upwind rows forward, downwind adjoint)
+  const int32_t* step_k;
+  const int64_t* step_e;
+  const int64_t* step_base;
+  const int32_t* n_steps;
   const int64_t* row_ptr;  // up_ptr (forward) or dn_ptr (adjoint)
   const int2* ent;         // up (forward) or dn (adjoint)
   int64_t n_ent;           // entries in `ent`
@@ -116,11 +126,7 @@ struct SweepArgs {
   int32_t g0;      // first group handled by this launch
   int32_t D;
   int32_t ring_mask;
-  int32_t stage_entries;  // LDS staging capacity per buffer (entries)
-  int32_t lp_cap;         // level-table capacity in LDS (>= depth + 2 of every unit)
-  int32_t stage_off;      // byte offsets in the dynamic LDS
-  int32_t lp_off;
-  int32_t lev_off;
+  int32_t stage_off;      // byte offset of the staging buffers in the dynamic LDS
 };
 
 // Per-call preparation of the per-task denominators and sources (cell order,
@@ -229,9 +235,13 @@ hipError_t launch_pbc_adj(const PbcAdjArgs& a, int32_t n_blocks, hipStream_t s);
 
 // launchers (kernels in dag.hip / sweep.hip / chem.hip)
 hipError_t launch_ion_limit(const IonArgs& a, unsigned long long* out, hipStream_t s);
+// Device address of the current device's scratch word of sweep_ion_step_noalloc
+// (looked up once per device).
+hipError_t ion_scratch(unsigned long long** out);
 hipError_t launch_ion_update(const IonArgs& a, double dt, hipStream_t s);
 constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build kernels
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s);
+constexpr int kMaxAligned = 4;  // most faces scheme (b) may share the outflow over
 hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cells, hipStream_t s);
 hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 // out[0] = max faces of a cell, out[1] += overflow ints for rows of row_cap entries
@@ -270,13 +280,25 @@ hipError_t launch_adj_reduce(const AdjReduceArgs& a, double* dk, double* de, hip
 hipError_t launch_d2f_pair(const double* a, const double* b, float* oa, float* ob, int64_t n,
                            hipStream_t s);
 hipError_t set_sweep_lds_limit(int32_t bytes);
-// Dynamic LDS layout of a sweep workgroup: [ring: ring*gn f32][staging: 2*stage int2]
-// [level pointers: lp_cap i32][level entries: lp_cap i64]
+// Row entries each sweep thread stages per step (a step holds at most
+// kStageCh x threads - 8 entries in LDS).
+constexpr int kStageCh = 4;
+// Largest sweep workgroup for gn packed groups: one group fits 1024 threads'
+// registers (128 VGPRs each), more groups need the 256 VGPRs of 512 threads.
+constexpr int kSweepMaxBlock(int gn) { return gn == 1 ? 1024 : 512; }
+// Dynamic LDS layout of a sweep workgroup of `block` threads: values (ring
+// slots, a zero slot, a sink, 2 x kStageCh x block prefetched slots) x gn FP32, then two
+// staging buffers of kStageCh x block + 8 entries.
 struct LdsLayout {
-  int32_t stage_off, lp_off, lev_off;
+  int32_t stage_off;
   size_t bytes;
 };
-LdsLayout sweep_lds_layout(int32_t gn, int32_t ring, int32_t stage, int32_t lp_cap);
-constexpr int kStageEntries = 4096;  // row entries staged in LDS per level
+LdsLayout sweep_lds_layout(int32_t gn, int32_t ring, int32_t block);
+// Steps of the level-synchronous sweep with at most cap_t tasks and about
+// cap_e row entries each (see k_steps), written from step_base[u] per unit.
+hipError_t launch_steps(const Unit* units, int32_t n_units, const int32_t* lp, const int64_t* lev_up,
+                        const int64_t* lev_dn, const int64_t* up_ptr, const int64_t* dn_ptr,
+                        const int64_t* step_base, int32_t cap_t, int32_t cap_e, int32_t* step_k,
+                        int64_t* step_eu, int64_t* step_ed, int32_t* n_steps, hipStream_t s);
 
 }  // namespace sweep

@@ -51,6 +51,41 @@ __device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, uint32
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)vo, 0, 0);
 }
 
+// GN consecutive FP32 values at byte offset vo + so of a buffer (one access for
+// GN = 2 or 4; offsets past the buffer's end read zeros and drop stores).
+template <int GN>
+__device__ __forceinline__ void ld_gn(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float* v) {
+  if constexpr (GN == 4) {
+    const int4 x = __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+    v[0] = __int_as_float(x.x);
+    v[1] = __int_as_float(x.y);
+    v[2] = __int_as_float(x.z);
+    v[3] = __int_as_float(x.w);
+  } else if constexpr (GN == 2) {
+    const int2 x = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+    v[0] = __int_as_float(x.x);
+    v[1] = __int_as_float(x.y);
+  } else {
+#pragma unroll
+    for (int g = 0; g < GN; ++g) v[g] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)(vo + 4u * g), (int)so, 0));
+  }
+}
+
+template <int GN>
+__device__ __forceinline__ void st_gn(const float* v, __amdgpu_buffer_rsrc_t r, uint32_t vo) {
+  if constexpr (GN == 4) {
+    const int4 x = make_int4(__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]),
+                             __float_as_int(v[3]));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) int, x), r, (int)vo, 0, 0);
+  } else if constexpr (GN == 2) {
+    const int2 x = make_int2(__float_as_int(v[0]), __float_as_int(v[1]));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) int, x), r, (int)vo, 0, 0);
+  } else {
+#pragma unroll
+    for (int g = 0; g < GN; ++g) st_f32(v[g], r, vo + 4u * g);
+  }
+}
+
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
@@ -71,11 +106,7 @@ struct UnitBufs {
   int64_t ue0;                   // first row entry of the unit
 };
 
-// One slot after the ring: a sink for the results of threads without a task.
-constexpr int kSlotSink = 0;
-constexpr int kSlots = 1;
-
-// Record of one task: cell, row [r0, r1) relative to its level's first entry,
+// Record of one task: cell, row [r0, r1) relative to its step's first entry,
 // denominator and source per group.
 template <int GN>
 struct TaskRec {
@@ -87,16 +118,23 @@ struct TaskRec {
 
 // Per-step values, uniform over the workgroup.
 struct LevelInfo {
-  int l, k0, k1;  // level and its task range
-  int ne;         // row entries of the level
-  int nst;        // entries of the level held in LDS staging
-  int64_t e0;     // first row entry of the level
+  int k0, k1;     // the step's task range (schedule positions)
+  int ne;         // row entries of the step
+  int nst;        // entries of the step held in LDS staging
+  int64_t e0;     // first row entry of the step
 };
 
-// Loads in flight for one step: the thread's share of the level's row block
-// (raw entries, two per load) and the record of the thread's first task of the
-// level, with the step's level bounds.  Lanes past the level read past the
-// buffers' ends (no memory traffic, value 0).
+// Entries of a staged row hold an LDS value slot instead of a schedule position:
+// the ring slot of a result inside the window, or the slot the older value (or
+// periodic inflow, with kPerSlot set) was prefetched into; -1 when the value
+// has to be read from global memory at solve time.
+constexpr int kPerSlot = 0x40000000;
+constexpr int kSlotMask = 0x3fffffff;
+
+// Loads in flight for one step: the thread's share of the step's row block
+// (raw entries, two per load) and the record of the thread's task of the step,
+// with the step's bounds.  Lanes past the step read past the buffers' ends (no
+// memory traffic, value 0).
 template <int GN, int CH>
 struct Pref {
   LevelInfo L;
@@ -113,17 +151,14 @@ __device__ __forceinline__ void load_rec(const SweepArgs& a, const UnitBufs& B, 
   t.c = ld_b32(B.sched, 4u * (uint32_t)k, 0);
   t.r0 = (int)((uint32_t)ld_b32(B.rp, 8u * (uint32_t)k, 0) - (uint32_t)e0);
   t.r1 = (int)((uint32_t)ld_b32(B.rp, 8u * (uint32_t)(k + 1), 0) - (uint32_t)e0);
-#pragma unroll
-  for (int g = 0; g < GN; ++g) {
-    t.den[g] = ld_f32(B.den, 4u * (uint32_t)(k * a.G + g), 0);
-    t.src[g] = ld_f32(B.src, 4u * (uint32_t)(k * a.G + g), 0);
-  }
+  ld_gn<GN>(B.den, 4u * (uint32_t)(k * a.G), 0, t.den);
+  ld_gn<GN>(B.src, 4u * (uint32_t)(k * a.G), 0, t.src);
 }
 
 // Every thread issues the same loads at every step (fixed count, so the waits
-// for the loads in flight stay exact); the offsets of lanes past the level are
+// for the loads in flight stay exact); the offsets of lanes past the step are
 // moved past the buffers' ends.  Entry pair i of thread t is entries
-// 2 (t + i nthr) and 2 (t + i nthr) + 1 of the level's block.
+// 2 (t + i nthr) and 2 (t + i nthr) + 1 of the step's block.
 template <int GN, int CH>
 __device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B, int tid, int nthr,
                                            Pref<GN, CH>& P) {
@@ -139,11 +174,8 @@ __device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B
   P.c = ld_b32(B.sched, act ? 4u * (uint32_t)tid : kOob, 4u * k0);
   P.rp = ld_b128(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
   const uint32_t vo = act ? 4u * (uint32_t)(tid * a.G) : kOob, so = 4u * k0 * (uint32_t)a.G;
-#pragma unroll
-  for (int g = 0; g < GN; ++g) {
-    P.den[g] = ld_f32(B.den, vo + 4u * g, so);
-    P.src[g] = ld_f32(B.src, vo + 4u * g, so);
-  }
+  ld_gn<GN>(B.den, vo, so, P.den);
+  ld_gn<GN>(B.src, vo, so, P.src);
 }
 
 // Inflow of one task per group (and the periodic part of it).
@@ -153,10 +185,10 @@ struct Inflow {
   float pin[GN];
 };
 
-// Schedule positions whose results are in the LDS ring while a level is solved,
-// [lo, lo + n) with lo >= 0: forward, the last R positions up to the level's end;
-// adjoint (levels in reverse order), the R positions from the level's start.
-// The level's own writes never evict an upwind result inside the window.
+// Schedule positions whose results are in the LDS ring while a step is solved,
+// [lo, lo + n) with lo >= 0: forward, the last R positions up to the step's end;
+// adjoint (steps in reverse order), the R positions from the step's start.
+// The step's own writes never evict an upwind result inside the window.
 struct Window {
   int lo;
   uint32_t n;
@@ -182,20 +214,18 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& 
                                             float* ring) {
   float* rr = ring + (k & a.ring_mask) * GN;
   const uint32_t oc = 4u * (uint32_t)(t.c * a.G), ok = 4u * (uint32_t)(k * a.G);
+  float v[GN];
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
-    const float v = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
-    rr[g] = v;
-    st_f32(v, B.out, oc + 4u * g);
-    st_f32(v, B.outs, ok + 4u * g);
+    v[g] = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
+    rr[g] = v[g];
   }
-  if (PIN) {
-#pragma unroll
-    for (int g = 0; g < GN; ++g) st_f32(in.pin[g], B.pin, oc + 4u * g);
-  }
+  st_gn<GN>(v, B.out, oc);
+  st_gn<GN>(v, B.outs, ok);
+  if (PIN) st_gn<GN>(in.pin, B.pin, oc);
 }
 
-// The common step: at most one task per thread and every inflow staged.  Every
+// The common step: at most one task per thread and every inflow in LDS.  Every
 // memory operation is issued unconditionally (a thread without a task writes
 // the sink slot and stores past the buffers' ends, which are dropped), so each
 // step issues a fixed number of vector-memory operations.
@@ -207,14 +237,15 @@ __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& 
   float* rr = act ? ring + (k & a.ring_mask) * GN : sink;
   const uint32_t oc = act ? 4u * (uint32_t)(t.c * a.G) : kOob;
   const uint32_t ok = act ? 4u * (uint32_t)(k * a.G) : kOob;
+  float v[GN];
 #pragma unroll
   for (int g = 0; g < GN; ++g) {
-    const float v = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
-    rr[g] = v;
-    st_f32(v, B.out, oc + 4u * g);
-    st_f32(v, B.outs, ok + 4u * g);
-    if (PIN) st_f32(in.pin[g], B.pin, oc + 4u * g);
+    v[g] = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
+    rr[g] = v[g];
   }
+  st_gn<GN>(v, B.out, oc);
+  st_gn<GN>(v, B.outs, ok);
+  if (PIN) st_gn<GN>(in.pin, B.pin, oc);
 }
 
 // GN consecutive groups of one task from a [slot][G] array (one load; offsets
@@ -244,8 +275,8 @@ __device__ __forceinline__ void ld_groups(__amdgpu_buffer_rsrc_t r, uint32_t off
 // a periodic inflow -(partner + 1) from the previous pass (PER; zero without
 // one).  Every load of a batch is issued before the first is used, so a batch
 // costs one memory round trip whatever its mix.  The sum is the same sequence
-// of rounded products and additions in row order on every path; entries past
-// the row's end (the rest of the batch) are skipped by a select.
+// of fused multiply-adds in row order on every path; entries past the row's end
+// (the rest of the batch) are skipped.
 template <int GN, bool PER, bool STAGED>
 __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs& B,
                                              const TaskRec<GN>& t, const int2* stg, uint32_t eoff,
@@ -281,44 +312,95 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
         const float x = inw[q] ? rv[q][g] : (per ? pv[q][g] : gv[q][g]);
-        const float pr = __fmul_rn(y, x);
-        in.acc[g] = val ? __fadd_rn(in.acc[g], pr) : in.acc[g];
-        if (PER) in.pin[g] = (val && per) ? __fadd_rn(in.pin[g], pr) : in.pin[g];
+        in.acc[g] = val ? __builtin_fmaf(y, x, in.acc[g]) : in.acc[g];
+        if (PER) in.pin[g] = (val && per) ? __builtin_fmaf(y, x, in.pin[g]) : in.pin[g];
       }
     }
   }
   return in;
 }
 
-// One workgroup per (mesh, direction) unit at a time, levels in order (reverse
-// for the adjoint), one barrier per level.  Each level's rows are one block of
-// entries; a level's block and the record of each thread's task are loaded NS - 1
-// steps ahead into registers (NS rotating sets) and copied into one of two LDS
-// staging buffers the step before the level is solved, so no load waits on the
-// critical path of a common step.
-// LVL_LDS = false (graphs deeper than the LDS level tables hold): the level
-// pointers and first entries are read from global memory at every step.
-template <int GN, bool REVERSE, bool PIN, int CH, bool LVL_LDS>
-__global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
+// Inflow of one task from its staged row, every value from LDS: each entry names
+// the LDS slot of its value (ring or prefetched), read in batches of 8 with the
+// same sequence of fused multiply-adds in row order as gather().  Entries past
+// the row's end read the zero slot with factor 0, which leaves the sum as it is
+// (it starts at +0 and never becomes -0).  `bad` is set when an entry's value
+// was not prefetched (the task is then recomputed by gather() from global
+// memory).
+template <int GN, bool PIN>
+__device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int2* stg,
+                                                 const float* vals, int zero, bool& bad) {
+  Inflow<GN> in;
+#pragma unroll
+  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
+  for (int rb = t.r0; rb < t.r1; rb += 8) {
+    int2 en[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) en[q] = stg[rb + q];
+    const int nr = t.r1 - rb;
+    float rv[8][GN], y[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool val = q < nr;
+      const int x = en[q].x;
+      bad |= val && x < 0;
+      y[q] = val ? __int_as_float(en[q].y) : 0.0f;
+      const float* v = vals + ((val && x >= 0) ? (x & kSlotMask) : zero) * GN;
+#pragma unroll
+      for (int g = 0; g < GN; ++g) rv[q][g] = v[g];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool per = PIN && q < nr && (en[q].x & kPerSlot) != 0 && en[q].x >= 0;
+#pragma unroll
+      for (int g = 0; g < GN; ++g) {
+        in.acc[g] = __builtin_fmaf(y[q], rv[q][g], in.acc[g]);
+        if (PIN) in.pin[g] = per ? __builtin_fmaf(y[q], rv[q][g], in.pin[g]) : in.pin[g];
+      }
+    }
+  }
+  return in;
+}
+
+// One workgroup per (mesh, direction) unit at a time, steps in order (reverse
+// for the adjoint), one barrier per step.  A step is a run of consecutive
+// schedule positions inside one level (levels wider than the workgroup or
+// with more entries than the staging buffer are cut into several), so its
+// tasks are independent.  Each step's row block and each thread's task record
+// are loaded NS - 1 steps ahead into registers (NS rotating sets).  Two steps
+// ahead, the holder of each staged entry whose upwind result lies outside the
+// LDS ring window (or that is a periodic inflow) loads that value from global
+// memory; the step before it is solved the holder copies the value into the
+// entry's own slot of the LDS value area and rewrites the entry to name its
+// slot (ring slot or prefetched slot).  The solve then reads only LDS, and no
+// load is waited for on the critical path of a common step.
+// A value is prefetched only when it is final: at the prefetch (after the
+// thread's solve of step t, for step t + 2) every step before t is complete,
+// which covers every result outside the window when the ring holds at least
+// three steps (R >= 3 x threads, as the host sizes it).
+//
+// LDS: [values: ring R slots | zero | sink | 2 x SE prefetched slots] x GN floats,
+// then two staging buffers of SE + 8 entries.
+template <int GN, bool REVERSE, bool PIN, int CH>
+__global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   constexpr int NS = 3;
   extern __shared__ __align__(16) unsigned char smem[];
-  float* ring = reinterpret_cast<float*>(smem);
+  float* vals = reinterpret_cast<float*>(smem);
   int2* stage = reinterpret_cast<int2*>(smem + a.stage_off);
-  int32_t* lps = reinterpret_cast<int32_t*>(smem + a.lp_off);
-  int64_t* levs = reinterpret_cast<int64_t*>(smem + a.lev_off);
   __shared__ int s_unit;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int SE = CH * nthr;
   const int SP = SE + 8;  // staging buffer stride
-  const int SMAX = SE - 8;  // entries staged per level; 8 padding entries follow them
+  const int SMAX = SE - 8;  // entries staged per step; 8 padding entries follow them
   const int R = a.ring_mask + 1;
-  float* sink = ring + (R + kSlotSink) * GN;
-  // the batches of 8 read up to 7 entries past a row (stale entries of earlier
-  // levels, or these) and the ring slots they name, with factor 0: every entry
-  // names a slot, every slot holds a finite value
-  for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(-1, 0);
-  for (int i = tid; i < R * GN; i += nthr) ring[i] = 0.0f;
+  const int zero = R;       // value slot that always holds zeros (padding entries)
+  const int sink = R + 1;   // value slot the threads without a task write
+  const int far0 = R + 2;   // prefetched slots of staging buffer b: far0 + b SE + entry index
+  float* ring = vals;
+  float* sinkp = vals + sink * GN;
+  for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(zero, 0);
+  for (int i = tid; i < (R + 2 + 2 * SE) * GN; i += nthr) vals[i] = 0.0f;
   for (int it = 0;; ++it) {
     int ui;
     if (a.work_counter != nullptr) {
@@ -330,33 +412,27 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
       ui = it == 0 ? (int)blockIdx.x : a.n_units;
     }
     if (ui >= a.n_units) break;
-    const Unit U = a.units[a.unit_order[ui]];
+    const int u = a.unit_order[ui];
+    const Unit U = a.units[u];
     const int64_t tb = U.task_base;
-    const int depth = U.depth;
-    if (depth <= 0) continue;
-    // level tables in LDS (the host sizes lp_cap >= depth + 2 for every unit)
-    if (LVL_LDS) {
-      for (int l = tid; l <= depth + 1; l += nthr) {
-        lps[l] = a.lp[U.lp_base + l];
-        levs[l] = a.lev[U.lp_base + l];
-      }
-    }
-    __syncthreads();
-    // level tables outside LDS are read through the scalar cache (constant
-    // address space: the sweep never writes them), so reading them never waits
-    // for the vector loads in flight
+    const int ns = a.n_steps[u];
+    if (ns <= 0) continue;
+    // step tables are read through the scalar cache (constant address space:
+    // the sweep never writes them), so reading them never waits for the vector
+    // loads in flight
     using cint = const __attribute__((address_space(4))) int32_t;
     using clong = const __attribute__((address_space(4))) int64_t;
-    cint* lpg = (cint*)(a.lp + U.lp_base);
-    clong* levg = (clong*)(a.lev + U.lp_base);
-    auto LP = [&](int l) -> int { return LVL_LDS ? lps[l] : lpg[l]; };
-    auto LEV = [&](int l) -> int64_t { return LVL_LDS ? levs[l] : levg[l]; };
+    cint* SK = (cint*)(a.step_k + a.step_base[u]);
+    clong* SEn = (clong*)(a.step_e + a.step_base[u]);
     const int64_t obase = ((int64_t)U.dir * a.C_total + U.cell_off) * a.G + a.g0;
     const int C = U.n_cells;
     UnitBufs B;
-    B.ue0 = LEV(0) < LEV(depth) ? LEV(0) : LEV(depth);
-    const int64_t ue1 = LEV(0) < LEV(depth) ? LEV(depth) : LEV(0);
-    B.ent = rsrc(a.ent + B.ue0, 8 * (ue1 - B.ue0));
+    {
+      const int64_t ea = SEn[0], eb = SEn[ns];
+      B.ue0 = ea < eb ? ea : eb;
+      const int64_t ue1 = ea < eb ? eb : ea;
+      B.ent = rsrc(a.ent + B.ue0, 8 * (ue1 - B.ue0));
+    }
     B.sched = rsrc(a.sched + tb, 4 * (int64_t)C);
     B.rp = rsrc(a.row_ptr + tb, 8 * ((int64_t)C + 1));
     B.den = rsrc(a.tden + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
@@ -365,48 +441,110 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
     B.prev = rsrc(a.phi_prev == nullptr ? nullptr : a.phi_prev + obase, 4 * ((int64_t)C * a.G - a.g0));
     B.out = rsrc(a.out + obase, 4 * ((int64_t)C * a.G - a.g0));
     B.pin = rsrc(a.pin == nullptr ? nullptr : a.pin + obase, 4 * ((int64_t)C * a.G - a.g0));
-    // level solved at step s (steps past the last one repeat it: their loads are
-    // issued and never used)
+    // step solved at iteration s (iterations past the last one repeat it: their
+    // loads are issued and never used)
     auto info = [&](int s) -> LevelInfo {
-      s = s < depth - 1 ? s : depth - 1;
+      s = s < ns - 1 ? s : ns - 1;
+      const int st = REVERSE ? ns - 1 - s : s;
       LevelInfo L;
-      L.l = REVERSE ? depth - 1 - s : s;
       // the values are uniform: keep them in scalar registers
-      L.k0 = __builtin_amdgcn_readfirstlane(LP(L.l));
-      L.k1 = __builtin_amdgcn_readfirstlane(LP(L.l + 1));
-      L.e0 = uniform64(LEV(L.l));
-      L.ne = (int)(uniform64(LEV(L.l + 1)) - L.e0);
+      L.k0 = __builtin_amdgcn_readfirstlane(SK[st]);
+      L.k1 = __builtin_amdgcn_readfirstlane(SK[st + 1]);
+      L.e0 = uniform64(SEn[st]);
+      L.ne = (int)(uniform64(SEn[st + 1]) - L.e0);
       L.nst = L.ne < SMAX ? L.ne : SMAX;
       return L;
     };
     Pref<GN, CH> P[NS];
+    float F[CH][GN], FP[CH][GN];  // prefetched values of the thread's staged entries
     TaskRec<GN> cur;
     LevelInfo curL;
+    // results final at the last prefetch: forward, positions below vis; adjoint,
+    // positions from vis up
+    int vis = REVERSE ? 0x7fffffff : 0, visF = vis;
+    auto prefetchable = [&](int p, const Window& w, int v) -> bool {
+      return !w.has(p) && (p < 0 || (REVERSE ? p >= v : p < v));
+    };
     auto issue = [&](int s, Pref<GN, CH>& Q) {
       Q.L = info(s);
       issue_pref<GN, CH>(a, B, tid, nthr, Q);
     };
-    // raw entries into the staging buffer of step s, followed by 8 padding
-    // entries (a task of the level inside the window, factor 0); the thread's
-    // record into `cur`
+    // the older results and periodic inflows of the thread's staged entries of
+    // step s (one load per entry; the others read past the buffers' ends)
+    auto farload = [&](const Pref<GN, CH>& Q) {
+      const LevelInfo& L = Q.L;
+      const Window w = window<REVERSE>(L.k0, L.k1, R);
+      uint32_t po = 0, pp = 0;  // per entry: an older result / a periodic inflow to load
+#pragma unroll
+      for (int i = 0; i < CH / 2; ++i) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int idx = 2 * (tid + i * nthr) + h;
+          const int p = h ? Q.st[i].z : Q.st[i].x;
+          const bool pf = idx < L.nst && prefetchable(p, w, vis);
+          po |= (uint32_t)(pf && p >= 0) << (2 * i + h);
+          pp |= (uint32_t)(pf && p < 0) << (2 * i + h);
+        }
+      }
+      // the loads of a wavefront whose lanes need none are not issued
+      if (__ballot(po != 0u) != 0ull) {
+#pragma unroll
+        for (int i = 0; i < CH / 2; ++i)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int p = h ? Q.st[i].z : Q.st[i].x;
+            ld_groups<GN>(B.outs, (po >> (2 * i + h)) & 1u ? 4u * (uint32_t)(p * a.G) : kOob,
+                          F[2 * i + h]);
+          }
+      }
+      if (PIN && __ballot(pp != 0u) != 0ull) {
+#pragma unroll
+        for (int i = 0; i < CH / 2; ++i)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int p = h ? Q.st[i].z : Q.st[i].x;
+            ld_groups<GN>(B.prev, (pp >> (2 * i + h)) & 1u ? 4u * (uint32_t)((-p - 1) * a.G) : kOob,
+                          FP[2 * i + h]);
+          }
+      }
+      visF = vis;
+    };
+    // staged entries of step s (value slots, followed by 8 padding entries that
+    // name the zero slot with factor 0) and the prefetched values into the staging
+    // buffer and value slots of s's parity; the thread's record into `cur`
     auto publish = [&](int s, const Pref<GN, CH>& Q) {
       const LevelInfo& L = Q.L;
-      int2* dst = stage + (s & 1) * SP;
-      const int pad = REVERSE ? L.k0 : L.k1 - 1;
+      const int b = s & 1;
+      int2* dst = stage + b * SP;
+      const Window w = window<REVERSE>(L.k0, L.k1, R);
 #pragma unroll
       for (int i = 0; i < CH / 2; ++i) {
         if (2 * i * nthr >= L.nst + 8) break;
-        const int idx = 2 * (tid + i * nthr);
+        const int idx0 = 2 * (tid + i * nthr);
         int4 v = Q.st[i];
-        if (idx >= L.nst) {
-          v.x = pad;
-          v.y = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int idx = idx0 + h;
+          const int p = h ? v.z : v.x;
+          const bool val = idx < L.nst;
+          const bool pf = val && prefetchable(p, w, visF);
+          const int fs = far0 + b * SE + idx;
+          int slot = !val ? zero : (w.has(p) ? (p & a.ring_mask) : (pf ? fs : -1));
+          if (PIN && pf && p < 0) slot |= kPerSlot;
+          if (pf) {
+#pragma unroll
+            for (int g = 0; g < GN; ++g)
+              vals[fs * GN + g] = (PIN && p < 0) ? FP[2 * i + h][g] : F[2 * i + h][g];
+          }
+          if (h) {
+            v.z = slot;
+            v.w = val ? v.w : 0;
+          } else {
+            v.x = slot;
+            v.y = val ? v.y : 0;
+          }
         }
-        if (idx + 1 >= L.nst) {
-          v.z = pad;
-          v.w = 0;
-        }
-        if (idx < L.nst + 8) *reinterpret_cast<int4*>(dst + idx) = v;
+        if (idx0 < L.nst + 8) *reinterpret_cast<int4*>(dst + idx0) = v;
       }
       curL = L;
       const bool act = L.k0 + tid < L.k1;
@@ -424,38 +562,47 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
       const int64_t e0 = curL.e0;
       const int2* stg = stage + (s & 1) * SP;
       const Window w = window<REVERSE>(k0, k1, R);
-      const bool staged = curL.nst == curL.ne;
-      if (staged && k1 - k0 <= nthr) {
-        const Inflow<GN> in = gather<GN, PIN, true>(a, B, cur, stg, 0u, ring, w);
-        finish_fast<GN, PIN>(a, B, cur, k0 + tid, in, ring, sink);
+      const uint32_t eoff = 8u * (uint32_t)(e0 - B.ue0);
+      vis = REVERSE ? k1 : k0;
+      if (curL.nst == curL.ne && k1 - k0 <= nthr) {
+        bool bad = false;
+        Inflow<GN> in = gather_lds<GN, PIN>(cur, stg, vals, zero, bad);
+        if (bad) {  // a value that was not prefetched (rare): the row from global memory
+          in = gather<GN, PIN, false>(a, B, cur, nullptr, eoff, ring, w);
+          __builtin_amdgcn_s_waitcnt(0);
+        }
+        finish_fast<GN, PIN>(a, B, cur, k0 + tid, in, ring, sinkp);
         return;
       }
-      const uint32_t eoff = 8u * (uint32_t)(e0 - B.ue0);
       for (int k = k0 + tid; k < k1; k += nthr) {
         TaskRec<GN> t;
         if (k == k0 + tid) t = cur; else load_rec<GN>(a, B, k, e0, t);
-        const Inflow<GN> in = staged ? gather<GN, PIN, true>(a, B, t, stg, 0u, ring, w)
-                                     : gather<GN, PIN, false>(a, B, t, nullptr, eoff, ring, w);
+        const Inflow<GN> in = gather<GN, PIN, false>(a, B, t, nullptr, eoff, ring, w);
         finish_task<GN, PIN>(a, B, t, k, in, ring);
       }
       // the uncommon steps leave no memory operation of theirs in flight, so the
       // waits of the common steps are counted exactly
       __builtin_amdgcn_s_waitcnt(0);
     };
-    // prologue: steps 0 .. NS - 1 in flight, step 0 staged.  Step s then solves,
-    // issues the loads of step s + NS into the set it freed and publishes step
-    // s + 1 (loaded NS - 1 steps earlier).
+    // prologue: steps 0 .. NS - 1 in flight, the values of steps 0 and 1
+    // prefetched, step 0 staged.  Iteration s then solves step s, stages step
+    // s + 1 (its values were prefetched an iteration earlier), issues the loads
+    // of step s + NS into the set it freed and prefetches the values of step
+    // s + 2.
 #pragma unroll
     for (int j = 0; j < NS; ++j) issue(j, P[j]);
+    farload(P[0]);
     publish(0, P[0]);
+    farload(P[1]);
     __syncthreads();
-    for (int s = 0; s < depth; s += NS) {
+    for (int s = 0; s < ns; s += NS) {
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
-        if (s + j >= depth) break;
+        if (s + j >= ns) break;
         solve(s + j);
+        if (s + j + 1 < ns) publish(s + j + 1, P[(j + 1) % NS]);
         issue(s + j + NS, P[j]);
-        if (s + j + 1 < depth) publish(s + j + 1, P[(j + 1) % NS]);
+        farload(P[(j + 2) % NS]);
         __syncthreads();
       }
     }
@@ -465,27 +612,20 @@ __global__ __launch_bounds__(kStageEntries / CH) void k_sweep(SweepArgs a) {
 template <int GN, bool REVERSE, bool PIN>
 hipError_t launch_sweep_p(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
-  // kStageEntries entries staged per level whatever the block size; level
-  // tables outside LDS (lp_cap == 0) only with 512 threads
-  if (a.lp_cap == 0) {
-    if (block != 512) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 8, false>), dim3(grid), dim3(block), lds, s, a);
-    return hipGetLastError();
-  }
-  switch (kStageEntries / block) {
-    case 4: hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 4, true>), dim3(grid), dim3(block), lds, s, a); break;
-    case 8: hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 8, true>), dim3(grid), dim3(block), lds, s, a); break;
-    case 16: hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, 16, true>), dim3(grid), dim3(block), lds, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+  if ((block != 256 && block != 512 && block != 1024) || block > kSweepMaxBlock(GN))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, kStageCh>), dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
-// The forward sweep stores the periodic inflow per task only when asked to.
+// The forward sweep stores the periodic inflow per task only when asked to (a
+// forward pass with periodic inflows always is; launches without it take no
+// inflow from a previous pass).
 template <int GN, bool REVERSE>
 hipError_t launch_sweep_g(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
   if (!REVERSE && a.pin != nullptr) return launch_sweep_p<GN, false, true>(a, grid, block, lds, s);
+  if (a.phi_prev != nullptr) return hipErrorInvalidValue;
   return launch_sweep_p<GN, REVERSE, false>(a, grid, block, lds, s);
 }
 
@@ -832,17 +972,13 @@ inline unsigned grid1d(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-LdsLayout sweep_lds_layout(int32_t gn, int32_t ring, int32_t stage, int32_t lp_cap) {
+LdsLayout sweep_lds_layout(int32_t gn, int32_t ring, int32_t block) {
   LdsLayout L;
-  size_t off = (size_t)gn * (ring + kSlots) * sizeof(float);  // the ring and its slots
+  const size_t se = (size_t)kStageCh * block;
+  size_t off = (size_t)gn * (ring + 2 + 2 * se) * sizeof(float);  // ring, zero, sink, prefetched
   off = (off + 15) & ~(size_t)15;
   L.stage_off = (int32_t)off;
-  off += 2 * ((size_t)stage + 8) * sizeof(int2);  // two staging buffers, 8 entries of padding
-  L.lp_off = (int32_t)off;
-  off += (size_t)lp_cap * sizeof(int32_t);
-  off = (off + 7) & ~(size_t)7;
-  L.lev_off = (int32_t)off;
-  off += (size_t)lp_cap * sizeof(int64_t);
+  off += 2 * (se + 8) * sizeof(int2);  // two staging buffers, 8 entries of padding
   L.bytes = off;
   return L;
 }
@@ -867,15 +1003,8 @@ hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
 
 template <int GN, bool REVERSE, bool PIN>
 hipError_t set_lds_g(int32_t bytes) {
-  const void* fns[] = {(const void*)k_sweep<GN, REVERSE, PIN, 4, true>,
-                       (const void*)k_sweep<GN, REVERSE, PIN, 8, true>,
-                       (const void*)k_sweep<GN, REVERSE, PIN, 16, true>,
-                       (const void*)k_sweep<GN, REVERSE, PIN, 8, false>};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_sweep<GN, REVERSE, PIN, kStageCh>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <int GN>

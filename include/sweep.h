@@ -50,13 +50,14 @@
  *     order (global cell id = mesh offset + local id);
  *   - work is enqueued on the caller's `stream` (a hipStream_t, NULL = null
  *     stream); only sweep_build_dag, sweep_dag_export, sweep_dag_level_widths,
- *     sweep_tune, sweep_ion_step, sweep_sync, and sweep_forward /
- *     sweep_adjoint with pbc_tol or check set synchronise that stream;
+ *     sweep_tune, sweep_ion_step, sweep_ion_step_noalloc, sweep_sync, and
+ *     sweep_forward / sweep_adjoint with pbc_tol or check set synchronise
+ *     that stream;
  *   - inputs that only the kernels see (kappa and emission negative or not
  *     finite, a task whose denominator Aperp + kappa V is not positive, loss
  *     gradients that are not finite) raise an error flag kept with the DAG;
  *     the next call on that DAG that synchronises (sweep_sync, sweep_dag_export,
- *     sweep_tune, sweep_ion_step, pbc_tol or check) returns
+ *     sweep_tune, sweep_ion_step(_noalloc), pbc_tol or check) returns
  *     SWEEP_ERR_INVALID_ARG for it and clears it.  The outputs of the call that
  *     saw such input are not meaningful;
  *   - the caller owns every array argument and output; outputs are fully
@@ -326,6 +327,20 @@ typedef struct {
 sweep_status_t sweep_ion_step(sweep_dag_t dag, const float* absorbed, const sweep_ion_params_t* p,
                               double t_left, double* neutral, float* kappa, double* dt,
                               void* stream);
+
+/* sweep_ion_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * arguments, kernels and results, but the per-step minimum it reduces into is a
+ * static 8-byte device array of the library (each GPU holds its own copy until
+ * the process ends) instead of a buffer allocated with the DAG.  It calls no
+ * allocating routine.  One word serves every mesh size, so no input is too
+ * large for it.  Every call on a GPU shares that GPU's word: calls that overlap
+ * on one GPU (several streams or host threads) race and must be serialised by
+ * the caller.  The word is reset by a kernel at the start of each call.
+ * Synchronises `stream` once.  Errors: INVALID_ARG, NOT_BUILT, HIP. */
+sweep_status_t sweep_ion_step_noalloc(sweep_dag_t dag, const float* absorbed,
+                                      const sweep_ion_params_t* p, double t_left, double* neutral,
+                                      float* kappa, double* dt, void* stream);
 
 /* The absorption coefficient of the neutral hydrogen for the next sweep of a
  * photoionisation run: kappa[c] = n_H y[c] sigma_H length_unit (DEVICE

@@ -21,7 +21,8 @@ from ._binding import (SweepError, SweepLibraryError, sweep_adjoint, sweep_build
                        sweep_dag_export, sweep_dag_info, sweep_destroy_dag, sweep_forward,
                        sweep_last_error, sweep_profile_enable, sweep_profile_read,
                        sweep_ion_step, sweep_profile_reset, sweep_saved_bytes, sweep_tune,
-                       sweep_sync, sweep_dag_depths, sweep_dag_level_widths, sweep_ion_kappa)
+                       sweep_sync, sweep_dag_depths, sweep_dag_level_widths, sweep_ion_kappa,
+                       sweep_ion_step_noalloc)
 
 TOTAL_NAMES = ("emitted", "absorbed", "escaped", "pbc_in", "pbc_out", "scat_net", "pbc_err_max",
                "pbc_err_l1")
@@ -248,10 +249,12 @@ def tune(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, reps: int = 3, s
 
 
 def ion_step(dag: Dag, absorbed: torch.Tensor, neutral: torch.Tensor, kappa: torch.Tensor,
-             params: dict, t_left: float, stream=None) -> float:
+             params: dict, t_left: float, stream=None, no_alloc: bool = False) -> float:
     """One photoionisation chemistry step (sweep_ion_step): updates `neutral` (float64
     CUDA [C]) and writes `kappa` (float32 CUDA [C, 1]) in place; returns the step (s).
-    params: n_H, sigma_H, alpha_B, photon_rate, length_unit, dt_max (s), courant."""
+    params: n_H, sigma_H, alpha_B, photon_rate, length_unit, dt_max (s), courant.
+    no_alloc: use sweep_ion_step_noalloc (the library's static scratch word; calls
+    that overlap on one GPU race)."""
     C = dag.n_cells
     if not (neutral.is_cuda and neutral.dtype == torch.float64 and neutral.numel() == C
             and neutral.is_contiguous()):
@@ -262,8 +265,9 @@ def ion_step(dag: Dag, absorbed: torch.Tensor, neutral: torch.Tensor, kappa: tor
     for k in ("n_H", "sigma_H", "alpha_B", "photon_rate", "length_unit", "dt_max", "courant"):
         setattr(p, k, float(params[k]))
     dt = ctypes.c_double()
-    B.check(sweep_ion_step(dag.handle, _ptr(absorbed), ctypes.byref(p), float(t_left), _ptr(neutral),
-                           _ptr(kappa), ctypes.byref(dt), _stream(stream)))
+    fn = sweep_ion_step_noalloc if no_alloc else sweep_ion_step
+    B.check(fn(dag.handle, _ptr(absorbed), ctypes.byref(p), float(t_left), _ptr(neutral), _ptr(kappa),
+               ctypes.byref(dt), _stream(stream)))
     return float(dt.value)
 
 

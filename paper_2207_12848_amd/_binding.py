@@ -25,7 +25,7 @@ EXPORTED = ("sweep_last_error", "sweep_build_dag", "sweep_destroy_dag", "sweep_d
             "sweep_dag_export", "sweep_saved_bytes", "sweep_forward", "sweep_adjoint",
             "sweep_tune", "sweep_ion_step", "sweep_profile_enable", "sweep_profile_reset",
             "sweep_profile_read", "sweep_sync", "sweep_dag_depths", "sweep_dag_level_widths",
-            "sweep_ion_kappa")
+            "sweep_ion_kappa", "sweep_ion_step_noalloc")
 
 
 class SweepLibraryError(RuntimeError):
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "sweep_dag_depths": (ctypes.c_int, [P, P]),
         "sweep_dag_level_widths": (ctypes.c_int, [P, I32, P, I32, P]),
         "sweep_ion_kappa": (ctypes.c_int, [P, P, P, P, P]),
+        "sweep_ion_step_noalloc": (ctypes.c_int, [P, P, P, ctypes.c_double, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -195,3 +196,7 @@ def sweep_dag_level_widths(dag, mesh, width, n_levels, stream) -> int:
 
 def sweep_ion_kappa(dag, params, neutral, kappa, stream) -> int:
     return load().sweep_ion_kappa(dag, params, neutral, kappa, stream)
+
+
+def sweep_ion_step_noalloc(dag, absorbed, params, t_left, neutral, kappa, dt, stream) -> int:
+    return load().sweep_ion_step_noalloc(dag, absorbed, params, t_left, neutral, kappa, dt, stream)

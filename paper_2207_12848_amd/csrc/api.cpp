@@ -1642,6 +1642,18 @@ sweep_status_t sweep_ion_step(sweep_dag_t d, const float* absorbed, const sweep_
                   d->ion_min.as<unsigned long long>());
 }
 
+sweep_status_t sweep_ion_step_noalloc(sweep_dag_t d, const float* absorbed,
+                                      const sweep_ion_params_t* p, double t_left, double* neutral,
+                                      float* kappa, double* dt, void* stream) {
+  g_err.clear();
+  ST_TRY(check_ion_args(d, absorbed, p, t_left, neutral, kappa, dt));
+  hipStream_t s = (hipStream_t)stream;
+  StreamScope stream_scope(s);
+  unsigned long long* scratch = nullptr;  // the library's static scratch word on this device
+  HIP_TRY(sweep::ion_scratch(&scratch));
+  return ion_step(d, absorbed, p, t_left, neutral, kappa, dt, s, scratch);
+}
+
 sweep_status_t sweep_sync(sweep_dag_t d, void* stream) {
   g_err.clear();
   if (!dag_ok(d)) return fail(SWEEP_ERR_NOT_BUILT, "DAG handle is NULL or was not built");

@@ -8,6 +8,8 @@
 //            b = u + P dt / (n_H V), taken as 2b / (1 + sqrt(1 + 4ab)) (no
 //            cancellation for any a, b >= 0)
 // Both are elementwise and HBM-bound (20 bytes per cell); FP64 throughout.
+#include <mutex>
+
 #include "internal.h"
 
 namespace sweep {
@@ -72,6 +74,33 @@ hipError_t launch_ion_kappa(const IonArgs& a, hipStream_t s) {
   if (a.n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ion_kappa, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// Scratch of sweep_ion_step_noalloc: the step limit's minimum over the cells,
+// as the bits of a positive double (8 bytes, the whole of it).  Each GPU holds
+// its own copy until the process ends; every call on that GPU shares it (calls
+// that overlap on one GPU race for it).  Host code never passes this name to a
+// kernel or a copy: it uses the device address ion_scratch() looks up.
+static __device__ __align__(256) unsigned long long scratch[1];
+
+constexpr int kMaxDevices = 64;
+
+hipError_t ion_scratch(unsigned long long** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (addr[dev] == nullptr) {  // once per device, with that device current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *out = static_cast<unsigned long long*>(addr[dev]);
+  return hipSuccess;
 }
 
 hipError_t launch_ion_limit(const IonArgs& a, unsigned long long* out, hipStream_t s) {

@@ -235,6 +235,9 @@ hipError_t launch_pbc_adj(const PbcAdjArgs& a, int32_t n_blocks, hipStream_t s);
 
 // launchers (kernels in dag.hip / sweep.hip / chem.hip)
 hipError_t launch_ion_limit(const IonArgs& a, unsigned long long* out, hipStream_t s);
+// Device address of the current device's scratch word of sweep_ion_step_noalloc
+// (looked up once per device).
+hipError_t ion_scratch(unsigned long long** out);
 hipError_t launch_ion_update(const IonArgs& a, double dt, hipStream_t s);
 constexpr int kTileCellsHost = 32;  // cells per tile of the cell-order build kernels
 hipError_t launch_count(const DagBuildArgs& a, int32_t n_cblocks, int32_t lds_limit, hipStream_t s);

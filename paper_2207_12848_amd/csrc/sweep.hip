@@ -31,58 +31,74 @@ constexpr uint32_t kOob = 0x7ffffff0u;     // an offset past the end of any buff
 
 template <class T>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T* p, int64_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0,
-                                           (int)(p == nullptr ? 0 : bytes), kBufFlags);
+  // the arguments are uniform; read from the first lane so that the descriptor
+  // is built in scalar registers (a descriptor in vector registers costs a
+  // loop over the distinct values at every access)
+  const uint64_t a = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const int n = __builtin_amdgcn_readfirstlane((int)(p == nullptr ? 0 : bytes));
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, n,
+                                           kBufFlags);
 }
 
+// Cache policy of the accesses the sweep makes once per step and never again
+// (row entries, task records, results in cell order): non-temporal, so the L2
+// keeps the schedule-order results that later steps read back.
+constexpr int kStream = 2;
+
+template <int POL = 0>
 __device__ __forceinline__ int2 ld_b64(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  return __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+  return __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, POL));
 }
+template <int POL = 0>
 __device__ __forceinline__ int4 ld_b128(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+  return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, POL));
 }
+template <int POL = 0>
 __device__ __forceinline__ int ld_b32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, POL);
 }
 __device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
   return __int_as_float(ld_b32(r, vo, so));
 }
+template <int POL = 0>
 __device__ __forceinline__ void st_f32(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo) {
-  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)vo, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_int(v), r, (int)vo, 0, POL);
 }
 
 // GN consecutive FP32 values at byte offset vo + so of a buffer (one access for
 // GN = 2 or 4; offsets past the buffer's end read zeros and drop stores).
-template <int GN>
+template <int GN, int POL = 0>
 __device__ __forceinline__ void ld_gn(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so, float* v) {
   if constexpr (GN == 4) {
-    const int4 x = __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+    const int4 x = __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, POL));
     v[0] = __int_as_float(x.x);
     v[1] = __int_as_float(x.y);
     v[2] = __int_as_float(x.z);
     v[3] = __int_as_float(x.w);
   } else if constexpr (GN == 2) {
-    const int2 x = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+    const int2 x = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, POL));
     v[0] = __int_as_float(x.x);
     v[1] = __int_as_float(x.y);
   } else {
 #pragma unroll
-    for (int g = 0; g < GN; ++g) v[g] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)(vo + 4u * g), (int)so, 0));
+    for (int g = 0; g < GN; ++g) v[g] = __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)(vo + 4u * g), (int)so, POL));
   }
 }
 
-template <int GN>
+template <int GN, int POL = 0>
 __device__ __forceinline__ void st_gn(const float* v, __amdgpu_buffer_rsrc_t r, uint32_t vo) {
   if constexpr (GN == 4) {
     const int4 x = make_int4(__float_as_int(v[0]), __float_as_int(v[1]), __float_as_int(v[2]),
                              __float_as_int(v[3]));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) int, x), r, (int)vo, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) int, x), r, (int)vo, 0, POL);
   } else if constexpr (GN == 2) {
     const int2 x = make_int2(__float_as_int(v[0]), __float_as_int(v[1]));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) int, x), r, (int)vo, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) int, x), r, (int)vo, 0, POL);
   } else {
 #pragma unroll
-    for (int g = 0; g < GN; ++g) st_f32(v[g], r, vo + 4u * g);
+    for (int g = 0; g < GN; ++g) st_f32<POL>(v[g], r, vo + 4u * g);
   }
 }
 
@@ -124,12 +140,11 @@ struct LevelInfo {
   int64_t e0;     // first row entry of the step
 };
 
-// Entries of a staged row hold an LDS value slot instead of a schedule position:
-// the ring slot of a result inside the window, or the slot the older value (or
-// periodic inflow, with kPerSlot set) was prefetched into; -1 when the value
-// has to be read from global memory at solve time.
-constexpr int kPerSlot = 0x40000000;
-constexpr int kSlotMask = 0x3fffffff;
+// Entries of a staged row hold the LDS byte address of their value instead of a
+// schedule position (the ring slot of a result inside the window, or the slot
+// the older value or periodic inflow was prefetched into) and their factor,
+// negated for a periodic inflow.  An entry whose value is not in LDS names the
+// zero slot and marks its step for the global-memory path.
 
 // Loads in flight for one step: the thread's share of the step's row block
 // (raw entries, two per load) and the record of the thread's task of the step,
@@ -140,7 +155,10 @@ struct Pref {
   LevelInfo L;
   int4 st[CH / 2];
   int c;
-  int4 rp;  // row pointers of the task and the next one (low words: x and z)
+  // low words of the row pointers of the task and the next one (two loads: a
+  // register a load writes and nothing reads would be reused while the load is
+  // in flight, and the wait for it would stall the next solve)
+  int rp0, rp1;
   float den[GN];
   float src[GN];
 };
@@ -167,15 +185,16 @@ __device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B
 #pragma unroll
   for (int i = 0; i < CH / 2; ++i) {
     const int idx = 2 * (tid + i * nthr);
-    P.st[i] = ld_b128(B.ent, idx < L.nst ? 8u * (uint32_t)idx : kOob, eoff);
+    P.st[i] = ld_b128<kStream>(B.ent, idx < L.nst ? 8u * (uint32_t)idx : kOob, eoff);
   }
   const bool act = L.k0 + tid < L.k1;
   const uint32_t k0 = (uint32_t)L.k0;
-  P.c = ld_b32(B.sched, act ? 4u * (uint32_t)tid : kOob, 4u * k0);
-  P.rp = ld_b128(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
+  P.c = ld_b32<kStream>(B.sched, act ? 4u * (uint32_t)tid : kOob, 4u * k0);
+  P.rp0 = ld_b32<kStream>(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
+  P.rp1 = ld_b32<kStream>(B.rp, act ? 8u * (uint32_t)tid + 8u : kOob, 8u * k0);
   const uint32_t vo = act ? 4u * (uint32_t)(tid * a.G) : kOob, so = 4u * k0 * (uint32_t)a.G;
-  ld_gn<GN>(B.den, vo, so, P.den);
-  ld_gn<GN>(B.src, vo, so, P.src);
+  ld_gn<GN, kStream>(B.den, vo, so, P.den);
+  ld_gn<GN, kStream>(B.src, vo, so, P.src);
 }
 
 // Inflow of one task per group (and the periodic part of it).
@@ -220,9 +239,9 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& 
     v[g] = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
     rr[g] = v[g];
   }
-  st_gn<GN>(v, B.out, oc);
+  st_gn<GN, kStream>(v, B.out, oc);
   st_gn<GN>(v, B.outs, ok);
-  if (PIN) st_gn<GN>(in.pin, B.pin, oc);
+  if (PIN) st_gn<GN, kStream>(in.pin, B.pin, oc);
 }
 
 // The common step: at most one task per thread and every inflow in LDS.  Every
@@ -243,9 +262,9 @@ __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& 
     v[g] = __fdiv_rn(__fadd_rn(in.acc[g], t.src[g]), t.den[g]);
     rr[g] = v[g];
   }
-  st_gn<GN>(v, B.out, oc);
+  st_gn<GN, kStream>(v, B.out, oc);
   st_gn<GN>(v, B.outs, ok);
-  if (PIN) st_gn<GN>(in.pin, B.pin, oc);
+  if (PIN) st_gn<GN, kStream>(in.pin, B.pin, oc);
 }
 
 // GN consecutive groups of one task from a [slot][G] array (one load; offsets
@@ -320,16 +339,16 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
   return in;
 }
 
-// Inflow of one task from its staged row, every value from LDS: each entry names
-// the LDS slot of its value (ring or prefetched), read in batches of 8 with the
-// same sequence of fused multiply-adds in row order as gather().  Entries past
-// the row's end read the zero slot with factor 0, which leaves the sum as it is
-// (it starts at +0 and never becomes -0).  `bad` is set when an entry's value
-// was not prefetched (the task is then recomputed by gather() from global
-// memory).
+// Inflow of one task from its staged row, every value from LDS (`lds`: the base
+// the entries' addresses are relative to), in batches of 8 with the same
+// sequence of fused multiply-adds in row order as gather().  The entries of a
+// batch past the row's end (the next row's, or padding naming the zero slot)
+// take factor 0, and a non-periodic entry adds 0 to the periodic part; adding
+// +-0 x (x finite) leaves a sum that starts at +0 and only grows unchanged, so
+// the result is gather()'s bit for bit.
 template <int GN, bool PIN>
 __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int2* stg,
-                                                 const float* vals, int zero, bool& bad) {
+                                                 const unsigned char* lds) {
   Inflow<GN> in;
 #pragma unroll
   for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
@@ -341,21 +360,33 @@ __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int
     float rv[8][GN], y[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const bool val = q < nr;
-      const int x = en[q].x;
-      bad |= val && x < 0;
-      y[q] = val ? __int_as_float(en[q].y) : 0.0f;
-      const float* v = vals + ((val && x >= 0) ? (x & kSlotMask) : zero) * GN;
+      y[q] = q < nr ? __int_as_float(en[q].y) : 0.0f;
+      // value slots are GN floats at a multiple of GN floats: one LDS read
+      const unsigned char* v = lds + en[q].x;
+      if constexpr (GN == 4) {
+        const float4 x = *reinterpret_cast<const float4*>(v);
+        rv[q][0] = x.x;
+        rv[q][1] = x.y;
+        rv[q][2] = x.z;
+        rv[q][3] = x.w;
+      } else if constexpr (GN == 2) {
+        const float2 x = *reinterpret_cast<const float2*>(v);
+        rv[q][0] = x.x;
+        rv[q][1] = x.y;
+      } else {
 #pragma unroll
-      for (int g = 0; g < GN; ++g) rv[q][g] = v[g];
+        for (int g = 0; g < GN; ++g) rv[q][g] = reinterpret_cast<const float*>(v)[g];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const bool per = PIN && q < nr && (en[q].x & kPerSlot) != 0 && en[q].x >= 0;
+      const float ya = __builtin_fabsf(y[q]);
+      // factor of a periodic inflow: -y clamped to [0, FLT_MAX]
+      const float yp = PIN ? __builtin_amdgcn_fmed3f(-y[q], 0.0f, 3.40282347e38f) : 0.0f;
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
-        in.acc[g] = __builtin_fmaf(y[q], rv[q][g], in.acc[g]);
-        if (PIN) in.pin[g] = per ? __builtin_fmaf(y[q], rv[q][g], in.pin[g]) : in.pin[g];
+        in.acc[g] = __builtin_fmaf(ya, rv[q][g], in.acc[g]);
+        if (PIN) in.pin[g] = __builtin_fmaf(yp, rv[q][g], in.pin[g]);
       }
     }
   }
@@ -388,6 +419,9 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   float* vals = reinterpret_cast<float*>(smem);
   int2* stage = reinterpret_cast<int2*>(smem + a.stage_off);
   __shared__ int s_unit;
+  // s_bad[b]: the running number of the last step staged in buffer b with an
+  // entry whose value is not in LDS (such a step is solved from global memory)
+  __shared__ int s_bad[2];
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
   const int SE = CH * nthr;
@@ -399,14 +433,16 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   const int far0 = R + 2;   // prefetched slots of staging buffer b: far0 + b SE + entry index
   float* ring = vals;
   float* sinkp = vals + sink * GN;
-  for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(zero, 0);
+  for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(zero * GN * 4, 0);
   for (int i = tid; i < (R + 2 + 2 * SE) * GN; i += nthr) vals[i] = 0.0f;
+  if (tid < 2) s_bad[tid] = -1;
+  int gbase = 0;  // running number of this workgroup's step 0 of the current unit
   for (int it = 0;; ++it) {
     int ui;
     if (a.work_counter != nullptr) {
       if (tid == 0) s_unit = atomicAdd(a.work_counter, 1);
       __syncthreads();
-      ui = s_unit;
+      ui = __builtin_amdgcn_readfirstlane(s_unit);  // uniform: the unit's buffers stay scalar
       __syncthreads();
     } else {
       ui = it == 0 ? (int)blockIdx.x : a.n_units;
@@ -486,8 +522,9 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
           pp |= (uint32_t)(pf && p < 0) << (2 * i + h);
         }
       }
-      // the loads of a wavefront whose lanes need none are not issued
-      if (__ballot(po != 0u) != 0ull) {
+      // issued whether or not a lane needs them (lanes that need none read past
+      // the buffer's end): a fixed count of loads keeps the waits exact
+      {
 #pragma unroll
         for (int i = 0; i < CH / 2; ++i)
 #pragma unroll
@@ -497,7 +534,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
                           F[2 * i + h]);
           }
       }
-      if (PIN && __ballot(pp != 0u) != 0ull) {
+      if (PIN) {
 #pragma unroll
         for (int i = 0; i < CH / 2; ++i)
 #pragma unroll
@@ -527,21 +564,24 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
           const int idx = idx0 + h;
           const int p = h ? v.z : v.x;
           const bool val = idx < L.nst;
-          const bool pf = val && prefetchable(p, w, visF);
+          // without periodic inflows (PIN false) a periodic entry reads the zero slot
+          const bool pf = val && prefetchable(p, w, visF) && (PIN || p >= 0);
           const int fs = far0 + b * SE + idx;
-          int slot = !val ? zero : (w.has(p) ? (p & a.ring_mask) : (pf ? fs : -1));
-          if (PIN && pf && p < 0) slot |= kPerSlot;
+          const bool inw = w.has(p);
+          const int slot = !val ? zero : (inw ? (p & a.ring_mask) : (pf ? fs : zero));
+          if (val && !inw && !pf && (PIN || p >= 0)) s_bad[b] = gbase + s;
           if (pf) {
 #pragma unroll
             for (int g = 0; g < GN; ++g)
               vals[fs * GN + g] = (PIN && p < 0) ? FP[2 * i + h][g] : F[2 * i + h][g];
           }
+          const int addr = slot * (GN * 4);
           if (h) {
-            v.z = slot;
-            v.w = val ? v.w : 0;
+            v.z = addr;
+            v.w = !val ? 0 : ((PIN && pf && p < 0) ? (v.w ^ (int)0x80000000) : v.w);
           } else {
-            v.x = slot;
-            v.y = val ? v.y : 0;
+            v.x = addr;
+            v.y = !val ? 0 : ((PIN && pf && p < 0) ? (v.y ^ (int)0x80000000) : v.y);
           }
         }
         if (idx0 < L.nst + 8) *reinterpret_cast<int4*>(dst + idx0) = v;
@@ -549,8 +589,8 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       curL = L;
       const bool act = L.k0 + tid < L.k1;
       cur.c = act ? Q.c : -1;
-      cur.r0 = act ? (int)((uint32_t)Q.rp.x - (uint32_t)L.e0) : 0;
-      cur.r1 = act ? (int)((uint32_t)Q.rp.z - (uint32_t)L.e0) : 0;
+      cur.r0 = act ? (int)((uint32_t)Q.rp0 - (uint32_t)L.e0) : 0;
+      cur.r1 = act ? (int)((uint32_t)Q.rp1 - (uint32_t)L.e0) : 0;
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
         cur.den[g] = Q.den[g];
@@ -564,13 +604,9 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       const Window w = window<REVERSE>(k0, k1, R);
       const uint32_t eoff = 8u * (uint32_t)(e0 - B.ue0);
       vis = REVERSE ? k1 : k0;
-      if (curL.nst == curL.ne && k1 - k0 <= nthr) {
-        bool bad = false;
-        Inflow<GN> in = gather_lds<GN, PIN>(cur, stg, vals, zero, bad);
-        if (bad) {  // a value that was not prefetched (rare): the row from global memory
-          in = gather<GN, PIN, false>(a, B, cur, nullptr, eoff, ring, w);
-          __builtin_amdgcn_s_waitcnt(0);
-        }
+      const bool bad = __builtin_amdgcn_readfirstlane(s_bad[s & 1]) == gbase + s;
+      if (curL.nst == curL.ne && k1 - k0 <= nthr && !bad) {
+        const Inflow<GN> in = gather_lds<GN, PIN>(cur, stg, smem);
         finish_fast<GN, PIN>(a, B, cur, k0 + tid, in, ring, sinkp);
         return;
       }
@@ -600,12 +636,16 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       for (int j = 0; j < NS; ++j) {
         if (s + j >= ns) break;
         solve(s + j);
-        if (s + j + 1 < ns) publish(s + j + 1, P[(j + 1) % NS]);
+        // unconditional (past the last step it stages a copy of the last step
+        // into the staging buffer no solve reads), so every set of loads is
+        // consumed on every path and the waits stay exact
+        publish(s + j + 1, P[(j + 1) % NS]);
         issue(s + j + NS, P[j]);
         farload(P[(j + 2) % NS]);
         __syncthreads();
       }
     }
+    gbase += ns + 1;  // past the last step's number and the one staged after it
   }
 }
 

@@ -109,10 +109,10 @@ def make_workload(name: str) -> dict:
     return getattr(W, name)()
 
 
-def fwd_opts(w: dict, form: str = "batched", block: int = 0, ring: int = 0) -> dict:
+def fwd_opts(w: dict, form: str = "batched", block: int = 0, ring: int = 0, pack: int = 0) -> dict:
     return dict(boundary=w.get("boundary", "vacuum"), n_pbc=int(w.get("n_pbc", 1)),
                 albedo=float(w.get("albedo", 0.0)), n_scat=int(w.get("n_scat", 1)), form=form,
-                block=block, ring=ring, law=w.get("law", "upwind"))
+                block=block, ring=ring, pack=pack, law=w.get("law", "upwind"))
 
 
 def updates_per_pass(w: dict) -> int:
@@ -306,6 +306,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c3_batched_groups", choices=WORKLOADS)
     ap.add_argument("--block", type=int, default=0, help="sweep workgroup size (0 = tuned)")
     ap.add_argument("--ring", type=int, default=0, help="LDS ring capacity (0 = tuned)")
+    ap.add_argument("--pack", type=int, default=0,
+                    help="groups swept together per work item, 1-4 (0 = automatic)")
     ap.add_argument("--hii-side", type=int, default=32,
                     help="lattice side of the hii_rtype workload")
     ap.add_argument("--law", default="upwind", choices=("upwind", "exp"),
@@ -356,7 +358,7 @@ def main() -> int:
     emission = torch.as_tensor(w["emission"]).to(dev).contiguous()
     gJ = torch.zeros((C, G), dtype=torch.float32, device=dev)
     gA = torch.full((C, G), 1.0 / (4.0 * math.pi), dtype=torch.float32, device=dev)
-    fo = fwd_opts(w, "batched", args.block, args.ring)
+    fo = fwd_opts(w, "batched", args.block, args.ring, args.pack)
 
     # validate the mesh once; the timed steps rebuild the graphs without re-checking it
     dag0 = sw.build_dag(meshes, w["dirs"], validate=True, scheme=args.scheme)
@@ -364,7 +366,7 @@ def main() -> int:
     tuned = None
     if args.tune:
         tuned = sw.tune(dag0, kappa, emission, reps=2, **fwd_opts(w))
-        fo["block"], fo["ring"] = tuned["block"], tuned["ring"]
+        fo["block"], fo["ring"], fo["pack"] = tuned["block"], tuned["ring"], tuned["pack"]
         log("tuned launch shape: %s" % tuned)
     dag0.close()
 
@@ -489,7 +491,8 @@ def main() -> int:
                    "n_pbc": fo["n_pbc"], "n_scat": fo["n_scat"], "albedo": fo["albedo"],
                    "law": fo["law"], "scheme": args.scheme,
                    "adjoint": True, "updates_per_step": n_updates, "form": "batched",
-                   "block": fo["block"] or "default", "ring": fo["ring"] or "default"},
+                   "block": fo["block"] or "default", "ring": fo["ring"] or "default",
+                   "pack": fo["pack"] or "auto"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "plain": plain,

@@ -185,6 +185,11 @@ typedef struct {
                         (mesh, direction) units from a shared counter until none is
                         left); 0 = as many as the GPU holds at once.  Results do not
                         depend on it */
+  int32_t pack;      /* batched form: groups swept together by one workgroup (1 to 4);
+                        the G groups are cut into chunks of `pack` (and a last chunk of
+                        the rest), every (mesh, direction, chunk) a separate work item.
+                        0 = the smallest packing dividing G whose work items fit one per
+                        compute unit (else 4).  Results do not depend on it */
 } sweep_fwd_opts_t;
 
 /* Message of the last failed call on this thread ("" if none). */

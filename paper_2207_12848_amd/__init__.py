@@ -56,7 +56,7 @@ def upload_mesh(mesh: dict, device="cuda") -> dict:
 
 def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", block=0, ring=0,
               use_graph=False, law="upwind", merge=False, warm_start=False,
-              pbc_tol=0.0, check=False, grid=0) -> B.sweep_fwd_opts_t:
+              pbc_tol=0.0, check=False, grid=0, pack=0) -> B.sweep_fwd_opts_t:
     o = B.sweep_fwd_opts_t()
     o.boundary = {"vacuum": B.SWEEP_BOUNDARY_VACUUM, "periodic": B.SWEEP_BOUNDARY_PERIODIC}[boundary]
     o.n_pbc = int(n_pbc)
@@ -72,6 +72,7 @@ def _fwd_opts(boundary="vacuum", n_pbc=1, albedo=0.0, n_scat=1, form="batched", 
     o.pbc_tol = float(pbc_tol)
     o.check = int(bool(check))
     o.grid = int(grid)
+    o.pack = int(pack)
     return o
 
 
@@ -245,7 +246,7 @@ def tune(dag: Dag, kappa: torch.Tensor, emission: torch.Tensor, reps: int = 3, s
     ms = ctypes.c_double()
     B.check(sweep_tune(dag.handle, G, _ptr(kappa), _ptr(emission), ctypes.byref(o), int(reps),
                        ctypes.byref(best), ctypes.byref(ms), _stream(stream)))
-    return {"block": int(best.block), "ring": int(best.ring), "ms": float(ms.value)}
+    return {"block": int(best.block), "ring": int(best.ring), "pack": int(best.pack), "ms": float(ms.value)}
 
 
 def ion_step(dag: Dag, absorbed: torch.Tensor, neutral: torch.Tensor, kappa: torch.Tensor,

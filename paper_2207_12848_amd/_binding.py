@@ -74,7 +74,7 @@ class sweep_fwd_opts_t(ctypes.Structure):
                 ("form", ctypes.c_int32), ("block", ctypes.c_int32), ("ring", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("law", ctypes.c_int32), ("merge", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("pbc_tol", ctypes.c_double),
-                ("check", ctypes.c_int32), ("grid", ctypes.c_int32)]
+                ("check", ctypes.c_int32), ("grid", ctypes.c_int32), ("pack", ctypes.c_int32)]
 
 
 _lib = None

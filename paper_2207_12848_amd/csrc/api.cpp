@@ -253,7 +253,7 @@ struct sweep_dag_s {
   std::vector<int64_t> unit_up, unit_dn;  // row entries of every unit
   // step tables of the level-synchronous sweep, one per workgroup size
   struct StepTable {
-    int32_t block = 0;
+    int32_t block = 0, cap_e = 0;  // threads, staged entries per step
     Buf k, eu, ed, base, n;
   };
   std::vector<std::unique_ptr<StepTable>> steps;
@@ -379,7 +379,7 @@ sweep_status_t ensure_reduce_tables(sweep_dag_t d, int32_t G) {
 }
 
 struct FwdPlan {
-  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm, check, grid;
+  int32_t boundary, n_pbc, n_scat, form, block, ring, use_graph, law, merge, warm, check, grid, pack;
   float albedo;
   double pbc_tol;
 };
@@ -400,6 +400,8 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
   p->check = o ? (o->check != 0) : 0;
   p->grid = o ? o->grid : 0;
   if (p->grid < 0) return fail(SWEEP_ERR_INVALID_ARG, "grid must be >= 0");
+  p->pack = o ? o->pack : 0;
+  if (p->pack < 0 || p->pack > 4) return fail(SWEEP_ERR_INVALID_ARG, "pack must be in [0, 4]");
   if (!(p->pbc_tol >= 0.0) || !std::isfinite(p->pbc_tol))
     return fail(SWEEP_ERR_INVALID_ARG, "pbc_tol must be finite and >= 0");
   if (p->law != SWEEP_LAW_UPWIND && p->law != SWEEP_LAW_EXP)
@@ -419,17 +421,32 @@ sweep_status_t read_opts(const sweep_fwd_opts_t* o, FwdPlan* p) {
 }
 
 // Group chunks: groups are independent, a launch packs up to 4 of them per task.
-std::vector<std::pair<int, int>> group_chunks(int G, bool plain) {
-  std::vector<std::pair<int, int>> ch;
+// One sweep launch: groups [g0, g0 + n_chunks x gn) as n_chunks independent
+// chunks of gn packed groups.
+struct GroupLaunch {
+  int g0, gn, n_chunks;
+};
+
+// The launches of one sweep of G groups.  Plain form: one group per launch.
+// Batched form, packing `pack` (0 = automatic): chunks of pack groups in one
+// launch (a unit's chunks are swept side by side on different compute units,
+// each with less work per step) and a last launch for the G mod pack groups
+// left.  The automatic packing is the smallest one dividing G whose
+// n_units x G / pack work items still fit one per compute unit, else 4.
+std::vector<GroupLaunch> group_plan(sweep_dag_t d, int G, bool plain, int pack) {
+  std::vector<GroupLaunch> ch;
   if (plain) {
-    for (int g = 0; g < G; ++g) ch.push_back({g, 1});
+    for (int g = 0; g < G; ++g) ch.push_back({g, 1, 1});
     return ch;
   }
-  for (int g = 0; g < G;) {
-    const int n = std::min(4, G - g);
-    ch.push_back({g, n});
-    g += n;
-  }
+  const int64_t n_units = (int64_t)d->units.size();
+  int gn = pack;
+  for (int c = 1; gn == 0 && c <= std::min(G, 4); ++c)
+    if (G % c == 0 && n_units * (G / c) <= d->cu_count) gn = c;
+  if (gn == 0) gn = 4;
+  gn = std::min(gn, G);
+  ch.push_back({0, gn, G / gn});
+  if (G % gn != 0) ch.push_back({G - G % gn, G % gn, 1});
   return ch;
 }
 
@@ -444,15 +461,15 @@ int default_ring(sweep_dag_t d, int gn, int block) {
 
 // The step table of `block`-thread sweeps (built on first use, kept with the DAG).
 sweep_status_t ensure_steps(sweep_dag_t d, int block, hipStream_t s, sweep_dag_s::StepTable** out) {
+  const int cap_t = block, cap_e = sweep::kStageCh * block - 8;
   for (auto& t : d->steps)
-    if (t->block == block) {
+    if (t->block == block && t->cap_e == cap_e) {
       *out = t.get();
       return SWEEP_OK;
     }
   if (g_capturing)  // prepare_steps builds every table a captured sequence needs beforehand
     return fail(SWEEP_ERR_HIP, "step table of %d threads missing during graph capture", block);
   const int n_units = (int)d->units.size();
-  const int cap_t = block, cap_e = sweep::kStageCh * block - 8;
   // capacity per unit: a level of w tasks and e entries gives at most
   // w / cap_t + 1.15 e / cap_e + 2 steps, and the levels' e sum to at most the
   // unit's upwind plus downwind entries
@@ -464,6 +481,7 @@ sweep_status_t ensure_steps(sweep_dag_t d, int block, hipStream_t s, sweep_dag_s
   }
   std::unique_ptr<sweep_dag_s::StepTable> t(new sweep_dag_s::StepTable());
   t->block = block;
+  t->cap_e = cap_e;
   const int64_t total = base[n_units];
   HIP_TRY(t->k.alloc(4 * total));
   HIP_TRY(t->eu.alloc(8 * total));
@@ -489,9 +507,8 @@ sweep_status_t ensure_steps(sweep_dag_t d, int block, hipStream_t s, sweep_dag_s
 // Builds the step tables the sweeps of a call with these options use (before
 // any capture: building one synchronises the stream).
 sweep_status_t prepare_steps(sweep_dag_t d, const FwdPlan& p, int32_t G, hipStream_t s) {
-  for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
-    (void)g0;
-    const int block = p.block > 0 ? p.block : sweep::kSweepMaxBlock(gn);
+  for (const GroupLaunch& c : group_plan(d, G, p.form == SWEEP_FORM_PLAIN, p.pack)) {
+    const int block = p.block > 0 ? p.block : sweep::kSweepMaxBlock(c.gn);
     sweep_dag_s::StepTable* t = nullptr;
     ST_TRY(ensure_steps(d, block, s, &t));
   }
@@ -552,7 +569,8 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
   a.G = G;
   a.D = d->D;
   const int n_units = (int)d->units.size();
-  for (auto [g0, gn] : group_chunks(G, p.form == SWEEP_FORM_PLAIN)) {
+  for (const GroupLaunch& c : group_plan(d, G, p.form == SWEEP_FORM_PLAIN, p.pack)) {
+    const int gn = c.gn;
     const int block = p.block > 0 ? p.block : sweep::kSweepMaxBlock(gn);
     if (block > sweep::kSweepMaxBlock(gn))
       return fail(SWEEP_ERR_INVALID_ARG, "block %d: at most %d threads with %d packed groups", block,
@@ -569,7 +587,8 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
     a.step_e = reverse ? stp->ed.as<int64_t>() : stp->eu.as<int64_t>();
     a.step_base = stp->base.as<int64_t>();
     a.n_steps = stp->n.as<int32_t>();
-    a.g0 = g0;
+    a.g0 = c.g0;
+    a.n_chunks = 1;
     a.ring_mask = ring - 1;
     a.stage_off = L.stage_off;
     if (p.form == SWEEP_FORM_PLAIN) {
@@ -585,7 +604,8 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
     } else {
       int per_cu = std::max(1, (int)((size_t)kMaxLds / (L.bytes + 256)));
       per_cu = std::min(per_cu, std::max(1, 2048 / block));
-      int grid = std::min(n_units, d->cu_count * per_cu);
+      a.n_chunks = c.n_chunks;
+      int grid = (int)std::min<int64_t>((int64_t)n_units * c.n_chunks, (int64_t)d->cu_count * per_cu);
       if (p.grid > 0) grid = std::min(grid, p.grid);
       a.work_counter = d->counter.as<int32_t>();
       a.unit_order = d->order_d.as<int32_t>();
@@ -643,7 +663,7 @@ void opts_key(std::vector<uint64_t>& k, const FwdPlan& p) {
   std::memcpy(&ab, &p.albedo, 4);
   k.insert(k.end(), {(uint64_t)p.boundary, (uint64_t)p.n_pbc, (uint64_t)p.n_scat, (uint64_t)p.form,
                      (uint64_t)p.block, (uint64_t)p.ring, (uint64_t)ab, (uint64_t)p.law,
-                     (uint64_t)p.merge, (uint64_t)p.warm, (uint64_t)p.grid});
+                     (uint64_t)p.merge, (uint64_t)p.warm, (uint64_t)p.grid, (uint64_t)p.pack});
   uint64_t tb;
   std::memcpy(&tb, &p.pbc_tol, 8);
   k.push_back(tb);
@@ -893,7 +913,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
-  HIP_TRY(cnt.alloc(4 * (T + 64 * (int64_t)n_units)));  // Kahn's counters in global memory
+  HIP_TRY(cnt.alloc(4 * T));  // Kahn's counters in global memory
   HIP_TRY(inv.alloc(4 * T));
   HIP_TRY(D->sched.alloc(4 * T));
   HIP_TRY(D->lp.alloc(4 * (T + 2 * (int64_t)n_units)));
@@ -935,7 +955,6 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.wface = wface.as<float>();
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
-  a.n_tasks = T;
   a.inv = inv.as<int32_t>();
   a.sched = D->sched.as<int32_t>();
   a.lp = D->lp.as<int32_t>();
@@ -1532,7 +1551,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
     (void)hipEventDestroy(e0);
     return fail(SWEEP_ERR_HIP, "hipEventCreate failed");
   }
-  const int gn = std::min(G, 4);
+  const int gn = group_plan(d, G, false, p.pack)[0].gn;
   double best_t = -1.0;
   FwdPlan bp = p;
   sweep_status_t st = SWEEP_OK;
@@ -1576,6 +1595,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   else std::memset(best, 0, sizeof(*best));
   best->block = bp.block;
   best->ring = bp.ring;
+  best->pack = gn;
   *best_ms = best_t;
   return SWEEP_OK;
 }

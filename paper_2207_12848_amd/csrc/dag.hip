@@ -25,7 +25,12 @@ constexpr int kCountBlock = 256;
 // workgroups with their face tiles and staged rows keep 16 wavefronts per CU
 constexpr int kCountThreads = 512;
 constexpr int kTileCells = 32;  // cells per tile of the cell-order kernels
-constexpr int kKahnBlock = 576;  // 8 worker wavefronts and one that stores the schedule
+// Workgroup of Kahn's algorithm: 15 worker wavefronts and one that stores the
+// schedule (the largest workgroup).  A level's frontier is processed in rounds
+// of one task per worker thread, each round a chain of dependent memory round
+// trips (row loads, then counter decrements), so a typical level of a few
+// hundred tasks takes one round.
+constexpr int kKahnBlock(int) { return 1024; }
 
 __device__ __forceinline__ double orient(double ox, double oy, double oz, const double* n) {
   const double a = ox * n[0];
@@ -471,7 +476,7 @@ __device__ __forceinline__ int wave_inclusive_sum(int x) {
 // -1 padded; NCH covers the longest list, or the whole row when some list
 // continues in the overflow area).
 template <bool LDSCNT, int NCH>
-__global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
+__global__ __launch_bounds__(kKahnBlock(NCH)) void k_kahn(DagBuildArgs a) {
   extern __shared__ uint32_t nib[];
   __shared__ int fr[2][kFrontierCap];
   __shared__ int s_cnt[3];
@@ -665,14 +670,13 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           }
         }
       } else {
-        // counters in global memory: as above, every entry of the wavefront's
-        // non-empty chunks issues one atomic without a branch (padding entries
-        // subtract zero from a per-lane dummy word past the counters), so all
-        // of them are in flight before the first result is used
+        // counters in global memory: every real entry of the wavefront's
+        // non-empty chunks issues its atomic before the first result is used;
+        // padding lanes issue none (the memory system is the bottleneck here:
+        // an atomic on a shared dummy word costs as much as a real one)
         int nq = 0;
 #pragma unroll
         for (int q = 0; q < NCH; ++q) nq += __ballot(v[q].x >= 0) != 0ull ? 1 : 0;
-        uint32_t* dummy = reinterpret_cast<uint32_t*>(a.cnt + a.n_tasks + 64 * (int64_t)blockIdx.x + lane);
         uint32_t old[4 * NCH];
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
@@ -680,12 +684,12 @@ __global__ __launch_bounds__(kKahnBlock) void k_kahn(DagBuildArgs a) {
           const int xs[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const bool real = xs[i] >= 0;
             const int nb = xs[i] & ~kBigFlag;
             const uint32_t sh = (uint32_t)(nb & 3) * 8u;
-            old[4 * q + i] = __hip_atomic_fetch_add(real ? cntw + (nb >> 2) : dummy,
-                                                    real ? 0u - (1u << sh) : 0u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+            old[4 * q + i] = xs[i] >= 0 ? __hip_atomic_fetch_add(cntw + (nb >> 2), 0u - (1u << sh),
+                                                                 __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_WORKGROUP)
+                                        : 0u;
           }
         }
 #pragma unroll
@@ -1083,13 +1087,13 @@ hipError_t launch_kahn_n(const DagBuildArgs& a, size_t lds, hipStream_t s) {
   hipError_t e = hipFuncSetAttribute((const void*)k_kahn<true, NCH>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_kahn<true, NCH>), dim3(a.n_units), dim3(kKahnBlock), lds, s, a);
+  hipLaunchKernelGGL((k_kahn<true, NCH>), dim3(a.n_units), dim3(kKahnBlock(NCH)), lds, s, a);
   return hipGetLastError();
 }
 
 template <int NCH>
 hipError_t launch_kahn_g(const DagBuildArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_kahn<false, NCH>), dim3(a.n_units), dim3(kKahnBlock), 0, s, a);
+  hipLaunchKernelGGL((k_kahn<false, NCH>), dim3(a.n_units), dim3(kKahnBlock(NCH)), 0, s, a);
   return hipGetLastError();
 }
 

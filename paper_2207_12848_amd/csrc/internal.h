@@ -79,9 +79,7 @@ struct DagBuildArgs {
   // in its sign: outflow +w, inflow -w, neither NaN
   float* wface;
   float2* bnd;  // (sum of w over wall outflow faces, over periodic outflow faces)
-  int32_t* cnt;     // [T] counters kept in global memory, then 64 per unit that take
-                    // the zero decrements of padding entries (see k_kahn)
-  int64_t n_tasks;  // T
+  int32_t* cnt;    // [T] words: Kahn's counters kept in global memory
   int32_t* inv;    // cell -> position in the unit's schedule
   // per task, schedule order within the unit
   int32_t* sched;  // position -> cell
@@ -103,7 +101,11 @@ struct SweepArgs {
   const Unit* units;
   const int32_t* unit_order;  // processing order of the units (longest first)
   int32_t n_units;
-  int32_t* work_counter;  // persistent form: next unit to take; nullptr: unit = blockIdx.x
+  // groups [g0, g0 + n_chunks x GN) are swept as n_chunks independent chunks of
+  // GN packed groups: work item i is unit unit_order[i / n_chunks], groups from
+  // g0 + (i % n_chunks) GN (the chunks of the longest units first)
+  int32_t n_chunks;
+  int32_t* work_counter;  // persistent form: next work item; nullptr: item = blockIdx.x
   const int32_t* sched;
   // steps of the level-synchronous sweep (see k_steps): unit u's steps start at
   // step_base[u]; step i covers schedule positions [step_k[i], step_k[i + 1]) and
@@ -123,7 +125,7 @@ struct SweepArgs {
   float* pin;              // forward, periodic: inflow through periodic faces per task, or nullptr
   int64_t C_total;
   int32_t G;       // group stride
-  int32_t g0;      // first group handled by this launch
+  int32_t g0;      // first group handled by this launch (see n_chunks)
   int32_t D;
   int32_t ring_mask;
   int32_t stage_off;      // byte offset of the staging buffers in the dynamic LDS
@@ -281,14 +283,17 @@ hipError_t launch_d2f_pair(const double* a, const double* b, float* oa, float* o
                            hipStream_t s);
 hipError_t set_sweep_lds_limit(int32_t bytes);
 // Row entries each sweep thread stages per step (a step holds at most
-// kStageCh x threads - 8 entries in LDS).
+// kStageCh x threads - 8 entries in LDS).  Twice as many (fewer, larger steps,
+// which the LDS holds with two packed groups) measured slower on the clustered
+// 2M-cell mesh: each step then keeps more loads in flight than the memory
+// system returns in time.
 constexpr int kStageCh = 4;
 // Largest sweep workgroup for gn packed groups: one group fits 1024 threads'
 // registers (128 VGPRs each), more groups need the 256 VGPRs of 512 threads.
 constexpr int kSweepMaxBlock(int gn) { return gn == 1 ? 1024 : 512; }
 // Dynamic LDS layout of a sweep workgroup of `block` threads: values (ring
-// slots, a zero slot, a sink, 2 x kStageCh x block prefetched slots) x gn FP32, then two
-// staging buffers of kStageCh x block + 8 entries.
+// slots, a zero slot, a sink, 2 x kStageCh x block prefetched slots) x gn FP32,
+// then two staging buffers of kStageCh x block + 8 entries.
 struct LdsLayout {
   int32_t stage_off;
   size_t bytes;

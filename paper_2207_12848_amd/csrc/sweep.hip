@@ -445,10 +445,11 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       ui = __builtin_amdgcn_readfirstlane(s_unit);  // uniform: the unit's buffers stay scalar
       __syncthreads();
     } else {
-      ui = it == 0 ? (int)blockIdx.x : a.n_units;
+      ui = it == 0 ? (int)blockIdx.x : a.n_units * a.n_chunks;
     }
-    if (ui >= a.n_units) break;
-    const int u = a.unit_order[ui];
+    if (ui >= a.n_units * a.n_chunks) break;
+    const int u = a.unit_order[ui / a.n_chunks];
+    const int g0 = a.g0 + (ui % a.n_chunks) * GN;
     const Unit U = a.units[u];
     const int64_t tb = U.task_base;
     const int ns = a.n_steps[u];
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
     using clong = const __attribute__((address_space(4))) int64_t;
     cint* SK = (cint*)(a.step_k + a.step_base[u]);
     clong* SEn = (clong*)(a.step_e + a.step_base[u]);
-    const int64_t obase = ((int64_t)U.dir * a.C_total + U.cell_off) * a.G + a.g0;
+    const int64_t obase = ((int64_t)U.dir * a.C_total + U.cell_off) * a.G + g0;
     const int C = U.n_cells;
     UnitBufs B;
     {
@@ -471,12 +472,12 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
     }
     B.sched = rsrc(a.sched + tb, 4 * (int64_t)C);
     B.rp = rsrc(a.row_ptr + tb, 8 * ((int64_t)C + 1));
-    B.den = rsrc(a.tden + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
-    B.src = rsrc(a.tsrc + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
-    B.outs = rsrc(a.out_s + tb * a.G + a.g0, 4 * ((int64_t)C * a.G - a.g0));
-    B.prev = rsrc(a.phi_prev == nullptr ? nullptr : a.phi_prev + obase, 4 * ((int64_t)C * a.G - a.g0));
-    B.out = rsrc(a.out + obase, 4 * ((int64_t)C * a.G - a.g0));
-    B.pin = rsrc(a.pin == nullptr ? nullptr : a.pin + obase, 4 * ((int64_t)C * a.G - a.g0));
+    B.den = rsrc(a.tden + tb * a.G + g0, 4 * ((int64_t)C * a.G - g0));
+    B.src = rsrc(a.tsrc + tb * a.G + g0, 4 * ((int64_t)C * a.G - g0));
+    B.outs = rsrc(a.out_s + tb * a.G + g0, 4 * ((int64_t)C * a.G - g0));
+    B.prev = rsrc(a.phi_prev == nullptr ? nullptr : a.phi_prev + obase, 4 * ((int64_t)C * a.G - g0));
+    B.out = rsrc(a.out + obase, 4 * ((int64_t)C * a.G - g0));
+    B.pin = rsrc(a.pin == nullptr ? nullptr : a.pin + obase, 4 * ((int64_t)C * a.G - g0));
     // step solved at iteration s (iterations past the last one repeat it: their
     // loads are issued and never used)
     auto info = [&](int s) -> LevelInfo {

@@ -9,7 +9,9 @@ oracle checks element by element (through the C ABI):
   (1,536 units) at reduced cell counts;
 - levels wider than the workgroup, cut into several steps (small workgroups);
 - rings too small to hold three steps, where values that could not be prefetched
-  are read from global memory at solve time.
+  are read from global memory at solve time;
+- every packing of the groups into work items (1 to 4 groups per workgroup),
+  which must agree bit for bit.
 
 Tolerances as in test_gpu_parity: graphs bit-exact, J and absorbed within 1e-5
 relative (elementwise above 1e-20 of the maximum, and in L1), gradients within
@@ -175,17 +177,32 @@ def test_wide_levels_cut_into_steps(block):
     check_against_oracle(w, g)
 
 
-@pytest.mark.parametrize("G", [1, 4])
-def test_small_ring_reads_unprefetched_values(G):
+@pytest.mark.parametrize("G,pack", [(1, 0), (4, 4), (4, 2)])
+def test_small_ring_reads_unprefetched_values(G, pack):
     """A ring of 64 slots holds less than three steps, so upwind results that are
     outside the ring but not yet final when the values are prefetched are read
     from global memory when the task is solved."""
     w = W.small_random(2500, 24, G=G, seed=35, periodic=True, n_pbc=2)
-    g = gpu_run(w, ring=64, block=256)
+    g = gpu_run(w, ring=64, block=256, pack=pack)
     d = gpu_run(w)
     check_against_oracle(w, g)
     # the arithmetic does not depend on where a value came from
     assert np.array_equal(g["J"], d["J"]) and np.array_equal(g["dk"], d["dk"])
+
+
+def test_packings_agree_bit_for_bit():
+    """Four groups swept as 4 x 1, 2 x 2, 3 + 1 and 1 x 4 packed groups per work
+    item (periodic passes, scattering, forward and adjoint): identical results,
+    and the oracle's."""
+    w = W.small_random(3000, 24, G=4, seed=36, periodic=True, n_pbc=3, albedo=0.3, n_scat=2)
+    runs = {p: gpu_run(w, pack=p) for p in (1, 2, 3, 4)}
+    for p in (2, 3, 4):
+        for k in ("J", "A", "dk", "de"):
+            assert np.array_equal(runs[p][k], runs[1][k]), (p, k)
+    check_against_oracle(w, runs[2])
+    sw = _sw()
+    with pytest.raises(sw.SweepError, match="INVALID_ARG"):
+        gpu_run(w, pack=5)
 
 
 def test_c3_recipe_full_size_on_eleven_directions():
@@ -197,7 +214,8 @@ def test_c3_recipe_full_size_on_eleven_directions():
     sw = _sw()
     w = W.c3_batched_groups()
     w = dict(w, dirs=np.ascontiguousarray(w["dirs"][:11]))
-    g = gpu_run(w)
+    # two groups per work item, as the full 84 directions take by default
+    g = gpu_run(w, pack=2)
     assert g["info"]["kahn_lds_counters"] == 0
     assert g["info"]["max_depth"] > 2700
     dag_matches_oracle(g["dag"], w)

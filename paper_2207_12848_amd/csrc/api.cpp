@@ -261,7 +261,7 @@ struct sweep_dag_s {
   int32_t red_G = 0, red_blocks = 0, red_cpb = 0;
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
-  Buf xpass, pbc_extra;  // periodic adjoint: recomputed passes, transposed coupling
+  Buf xpass, lam_b;  // periodic adjoint: recomputed passes, the other pass's lambda
   Buf phi_a, phi_b, phi_w, pin, pin_prev, pin_prev2, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
       tsrc, cds, out_s, ion_min;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
@@ -518,7 +518,7 @@ sweep_status_t prepare_steps(sweep_dag_t d, const FwdPlan& p, int32_t G, hipStre
 // Per-task denominators and sources for one sweep (schedule order).
 sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
                         const float* gsrc, const float* jsum_prev, float albedo, int32_t law,
-                        hipStream_t s, bool use_gsrc = true, const double* extra = nullptr) {
+                        hipStream_t s, bool use_gsrc = true) {
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
@@ -539,7 +539,6 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.law = law;
   q.use_gsrc = use_gsrc ? 1 : 0;
   q.C_total = d->C_total;
-  q.extra = extra;
   q.tden = d->tden.as<float>();
   q.tsrc = d->tsrc.as<float>();
   q.cds = d->cds.as<float2>();
@@ -1433,7 +1432,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   HIP_TRY(d->de64.alloc(8 * CG));
   if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
   if (p.n_scat > 1 && P > 1) HIP_TRY(d->xpass.alloc(4 * DCG * (P - 1)));
-  if (P > 1) HIP_TRY(d->pbc_extra.alloc(8 * DCG));
+  if (P > 1) HIP_TRY(d->lam_b.alloc(4 * DCG));
   if (periodic) HIP_TRY(d->pin.alloc(4 * DCG));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
@@ -1466,25 +1465,15 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
       }
       for (int ps = P - 1; ps >= 0; --ps) {
         const bool loss_pass = ps == P - 1;
-        if (!loss_pass) {
-          // the periodic coupling's adjoint: lam (of pass ps + 1) to the partners
-          HIP_TRY(sweep::launch_fill_f32(reinterpret_cast<float*>(d->pbc_extra.p), 2 * DCG, 0.0f, st));
-          sweep::PbcAdjArgs b{};
-          b.units = d->units_d.as<Unit>();
-          b.n_units = (int32_t)d->units.size();
-          b.blk_base = d->blk_base.as<int32_t>();
-          b.sched = d->sched.as<int32_t>();
-          b.up_ptr = d->up_ptr.as<int64_t>();
-          b.up = d->up.as<int2>();
-          b.lam = d->lam.as<float>();
-          b.extra = d->pbc_extra.as<double>();
-          b.C_total = d->C_total;
-          b.G = G;
-          HIP_TRY(sweep::launch_pbc_adj(b, d->n_blocks, st));
-        }
+        // pass ps's lambda; the periodic outflow entries of the downwind rows take
+        // the later pass's lambda at their partners (the adjoint of the forward
+        // pass's periodic inflow), so the two alternate between two buffers
+        float* lam_ps = ((P - 1 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>();
+        const float* lam_next = loss_pass ? nullptr
+                                          : (((P - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
         ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st,
-                        loss_pass, loss_pass ? nullptr : d->pbc_extra.as<double>()));
-        ST_TRY(run_sweep(d, true, p, G, nullptr, d->lam.as<float>(), nullptr, st));
+                        loss_pass));
+        ST_TRY(run_sweep(d, true, p, G, lam_next, lam_ps, nullptr, st));
         sweep::AdjReduceArgs q{};
         q.D = d->D;
         q.G = G;
@@ -1496,7 +1485,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
         q.gsrc = d->gsrc.as<float>();
         q.use_g = loss_pass ? 1 : 0;
         q.accumulate = loss_pass ? 0 : 1;
-        q.lam = d->lam.as<float>();
+        q.lam = lam_ps;
         q.phi = xp(it, ps);
         q.kappa = kappa;
         q.vol = d->vol.as<float>();
@@ -1518,7 +1507,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                  (uint64_t)saved_bytes, pkey(dL_dJ), pkey(dL_dabsorbed),
                                  pkey(dL_dkappa), pkey(dL_demission)};
     opts_key(key, p);
-    for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->pbc_extra,
+    for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->lam_b,
                          &d->pin, &d->tden, &d->tsrc, &d->cds, &d->out_s})
       key.push_back(pkey(b->p));
     ST_TRY(run_graph(d, key, s, body));

@@ -150,7 +150,6 @@ struct PrepArgs {
   int32_t law;             // SWEEP_LAW_UPWIND / SWEEP_LAW_EXP
   int32_t use_gsrc;        // adjoint: add r * gsrc (the pass that carries the loss)
   int64_t C_total;
-  const double* extra;     // adjoint: per-task source [D][C_total][G] or nullptr
   float2* cds;             // [T][G] cell order (scratch): (denominator, source)
   int32_t* flag;           // device error bits (atomicOr): kErrKappa, kErrEmission, kErrCell
   float* tden;             // [T][G] schedule order
@@ -218,22 +217,6 @@ struct IonArgs {
   double n_H, sigma_H, alpha_B, photon_rate, length_unit;
   double l3;               // length_unit^3
 };
-
-// Adjoint of the periodic coupling (one pass): scatter w lambda(c) of every
-// periodic inflow entry of task (c, d) to its partner (nb, d).
-struct PbcAdjArgs {
-  const Unit* units;
-  int32_t n_units;
-  const int32_t* blk_base;
-  const int32_t* sched;
-  const int64_t* up_ptr;
-  const int2* up;
-  const float* lam;        // [D][C_total][G] adjoint of the later pass
-  double* extra;           // [D][C_total][G] accumulated (zeroed by the caller)
-  int64_t C_total;
-  int32_t G;
-};
-hipError_t launch_pbc_adj(const PbcAdjArgs& a, int32_t n_blocks, hipStream_t s);
 
 // launchers (kernels in dag.hip / sweep.hip / chem.hip)
 hipError_t launch_ion_limit(const IonArgs& a, unsigned long long* out, hipStream_t s);

@@ -412,8 +412,13 @@ __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int
 //
 // LDS: [values: ring R slots | zero | sink | 2 x SE prefetched slots] x GN floats,
 // then two staging buffers of SE + 8 entries.
-template <int GN, bool REVERSE, bool PIN, int CH>
+// PER: periodic entries (a negative position -(partner + 1)) take the partner's
+// value in phi_prev, the previous forward pass or, in the adjoint, the later
+// pass's lambda (else zero).  The forward sweep with PER also stores each task's
+// periodic inflow (pin).
+template <int GN, bool REVERSE, bool PER, int CH>
 __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
+  constexpr bool PIN = PER && !REVERSE;
   constexpr int NS = 3;
   extern __shared__ __align__(16) unsigned char smem[];
   float* vals = reinterpret_cast<float*>(smem);
@@ -535,7 +540,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
                           F[2 * i + h]);
           }
       }
-      if (PIN) {
+      if (PER) {
 #pragma unroll
         for (int i = 0; i < CH / 2; ++i)
 #pragma unroll
@@ -565,16 +570,16 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
           const int idx = idx0 + h;
           const int p = h ? v.z : v.x;
           const bool val = idx < L.nst;
-          // without periodic inflows (PIN false) a periodic entry reads the zero slot
-          const bool pf = val && prefetchable(p, w, visF) && (PIN || p >= 0);
+          // without periodic values (PER false) a periodic entry reads the zero slot
+          const bool pf = val && prefetchable(p, w, visF) && (PER || p >= 0);
           const int fs = far0 + b * SE + idx;
           const bool inw = w.has(p);
           const int slot = !val ? zero : (inw ? (p & a.ring_mask) : (pf ? fs : zero));
-          if (val && !inw && !pf && (PIN || p >= 0)) s_bad[b] = gbase + s;
+          if (val && !inw && !pf && (PER || p >= 0)) s_bad[b] = gbase + s;
           if (pf) {
 #pragma unroll
             for (int g = 0; g < GN; ++g)
-              vals[fs * GN + g] = (PIN && p < 0) ? FP[2 * i + h][g] : F[2 * i + h][g];
+              vals[fs * GN + g] = (PER && p < 0) ? FP[2 * i + h][g] : F[2 * i + h][g];
           }
           const int addr = slot * (GN * 4);
           if (h) {
@@ -614,7 +619,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       for (int k = k0 + tid; k < k1; k += nthr) {
         TaskRec<GN> t;
         if (k == k0 + tid) t = cur; else load_rec<GN>(a, B, k, e0, t);
-        const Inflow<GN> in = gather<GN, PIN, false>(a, B, t, nullptr, eoff, ring, w);
+        const Inflow<GN> in = gather<GN, PER, false>(a, B, t, nullptr, eoff, ring, w);
         finish_task<GN, PIN>(a, B, t, k, in, ring);
       }
       // the uncommon steps leave no memory operation of theirs in flight, so the
@@ -650,24 +655,31 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   }
 }
 
-template <int GN, bool REVERSE, bool PIN>
+template <int GN, bool REVERSE, bool PER>
 hipError_t launch_sweep_p(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
   if ((block != 256 && block != 512 && block != 1024) || block > kSweepMaxBlock(GN))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sweep<GN, REVERSE, PIN, kStageCh>), dim3(grid), dim3(block), lds, s, a);
+  hipLaunchKernelGGL((k_sweep<GN, REVERSE, PER, kStageCh>), dim3(grid), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 
-// The forward sweep stores the periodic inflow per task only when asked to (a
-// forward pass with periodic inflows always is; launches without it take no
-// inflow from a previous pass).
+// Forward: the variant that stores the periodic inflow per task when asked to
+// (every forward pass with periodic boundaries is; its first pass has no
+// previous pass and reads zeros); a forward launch without it takes no values
+// from a previous pass.  Adjoint: the periodic variant when the later pass's
+// lambda is given.
 template <int GN, bool REVERSE>
 hipError_t launch_sweep_g(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
-  if (!REVERSE && a.pin != nullptr) return launch_sweep_p<GN, false, true>(a, grid, block, lds, s);
+  if (REVERSE) {
+    if (a.pin != nullptr) return hipErrorInvalidValue;
+    if (a.phi_prev != nullptr) return launch_sweep_p<GN, true, true>(a, grid, block, lds, s);
+    return launch_sweep_p<GN, true, false>(a, grid, block, lds, s);
+  }
+  if (a.pin != nullptr) return launch_sweep_p<GN, false, true>(a, grid, block, lds, s);
   if (a.phi_prev != nullptr) return hipErrorInvalidValue;
-  return launch_sweep_p<GN, REVERSE, false>(a, grid, block, lds, s);
+  return launch_sweep_p<GN, false, false>(a, grid, block, lds, s);
 }
 
 template <bool REVERSE>
@@ -764,7 +776,6 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
         s = (double)a.gsrc[cg];
         if (exp_law) s *= exp_r(ap, kap * V);
       }
-      if (a.extra != nullptr) s += a.extra[((int64_t)U.dir * a.C_total + ci) * a.G + g];
     }
     // invalid inputs raise the DAG's error flag (reported by the next call that
     // synchronises); the kernels run on regardless
@@ -978,29 +989,6 @@ __global__ void k_adj_reduce(AdjReduceArgs a, double* dk, double* de) {
   a.gsrc_next[i] = (float)(a.accumulate ? (double)a.gsrc_next[i] + gn : gn);
 }
 
-// Adjoint of the periodic coupling, one thread per task in schedule order: the
-// forward pass takes w x(nb) of the previous pass through each periodic inflow
-// entry -(nb + 1) of the task's upwind row, so the previous pass's adjoint gets
-// w lambda(c) at the partner nb (FP64 atomics: partners receive from several
-// tasks; the sum order is not fixed, which moves results by rounding only).
-__global__ __launch_bounds__(256) void k_pbc_adj(PbcAdjArgs a) {
-  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
-  const Unit U = a.units[u];
-  const int k = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
-  if (k >= U.n_cells) return;
-  const int64_t t = U.task_base + k;
-  const int c = a.sched[t];
-  const int64_t obase = (int64_t)U.dir * a.C_total + U.cell_off;
-  for (int64_t e = a.up_ptr[t]; e < a.up_ptr[t + 1]; ++e) {
-    const int2 en = a.up[e];
-    if (en.x >= 0) continue;
-    const int nb = -en.x - 1;
-    const double w = (double)__int_as_float(en.y);
-    for (int g = 0; g < a.G; ++g)
-      atomicAdd(&a.extra[(obase + nb) * a.G + g], w * (double)a.lam[(obase + c) * a.G + g]);
-  }
-}
-
 __global__ void k_d2f_pair(const double* a, const double* b, float* oa, float* ob, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -1042,9 +1030,9 @@ hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int GN, bool REVERSE, bool PIN>
+template <int GN, bool REVERSE, bool PER>
 hipError_t set_lds_g(int32_t bytes) {
-  return hipFuncSetAttribute((const void*)k_sweep<GN, REVERSE, PIN, kStageCh>,
+  return hipFuncSetAttribute((const void*)k_sweep<GN, REVERSE, PER, kStageCh>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
@@ -1053,7 +1041,8 @@ hipError_t set_lds_gn(int32_t bytes) {
   hipError_t e;
   if ((e = set_lds_g<GN, false, false>(bytes)) != hipSuccess) return e;
   if ((e = set_lds_g<GN, false, true>(bytes)) != hipSuccess) return e;
-  return set_lds_g<GN, true, false>(bytes);
+  if ((e = set_lds_g<GN, true, false>(bytes)) != hipSuccess) return e;
+  return set_lds_g<GN, true, true>(bytes);
 }
 
 hipError_t set_sweep_lds_limit(int32_t bytes) {
@@ -1084,12 +1073,6 @@ hipError_t launch_adj_init(const float* dJ, const float* dA, const float* kappa,
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_adj_init, dim3(grid1d(n, 256)), dim3(256), 0, s, dJ, dA, kappa, vol,
                      jsum_last, albedo, G, n, gsrc, dk, de, flag);
-  return hipGetLastError();
-}
-
-hipError_t launch_pbc_adj(const PbcAdjArgs& a, int32_t n_blocks, hipStream_t s) {
-  if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pbc_adj, dim3(n_blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

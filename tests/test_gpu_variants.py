@@ -11,7 +11,8 @@ oracle checks element by element (through the C ABI):
 - rings too small to hold three steps, where values that could not be prefetched
   are read from global memory at solve time;
 - every packing of the groups into work items (1 to 4 groups per workgroup),
-  which must agree bit for bit.
+  which must agree bit for bit, and the periodic adjoint, which must not depend
+  on the run or the grid.
 
 Tolerances as in test_gpu_parity: graphs bit-exact, J and absorbed within 1e-5
 relative (elementwise above 1e-20 of the maximum, and in L1), gradients within
@@ -188,6 +189,19 @@ def test_small_ring_reads_unprefetched_values(G, pack):
     check_against_oracle(w, g)
     # the arithmetic does not depend on where a value came from
     assert np.array_equal(g["J"], d["J"]) and np.array_equal(g["dk"], d["dk"])
+
+
+def test_periodic_adjoint_is_deterministic():
+    """The adjoint of the periodic passes takes the later pass's lambda through the
+    periodic outflow entries of the downwind rows inside the sweep (no atomics):
+    repeated runs and different grids give identical gradients."""
+    w = W.small_random(2500, 24, G=2, seed=37, periodic=True, n_pbc=4, albedo=0.2, n_scat=2)
+    a = gpu_run(w)
+    b = gpu_run(w)
+    c = gpu_run(w, grid=3)
+    for k in ("dk", "de"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    check_against_oracle(w, a)
 
 
 def test_packings_agree_bit_for_bit():

@@ -243,7 +243,7 @@ struct sweep_dag_s {
   std::vector<int32_t> order;  // units, deepest first
   std::vector<int32_t> identity;
   Buf units_d, order_d, identity_d, sched, indeg, lp, lev_up, lev_dn, up_ptr, dn_ptr, up, dn,
-      aperp, bnd, vol, counter, blk_base;
+      aperp, aperp_s, bnd, vol, counter, blk_base;
   int32_t n_blocks = 0;  // 256-task blocks over all units (prep kernel)
   int32_t max_depth = 0;
   int32_t max_cells = 0;  // cells of the largest mesh
@@ -263,7 +263,7 @@ struct sweep_dag_s {
   // workspaces
   Buf xpass, lam_b;  // periodic adjoint: recomputed passes, the other pass's lambda
   Buf phi_a, phi_b, phi_w, pin, pin_prev, pin_prev2, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
-      tsrc, cds, out_s, ion_min;
+      tsrc, crec, out_s, ion_min;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
   struct GraphEntry {
     std::vector<uint64_t> key;
@@ -521,13 +521,13 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
                         hipStream_t s, bool use_gsrc = true) {
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
+  HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
   sweep::PrepArgs q{};
   q.units = d->units_d.as<Unit>();
   q.n_units = (int32_t)d->units.size();
   q.blk_base = d->blk_base.as<int32_t>();
   q.sched = d->sched.as<int32_t>();
-  q.aperp = d->aperp.as<float>();
+  q.aperp_s = d->aperp_s.as<float>();
   q.kappa = kappa;
   q.vol = d->vol.as<float>();
   q.emission = emission;
@@ -539,9 +539,9 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.law = law;
   q.use_gsrc = use_gsrc ? 1 : 0;
   q.C_total = d->C_total;
+  q.crec = d->crec.as<float2>();
   q.tden = d->tden.as<float>();
   q.tsrc = d->tsrc.as<float>();
-  q.cds = d->cds.as<float2>();
   q.flag = d->flag.as<int32_t>();
   ProfScope ps("prep", s);
   HIP_TRY(sweep::launch_prep(q, d->n_blocks, s));
@@ -911,6 +911,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_up.alloc(4 * T));
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
+  HIP_TRY(D->aperp_s.alloc(4 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
   HIP_TRY(cnt.alloc(4 * T));  // Kahn's counters in global memory
   HIP_TRY(inv.alloc(4 * T));
@@ -951,6 +952,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.rowlen_up = rowlen_up.as<int32_t>();
   a.rowlen_dn = rowlen_dn.as<int32_t>();
   a.aperp = D->aperp.as<float>();
+  a.aperp_s = D->aperp_s.as<float>();
   a.wface = wface.as<float>();
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
@@ -1147,7 +1149,7 @@ sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
   info->min_depth = mn;
   info->mean_depth = sum / d->units.size();
   const Buf* bufs[] = {&d->sched, &d->indeg, &d->lp, &d->lev_up, &d->lev_dn,
-                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->bnd, &d->vol};
+                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->aperp_s, &d->bnd, &d->vol};
   int64_t b = 0;
   for (const Buf* x : bufs) b += (int64_t)x->bytes;
   info->device_bytes = b;
@@ -1270,7 +1272,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   ST_TRY(ensure_mesh_tables(d));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
+  HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   sweep::ReduceArgs r{};
   r.units = d->units_d.as<Unit>();
@@ -1385,7 +1387,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
                                  pkey(totals), pkey(saved), (uint64_t)saved_bytes};
     opts_key(key, p);
     for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->pin_prev2,
-                         &d->jsum_a, &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->cds, &d->out_s,
+                         &d->jsum_a, &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->crec, &d->out_s,
                          &d->mesh_blk_base, &d->blk_mesh, &d->blk_cell0})
       key.push_back(pkey(b->p));
     ST_TRY(run_graph(d, key, s, body));
@@ -1436,7 +1438,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   if (periodic) HIP_TRY(d->pin.alloc(4 * DCG));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
+  HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   const float* phi_final = (const float*)saved;
   auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
@@ -1508,7 +1510,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                  pkey(dL_dkappa), pkey(dL_demission)};
     opts_key(key, p);
     for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->lam_b,
-                         &d->pin, &d->tden, &d->tsrc, &d->cds, &d->out_s})
+                         &d->pin, &d->tden, &d->tsrc, &d->crec, &d->out_s})
       key.push_back(pkey(b->p));
     ST_TRY(run_graph(d, key, s, body));
   }
@@ -1531,7 +1533,7 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
   HIP_TRY(d->phi_a.alloc(4 * DCG));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
-  HIP_TRY(d->cds.alloc(8 * (size_t)d->T * G));
+  HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   ST_TRY(run_prep(d, G, kappa, emission, nullptr, nullptr, p.albedo, p.law, s));
   hipEvent_t e0 = nullptr, e1 = nullptr;

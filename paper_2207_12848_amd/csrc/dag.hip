@@ -8,7 +8,8 @@
 //   k_kahn    per unit, one workgroup: levels by Kahn's algorithm (algorithm 2's
 //             counters), ready cells compacted with wavefront ballots
 //   k_gather_len, k_fill  row lengths and rows of the upwind/downwind lists,
-//             stored in schedule order so a level's rows are contiguous
+//             stored in schedule order so a level's rows are contiguous (and
+//             Aperp in schedule order, for the per-call preparation)
 #include <hipcub/hipcub.hpp>
 
 #include <type_traits>
@@ -795,6 +796,7 @@ __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
   const int c = k < scheduled ? a.sched[t] : -1;
   a.len_up[t] = c >= 0 ? a.rowlen_up[U.task_base + c] : 0;
   a.len_dn[t] = c >= 0 ? a.rowlen_dn[U.task_base + c] : 0;
+  a.aperp_s[t] = c >= 0 ? a.aperp[U.task_base + c] : 0.0f;
 }
 
 // Per mesh: the largest face count of a cell, and the overflow room the wide

@@ -74,6 +74,7 @@ struct DagBuildArgs {
   int32_t* rowlen_up;
   int32_t* rowlen_dn;
   float* aperp;
+  float* aperp_s;  // the same per task in schedule order (written by k_gather_len)
   // per (direction, face) of every mesh, at D * face_off + d * n_faces + f: the face
   // weight w = A |Omega . n| rounded once to FP32 from FP64, with the face's class
   // in its sign: outflow +w, inflow -w, neither NaN
@@ -131,14 +132,14 @@ struct SweepArgs {
   int32_t stage_off;      // byte offset of the staging buffers in the dynamic LDS
 };
 
-// Per-call preparation of the per-task denominators and sources (cell order,
-// then schedule order).
+// Per-call preparation of the per-task denominators and sources, written in
+// schedule order.
 struct PrepArgs {
   const Unit* units;
   int32_t n_units;
   const int32_t* blk_base;
   const int32_t* sched;
-  const float* aperp;      // per task, cell order
+  const float* aperp_s;    // per task, schedule order
   const float* kappa;      // [C][G]
   const float* vol;        // [C]
   const float* emission;   // forward source [C][G] (divided by D), or
@@ -150,8 +151,8 @@ struct PrepArgs {
   int32_t law;             // SWEEP_LAW_UPWIND / SWEEP_LAW_EXP
   int32_t use_gsrc;        // adjoint: add r * gsrc (the pass that carries the loss)
   int64_t C_total;
-  float2* cds;             // [T][G] cell order (scratch): (denominator, source)
   int32_t* flag;           // device error bits (atomicOr): kErrKappa, kErrEmission, kErrCell
+  float2* crec;            // [C_total][G] scratch: (kappa, source of the cell)
   float* tden;             // [T][G] schedule order
   float* tsrc;             // [T][G] schedule order
 };

@@ -738,9 +738,36 @@ __device__ __forceinline__ double dh_dt(double t) {
 }
 
 // Per-task denominators (Aperp + kappa V, or the exponential law's den) and
-// sources, first in cell order within each unit (every access coalesced), as
-// (denominator, source) pairs.  The adjoint source of the exponential law is
+// sources, in schedule order (what the sweep streams).  The sources do not
+// depend on the direction: a first pass over the cells packs each cell's
+// (kappa, source) per group into one record, so that the pass over the tasks
+// reads its Aperp (schedule order) and writes its outputs coalesced, and
+// gathers one record and the cell's volume from arrays every direction shares
+// (which stay cache resident).  The adjoint source of the exponential law is
 // r g, g being the derivative with respect to the cell average.
+__global__ __launch_bounds__(256) void k_prep_cells(PrepArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.C_total * a.G) return;
+  const int64_t ci = i / a.G;
+  const double kap = (double)a.kappa[i];
+  double s;
+  if (a.emission != nullptr) {
+    s = (double)a.emission[i];
+    if (a.jsum_prev != nullptr) s += (double)a.albedo * kap * (double)a.vol[ci] * (double)a.jsum_prev[i];
+    s *= (double)a.inv_D;
+  } else {
+    s = a.use_gsrc ? (double)a.gsrc[i] : 0.0;
+  }
+  // invalid inputs raise the DAG's error flag (reported by the next call that
+  // synchronises); the kernels run on regardless
+  int32_t bad = 0;
+  if (!(kap >= 0.0 && kap <= DBL_MAX)) bad |= kErrKappa;
+  if (a.emission != nullptr && !((double)a.emission[i] >= 0.0 && (double)a.emission[i] <= DBL_MAX))
+    bad |= kErrEmission;
+  if (bad != 0) atomicOr(a.flag, bad);
+  a.crec[i] = make_float2(a.kappa[i], (float)s);
+}
+
 __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_units, int b) {
   int lo = 0, hi = n_units - 1;
   while (lo < hi) {
@@ -754,55 +781,25 @@ template <bool EXP_LAW>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
   const Unit U = a.units[u];
-  const int c = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
-  if (c >= U.n_cells) return;
-  const int64_t t = U.task_base + c;  // cell order: every access is coalesced
-  const int64_t ci = (int64_t)U.cell_off + c;
-  const double V = (double)a.vol[ci];
-  const double ap = (double)a.aperp[t];
-  for (int g = 0; g < a.G; ++g) {
-    const int64_t cg = ci * a.G + g;
-    const double kap = (double)a.kappa[cg];
-    const bool exp_law = EXP_LAW;
-    const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
-    double s;
-    if (a.emission != nullptr) {
-      s = (double)a.emission[cg];
-      if (a.jsum_prev != nullptr) s += (double)a.albedo * kap * V * (double)a.jsum_prev[cg];
-      s *= (double)a.inv_D;
-    } else {
-      s = 0.0;
-      if (a.use_gsrc) {
-        s = (double)a.gsrc[cg];
-        if (exp_law) s *= exp_r(ap, kap * V);
-      }
-    }
-    // invalid inputs raise the DAG's error flag (reported by the next call that
-    // synchronises); the kernels run on regardless
-    int32_t bad = 0;
-    if (!(kap >= 0.0 && kap <= DBL_MAX)) bad |= kErrKappa;
-    if (a.emission != nullptr && !((double)a.emission[cg] >= 0.0 && (double)a.emission[cg] <= DBL_MAX))
-      bad |= kErrEmission;
-    if (!(den > 0.0 && den <= DBL_MAX)) bad |= kErrCell;
-    if (bad != 0) atomicOr(a.flag, bad);
-    a.cds[t * a.G + g] = make_float2((float)den, (float)s);
-  }
-}
-
-// The same values in schedule order (what the sweep streams): a gather of two
-// arrays per unit, which the unit-by-unit block order keeps cache resident.
-__global__ __launch_bounds__(256) void k_prep_order(PrepArgs a) {
-  const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
-  const Unit U = a.units[u];
   const int k = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
   if (k >= U.n_cells) return;
-  const int64_t t = U.task_base + k;
-  const int64_t tc = U.task_base + a.sched[t];
+  const int64_t t = U.task_base + k;  // schedule position
+  const int64_t ci = (int64_t)U.cell_off + a.sched[t];
+  const double V = (double)a.vol[ci];
+  const double ap = (double)a.aperp_s[t];
+  int32_t bad = 0;
   for (int g = 0; g < a.G; ++g) {
-    const float2 v = a.cds[tc * a.G + g];  // one gathered access per task and group
-    a.tden[t * a.G + g] = v.x;
-    a.tsrc[t * a.G + g] = v.y;
+    const float2 r = a.crec[ci * a.G + g];
+    const double kap = (double)r.x;
+    const bool exp_law = EXP_LAW;
+    const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
+    double s = (double)r.y;
+    if (exp_law && a.emission == nullptr) s *= exp_r(ap, kap * V);
+    if (!(den > 0.0 && den <= DBL_MAX)) bad |= kErrCell;
+    a.tden[t * a.G + g] = (float)den;
+    a.tsrc[t * a.G + g] = (float)s;
   }
+  if (bad != 0) atomicOr(a.flag, bad);
 }
 
 // ----------------------------------------------------------------------- reductions
@@ -1024,9 +1021,9 @@ hipError_t launch_sweep_adj(const SweepArgs& a, int32_t gn, int32_t grid, int32_
 
 hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
   if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep_cells, dim3(grid1d(a.C_total * a.G, 256)), dim3(256), 0, s, a);
   if (a.law == SWEEP_LAW_EXP) hipLaunchKernelGGL(k_prep<true>, dim3(n_blocks), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(k_prep<false>, dim3(n_blocks), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_prep_order, dim3(n_blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

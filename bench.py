@@ -143,12 +143,12 @@ def host_cpu() -> dict:
     return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
 
 
-def sample_dirs(w: dict, n_updates: int) -> int:
+def sample_dirs(w: dict, n_updates: int, budget: float = CPU_SAMPLE_UPDATES) -> int:
     """Directions of the oracle's bounded sample (all of them when the step is small)."""
     D = len(w["dirs"])
-    if n_updates <= CPU_SAMPLE_UPDATES:
+    if n_updates <= budget:
         return D
-    return max(1, int(D * CPU_SAMPLE_UPDATES / n_updates))
+    return max(1, int(D * budget / n_updates))
 
 
 def parity(gpu: dict, ref: dict, dk, de) -> dict:
@@ -179,7 +179,7 @@ def parity(gpu: dict, ref: dict, dk, de) -> dict:
     return par
 
 
-def cpu_baseline(w: dict, n_updates: int, gpu_full: dict, gpu_run) -> dict:
+def cpu_baseline(w: dict, n_updates: int, gpu_full: dict, gpu_run, threads: int = 0) -> dict:
     """The FP64 oracle on the host, timed over one step (forward and adjoint) of the
     same workload, and its element-wise comparison with the GPU.  A step larger than
     CPU_SAMPLE_UPDATES is sampled: the oracle then runs the same step for the first
@@ -189,8 +189,12 @@ def cpu_baseline(w: dict, n_updates: int, gpu_full: dict, gpu_run) -> dict:
 
     import oracle
     oracle.build()
+    budget = CPU_SAMPLE_UPDATES
+    if threads > 0:  # fewer threads: a proportionally smaller sample (same run time)
+        budget *= min(1.0, threads / max(1, oracle.num_threads()))
+        oracle.set_threads(threads)
     D = len(w["dirs"])
-    k = sample_dirs(w, n_updates)
+    k = sample_dirs(w, n_updates, budget)
     ws = w if k == D else dict(w, dirs=np.ascontiguousarray(w["dirs"][:k]))
     sample_updates = n_updates * k // D
     t0 = time.perf_counter()
@@ -316,6 +320,8 @@ def main() -> int:
                     help="transport scheme: (a) area-weighted outflow or (b) the three most "
                          "aligned outflow faces")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="OpenMP threads of the oracle baseline (0 = all)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--tune", action="store_true",
                     help="pick block and ring with the library's autotuner before timing")
@@ -467,7 +473,7 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, n_updates, gpu, run_sample)
+        cpu = cpu_baseline(w, n_updates, gpu, run_sample, args.cpu_threads)
         log("cpu baseline: %.3g updates/s on %d threads" % (cpu["value"], cpu["cores"]))
 
     depth_max = int(info["max_depth"])

@@ -246,6 +246,13 @@ def num_threads() -> int:
     return int(lib.orc_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """Run the oracle's direction loops on n OpenMP threads."""
+    lib = _load()
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads(int(n))
+
+
 def absorbed_loss_grads(w: dict):
     """Upstream gradients of L = sum_c V_c kappa_a,c J_c = sum_c absorbed_c / (4 pi)."""
     G = int(w["G"])

@@ -750,3 +750,12 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Sets the number of OpenMP threads of the loops above (n >= 1). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -528,9 +528,8 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
           pp |= (uint32_t)(pf && p < 0) << (2 * i + h);
         }
       }
-      // issued whether or not a lane needs them (lanes that need none read past
-      // the buffer's end): a fixed count of loads keeps the waits exact
-      {
+      // the loads of a wavefront whose lanes need none are not issued
+      if (__ballot(po != 0u) != 0ull) {
 #pragma unroll
         for (int i = 0; i < CH / 2; ++i)
 #pragma unroll
@@ -540,7 +539,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
                           F[2 * i + h]);
           }
       }
-      if (PER) {
+      if (PER && __ballot(pp != 0u) != 0ull) {
 #pragma unroll
         for (int i = 0; i < CH / 2; ++i)
 #pragma unroll

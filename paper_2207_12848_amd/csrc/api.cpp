@@ -1026,6 +1026,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));
   }
   // (no synchronisation here: the depths and the cycle flag are read once, at the end)
+  HIP_TRY(sweep::launch_sort_levels(a, s));
   HIP_TRY(sweep::launch_gather_len(a, n_blocks, s));
   // row lengths in schedule order -> row pointers
   HIP_TRY(D->up_ptr.alloc(8 * (T + 1)));

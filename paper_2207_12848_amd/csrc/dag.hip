@@ -499,7 +499,6 @@ __global__ __launch_bounds__(kKahnBlock(NCH)) void k_kahn(DagBuildArgs a) {
   uint32_t* cntw = reinterpret_cast<uint32_t*>(cnt);
   int32_t* sched = a.sched + tb;
   int32_t* spill = sched;  // frontier entries beyond the LDS copy (rewritten in place)
-  int32_t* inv = a.inv + tb;
   int32_t* lp = a.lp + U.lp_base;
   const int W = a.dn_width;
   const int Wr4 = W / 4;  // chunks per row
@@ -563,7 +562,8 @@ __global__ __launch_bounds__(kKahnBlock(NCH)) void k_kahn(DagBuildArgs a) {
   __syncthreads();
   const int4* sent4 = reinterpret_cast<const int4*>(a.dnw + a.dn_sentinel);
   // The last wavefront makes every global store of the level loop (the
-  // schedule, its inverse and the level pointers) and never waits for a load;
+  // schedule and the level pointers; the inverse schedule is written when the
+  // levels are sorted, k_sort_levels) and never waits for a load;
   // the other wavefronts process the frontier and only load, so their waits for
   // row loads never include a store (the vector-memory counter is in order).
   const int nwork = nthr - 64;
@@ -581,15 +581,7 @@ __global__ __launch_bounds__(kKahnBlock(NCH)) void k_kahn(DagBuildArgs a) {
       // the level's cells in slot order form the schedule (entries past the LDS
       // copy are in place already; each store is issued without waiting)
       const int n = min(tail - head, kFrontierCap);
-      for (int i = lane; i < n; i += 64) {
-        const int c = frc[i];
-        sched[head + i] = c;
-        inv[c] = head + i;
-      }
-      for (int i = n + lane; i < tail - head; i += 64) {
-        const int k = head + i;
-        inv[spill[k]] = k;
-      }
+      for (int i = lane; i < n; i += 64) sched[head + i] = frc[i];
       if (lane == 0) lp[l + 1] = tail;
     }
     for (int kb = head; !writer && kb < tail; kb += nwork) {
@@ -780,6 +772,58 @@ __global__ __launch_bounds__(kKahnBlock(NCH)) void k_kahn(DagBuildArgs a) {
   if (tid == 0) {
     a.depth[blockIdx.x] = l;
     if (tail != C) atomicOr(a.err, 1);
+  }
+}
+
+// Every level's cells in ascending cell id (the canonical order, so the
+// schedule no longer depends on the order Kahn's wavefronts appended them),
+// and the inverse schedule.  Workgroup b of a unit sorts the unit's levels b,
+// b + kSortPerUnit, ... in LDS (bitonic, padded to a power of two); a level
+// wider than kSortCap keeps its order.  Consecutive tasks of a level then lie
+// close in the spatially numbered cells, so the per-task gathers and the
+// cell-order result stores of the later kernels share cache lines.
+constexpr int kSortCap = 4096;
+constexpr int kSortBlock = 256;
+constexpr int kSortPerUnit = 16;  // workgroups per unit
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_levels(DagBuildArgs a) {
+  __shared__ int key[kSortCap];
+  const int u = blockIdx.x / kSortPerUnit;
+  const Unit U = a.units[u];
+  const int depth = a.depth[u];
+  int32_t* sched = a.sched + U.task_base;
+  int32_t* inv = a.inv + U.task_base;
+  const int32_t* lp = a.lp + U.lp_base;
+  for (int l = blockIdx.x % kSortPerUnit; l < depth; l += kSortPerUnit) {
+    const int k0 = lp[l], n = lp[l + 1] - k0;
+    if (n > kSortCap || n < 2) {
+      for (int i = threadIdx.x; i < n; i += kSortBlock) inv[sched[k0 + i]] = k0 + i;
+      continue;
+    }
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += kSortBlock) key[i] = i < n ? sched[k0 + i] : INT_MAX;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1)
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < P / 2; i += kSortBlock) {
+          const int lo = 2 * i - (i & (stride - 1));  // pair (lo, lo + stride)
+          const int hi = lo + stride;
+          const bool up = (lo & size) == 0;
+          const int x = key[lo], y = key[hi];
+          if ((x > y) == up) {
+            key[lo] = y;
+            key[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < n; i += kSortBlock) {
+      const int c = key[i];
+      sched[k0 + i] = c;
+      inv[c] = k0 + i;
+    }
+    __syncthreads();  // the next level reuses the keys
   }
 }
 
@@ -1125,6 +1169,12 @@ hipError_t launch_kahn(const DagBuildArgs& a, bool lds_counters, int32_t max_cel
 hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s) {
   if (n_big <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_mark, dim3((n_big + 63) / 64), dim3(64), 0, s, a, n_big);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_levels(const DagBuildArgs& a, hipStream_t s) {
+  if (a.n_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_levels, dim3(a.n_units * kSortPerUnit), dim3(kSortBlock), 0, s, a);
   return hipGetLastError();
 }
 

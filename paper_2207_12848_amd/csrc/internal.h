@@ -81,7 +81,7 @@ struct DagBuildArgs {
   float* wface;
   float2* bnd;  // (sum of w over wall outflow faces, over periodic outflow faces)
   int32_t* cnt;    // [T] words: Kahn's counters kept in global memory
-  int32_t* inv;    // cell -> position in the unit's schedule
+  int32_t* inv;    // cell -> position in the unit's schedule (written by k_sort_levels)
   // per task, schedule order within the unit
   int32_t* sched;  // position -> cell
   int32_t* lp;     // level pointers
@@ -234,6 +234,8 @@ hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_face_stats(const int64_t* face_ptr, int32_t n_cells, int32_t row_cap, int32_t n_dirs,
                              unsigned long long* out, hipStream_t s);
 hipError_t launch_face_codes(const MeshDev& m, int32_t* fcode, hipStream_t s);
+// Sorts every level of the schedule by cell id and writes the inverse schedule.
+hipError_t launch_sort_levels(const DagBuildArgs& a, hipStream_t s);
 hipError_t launch_gather_len(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_mark(const DagBuildArgs& a, int32_t n_big, hipStream_t s);
 size_t count_lds_bytes(int max_faces, int dn_width);

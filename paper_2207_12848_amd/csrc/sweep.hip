@@ -436,6 +436,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   const int zero = R;       // value slot that always holds zeros (padding entries)
   const int sink = R + 1;   // value slot the threads without a task write
   const int far0 = R + 2;   // prefetched slots of staging buffer b: far0 + b SE + entry index
+  const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wavefront's first thread
   float* ring = vals;
   float* sinkp = vals + sink * GN;
   for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(zero * GN * 4, 0);
@@ -519,6 +520,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       uint32_t po = 0, pp = 0;  // per entry: an older result / a periodic inflow to load
 #pragma unroll
       for (int i = 0; i < CH / 2; ++i) {
+        if (2 * (wbase + i * nthr) >= L.nst) continue;  // no entry of this wavefront
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int idx = 2 * (tid + i * nthr) + h;
@@ -561,9 +563,22 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       const Window w = window<REVERSE>(L.k0, L.k1, R);
 #pragma unroll
       for (int i = 0; i < CH / 2; ++i) {
-        if (2 * i * nthr >= L.nst + 8) break;
         const int idx0 = 2 * (tid + i * nthr);
         int4 v = Q.st[i];
+        if (2 * (wbase + i * nthr) >= L.nst + 8) {
+          // no entry of this wavefront in the step: the registers loaded for it
+          // (entries and prefetched values) are only consumed (a load nothing
+          // reads would leave its wait to a later reuse of the registers)
+          asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int g = 0; g < GN; ++g) {
+              asm volatile("" ::"v"(F[2 * i + h][g]));
+              if (PER) asm volatile("" ::"v"(FP[2 * i + h][g]));
+            }
+          continue;
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int idx = idx0 + h;

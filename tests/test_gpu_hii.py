@@ -86,6 +86,33 @@ def test_hii_evolution_matches_oracle():
     assert np.abs(y_g - y_o).max() <= 1e-3
 
 
+def test_hii_evolution_fixed_steps_matches_oracle():
+    """A step limit below every chemistry limit of the run (the shortest is about
+    4.5e-5 t_rec on this mesh) makes both sides take the same 100 steps, so the
+    neutral fractions are compared cell by cell.  Bound: the sweep's absorbed
+    rates agree to 1e-5 relative per element, and each step moves y by its own
+    photoionisation term, so the accumulated difference stays below 1e-5 of the
+    total change of y (at most 1)."""
+    sw = _sw()
+    w = W.hii_rtype(16, 24)
+    w["hii"] = dict(w["hii"], dt_max_trec=2e-5)
+    p = _params(w)
+    t_end = 0.002 * H.recombination_time(p)
+    dts_o, dts_g = [], []
+    t_o, y_o = H.evolve(w, t_end, record=lambda s, t, y, a, dt: dts_o.append(dt))
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    e = torch.tensor(np.asarray(w["emission"], np.float32), device="cuda")
+    t_g, y_g, n = sw.evolve_ionisation(dag, e, p, t_end, record=lambda s, t, y, a, dt: dts_g.append(dt))
+    y_g = y_g.cpu().numpy()
+    assert len(dts_o) == n == len(dts_g)
+    assert dts_g == dts_o  # every step is the step limit (the last: what is left)
+    assert t_g == t_o
+    dy = np.abs(y_g - y_o).max()
+    print("%d steps, max |dy| %.3e, min y %.4f" % (n, dy, y_o.min()))
+    assert y_o.min() < 0.5  # the run ionises cells
+    assert dy <= 1e-5
+
+
 @pytest.mark.parametrize("n_side", [32, 64])
 def test_rtype_expansion_against_analytic(n_side):
     """The paper's setup (12.8 kpc box, 1e49 photons/s, n_H = 1e-3, 84 directions)

@@ -243,7 +243,7 @@ struct sweep_dag_s {
   std::vector<int32_t> order;  // units, deepest first
   std::vector<int32_t> identity;
   Buf units_d, order_d, identity_d, sched, indeg, lp, lev_up, lev_dn, up_ptr, dn_ptr, up, dn,
-      aperp, aperp_s, bnd, vol, counter, blk_base;
+      aperp, aperp_s, vol_s, bnd, vol, counter, blk_base;
   int32_t n_blocks = 0;  // 256-task blocks over all units (prep kernel)
   int32_t max_depth = 0;
   int32_t max_cells = 0;  // cells of the largest mesh
@@ -518,7 +518,7 @@ sweep_status_t prepare_steps(sweep_dag_t d, const FwdPlan& p, int32_t G, hipStre
 // Per-task denominators and sources for one sweep (schedule order).
 sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
                         const float* gsrc, const float* jsum_prev, float albedo, int32_t law,
-                        hipStream_t s, bool use_gsrc = true) {
+                        hipStream_t s) {
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
@@ -528,6 +528,7 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.blk_base = d->blk_base.as<int32_t>();
   q.sched = d->sched.as<int32_t>();
   q.aperp_s = d->aperp_s.as<float>();
+  q.vol_s = d->vol_s.as<float>();
   q.kappa = kappa;
   q.vol = d->vol.as<float>();
   q.emission = emission;
@@ -537,7 +538,6 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.inv_D = 1.0f / (float)d->D;
   q.G = G;
   q.law = law;
-  q.use_gsrc = use_gsrc ? 1 : 0;
   q.C_total = d->C_total;
   q.crec = d->crec.as<float2>();
   q.tden = d->tden.as<float>();
@@ -912,6 +912,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
   HIP_TRY(D->aperp_s.alloc(4 * T));
+  HIP_TRY(D->vol_s.alloc(4 * T));
   HIP_TRY(D->bnd.alloc(8 * T));
   HIP_TRY(cnt.alloc(4 * T));  // Kahn's counters in global memory
   HIP_TRY(inv.alloc(4 * T));
@@ -953,6 +954,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.rowlen_dn = rowlen_dn.as<int32_t>();
   a.aperp = D->aperp.as<float>();
   a.aperp_s = D->aperp_s.as<float>();
+  a.vol_s = D->vol_s.as<float>();
   a.wface = wface.as<float>();
   a.bnd = D->bnd.as<float2>();
   a.cnt = cnt.as<int32_t>();
@@ -1150,7 +1152,7 @@ sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
   info->min_depth = mn;
   info->mean_depth = sum / d->units.size();
   const Buf* bufs[] = {&d->sched, &d->indeg, &d->lp, &d->lev_up, &d->lev_dn,
-                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->aperp_s, &d->bnd, &d->vol};
+                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->aperp_s, &d->vol_s, &d->bnd, &d->vol};
   int64_t b = 0;
   for (const Buf* x : bufs) b += (int64_t)x->bytes;
   info->device_bytes = b;
@@ -1474,8 +1476,12 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
         float* lam_ps = ((P - 1 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>();
         const float* lam_next = loss_pass ? nullptr
                                           : (((P - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
-        ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st,
-                        loss_pass));
+        // the passes before the last have no source of their own: the denominators
+        // of the loss pass stand and only the sources are cleared
+        if (loss_pass)
+          ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
+        else
+          HIP_TRY(sweep::launch_fill_f32(d->tsrc.as<float>(), d->T * G, 0.0f, st));
         ST_TRY(run_sweep(d, true, p, G, lam_next, lam_ps, nullptr, st));
         sweep::AdjReduceArgs q{};
         q.D = d->D;

@@ -841,6 +841,7 @@ __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
   a.len_up[t] = c >= 0 ? a.rowlen_up[U.task_base + c] : 0;
   a.len_dn[t] = c >= 0 ? a.rowlen_dn[U.task_base + c] : 0;
   a.aperp_s[t] = c >= 0 ? a.aperp[U.task_base + c] : 0.0f;
+  a.vol_s[t] = c >= 0 ? (float)a.meshes[U.mesh].cell_volume[c] : 0.0f;
 }
 
 // Per mesh: the largest face count of a cell, and the overflow room the wide

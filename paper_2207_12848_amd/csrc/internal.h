@@ -75,6 +75,7 @@ struct DagBuildArgs {
   int32_t* rowlen_dn;
   float* aperp;
   float* aperp_s;  // the same per task in schedule order (written by k_gather_len)
+  float* vol_s;    // the cell's volume per task, schedule order (written by k_gather_len)
   // per (direction, face) of every mesh, at D * face_off + d * n_faces + f: the face
   // weight w = A |Omega . n| rounded once to FP32 from FP64, with the face's class
   // in its sign: outflow +w, inflow -w, neither NaN
@@ -140,6 +141,7 @@ struct PrepArgs {
   const int32_t* blk_base;
   const int32_t* sched;
   const float* aperp_s;    // per task, schedule order
+  const float* vol_s;      // the cell's volume per task, schedule order
   const float* kappa;      // [C][G]
   const float* vol;        // [C]
   const float* emission;   // forward source [C][G] (divided by D), or
@@ -149,7 +151,6 @@ struct PrepArgs {
   float inv_D;
   int32_t G;
   int32_t law;             // SWEEP_LAW_UPWIND / SWEEP_LAW_EXP
-  int32_t use_gsrc;        // adjoint: add r * gsrc (the pass that carries the loss)
   int64_t C_total;
   int32_t* flag;           // device error bits (atomicOr): kErrKappa, kErrEmission, kErrCell
   float2* crec;            // [C_total][G] scratch: (kappa, source of the cell)

@@ -770,7 +770,7 @@ __global__ __launch_bounds__(256) void k_prep_cells(PrepArgs a) {
     if (a.jsum_prev != nullptr) s += (double)a.albedo * kap * (double)a.vol[ci] * (double)a.jsum_prev[i];
     s *= (double)a.inv_D;
   } else {
-    s = a.use_gsrc ? (double)a.gsrc[i] : 0.0;
+    s = (double)a.gsrc[i];
   }
   // invalid inputs raise the DAG's error flag (reported by the next call that
   // synchronises); the kernels run on regardless
@@ -791,27 +791,52 @@ __device__ __forceinline__ int unit_of_block(const int32_t* blk_base, int n_unit
   return lo;
 }
 
+// Tasks of a workgroup whose G values per task are staged in LDS, so that the
+// workgroup's [tasks][G] block of denominators and sources is written with
+// consecutive threads on consecutive words (G up to kPrepStageG; larger G is
+// written per task).
+constexpr int kPrepStageG = 8;
+
 template <bool EXP_LAW>
 __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+  __shared__ float sden[256 * kPrepStageG], ssrc[256 * kPrepStageG];
   const int u = unit_of_block(a.blk_base, a.n_units, blockIdx.x);
   const Unit U = a.units[u];
-  const int k = (blockIdx.x - a.blk_base[u]) * 256 + threadIdx.x;
-  if (k >= U.n_cells) return;
-  const int64_t t = U.task_base + k;  // schedule position
-  const int64_t ci = (int64_t)U.cell_off + a.sched[t];
-  const double V = (double)a.vol[ci];
-  const double ap = (double)a.aperp_s[t];
+  const int k0 = (blockIdx.x - a.blk_base[u]) * 256;
+  const int k = k0 + threadIdx.x;
+  const int G = a.G;
+  const bool stage = G <= kPrepStageG;
   int32_t bad = 0;
-  for (int g = 0; g < a.G; ++g) {
-    const float2 r = a.crec[ci * a.G + g];
-    const double kap = (double)r.x;
-    const bool exp_law = EXP_LAW;
-    const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
-    double s = (double)r.y;
-    if (exp_law && a.emission == nullptr) s *= exp_r(ap, kap * V);
-    if (!(den > 0.0 && den <= DBL_MAX)) bad |= kErrCell;
-    a.tden[t * a.G + g] = (float)den;
-    a.tsrc[t * a.G + g] = (float)s;
+  if (k < U.n_cells) {
+    const int64_t t = U.task_base + k;  // schedule position
+    const int64_t ci = (int64_t)U.cell_off + a.sched[t];
+    const double V = (double)a.vol_s[t];
+    const double ap = (double)a.aperp_s[t];
+    for (int g = 0; g < G; ++g) {
+      const float2 r = a.crec[ci * G + g];
+      const double kap = (double)r.x;
+      const bool exp_law = EXP_LAW;
+      const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
+      double s = (double)r.y;
+      if (exp_law && a.emission == nullptr) s *= exp_r(ap, kap * V);
+      if (!(den > 0.0 && den <= DBL_MAX)) bad |= kErrCell;
+      if (stage) {
+        sden[threadIdx.x * G + g] = (float)den;
+        ssrc[threadIdx.x * G + g] = (float)s;
+      } else {
+        a.tden[t * G + g] = (float)den;
+        a.tsrc[t * G + g] = (float)s;
+      }
+    }
+  }
+  if (stage) {
+    __syncthreads();
+    const int n = min(256, U.n_cells - k0) * G;
+    const int64_t base = (U.task_base + k0) * G;
+    for (int i = threadIdx.x; i < n; i += 256) {
+      a.tden[base + i] = sden[i];
+      a.tsrc[base + i] = ssrc[i];
+    }
   }
   if (bad != 0) atomicOr(a.flag, bad);
 }

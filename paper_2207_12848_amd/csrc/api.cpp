@@ -262,8 +262,13 @@ struct sweep_dag_s {
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
   Buf xpass, lam_b;  // periodic adjoint: recomputed passes, the other pass's lambda
-  Buf phi_a, phi_b, phi_w, pin, pin_prev, pin_prev2, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden,
-      tsrc, crec, out_s, ion_min;
+  Buf phi_a, phi_b, phi_w, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, crec, out_s,
+      ion_min;
+  // periodic half-faces (built with the DAG; see sweep::PinArgs) and, per call, the
+  // periodic tasks' own sources and two passes' periodic inflow sums
+  Buf pcell, pf_ptr, pnb, pwf, pwa, ptask, pc_map, pbase, psum_a, psum_b;
+  int32_t n_pc = 0;
+  int64_t n_pf = 0;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
   struct GraphEntry {
     std::vector<uint64_t> key;
@@ -545,6 +550,43 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   q.flag = d->flag.as<int32_t>();
   ProfScope ps("prep", s);
   HIP_TRY(sweep::launch_prep(q, d->n_blocks, s));
+  return SWEEP_OK;
+}
+
+// Per-call buffers of the periodic fold: the periodic tasks' own sources and the
+// inflow sums of two passes.
+sweep_status_t alloc_periodic(sweep_dag_t d, int32_t G) {
+  const int64_t n = std::max<int64_t>((int64_t)d->n_pc * G, 1);
+  HIP_TRY(d->pbase.alloc(4 * (size_t)n * d->D));
+  HIP_TRY(d->psum_a.alloc(8 * (size_t)n));
+  HIP_TRY(d->psum_b.alloc(8 * (size_t)n));
+  return SWEEP_OK;
+}
+
+// Folds the periodic coupling of one pass into its sources (sweep::PinArgs):
+// forward, the previous pass's exit values through the inflow half-faces
+// (their sum over directions into `psum` when given); adjoint, the later pass's
+// lambda through the outflow half-faces.  `fresh`: tsrc holds the sources that
+// run_prep (or a clear) just wrote, which are saved for the later passes.
+sweep_status_t run_pin(sweep_dag_t d, bool adjoint, int32_t G, const float* other, double* psum,
+                       bool& fresh, hipStream_t s) {
+  sweep::PinArgs q{};
+  q.D = d->D;
+  q.G = G;
+  q.C_total = d->C_total;
+  q.n_pc = d->n_pc;
+  q.n_pf = d->n_pf;
+  q.pf_ptr = d->pf_ptr.as<int32_t>();
+  q.pnb = d->pnb.as<int32_t>();
+  q.pw = adjoint ? d->pwa.as<float>() : d->pwf.as<float>();
+  q.ptask = d->ptask.as<int32_t>();
+  q.other = other;
+  q.tsrc = d->tsrc.as<float>();
+  q.pbase = d->pbase.as<float>();
+  q.capture = fresh ? 1 : 0;
+  q.psum = psum;
+  HIP_TRY(sweep::launch_pin(q, s));
+  fresh = false;
   return SWEEP_OK;
 }
 
@@ -1057,6 +1099,55 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   for (int m = 0; m < n_meshes; ++m)
     HIP_TRY(sweep::launch_d2f(meshes[m].cell_volume, D->vol.as<float>() + D->mesh_off[m],
                               meshes[m].n_cells, s));
+  if (D->has_shift) {
+    // the periodic cells and half-faces: counts per cell, two scans, the lists
+    const int64_t C1 = (int64_t)D->C_total + 1;
+    Buf npf, pflag, pf_off, pc_off, ptmp;
+    HIP_TRY(npf.alloc(4 * C1));
+    HIP_TRY(pflag.alloc(4 * C1));
+    HIP_TRY(pf_off.alloc(8 * C1));
+    HIP_TRY(pc_off.alloc(8 * C1));
+    a.npf = npf.as<int32_t>();
+    a.pflag = pflag.as<int32_t>();
+    HIP_TRY(sweep::launch_fill_i32(a.npf + D->C_total, 1, 0, s));
+    HIP_TRY(sweep::launch_fill_i32(a.pflag + D->C_total, 1, 0, s));
+    for (int m = 0; m < n_meshes; ++m) HIP_TRY(sweep::launch_pcount(a, md[m], s));
+    size_t pt_bytes = 0;
+    HIP_TRY(sweep::launch_scan_len(a.npf, pf_off.as<int64_t>(), C1, nullptr, &pt_bytes, s));
+    HIP_TRY(ptmp.alloc(pt_bytes));
+    HIP_TRY(sweep::launch_scan_len(a.npf, pf_off.as<int64_t>(), C1, ptmp.p, &pt_bytes, s));
+    HIP_TRY(sweep::launch_scan_len(a.pflag, pc_off.as<int64_t>(), C1, ptmp.p, &pt_bytes, s));
+    int64_t totals[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(&totals[0], pf_off.as<int64_t>() + D->C_total, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&totals[1], pc_off.as<int64_t>() + D->C_total, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (totals[0] > INT32_MAX)
+      return fail(SWEEP_ERR_UNSUPPORTED, "%lld periodic half-faces (at most %d)", (long long)totals[0],
+                  INT32_MAX);
+    D->n_pf = totals[0];
+    D->n_pc = (int32_t)totals[1];
+    a.pf_off = pf_off.as<int64_t>();
+    a.pc_off = pc_off.as<int64_t>();
+    a.n_pc = D->n_pc;
+    a.n_pf = D->n_pf;
+    HIP_TRY(D->pcell.alloc(4 * std::max<int64_t>(D->n_pc, 1)));
+    HIP_TRY(D->pf_ptr.alloc(4 * ((int64_t)D->n_pc + 1)));
+    HIP_TRY(D->pnb.alloc(4 * std::max<int64_t>(D->n_pf, 1)));
+    HIP_TRY(D->pwf.alloc(4 * std::max<int64_t>(D->n_pf * n_dirs, 1)));
+    HIP_TRY(D->pwa.alloc(4 * std::max<int64_t>(D->n_pf * n_dirs, 1)));
+    HIP_TRY(D->ptask.alloc(4 * std::max<int64_t>((int64_t)D->n_pc * n_dirs, 1)));
+    HIP_TRY(D->pc_map.alloc(4 * (int64_t)D->C_total));
+    a.pcell = D->pcell.as<int32_t>();
+    a.pf_ptr = D->pf_ptr.as<int32_t>();
+    a.pnb = D->pnb.as<int32_t>();
+    a.pwf = D->pwf.as<float>();
+    a.pwa = D->pwa.as<float>();
+    a.ptask = D->ptask.as<int32_t>();
+    a.pc_map = D->pc_map.as<int32_t>();
+    HIP_TRY(sweep::launch_fill_i32(a.pf_ptr + D->n_pc, 1, (int32_t)D->n_pf, s));
+    for (int m = 0; m < n_meshes; ++m) HIP_TRY(sweep::launch_plist(a, md[m], m, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the local counts and scans are released here
+  }
   std::vector<int32_t> depth(n_units);
   int32_t err = 0;
   Buf ue_d;  // row entries per unit (the sweep addresses a unit's rows with 32-bit offsets)
@@ -1152,7 +1243,8 @@ sweep_status_t sweep_dag_info(sweep_dag_t d, sweep_dag_info_t* info) {
   info->min_depth = mn;
   info->mean_depth = sum / d->units.size();
   const Buf* bufs[] = {&d->sched, &d->indeg, &d->lp, &d->lev_up, &d->lev_dn,
-                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->aperp_s, &d->vol_s, &d->bnd, &d->vol};
+                       &d->up_ptr, &d->dn_ptr, &d->up, &d->dn, &d->aperp, &d->aperp_s, &d->vol_s, &d->bnd, &d->vol,
+                       &d->pcell, &d->pf_ptr, &d->pnb, &d->pwf, &d->pwa, &d->ptask, &d->pc_map};
   int64_t b = 0;
   for (const Buf* x : bufs) b += (int64_t)x->bytes;
   info->device_bytes = b;
@@ -1248,11 +1340,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   if (!saved) HIP_TRY(d->phi_a.alloc(4 * DCG));
   if (periodic && n_inner > 1) HIP_TRY(d->phi_b.alloc(4 * DCG));
   if (warm) HIP_TRY(d->phi_w.alloc(4 * DCG));
-  if (periodic) {
-    HIP_TRY(d->pin.alloc(4 * DCG));
-    HIP_TRY(d->pin_prev.alloc(8 * CG));
-  }
-  if (tol) HIP_TRY(d->pin_prev2.alloc(8 * CG));
+  if (periodic) ST_TRY(alloc_periodic(d, G));
   const int64_t n_tot = (int64_t)d->n_meshes * G * 8;
   std::vector<double> tot_host(tol ? n_tot : 0);
   if (!saved || merge) {
@@ -1302,29 +1390,42 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   auto body = [&](hipStream_t st) -> sweep_status_t {
     if (warm)  // the previous call's final phi, before this call overwrites `saved`
       HIP_TRY(hipMemcpyAsync(d->phi_w.p, saved, 4 * DCG, hipMemcpyDeviceToDevice, st));
+    bool fresh = false;  // tsrc holds the sources run_prep just wrote
     for (int it = 0; it < n_outer; ++it) {
       const float* jprev_it = it > 0 ? ckpt(it - 1) : nullptr;
       float* prev = (warm && it == 0) ? d->phi_w.as<float>() : nullptr;
+      // the periodic inflow of the last two passes, summed over directions
+      // (nullptr: a pass without a previous one, zero inflow)
+      const double* psum_last = nullptr;
+      const double* psum_before = nullptr;
       for (int ps = 0; ps < n_inner; ++ps) {
         float* dst = store_passes ? (ps == n_inner - 1 ? phi_final : pass_slot(ps))
                      : ((n_inner - 1 - ps) % 2 == 0) ? phi_final : d->phi_b.as<float>();
         const float* jprev = merge ? (ps > 0 ? jm(ps - 1) : nullptr) : jprev_it;
         const bool final_pass = ps + 1 == n_inner;
-        if (ps == 0 || merge)
+        if (ps == 0 || merge) {
           ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
-        ST_TRY(run_sweep(d, false, p, G, prev, dst, periodic ? d->pin.as<float>() : nullptr, st));
+          fresh = true;
+        }
+        double* psum_ps = nullptr;
+        if (periodic && prev != nullptr) {
+          psum_ps = (ps % 2 == 0) ? d->psum_a.as<double>() : d->psum_b.as<double>();
+          ST_TRY(run_pin(d, false, G, prev, psum_ps, fresh, st));
+        }
+        psum_before = psum_last;
+        psum_last = psum_ps;
+        ST_TRY(run_sweep(d, false, p, G, nullptr, dst, nullptr, st));
         if (tol) {
           // the full reduction after every pass: E against the previous pass's
-          // per-cell inflow (double-buffered sums), then the totals read back
-          double* sums[2] = {d->pin_prev.as<double>(), d->pin_prev2.as<double>()};
+          // inflow, then the totals read back
           sweep::ReduceArgs q = r;
           q.phi = dst;
-          q.pin = d->pin.as<float>();
-          q.pin_prev = ps > 0 ? sums[(ps + 1) % 2] : nullptr;
-          q.pin_sum = sums[ps % 2];
+          q.pc_map = d->pc_map.as<int32_t>();
+          q.psum = psum_last;
+          q.psum_prev = psum_before;
+          q.with_e = ps > 0 ? 1 : 0;
           q.jsum_prev = jprev;
           q.jsum = ckpt(it);
-          q.last = 1;
           {
             ProfScope pr("reduce", st);
             HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
@@ -1347,17 +1448,12 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
           prev = dst;
           continue;
         }
-        if (!final_pass && (merge || periodic)) {
-          // bookkeeping of a pass before the last: the per-cell periodic inflow (for E)
-          // and, merged, the direction sums that feed the next pass's source
+        if (!final_pass && merge) {
+          // the direction sums that feed the next merged pass's source
           sweep::ReduceArgs q = r;
           q.phi = dst;
-          q.pin = periodic ? d->pin.as<float>() : nullptr;
-          q.pin_prev = nullptr;
-          q.pin_sum = periodic ? d->pin_prev.as<double>() : nullptr;
           q.jsum_prev = jprev;
-          q.jsum = merge ? jm(ps) : nullptr;
-          q.last = merge ? 1 : 0;
+          q.jsum = jm(ps);
           HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
         }
         prev = dst;
@@ -1365,12 +1461,12 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
       if (tol) continue;  // the last pass's reduction is done
       sweep::ReduceArgs q = r;
       q.phi = phi_final;
-      q.pin = periodic ? d->pin.as<float>() : nullptr;
-      q.pin_prev = (periodic && n_inner > 1) ? d->pin_prev.as<double>() : nullptr;
-      q.pin_sum = nullptr;
+      q.pc_map = periodic ? d->pc_map.as<int32_t>() : nullptr;
+      q.psum = psum_last;
+      q.psum_prev = psum_before;
+      q.with_e = periodic && n_inner > 1 ? 1 : 0;
       q.jsum_prev = merge ? (n_inner > 1 ? jm(n_inner - 2) : nullptr) : jprev_it;
       q.jsum = merge ? jm(n_inner - 1) : ckpt(it);
-      q.last = 1;
       {
         ProfScope ps("reduce", st);
         HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
@@ -1389,7 +1485,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
                                  pkey(totals), pkey(saved), (uint64_t)saved_bytes};
     opts_key(key, p);
-    for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pin, &d->pin_prev, &d->pin_prev2,
+    for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pbase, &d->psum_a, &d->psum_b,
                          &d->jsum_a, &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->crec, &d->out_s,
                          &d->mesh_blk_base, &d->blk_mesh, &d->blk_cell0})
       key.push_back(pkey(b->p));
@@ -1438,7 +1534,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
   if (p.n_scat > 1 && P > 1) HIP_TRY(d->xpass.alloc(4 * DCG * (P - 1)));
   if (P > 1) HIP_TRY(d->lam_b.alloc(4 * DCG));
-  if (periodic) HIP_TRY(d->pin.alloc(4 * DCG));
+  if (periodic) ST_TRY(alloc_periodic(d, G));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
@@ -1460,29 +1556,35 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                    ckpt(p.n_scat - 1), p.albedo, G, d->C_total,
                                    d->gsrc.as<float>(), d->dk64.as<double>(),
                                    d->de64.as<double>(), d->flag.as<int32_t>(), st));
+    bool fresh = false;  // tsrc holds the sources run_prep (or the clear) just wrote
     for (int it = p.n_scat - 1; it >= 0; --it) {
       const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
       if (it != p.n_scat - 1) {
         ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
-        for (int ps = 0; ps < P; ++ps)
-          ST_TRY(run_sweep(d, false, p, G, ps > 0 ? xp(it, ps - 1) : nullptr, xp(it, ps),
-                           periodic ? d->pin.as<float>() : nullptr, st));
+        fresh = true;
+        for (int ps = 0; ps < P; ++ps) {
+          if (ps > 0) ST_TRY(run_pin(d, false, G, xp(it, ps - 1), nullptr, fresh, st));
+          ST_TRY(run_sweep(d, false, p, G, nullptr, xp(it, ps), nullptr, st));
+        }
       }
       for (int ps = P - 1; ps >= 0; --ps) {
         const bool loss_pass = ps == P - 1;
-        // pass ps's lambda; the periodic outflow entries of the downwind rows take
-        // the later pass's lambda at their partners (the adjoint of the forward
-        // pass's periodic inflow), so the two alternate between two buffers
+        // pass ps's lambda; through its periodic outflow faces a task takes the later
+        // pass's lambda at the partners (the adjoint of the forward pass's periodic
+        // inflow, folded into the sources), so the two alternate between two buffers
         float* lam_ps = ((P - 1 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>();
         const float* lam_next = loss_pass ? nullptr
                                           : (((P - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
         // the passes before the last have no source of their own: the denominators
         // of the loss pass stand and only the sources are cleared
-        if (loss_pass)
+        if (loss_pass) {
           ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
-        else
+        } else {
           HIP_TRY(sweep::launch_fill_f32(d->tsrc.as<float>(), d->T * G, 0.0f, st));
-        ST_TRY(run_sweep(d, true, p, G, lam_next, lam_ps, nullptr, st));
+          fresh = true;
+          ST_TRY(run_pin(d, true, G, lam_next, nullptr, fresh, st));
+        }
+        ST_TRY(run_sweep(d, true, p, G, nullptr, lam_ps, nullptr, st));
         sweep::AdjReduceArgs q{};
         q.D = d->D;
         q.G = G;
@@ -1517,7 +1619,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                  pkey(dL_dkappa), pkey(dL_demission)};
     opts_key(key, p);
     for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->lam_b,
-                         &d->pin, &d->tden, &d->tsrc, &d->crec, &d->out_s})
+                         &d->pbase, &d->tden, &d->tsrc, &d->crec, &d->out_s})
       key.push_back(pkey(b->p));
     ST_TRY(run_graph(d, key, s, body));
   }

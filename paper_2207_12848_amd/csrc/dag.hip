@@ -985,6 +985,62 @@ __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5)))
   }
 }
 
+// Periodic half-faces of every cell of mesh M (neighbour code -(nb + 2)).
+__global__ void k_pcount(DagBuildArgs a, MeshDev M) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M.n_cells) return;
+  int n = 0;
+  for (int64_t f = M.face_ptr[c]; f < M.face_ptr[c + 1]; ++f) n += M.fcode[f] < -1 ? 1 : 0;
+  a.npf[M.cell_off + c] = n;
+  a.pflag[M.cell_off + c] = n > 0 ? 1 : 0;
+}
+
+// The periodic cells of mesh M in cell order with their periodic half-faces in
+// face order: partner, the inflow and outflow weight of every direction (the
+// classes and weights k_fill gives the row entries), and the cell's task in
+// every direction.
+__global__ void k_plist(DagBuildArgs a, MeshDev M, int mesh) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= M.n_cells) return;
+  const int gc = M.cell_off + c;
+  const int64_t pc = a.pc_off[gc];
+  const bool per = a.pc_off[gc + 1] > pc;
+  a.pc_map[gc] = per ? (int)pc : -1;
+  if (!per) return;
+  a.pcell[pc] = gc;
+  a.pf_ptr[pc] = (int32_t)a.pf_off[gc];
+  int64_t j = a.pf_off[gc];
+  for (int64_t f = M.face_ptr[c]; f < M.face_ptr[c + 1]; ++f) {
+    const int code = M.fcode[f];
+    if (code >= -1) continue;
+    a.pnb[j] = M.cell_off + (-(code + 2));
+    for (int d = 0; d < a.D; ++d) {
+      const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces;
+      float fw, aw;
+      if (a.scheme == SWEEP_SCHEME_ALIGNED) {
+        // inflow: the neighbour's share through the twin; outflow: the cell's own
+        const float wi = wf[M.face_twin[f]];
+        const float ws = wf[f];
+        fw = isnan(wi) ? 0.0f : wi;
+        aw = isnan(ws) ? 0.0f : ws;
+      } else {
+        const float ws = wf[f];
+        const bool has = !isnan(ws);
+        const bool in = has && signbit(ws);
+        fw = in ? fabsf(ws) : 0.0f;
+        aw = has && !in ? fabsf(ws) : 0.0f;
+      }
+      a.pwf[(int64_t)d * a.n_pf + j] = fw;
+      a.pwa[(int64_t)d * a.n_pf + j] = aw;
+    }
+    ++j;
+  }
+  for (int d = 0; d < a.D; ++d) {
+    const Unit U = a.units[mesh * a.D + d];
+    a.ptask[(int64_t)d * a.n_pc + pc] = (int32_t)(U.task_base + a.inv[U.task_base + c]);
+  }
+}
+
 // First row entry of every level (per unit), so a level's rows form one block.
 __global__ void k_level_entries(DagBuildArgs a) {
   const Unit U = a.units[blockIdx.x];
@@ -1191,6 +1247,18 @@ hipError_t launch_fill(const DagBuildArgs& a, int32_t n_blocks, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<true>, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
   else
     hipLaunchKernelGGL(k_fill<false>, dim3(n_blocks), dim3(kFillBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcount(const DagBuildArgs& a, const MeshDev& m, hipStream_t s) {
+  if (m.n_cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pcount, dim3(grid1d(m.n_cells, 256)), dim3(256), 0, s, a, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_plist(const DagBuildArgs& a, const MeshDev& m, int32_t mesh, hipStream_t s) {
+  if (m.n_cells <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_plist, dim3(grid1d(m.n_cells, 256)), dim3(256), 0, s, a, m, mesh);
   return hipGetLastError();
 }
 

@@ -90,6 +90,21 @@ struct DagBuildArgs {
   int32_t* err;    // set to 1 if a unit could not be fully ordered
   int64_t* lev_up;  // per unit level table: first upwind-row entry of each level
   int64_t* lev_dn;
+  // periodic half-faces (the lists that fold the coupling between periodic passes
+  // into the sources, built after the rows; see PinArgs)
+  int32_t* npf;      // [C_total + 1] periodic half-faces of every cell (scan input)
+  int32_t* pflag;    // [C_total + 1] 1 for a cell with periodic half-faces (scan input)
+  const int64_t* pf_off;  // [C_total + 1] exclusive scan of npf
+  const int64_t* pc_off;  // [C_total + 1] exclusive scan of pflag
+  int32_t n_pc;      // periodic cells
+  int64_t n_pf;      // periodic half-faces
+  int32_t* pcell;    // [n_pc] global cell id
+  int32_t* pf_ptr;   // [n_pc + 1] first half-face of each periodic cell
+  int32_t* pnb;      // [n_pf] partner cell across the half-face (global id)
+  float* pwf;        // [D][n_pf] inflow weight (0 where the half-face is no inflow)
+  float* pwa;        // [D][n_pf] outflow weight (0 where the half-face is no outflow)
+  int32_t* ptask;    // [D][n_pc] task of (direction, periodic cell)
+  int32_t* pc_map;   // [C_total] periodic cell index of every cell, -1 for the others
   int32_t* len_up;  // [T+1] row lengths in schedule order (scan input)
   int32_t* len_dn;  // [T+1]
   int64_t* up_ptr;  // [T+1]
@@ -169,8 +184,10 @@ struct ReduceArgs {
   const int32_t* mesh_off;   // [n_meshes+1]
   const int32_t* mesh_cells;  // [n_meshes]
   const float* phi;          // [D][C][G]
-  const float* pin;          // [D][C][G] or nullptr
-  const double* pin_prev;    // [C][G] or nullptr
+  const int32_t* pc_map;     // [C_total] periodic cell index or -1 (nullptr: no periodic inflow)
+  const double* psum;        // [n_pc][G] periodic inflow of the pass summed over directions
+  const double* psum_prev;   // [n_pc][G] the same of the pass before, or nullptr (zero inflow)
+  int32_t with_e;            // 1: E of the pass against the pass before (sec. 2.7)
   const float2* bnd;         // per task, cell order
   const float* aperp;        // per task, cell order
   int32_t law;
@@ -182,10 +199,32 @@ struct ReduceArgs {
   float* jsum;               // [C][G] out
   float* J;                  // out
   float* absorbed;           // out
-  double* pin_sum;           // [C][G] out (periodic pass bookkeeping) or nullptr
   double* partial;           // [n_blocks][G][9]
   int32_t cells_per_block;
-  int32_t last;              // 1: final pass (write J/absorbed/totals), 0: only pin_sum
+};
+
+// Periodic coupling of a pass, folded into its sources: a task of a periodic
+// cell takes, through each periodic half-face that carries radiation into it
+// (forward) or out of it (adjoint), w times the other pass's value at the
+// partner cell (forward: the previous pass's exit value; adjoint: the later
+// pass's lambda).  These values are final before the pass starts, so the sum
+// (an FP32 FMA chain in face order) is added to the task's source beforehand
+// and the sweep itself reads no other pass.
+struct PinArgs {
+  int32_t D;
+  int32_t G;
+  int64_t C_total;
+  int32_t n_pc;
+  int64_t n_pf;
+  const int32_t* pf_ptr;   // [n_pc + 1]
+  const int32_t* pnb;      // [n_pf]
+  const float* pw;         // [D][n_pf] the pass's weights (inflow or outflow)
+  const int32_t* ptask;    // [D][n_pc]
+  const float* other;      // [D][C_total][G] the other pass's values
+  float* tsrc;             // [T][G] sources of the pass
+  float* pbase;            // [D][n_pc][G] the periodic tasks' own sources
+  int32_t capture;         // 1: tsrc holds the own sources (save them), 0: take pbase
+  double* psum;            // [n_pc][G] out: sum over directions, or nullptr
 };
 
 struct AdjReduceArgs {
@@ -260,6 +299,9 @@ hipError_t launch_sweep_fwd(const SweepArgs& a, int32_t gn, int32_t grid, int32_
 hipError_t launch_sweep_adj(const SweepArgs& a, int32_t gn, int32_t grid, int32_t block,
                             size_t lds_bytes, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, int32_t n_blocks, hipStream_t s);
+hipError_t launch_pin(const PinArgs& a, hipStream_t s);
+hipError_t launch_pcount(const DagBuildArgs& a, const MeshDev& m, hipStream_t s);
+hipError_t launch_plist(const DagBuildArgs& a, const MeshDev& m, int32_t mesh, hipStream_t s);
 hipError_t launch_totals(const double* partial, const int32_t* mesh_blk_base, int32_t n_meshes,
                          int32_t G, double* totals, hipStream_t s);
 hipError_t launch_adj_init(const float* dJ, const float* dA, const float* kappa, const float* vol,

@@ -841,6 +841,38 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
   if (bad != 0) atomicOr(a.flag, bad);
 }
 
+// Periodic coupling folded into the sources (PinArgs): one thread per
+// (periodic cell, group), every direction in turn.
+__global__ __launch_bounds__(256) void k_pin(PinArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)a.n_pc * a.G) return;
+  const int pc = (int)(i / a.G);
+  const int g = (int)(i % a.G);
+  const int f0 = a.pf_ptr[pc], f1 = a.pf_ptr[pc + 1];
+  double pn = 0.0;
+  for (int d = 0; d < a.D; ++d) {
+    const float* w = a.pw + (int64_t)d * a.n_pf;
+    const float* o = a.other + (int64_t)d * a.C_total * a.G + g;
+    float s = 0.0f;
+    for (int f = f0; f < f1; ++f) {
+      const float wf = w[f];
+      if (wf != 0.0f) s = __builtin_fmaf(wf, o[(int64_t)a.pnb[f] * a.G], s);
+    }
+    const int64_t t = a.ptask[(int64_t)d * a.n_pc + pc];
+    const int64_t b = ((int64_t)d * a.n_pc + pc) * a.G + g;
+    float base;
+    if (a.capture) {
+      base = a.tsrc[t * a.G + g];
+      a.pbase[b] = base;
+    } else {
+      base = a.pbase[b];
+    }
+    a.tsrc[t * a.G + g] = base + s;
+    pn += (double)s;
+  }
+  if (a.psum != nullptr) a.psum[i] = pn;
+}
+
 // ----------------------------------------------------------------------- reductions
 constexpr int kRedBlock = 256;
 constexpr int kNPart = 9;
@@ -865,21 +897,21 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(ReduceArgs a) {
     const double V = (double)a.vol[c];
     const double kap = (double)a.kappa[cg];
     const bool exp_law = a.law == SWEEP_LAW_EXP;
-    double js = 0.0, pn = 0.0, esc = 0.0, pout = 0.0;
+    double js = 0.0, esc = 0.0, pout = 0.0;
     for (int d = 0; d < a.D; ++d) {
       // phi holds the exit flux density x (phi itself under the upwind law)
       const double ph = (double)a.phi[d * stride + cg];
-      if (a.pin != nullptr) pn += (double)a.pin[d * stride + cg];
-      if (a.last) {
-        const int64_t t = a.units[m * a.D + d].task_base + lc;
-        const float2 b = a.bnd[t];
-        esc += (double)b.x * ph;
-        pout += (double)b.y * ph;
-        js += exp_law ? ph * exp_r((double)a.aperp[t], kap * V) : ph;
-      }
+      const int64_t t = a.units[m * a.D + d].task_base + lc;
+      const float2 b = a.bnd[t];
+      esc += (double)b.x * ph;
+      pout += (double)b.y * ph;
+      js += exp_law ? ph * exp_r((double)a.aperp[t], kap * V) : ph;
     }
-    if (a.pin_sum != nullptr) a.pin_sum[cg] = pn;
-    if (a.last) {
+    // the periodic inflow of the pass (and of the pass before), summed over
+    // directions when the pass's sources were folded
+    const int pc = a.pc_map != nullptr ? a.pc_map[c] : -1;
+    const double pn = pc >= 0 && a.psum != nullptr ? a.psum[(int64_t)pc * G + g] : 0.0;
+    {
       const double ka = (1.0 - (double)a.albedo) * kap;
       const double ks = (double)a.albedo * kap;
       const double ab = ka * V * js;
@@ -893,8 +925,8 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(ReduceArgs a) {
       v[3] = pn;
       v[4] = pout;
       v[5] = ks * V * (jp - js);
-      if (a.pin_prev != nullptr) {
-        const double po = a.pin_prev[cg];
+      if (a.with_e) {
+        const double po = pc >= 0 && a.psum_prev != nullptr ? a.psum_prev[(int64_t)pc * G + g] : 0.0;
         const double den = pn + po;
         v[6] = den > 0.0 ? fabs(pn - po) / den : 0.0;
         v[7] = fabs(pn - po);
@@ -902,7 +934,6 @@ __global__ __launch_bounds__(kRedBlock) void k_reduce(ReduceArgs a) {
       }
     }
   }
-  if (!a.last) return;
 #pragma unroll
   for (int k = 0; k < kNPart; ++k) part[i][k] = v[k];
   __syncthreads();
@@ -1087,6 +1118,13 @@ hipError_t set_sweep_lds_limit(int32_t bytes) {
   if ((e = set_lds_gn<2>(bytes)) != hipSuccess) return e;
   if ((e = set_lds_gn<3>(bytes)) != hipSuccess) return e;
   return set_lds_gn<4>(bytes);
+}
+
+hipError_t launch_pin(const PinArgs& a, hipStream_t s) {
+  const int64_t n = (int64_t)a.n_pc * a.G;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pin, dim3(grid1d(n, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, int32_t n_blocks, hipStream_t s) {

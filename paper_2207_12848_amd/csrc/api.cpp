@@ -590,9 +590,10 @@ sweep_status_t run_pin(sweep_dag_t d, bool adjoint, int32_t G, const float* othe
   return SWEEP_OK;
 }
 
-// One sweep of every unit (after run_prep).
-sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t G,
-                         const float* phi_prev, float* out, float* pin, hipStream_t s) {
+// One sweep of every unit (after run_prep, and run_pin for a periodic pass with
+// another pass before it, forward, or after it, adjoint).
+sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t G, float* out,
+                         hipStream_t s) {
   sweep::SweepArgs a{};
   a.units = d->units_d.as<Unit>();
   a.sched = d->sched.as<int32_t>();
@@ -601,11 +602,9 @@ sweep_status_t run_sweep(sweep_dag_t d, bool reverse, const FwdPlan& p, int32_t 
   a.n_ent = reverse ? d->n_dn : d->n_up;
   a.tden = d->tden.as<float>();
   a.tsrc = d->tsrc.as<float>();
-  a.phi_prev = phi_prev;
   a.out = out;
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   a.out_s = d->out_s.as<float>();
-  a.pin = pin;
   a.C_total = d->C_total;
   a.G = G;
   a.D = d->D;
@@ -1414,7 +1413,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
         }
         psum_before = psum_last;
         psum_last = psum_ps;
-        ST_TRY(run_sweep(d, false, p, G, nullptr, dst, nullptr, st));
+        ST_TRY(run_sweep(d, false, p, G, dst, st));
         if (tol) {
           // the full reduction after every pass: E against the previous pass's
           // inflow, then the totals read back
@@ -1564,7 +1563,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
         fresh = true;
         for (int ps = 0; ps < P; ++ps) {
           if (ps > 0) ST_TRY(run_pin(d, false, G, xp(it, ps - 1), nullptr, fresh, st));
-          ST_TRY(run_sweep(d, false, p, G, nullptr, xp(it, ps), nullptr, st));
+          ST_TRY(run_sweep(d, false, p, G, xp(it, ps), st));
         }
       }
       for (int ps = P - 1; ps >= 0; --ps) {
@@ -1584,7 +1583,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
           fresh = true;
           ST_TRY(run_pin(d, true, G, lam_next, nullptr, fresh, st));
         }
-        ST_TRY(run_sweep(d, true, p, G, nullptr, lam_ps, nullptr, st));
+        ST_TRY(run_sweep(d, true, p, G, lam_ps, st));
         sweep::AdjReduceArgs q{};
         q.D = d->D;
         q.G = G;
@@ -1666,11 +1665,11 @@ sweep_status_t sweep_tune(sweep_dag_t d, int32_t G, const float* kappa, const fl
       q.ring = ring;
       q.use_graph = 0;
       // one untimed sweep, then `reps` timed ones
-      st = run_sweep(d, false, q, G, nullptr, d->phi_a.as<float>(), nullptr, s);
+      st = run_sweep(d, false, q, G, d->phi_a.as<float>(), s);
       if (st != SWEEP_OK) break;
       if (hipEventRecord(e0, s) != hipSuccess) { st = fail(SWEEP_ERR_HIP, "hipEventRecord"); break; }
       for (int r = 0; r < reps && st == SWEEP_OK; ++r)
-        st = run_sweep(d, false, q, G, nullptr, d->phi_a.as<float>(), nullptr, s);
+        st = run_sweep(d, false, q, G, d->phi_a.as<float>(), s);
       if (st != SWEEP_OK) break;
       float ms = 0.0f;
       if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

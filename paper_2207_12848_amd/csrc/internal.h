@@ -135,11 +135,10 @@ struct SweepArgs {
   const int2* ent;         // up (forward) or dn (adjoint)
   int64_t n_ent;           // entries in `ent`
   const float* tden;       // [T][G] schedule order: Aperp + kappa V
-  const float* tsrc;       // [T][G] schedule order: source of the task
-  const float* phi_prev;   // forward: [D][C][G] previous periodic pass, or nullptr (zero inflow)
+  const float* tsrc;       // [T][G] schedule order: source of the task (periodic
+                           // coupling included, see PinArgs)
   float* out;              // phi (forward) or lambda (adjoint), [D][C][G]
   float* out_s;            // the same values in schedule order, [T][G]
-  float* pin;              // forward, periodic: inflow through periodic faces per task, or nullptr
   int64_t C_total;
   int32_t G;       // group stride
   int32_t g0;      // first group handled by this launch (see n_chunks)

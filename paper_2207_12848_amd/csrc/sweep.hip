@@ -116,9 +116,7 @@ struct UnitBufs {
   __amdgpu_buffer_rsrc_t den;    // [slot][G] at group g0 of the unit's first task
   __amdgpu_buffer_rsrc_t src;
   __amdgpu_buffer_rsrc_t outs;   // out_s at group g0 of the unit's first task: [slot][G]
-  __amdgpu_buffer_rsrc_t prev;   // phi_prev of this direction at group g0: [cell][G]
   __amdgpu_buffer_rsrc_t out;    // out of this direction at group g0: [cell][G]
-  __amdgpu_buffer_rsrc_t pin;    // pin of this direction at group g0: [cell][G]
   int64_t ue0;                   // first row entry of the unit
 };
 
@@ -197,11 +195,10 @@ __device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B
   ld_gn<GN, kStream>(B.src, vo, so, P.src);
 }
 
-// Inflow of one task per group (and the periodic part of it).
+// Inflow of one task per group.
 template <int GN>
 struct Inflow {
   float acc[GN];
-  float pin[GN];
 };
 
 // Schedule positions whose results are in the LDS ring while a step is solved,
@@ -227,7 +224,7 @@ __device__ __forceinline__ Window window(int k0, int k1, int R) {
   return w;
 }
 
-template <int GN, bool PIN>
+template <int GN>
 __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& B,
                                             const TaskRec<GN>& t, int k, const Inflow<GN>& in,
                                             float* ring) {
@@ -241,14 +238,13 @@ __device__ __forceinline__ void finish_task(const SweepArgs& a, const UnitBufs& 
   }
   st_gn<GN, kStream>(v, B.out, oc);
   st_gn<GN>(v, B.outs, ok);
-  if (PIN) st_gn<GN, kStream>(in.pin, B.pin, oc);
 }
 
 // The common step: at most one task per thread and every inflow in LDS.  Every
 // memory operation is issued unconditionally (a thread without a task writes
 // the sink slot and stores past the buffers' ends, which are dropped), so each
 // step issues a fixed number of vector-memory operations.
-template <int GN, bool PIN>
+template <int GN>
 __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& B,
                                             const TaskRec<GN>& t, int k, const Inflow<GN>& in,
                                             float* ring, float* sink) {
@@ -264,7 +260,6 @@ __device__ __forceinline__ void finish_fast(const SweepArgs& a, const UnitBufs& 
   }
   st_gn<GN, kStream>(v, B.out, oc);
   st_gn<GN>(v, B.outs, ok);
-  if (PIN) st_gn<GN, kStream>(in.pin, B.pin, oc);
 }
 
 // GN consecutive groups of one task from a [slot][G] array (one load; offsets
@@ -290,26 +285,27 @@ __device__ __forceinline__ void ld_groups(__amdgpu_buffer_rsrc_t r, uint32_t off
 // Inflow of one task in row order, in batches of 8 entries (the row's entries
 // from the LDS staging buffer, or from global memory for levels that were not
 // staged).  An entry inside the window reads its ring slot; an older result is
-// loaded from out_s (stored at least one barrier earlier by this workgroup) and
-// a periodic inflow -(partner + 1) from the previous pass (PER; zero without
-// one).  Every load of a batch is issued before the first is used, so a batch
+// loaded from out_s (stored at least one barrier earlier by this workgroup); a
+// periodic entry -(partner + 1) adds zero (the coupling between periodic passes
+// is folded into the sources).  Every load of a batch is issued before the first
+// is used, so a batch
 // costs one memory round trip whatever its mix.  The sum is the same sequence
 // of fused multiply-adds in row order on every path; entries past the row's end
 // (the rest of the batch) are skipped.
-template <int GN, bool PER, bool STAGED>
+template <int GN, bool STAGED>
 __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs& B,
                                              const TaskRec<GN>& t, const int2* stg, uint32_t eoff,
                                              const float* ring, Window w) {
   Inflow<GN> in;
 #pragma unroll
-  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
+  for (int g = 0; g < GN; ++g) in.acc[g] = 0.0f;
   for (int rb = t.r0; rb < t.r1; rb += 8) {
     int2 en[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       en[q] = STAGED ? stg[rb + q] : ld_b64(B.ent, 8u * (uint32_t)(rb + q), eoff);
     const int nr = t.r1 - rb;  // entries of the row in this batch
-    float gv[8][GN], pv[8][GN], rv[8][GN];
+    float gv[8][GN], rv[8][GN];
     bool inw[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -318,7 +314,6 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
       inw[q] = w.has(p);  // never for p < 0 (the window starts at lo >= 0)
       const bool glob = val && !inw[q] && p >= 0;
       ld_groups<GN>(B.outs, glob ? 4u * (uint32_t)(p * a.G) : kOob, gv[q]);
-      if (PER) ld_groups<GN>(B.prev, val && p < 0 ? 4u * (uint32_t)((-p - 1) * a.G) : kOob, pv[q]);
       const float* v = ring + (p & a.ring_mask) * GN;
 #pragma unroll
       for (int g = 0; g < GN; ++g) rv[q][g] = v[g];
@@ -326,13 +321,11 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const bool val = q < nr;
-      const bool per = PER && en[q].x < 0;
       const float y = __int_as_float(en[q].y);
 #pragma unroll
       for (int g = 0; g < GN; ++g) {
-        const float x = inw[q] ? rv[q][g] : (per ? pv[q][g] : gv[q][g]);
+        const float x = inw[q] ? rv[q][g] : gv[q][g];
         in.acc[g] = val ? __builtin_fmaf(y, x, in.acc[g]) : in.acc[g];
-        if (PER) in.pin[g] = (val && per) ? __builtin_fmaf(y, x, in.pin[g]) : in.pin[g];
       }
     }
   }
@@ -343,15 +336,15 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
 // the entries' addresses are relative to), in batches of 8 with the same
 // sequence of fused multiply-adds in row order as gather().  The entries of a
 // batch past the row's end (the next row's, or padding naming the zero slot)
-// take factor 0, and a non-periodic entry adds 0 to the periodic part; adding
-// +-0 x (x finite) leaves a sum that starts at +0 and only grows unchanged, so
-// the result is gather()'s bit for bit.
-template <int GN, bool PIN>
+// take factor 0 (a periodic entry names the zero slot); adding +-0 x (x finite)
+// leaves a sum that starts at +0 and only grows unchanged, so the result is
+// gather()'s bit for bit.
+template <int GN>
 __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int2* stg,
                                                  const unsigned char* lds) {
   Inflow<GN> in;
 #pragma unroll
-  for (int g = 0; g < GN; ++g) in.acc[g] = in.pin[g] = 0.0f;
+  for (int g = 0; g < GN; ++g) in.acc[g] = 0.0f;
   for (int rb = t.r0; rb < t.r1; rb += 8) {
     int2 en[8];
 #pragma unroll
@@ -380,14 +373,8 @@ __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const float ya = __builtin_fabsf(y[q]);
-      // factor of a periodic inflow: -y clamped to [0, FLT_MAX]
-      const float yp = PIN ? __builtin_amdgcn_fmed3f(-y[q], 0.0f, 3.40282347e38f) : 0.0f;
 #pragma unroll
-      for (int g = 0; g < GN; ++g) {
-        in.acc[g] = __builtin_fmaf(ya, rv[q][g], in.acc[g]);
-        if (PIN) in.pin[g] = __builtin_fmaf(yp, rv[q][g], in.pin[g]);
-      }
+      for (int g = 0; g < GN; ++g) in.acc[g] = __builtin_fmaf(y[q], rv[q][g], in.acc[g]);
     }
   }
   return in;
@@ -400,8 +387,7 @@ __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int
 // tasks are independent.  Each step's row block and each thread's task record
 // are loaded NS - 1 steps ahead into registers (NS rotating sets).  Two steps
 // ahead, the holder of each staged entry whose upwind result lies outside the
-// LDS ring window (or that is a periodic inflow) loads that value from global
-// memory; the step before it is solved the holder copies the value into the
+// LDS ring window loads that value from global memory; the step before it is solved the holder copies the value into the
 // entry's own slot of the LDS value area and rewrites the entry to name its
 // slot (ring slot or prefetched slot).  The solve then reads only LDS, and no
 // load is waited for on the critical path of a common step.
@@ -412,13 +398,11 @@ __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int
 //
 // LDS: [values: ring R slots | zero | sink | 2 x SE prefetched slots] x GN floats,
 // then two staging buffers of SE + 8 entries.
-// PER: periodic entries (a negative position -(partner + 1)) take the partner's
-// value in phi_prev, the previous forward pass or, in the adjoint, the later
-// pass's lambda (else zero).  The forward sweep with PER also stores each task's
-// periodic inflow (pin).
-template <int GN, bool REVERSE, bool PER, int CH>
+// Periodic entries (a negative position -(partner + 1)) name the zero slot: the
+// other pass's values through the periodic faces are folded into the sources
+// before the launch.
+template <int GN, bool REVERSE, int CH>
 __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
-  constexpr bool PIN = PER && !REVERSE;
   constexpr int NS = 3;
   extern __shared__ __align__(16) unsigned char smem[];
   float* vals = reinterpret_cast<float*>(smem);
@@ -481,9 +465,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
     B.den = rsrc(a.tden + tb * a.G + g0, 4 * ((int64_t)C * a.G - g0));
     B.src = rsrc(a.tsrc + tb * a.G + g0, 4 * ((int64_t)C * a.G - g0));
     B.outs = rsrc(a.out_s + tb * a.G + g0, 4 * ((int64_t)C * a.G - g0));
-    B.prev = rsrc(a.phi_prev == nullptr ? nullptr : a.phi_prev + obase, 4 * ((int64_t)C * a.G - g0));
     B.out = rsrc(a.out + obase, 4 * ((int64_t)C * a.G - g0));
-    B.pin = rsrc(a.pin == nullptr ? nullptr : a.pin + obase, 4 * ((int64_t)C * a.G - g0));
     // step solved at iteration s (iterations past the last one repeat it: their
     // loads are issued and never used)
     auto info = [&](int s) -> LevelInfo {
@@ -499,25 +481,26 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       return L;
     };
     Pref<GN, CH> P[NS];
-    float F[CH][GN], FP[CH][GN];  // prefetched values of the thread's staged entries
+    float F[CH][GN];  // prefetched values of the thread's staged entries
     TaskRec<GN> cur;
     LevelInfo curL;
     // results final at the last prefetch: forward, positions below vis; adjoint,
     // positions from vis up
     int vis = REVERSE ? 0x7fffffff : 0, visF = vis;
+    // (a periodic entry, p < 0, is never loaded: it names the zero slot)
     auto prefetchable = [&](int p, const Window& w, int v) -> bool {
-      return !w.has(p) && (p < 0 || (REVERSE ? p >= v : p < v));
+      return p >= 0 && !w.has(p) && (REVERSE ? p >= v : p < v);
     };
     auto issue = [&](int s, Pref<GN, CH>& Q) {
       Q.L = info(s);
       issue_pref<GN, CH>(a, B, tid, nthr, Q);
     };
-    // the older results and periodic inflows of the thread's staged entries of
-    // step s (one load per entry; the others read past the buffers' ends)
+    // the older results of the thread's staged entries of step s (one load per
+    // entry; the others read past the buffer's end)
     auto farload = [&](const Pref<GN, CH>& Q) {
       const LevelInfo& L = Q.L;
       const Window w = window<REVERSE>(L.k0, L.k1, R);
-      uint32_t po = 0, pp = 0;  // per entry: an older result / a periodic inflow to load
+      uint32_t po = 0;  // per entry: an older result to load
 #pragma unroll
       for (int i = 0; i < CH / 2; ++i) {
         if (2 * (wbase + i * nthr) >= L.nst) continue;  // no entry of this wavefront
@@ -525,9 +508,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
         for (int h = 0; h < 2; ++h) {
           const int idx = 2 * (tid + i * nthr) + h;
           const int p = h ? Q.st[i].z : Q.st[i].x;
-          const bool pf = idx < L.nst && prefetchable(p, w, vis);
-          po |= (uint32_t)(pf && p >= 0) << (2 * i + h);
-          pp |= (uint32_t)(pf && p < 0) << (2 * i + h);
+          po |= (uint32_t)(idx < L.nst && prefetchable(p, w, vis)) << (2 * i + h);
         }
       }
       // the loads of a wavefront whose lanes need none are not issued
@@ -539,16 +520,6 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
             const int p = h ? Q.st[i].z : Q.st[i].x;
             ld_groups<GN>(B.outs, (po >> (2 * i + h)) & 1u ? 4u * (uint32_t)(p * a.G) : kOob,
                           F[2 * i + h]);
-          }
-      }
-      if (PER && __ballot(pp != 0u) != 0ull) {
-#pragma unroll
-        for (int i = 0; i < CH / 2; ++i)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int p = h ? Q.st[i].z : Q.st[i].x;
-            ld_groups<GN>(B.prev, (pp >> (2 * i + h)) & 1u ? 4u * (uint32_t)((-p - 1) * a.G) : kOob,
-                          FP[2 * i + h]);
           }
       }
       visF = vis;
@@ -573,10 +544,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int g = 0; g < GN; ++g) {
-              asm volatile("" ::"v"(F[2 * i + h][g]));
-              if (PER) asm volatile("" ::"v"(FP[2 * i + h][g]));
-            }
+            for (int g = 0; g < GN; ++g) asm volatile("" ::"v"(F[2 * i + h][g]));
           continue;
         }
 #pragma unroll
@@ -584,24 +552,23 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
           const int idx = idx0 + h;
           const int p = h ? v.z : v.x;
           const bool val = idx < L.nst;
-          // without periodic values (PER false) a periodic entry reads the zero slot
-          const bool pf = val && prefetchable(p, w, visF) && (PER || p >= 0);
+          // a periodic entry (p < 0) reads the zero slot
+          const bool pf = val && prefetchable(p, w, visF);
           const int fs = far0 + b * SE + idx;
           const bool inw = w.has(p);
           const int slot = !val ? zero : (inw ? (p & a.ring_mask) : (pf ? fs : zero));
-          if (val && !inw && !pf && (PER || p >= 0)) s_bad[b] = gbase + s;
+          if (val && !inw && !pf && p >= 0) s_bad[b] = gbase + s;
           if (pf) {
 #pragma unroll
-            for (int g = 0; g < GN; ++g)
-              vals[fs * GN + g] = (PER && p < 0) ? FP[2 * i + h][g] : F[2 * i + h][g];
+            for (int g = 0; g < GN; ++g) vals[fs * GN + g] = F[2 * i + h][g];
           }
           const int addr = slot * (GN * 4);
           if (h) {
             v.z = addr;
-            v.w = !val ? 0 : ((PIN && pf && p < 0) ? (v.w ^ (int)0x80000000) : v.w);
+            v.w = !val ? 0 : v.w;
           } else {
             v.x = addr;
-            v.y = !val ? 0 : ((PIN && pf && p < 0) ? (v.y ^ (int)0x80000000) : v.y);
+            v.y = !val ? 0 : v.y;
           }
         }
         if (idx0 < L.nst + 8) *reinterpret_cast<int4*>(dst + idx0) = v;
@@ -626,15 +593,15 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       vis = REVERSE ? k1 : k0;
       const bool bad = __builtin_amdgcn_readfirstlane(s_bad[s & 1]) == gbase + s;
       if (curL.nst == curL.ne && k1 - k0 <= nthr && !bad) {
-        const Inflow<GN> in = gather_lds<GN, PIN>(cur, stg, smem);
-        finish_fast<GN, PIN>(a, B, cur, k0 + tid, in, ring, sinkp);
+        const Inflow<GN> in = gather_lds<GN>(cur, stg, smem);
+        finish_fast<GN>(a, B, cur, k0 + tid, in, ring, sinkp);
         return;
       }
       for (int k = k0 + tid; k < k1; k += nthr) {
         TaskRec<GN> t;
         if (k == k0 + tid) t = cur; else load_rec<GN>(a, B, k, e0, t);
-        const Inflow<GN> in = gather<GN, PER, false>(a, B, t, nullptr, eoff, ring, w);
-        finish_task<GN, PIN>(a, B, t, k, in, ring);
+        const Inflow<GN> in = gather<GN, false>(a, B, t, nullptr, eoff, ring, w);
+        finish_task<GN>(a, B, t, k, in, ring);
       }
       // the uncommon steps leave no memory operation of theirs in flight, so the
       // waits of the common steps are counted exactly
@@ -669,31 +636,13 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   }
 }
 
-template <int GN, bool REVERSE, bool PER>
-hipError_t launch_sweep_p(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
-                          hipStream_t s) {
-  if ((block != 256 && block != 512 && block != 1024) || block > kSweepMaxBlock(GN))
-    return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_sweep<GN, REVERSE, PER, kStageCh>), dim3(grid), dim3(block), lds, s, a);
-  return hipGetLastError();
-}
-
-// Forward: the variant that stores the periodic inflow per task when asked to
-// (every forward pass with periodic boundaries is; its first pass has no
-// previous pass and reads zeros); a forward launch without it takes no values
-// from a previous pass.  Adjoint: the periodic variant when the later pass's
-// lambda is given.
 template <int GN, bool REVERSE>
 hipError_t launch_sweep_g(const SweepArgs& a, int32_t grid, int32_t block, size_t lds,
                           hipStream_t s) {
-  if (REVERSE) {
-    if (a.pin != nullptr) return hipErrorInvalidValue;
-    if (a.phi_prev != nullptr) return launch_sweep_p<GN, true, true>(a, grid, block, lds, s);
-    return launch_sweep_p<GN, true, false>(a, grid, block, lds, s);
-  }
-  if (a.pin != nullptr) return launch_sweep_p<GN, false, true>(a, grid, block, lds, s);
-  if (a.phi_prev != nullptr) return hipErrorInvalidValue;
-  return launch_sweep_p<GN, false, false>(a, grid, block, lds, s);
+  if ((block != 256 && block != 512 && block != 1024) || block > kSweepMaxBlock(GN))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_sweep<GN, REVERSE, kStageCh>), dim3(grid), dim3(block), lds, s, a);
+  return hipGetLastError();
 }
 
 template <bool REVERSE>
@@ -1097,19 +1046,17 @@ hipError_t launch_prep(const PrepArgs& a, int32_t n_blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int GN, bool REVERSE, bool PER>
+template <int GN, bool REVERSE>
 hipError_t set_lds_g(int32_t bytes) {
-  return hipFuncSetAttribute((const void*)k_sweep<GN, REVERSE, PER, kStageCh>,
+  return hipFuncSetAttribute((const void*)k_sweep<GN, REVERSE, kStageCh>,
                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 template <int GN>
 hipError_t set_lds_gn(int32_t bytes) {
   hipError_t e;
-  if ((e = set_lds_g<GN, false, false>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<GN, false, true>(bytes)) != hipSuccess) return e;
-  if ((e = set_lds_g<GN, true, false>(bytes)) != hipSuccess) return e;
-  return set_lds_g<GN, true, true>(bytes);
+  if ((e = set_lds_g<GN, false>(bytes)) != hipSuccess) return e;
+  return set_lds_g<GN, true>(bytes);
 }
 
 hipError_t set_sweep_lds_limit(int32_t bytes) {

@@ -134,7 +134,7 @@ typedef struct {
   int32_t n_dirs;
   int64_t n_cells;        /* all meshes */
   int64_t n_tasks;        /* n_cells * n_dirs */
-  int64_t n_up_entries;   /* inflow-face entries (graph edges + periodic inflows) */
+  int64_t n_up_entries;   /* upwind-row entries: graph edges seen from the downwind side */
   int64_t n_down_entries; /* graph edges seen from the upwind side */
   int32_t max_depth;      /* longest critical path (levels) over all (mesh, direction) */
   int32_t min_depth;

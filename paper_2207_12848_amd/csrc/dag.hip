@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
         float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces + T.f0;
         int32_t* row = STAGE ? srow + threadIdx.x * W : a.dnw + t * W;  // LDS: [dj][ci][W]
         int32_t* ovf = nullptr;
-        int nup = 0, npin = 0, ndn = 0, npout = 0;
+        int nup = 0, ndn = 0;
         double ap = 0.0, wall = 0.0, per = 0.0;
         for (int f = fb; f < fe; ++f) {
           const double* n = nrm + 3 * f;
@@ -175,7 +175,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
             if (nb < 0) wall += w;
             else if (periodic) {
               per += w;
-              ++npout;
             } else {
               if (ndn < W) {
                 row[ndn] = nb;
@@ -195,9 +194,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
             }
           } else if (sv < -a.eps) {
             ws = -w;
-            if (nb >= 0) {
-              if (periodic) ++npin; else ++nup;
-            }
+            if (nb >= 0 && !periodic) ++nup;
           }
           wf[f] = ws;
         }
@@ -205,14 +202,14 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
         if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
         for (int q = ndn; q < W; ++q) row[q] = -1;
         a.indeg[t] = nup;
-        a.rowlen_up[t] = nup + npin;
-        a.rowlen_dn[t] = ndn + npout;  // the adjoint's rows also hold the periodic outflows
+        a.rowlen_up[t] = nup;
+        a.rowlen_dn[t] = ndn;
         a.aperp[t] = (float)ap;
         a.bnd[t] = make_float2((float)wall, (float)per);
         mi = max(mi, nup);
         mo = max(mo, ndn);
-        eu += (unsigned long long)(nup + npin);
-        ed += (unsigned long long)(ndn + npout);
+        eu += (unsigned long long)nup;
+        ed += (unsigned long long)ndn;
       }
       if (STAGE) {
         __syncthreads();
@@ -324,7 +321,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_aligned(DagBuildArgs a)
       const int n = min(nout, a.n_aligned);
       const float wb = n > 0 ? (float)(ap / n) : 0.0f;
       int32_t* row = a.dnw + t * W;
-      int ndn = 0, npout = 0;
+      int ndn = 0;
       double wall = 0.0, per = 0.0;
       for (int f = fb; f < fe; ++f) {
         bool chosen = false;
@@ -336,7 +333,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count_aligned(DagBuildArgs a)
         if (nb < 0) wall += wb;
         else if (shift != nullptr && shift[f] != 0) {
           per += wb;
-          ++npout;
         } else {
           row[ndn++] = nb;
         }
@@ -344,9 +340,9 @@ __global__ __launch_bounds__(kCountThreads) void k_count_aligned(DagBuildArgs a)
       for (int q = ndn; q < W; ++q) row[q] = -1;
       a.aperp[t] = (float)ap;
       a.bnd[t] = make_float2((float)wall, (float)per);
-      a.rowlen_dn[t] = ndn + npout;  // the adjoint's rows also hold the periodic outflows
+      a.rowlen_dn[t] = ndn;
       mo = max(mo, ndn);
-      ed += (unsigned long long)(ndn + npout);
+      ed += (unsigned long long)ndn;
     }
   };
   if (T.in_lds) {
@@ -392,18 +388,18 @@ __global__ __launch_bounds__(kCountThreads) void k_count_in(DagBuildArgs a) {
     const int64_t fb = M.face_ptr[c], fe = M.face_ptr[c + 1];
     for (int d = dj; d < a.D; d += kDirs) {
       const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces;
-      int nup = 0, npin = 0;
+      int nup = 0;
       for (int64_t f = fb; f < fe; ++f) {
         if (M.face_nbr[f] < 0) continue;
         if (isnan(wf[M.face_twin[f]])) continue;
-        if (M.face_shift != nullptr && M.face_shift[f] != 0) ++npin; else ++nup;
+        if (M.face_shift == nullptr || M.face_shift[f] == 0) ++nup;
       }
       const int64_t t = a.units[m * a.D + d].task_base + c;
       if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
       a.indeg[t] = nup;
-      a.rowlen_up[t] = nup + npin;
+      a.rowlen_up[t] = nup;
       mi = max(mi, nup);
-      eu += (unsigned long long)(nup + npin);
+      eu += (unsigned long long)nup;
     }
   }
   atomicMax(&s_max, mi);
@@ -963,21 +959,21 @@ __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5)))
         if (ALIGNED) {
           // radiation leaves through the faces the cell chose and enters through
           // the faces whose twin the neighbour chose
-          up = fo < nfj[j] && code[j] != -1 && !isnan(wi[j]);
-          dn = fo < nfj[j] && code[j] != -1 && !isnan(ws[j]);
+          up = fo < nfj[j] && code[j] >= 0 && !isnan(wi[j]);
+          dn = fo < nfj[j] && code[j] >= 0 && !isnan(ws[j]);
           w = ws[j];
           wu = wi[j];
         } else {
           const bool has = fo < nfj[j] && !isnan(ws[j]);
           const bool in = has && signbit(ws[j]);
-          up = in && code[j] != -1;           // interior or periodic inflow
-          dn = has && !in && code[j] != -1;   // interior or periodic outflow
+          up = in && code[j] >= 0;           // interior inflow
+          dn = has && !in && code[j] >= 0;   // interior outflow
           w = wu = fabsf(ws[j]);
         }
         const uint32_t mu = (uint32_t)(__ballot(up) >> (16 * g)) & 0xffffu;
         const uint32_t md = (uint32_t)(__ballot(dn) >> (16 * g)) & 0xffffu;
-        if (up) a.up[eu[j] + __popc(mu & below)] = make_int2(code[j] >= 0 ? pos[j] : code[j] + 1, __float_as_int(wu));
-        if (dn) a.dn[ed[j] + __popc(md & below)] = make_int2(code[j] >= 0 ? pos[j] : code[j] + 1, __float_as_int(w));
+        if (up) a.up[eu[j] + __popc(mu & below)] = make_int2(pos[j], __float_as_int(wu));
+        if (dn) a.dn[ed[j] + __popc(md & below)] = make_int2(pos[j], __float_as_int(w));
         eu[j] += __popc(mu);
         ed[j] += __popc(md);
       }

@@ -140,9 +140,9 @@ struct LevelInfo {
 
 // Entries of a staged row hold the LDS byte address of their value instead of a
 // schedule position (the ring slot of a result inside the window, or the slot
-// the older value or periodic inflow was prefetched into) and their factor,
-// negated for a periodic inflow.  An entry whose value is not in LDS names the
-// zero slot and marks its step for the global-memory path.
+// the older value was prefetched into) and their factor.  An entry whose value
+// is not in LDS names the zero slot and marks its step for the global-memory
+// path.
 
 // Loads in flight for one step: the thread's share of the step's row block
 // (raw entries, two per load) and the record of the thread's task of the step,
@@ -285,10 +285,8 @@ __device__ __forceinline__ void ld_groups(__amdgpu_buffer_rsrc_t r, uint32_t off
 // Inflow of one task in row order, in batches of 8 entries (the row's entries
 // from the LDS staging buffer, or from global memory for levels that were not
 // staged).  An entry inside the window reads its ring slot; an older result is
-// loaded from out_s (stored at least one barrier earlier by this workgroup); a
-// periodic entry -(partner + 1) adds zero (the coupling between periodic passes
-// is folded into the sources).  Every load of a batch is issued before the first
-// is used, so a batch
+// loaded from out_s (stored at least one barrier earlier by this workgroup).
+// Every load of a batch is issued before the first is used, so a batch
 // costs one memory round trip whatever its mix.  The sum is the same sequence
 // of fused multiply-adds in row order on every path; entries past the row's end
 // (the rest of the batch) are skipped.
@@ -311,8 +309,8 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
     for (int q = 0; q < 8; ++q) {
       const int p = en[q].x;
       const bool val = q < nr;
-      inw[q] = w.has(p);  // never for p < 0 (the window starts at lo >= 0)
-      const bool glob = val && !inw[q] && p >= 0;
+      inw[q] = w.has(p);
+      const bool glob = val && !inw[q];
       ld_groups<GN>(B.outs, glob ? 4u * (uint32_t)(p * a.G) : kOob, gv[q]);
       const float* v = ring + (p & a.ring_mask) * GN;
 #pragma unroll
@@ -336,9 +334,8 @@ __device__ __forceinline__ Inflow<GN> gather(const SweepArgs& a, const UnitBufs&
 // the entries' addresses are relative to), in batches of 8 with the same
 // sequence of fused multiply-adds in row order as gather().  The entries of a
 // batch past the row's end (the next row's, or padding naming the zero slot)
-// take factor 0 (a periodic entry names the zero slot); adding +-0 x (x finite)
-// leaves a sum that starts at +0 and only grows unchanged, so the result is
-// gather()'s bit for bit.
+// take factor 0; adding +-0 x (x finite) leaves a sum that starts at +0 and only
+// grows unchanged, so the result is gather()'s bit for bit.
 template <int GN>
 __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int2* stg,
                                                  const unsigned char* lds) {
@@ -398,9 +395,8 @@ __device__ __forceinline__ Inflow<GN> gather_lds(const TaskRec<GN>& t, const int
 //
 // LDS: [values: ring R slots | zero | sink | 2 x SE prefetched slots] x GN floats,
 // then two staging buffers of SE + 8 entries.
-// Periodic entries (a negative position -(partner + 1)) name the zero slot: the
-// other pass's values through the periodic faces are folded into the sources
-// before the launch.
+// The rows hold graph edges only: the other pass's values through the periodic
+// faces are folded into the sources before the launch.
 template <int GN, bool REVERSE, int CH>
 __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   constexpr int NS = 3;
@@ -487,9 +483,8 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
     // results final at the last prefetch: forward, positions below vis; adjoint,
     // positions from vis up
     int vis = REVERSE ? 0x7fffffff : 0, visF = vis;
-    // (a periodic entry, p < 0, is never loaded: it names the zero slot)
     auto prefetchable = [&](int p, const Window& w, int v) -> bool {
-      return p >= 0 && !w.has(p) && (REVERSE ? p >= v : p < v);
+      return !w.has(p) && (REVERSE ? p >= v : p < v);
     };
     auto issue = [&](int s, Pref<GN, CH>& Q) {
       Q.L = info(s);
@@ -552,12 +547,11 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
           const int idx = idx0 + h;
           const int p = h ? v.z : v.x;
           const bool val = idx < L.nst;
-          // a periodic entry (p < 0) reads the zero slot
           const bool pf = val && prefetchable(p, w, visF);
           const int fs = far0 + b * SE + idx;
           const bool inw = w.has(p);
           const int slot = !val ? zero : (inw ? (p & a.ring_mask) : (pf ? fs : zero));
-          if (val && !inw && !pf && p >= 0) s_bad[b] = gbase + s;
+          if (val && !inw && !pf) s_bad[b] = gbase + s;
           if (pf) {
 #pragma unroll
             for (int g = 0; g < GN; ++g) vals[fs * GN + g] = F[2 * i + h][g];

@@ -266,7 +266,7 @@ struct sweep_dag_s {
       ion_min;
   // periodic half-faces (built with the DAG; see sweep::PinArgs) and, per call, the
   // periodic tasks' own sources and two passes' periodic inflow sums
-  Buf pcell, pf_ptr, pnb, pwf, pwa, ptask, pc_map, pbase, psum_a, psum_b;
+  Buf pcell, pf_ptr, pnb, pwf, pwa, ptask, pc_map, pbase, pval, psum_a, psum_b;
   int32_t n_pc = 0;
   int64_t n_pf = 0;
   // captured pass sequences (use_graph): key = every argument and buffer they bake in
@@ -558,6 +558,7 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
 sweep_status_t alloc_periodic(sweep_dag_t d, int32_t G) {
   const int64_t n = std::max<int64_t>((int64_t)d->n_pc * G, 1);
   HIP_TRY(d->pbase.alloc(4 * (size_t)n * d->D));
+  HIP_TRY(d->pval.alloc(4 * (size_t)n * d->D));
   HIP_TRY(d->psum_a.alloc(8 * (size_t)n));
   HIP_TRY(d->psum_b.alloc(8 * (size_t)n));
   return SWEEP_OK;
@@ -584,6 +585,7 @@ sweep_status_t run_pin(sweep_dag_t d, bool adjoint, int32_t G, const float* othe
   q.tsrc = d->tsrc.as<float>();
   q.pbase = d->pbase.as<float>();
   q.capture = fresh ? 1 : 0;
+  q.pval = psum != nullptr ? d->pval.as<float>() : nullptr;
   q.psum = psum;
   HIP_TRY(sweep::launch_pin(q, s));
   fresh = false;
@@ -1144,7 +1146,12 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     a.ptask = D->ptask.as<int32_t>();
     a.pc_map = D->pc_map.as<int32_t>();
     HIP_TRY(sweep::launch_fill_i32(a.pf_ptr + D->n_pc, 1, (int32_t)D->n_pf, s));
-    for (int m = 0; m < n_meshes; ++m) HIP_TRY(sweep::launch_plist(a, md[m], m, s));
+    Buf pface;
+    HIP_TRY(pface.alloc(4 * std::max<int64_t>(D->n_pf, 1)));
+    a.pface = pface.as<int32_t>();
+    for (int m = 0; m < n_meshes; ++m) HIP_TRY(sweep::launch_plist(a, md[m], s));
+    for (int m = 0; m < n_meshes; ++m)
+      if (md[m].face_shift != nullptr) HIP_TRY(sweep::launch_pdir(a, md[m], m, s));
     HIP_TRY(hipStreamSynchronize(s));  // the local counts and scans are released here
   }
   std::vector<int32_t> depth(n_units);
@@ -1484,7 +1491,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
     std::vector<uint64_t> key = {1, (uint64_t)G, pkey(kappa), pkey(emission), pkey(J), pkey(absorbed),
                                  pkey(totals), pkey(saved), (uint64_t)saved_bytes};
     opts_key(key, p);
-    for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pbase, &d->psum_a, &d->psum_b,
+    for (const Buf* b : {&d->phi_a, &d->phi_b, &d->phi_w, &d->pbase, &d->pval, &d->psum_a, &d->psum_b,
                          &d->jsum_a, &d->jsum_b, &d->partial, &d->tden, &d->tsrc, &d->crec, &d->out_s,
                          &d->mesh_blk_base, &d->blk_mesh, &d->blk_cell0})
       key.push_back(pkey(b->p));
@@ -1576,11 +1583,15 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                           : (((P - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
         // the passes before the last have no source of their own: the denominators
         // of the loss pass stand and only the sources are cleared
+        // (once cleared, the sources stay zero but for the periodic tasks', which
+        // the fold rewrites from their saved zeros)
         if (loss_pass) {
           ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
         } else {
-          HIP_TRY(sweep::launch_fill_f32(d->tsrc.as<float>(), d->T * G, 0.0f, st));
-          fresh = true;
+          if (ps == P - 2) {
+            HIP_TRY(sweep::launch_fill_f32(d->tsrc.as<float>(), d->T * G, 0.0f, st));
+            fresh = true;
+          }
           ST_TRY(run_pin(d, true, G, lam_next, nullptr, fresh, st));
         }
         ST_TRY(run_sweep(d, true, p, G, lam_ps, st));
@@ -1618,7 +1629,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                  pkey(dL_dkappa), pkey(dL_demission)};
     opts_key(key, p);
     for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->lam_b,
-                         &d->pbase, &d->tden, &d->tsrc, &d->crec, &d->out_s})
+                         &d->pbase, &d->pval, &d->tden, &d->tsrc, &d->crec, &d->out_s})
       key.push_back(pkey(b->p));
     ST_TRY(run_graph(d, key, s, body));
   }

@@ -992,10 +992,8 @@ __global__ void k_pcount(DagBuildArgs a, MeshDev M) {
 }
 
 // The periodic cells of mesh M in cell order with their periodic half-faces in
-// face order: partner, the inflow and outflow weight of every direction (the
-// classes and weights k_fill gives the row entries), and the cell's task in
-// every direction.
-__global__ void k_plist(DagBuildArgs a, MeshDev M, int mesh) {
+// face order (the face and its partner).
+__global__ void k_plist(DagBuildArgs a, MeshDev M) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= M.n_cells) return;
   const int gc = M.cell_off + c;
@@ -1009,32 +1007,44 @@ __global__ void k_plist(DagBuildArgs a, MeshDev M, int mesh) {
   for (int64_t f = M.face_ptr[c]; f < M.face_ptr[c + 1]; ++f) {
     const int code = M.fcode[f];
     if (code >= -1) continue;
+    a.pface[j] = (int32_t)f;
     a.pnb[j] = M.cell_off + (-(code + 2));
-    for (int d = 0; d < a.D; ++d) {
-      const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces;
-      float fw, aw;
-      if (a.scheme == SWEEP_SCHEME_ALIGNED) {
-        // inflow: the neighbour's share through the twin; outflow: the cell's own
-        const float wi = wf[M.face_twin[f]];
-        const float ws = wf[f];
-        fw = isnan(wi) ? 0.0f : wi;
-        aw = isnan(ws) ? 0.0f : ws;
-      } else {
-        const float ws = wf[f];
-        const bool has = !isnan(ws);
-        const bool in = has && signbit(ws);
-        fw = in ? fabsf(ws) : 0.0f;
-        aw = has && !in ? fabsf(ws) : 0.0f;
-      }
-      a.pwf[(int64_t)d * a.n_pf + j] = fw;
-      a.pwa[(int64_t)d * a.n_pf + j] = aw;
-    }
     ++j;
   }
-  for (int d = 0; d < a.D; ++d) {
-    const Unit U = a.units[mesh * a.D + d];
-    a.ptask[(int64_t)d * a.n_pc + pc] = (int32_t)(U.task_base + a.inv[U.task_base + c]);
+}
+
+// Per (direction, periodic cell of mesh M): the inflow and outflow weight of
+// each periodic half-face (the classes and weights k_fill gives the row
+// entries, 0 where the half-face carries nothing that way) and the cell's task.
+__global__ void k_pdir(DagBuildArgs a, MeshDev M, int mesh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.D * a.n_pc) return;
+  const int pc = (int)(i % a.n_pc);
+  const int d = (int)(i / a.n_pc);
+  const int c = a.pcell[pc] - M.cell_off;
+  if (c < 0 || c >= M.n_cells) return;  // a cell of another mesh
+  const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces;
+  for (int j = a.pf_ptr[pc]; j < a.pf_ptr[pc + 1]; ++j) {
+    const int f = a.pface[j];
+    float fw, aw;
+    if (a.scheme == SWEEP_SCHEME_ALIGNED) {
+      // inflow: the neighbour's share through the twin; outflow: the cell's own
+      const float wi = wf[M.face_twin[f]];
+      const float ws = wf[f];
+      fw = isnan(wi) ? 0.0f : wi;
+      aw = isnan(ws) ? 0.0f : ws;
+    } else {
+      const float ws = wf[f];
+      const bool has = !isnan(ws);
+      const bool in = has && signbit(ws);
+      fw = in ? fabsf(ws) : 0.0f;
+      aw = has && !in ? fabsf(ws) : 0.0f;
+    }
+    a.pwf[(int64_t)d * a.n_pf + j] = fw;
+    a.pwa[(int64_t)d * a.n_pf + j] = aw;
   }
+  const Unit U = a.units[mesh * a.D + d];
+  a.ptask[i] = (int32_t)(U.task_base + a.inv[U.task_base + c]);
 }
 
 // First row entry of every level (per unit), so a level's rows form one block.
@@ -1252,9 +1262,16 @@ hipError_t launch_pcount(const DagBuildArgs& a, const MeshDev& m, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_plist(const DagBuildArgs& a, const MeshDev& m, int32_t mesh, hipStream_t s) {
+hipError_t launch_plist(const DagBuildArgs& a, const MeshDev& m, hipStream_t s) {
   if (m.n_cells <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_plist, dim3(grid1d(m.n_cells, 256)), dim3(256), 0, s, a, m, mesh);
+  hipLaunchKernelGGL(k_plist, dim3(grid1d(m.n_cells, 256)), dim3(256), 0, s, a, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_pdir(const DagBuildArgs& a, const MeshDev& m, int32_t mesh, hipStream_t s) {
+  const int64_t n = (int64_t)a.D * a.n_pc;
+  if (m.n_cells <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pdir, dim3(grid1d(n, 256)), dim3(256), 0, s, a, m, mesh);
   return hipGetLastError();
 }
 

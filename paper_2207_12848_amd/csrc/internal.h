@@ -100,6 +100,7 @@ struct DagBuildArgs {
   int64_t n_pf;      // periodic half-faces
   int32_t* pcell;    // [n_pc] global cell id
   int32_t* pf_ptr;   // [n_pc + 1] first half-face of each periodic cell
+  int32_t* pface;    // [n_pf] the half-face (index within its mesh; build only)
   int32_t* pnb;      // [n_pf] partner cell across the half-face (global id)
   float* pwf;        // [D][n_pf] inflow weight (0 where the half-face is no inflow)
   float* pwa;        // [D][n_pf] outflow weight (0 where the half-face is no outflow)
@@ -223,7 +224,8 @@ struct PinArgs {
   float* tsrc;             // [T][G] sources of the pass
   float* pbase;            // [D][n_pc][G] the periodic tasks' own sources
   int32_t capture;         // 1: tsrc holds the own sources (save them), 0: take pbase
-  double* psum;            // [n_pc][G] out: sum over directions, or nullptr
+  float* pval;             // [D][n_pc][G] the folded sums (needed with psum)
+  double* psum;            // [n_pc][G] out: their sum over directions (FP64), or nullptr
 };
 
 struct AdjReduceArgs {
@@ -300,7 +302,8 @@ hipError_t launch_sweep_adj(const SweepArgs& a, int32_t gn, int32_t grid, int32_
 hipError_t launch_reduce(const ReduceArgs& a, int32_t n_blocks, hipStream_t s);
 hipError_t launch_pin(const PinArgs& a, hipStream_t s);
 hipError_t launch_pcount(const DagBuildArgs& a, const MeshDev& m, hipStream_t s);
-hipError_t launch_plist(const DagBuildArgs& a, const MeshDev& m, int32_t mesh, hipStream_t s);
+hipError_t launch_plist(const DagBuildArgs& a, const MeshDev& m, hipStream_t s);
+hipError_t launch_pdir(const DagBuildArgs& a, const MeshDev& m, int32_t mesh, hipStream_t s);
 hipError_t launch_totals(const double* partial, const int32_t* mesh_blk_base, int32_t n_meshes,
                          int32_t G, double* totals, hipStream_t s);
 hipError_t launch_adj_init(const float* dJ, const float* dA, const float* kappa, const float* vol,

@@ -785,35 +785,43 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
 }
 
 // Periodic coupling folded into the sources (PinArgs): one thread per
-// (periodic cell, group), every direction in turn.
+// (direction, periodic cell, group).
 __global__ __launch_bounds__(256) void k_pin(PinArgs a) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)a.n_pc * a.G) return;
-  const int pc = (int)(i / a.G);
+  if (i >= (int64_t)a.D * a.n_pc * a.G) return;
   const int g = (int)(i % a.G);
+  const int64_t dp = i / a.G;
+  const int pc = (int)(dp % a.n_pc);
+  const int d = (int)(dp / a.n_pc);
   const int f0 = a.pf_ptr[pc], f1 = a.pf_ptr[pc + 1];
-  double pn = 0.0;
-  for (int d = 0; d < a.D; ++d) {
-    const float* w = a.pw + (int64_t)d * a.n_pf;
-    const float* o = a.other + (int64_t)d * a.C_total * a.G + g;
-    float s = 0.0f;
-    for (int f = f0; f < f1; ++f) {
-      const float wf = w[f];
-      if (wf != 0.0f) s = __builtin_fmaf(wf, o[(int64_t)a.pnb[f] * a.G], s);
-    }
-    const int64_t t = a.ptask[(int64_t)d * a.n_pc + pc];
-    const int64_t b = ((int64_t)d * a.n_pc + pc) * a.G + g;
-    float base;
-    if (a.capture) {
-      base = a.tsrc[t * a.G + g];
-      a.pbase[b] = base;
-    } else {
-      base = a.pbase[b];
-    }
-    a.tsrc[t * a.G + g] = base + s;
-    pn += (double)s;
+  const float* w = a.pw + (int64_t)d * a.n_pf;
+  const float* o = a.other + (int64_t)d * a.C_total * a.G + g;
+  float s = 0.0f;
+  for (int f = f0; f < f1; ++f) {
+    const float wf = w[f];
+    if (wf != 0.0f) s = __builtin_fmaf(wf, o[(int64_t)a.pnb[f] * a.G], s);
   }
-  if (a.psum != nullptr) a.psum[i] = pn;
+  const int64_t t = a.ptask[dp];
+  float base;
+  if (a.capture) {
+    base = a.tsrc[t * a.G + g];
+    a.pbase[i] = base;
+  } else {
+    base = a.pbase[i];
+  }
+  a.tsrc[t * a.G + g] = base + s;
+  if (a.pval != nullptr) a.pval[i] = s;
+}
+
+// The folded inflow of every (periodic cell, group) summed over directions in
+// order, in FP64.
+__global__ __launch_bounds__(256) void k_psum(PinArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)a.n_pc * a.G;
+  if (i >= n) return;
+  double pn = 0.0;
+  for (int d = 0; d < a.D; ++d) pn += (double)a.pval[(int64_t)d * n + i];
+  a.psum[i] = pn;
 }
 
 // ----------------------------------------------------------------------- reductions
@@ -1064,7 +1072,11 @@ hipError_t set_sweep_lds_limit(int32_t bytes) {
 hipError_t launch_pin(const PinArgs& a, hipStream_t s) {
   const int64_t n = (int64_t)a.n_pc * a.G;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pin, dim3(grid1d(n, 256)), dim3(256), 0, s, a);
+  if (a.psum != nullptr && a.pval == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pin, dim3(grid1d(n * a.D, 256)), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.psum == nullptr) return e;
+  hipLaunchKernelGGL(k_psum, dim3(grid1d(n, 256)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

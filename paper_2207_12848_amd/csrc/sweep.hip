@@ -995,6 +995,8 @@ __global__ void k_adj_reduce(AdjReduceArgs a, double* dk, double* de) {
     }
   } else {
     double lph = 0.0;
+    // (unrolled: the loads of eight directions in flight before the first is used)
+#pragma unroll 8
     for (int d = 0; d < a.D; ++d) {
       const double l = (double)a.lam[d * n + i];
       ls += l;

@@ -174,11 +174,10 @@ __device__ __forceinline__ void load_rec(const SweepArgs& a, const UnitBufs& B, 
 // Every thread issues the same loads at every step (fixed count, so the waits
 // for the loads in flight stay exact); the offsets of lanes past the step are
 // moved past the buffers' ends.  Entry pair i of thread t is entries
-// 2 (t + i nthr) and 2 (t + i nthr) + 1 of the step's block; its task is the
-// step's task ts (the thread's task slot).
+// 2 (t + i nthr) and 2 (t + i nthr) + 1 of the step's block.
 template <int GN, int CH>
-__device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B, int tid, int ts,
-                                           int nthr, Pref<GN, CH>& P) {
+__device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B, int tid, int nthr,
+                                           Pref<GN, CH>& P) {
   const LevelInfo& L = P.L;
   const uint32_t eoff = 8u * (uint32_t)(L.e0 - B.ue0);
 #pragma unroll
@@ -186,12 +185,12 @@ __device__ __forceinline__ void issue_pref(const SweepArgs& a, const UnitBufs& B
     const int idx = 2 * (tid + i * nthr);
     P.st[i] = ld_b128<kStream>(B.ent, idx < L.nst ? 8u * (uint32_t)idx : kOob, eoff);
   }
-  const bool act = L.k0 + ts < L.k1;
+  const bool act = L.k0 + tid < L.k1;
   const uint32_t k0 = (uint32_t)L.k0;
-  P.c = ld_b32<kStream>(B.sched, act ? 4u * (uint32_t)ts : kOob, 4u * k0);
-  P.rp0 = ld_b32<kStream>(B.rp, act ? 8u * (uint32_t)ts : kOob, 8u * k0);
-  P.rp1 = ld_b32<kStream>(B.rp, act ? 8u * (uint32_t)ts + 8u : kOob, 8u * k0);
-  const uint32_t vo = act ? 4u * (uint32_t)(ts * a.G) : kOob, so = 4u * k0 * (uint32_t)a.G;
+  P.c = ld_b32<kStream>(B.sched, act ? 4u * (uint32_t)tid : kOob, 4u * k0);
+  P.rp0 = ld_b32<kStream>(B.rp, act ? 8u * (uint32_t)tid : kOob, 8u * k0);
+  P.rp1 = ld_b32<kStream>(B.rp, act ? 8u * (uint32_t)tid + 8u : kOob, 8u * k0);
+  const uint32_t vo = act ? 4u * (uint32_t)(tid * a.G) : kOob, so = 4u * k0 * (uint32_t)a.G;
   ld_gn<GN, kStream>(B.den, vo, so, P.den);
   ld_gn<GN, kStream>(B.src, vo, so, P.src);
 }
@@ -418,9 +417,6 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
   const int sink = R + 1;   // value slot the threads without a task write
   const int far0 = R + 2;   // prefetched slots of staging buffer b: far0 + b SE + entry index
   const int wbase = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wavefront's first thread
-  // the thread's task slot: a step's tasks go to the last wavefronts, which
-  // stage the fewest entries (entries fill the threads from the first on)
-  const int ts = nthr - 1 - tid;
   float* ring = vals;
   float* sinkp = vals + sink * GN;
   for (int i = tid; i < 2 * SP; i += nthr) stage[i] = make_int2(zero * GN * 4, 0);
@@ -492,7 +488,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
     };
     auto issue = [&](int s, Pref<GN, CH>& Q) {
       Q.L = info(s);
-      issue_pref<GN, CH>(a, B, tid, ts, nthr, Q);
+      issue_pref<GN, CH>(a, B, tid, nthr, Q);
     };
     // the older results of the thread's staged entries of step s (one load per
     // entry; the others read past the buffer's end)
@@ -572,7 +568,7 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
         if (idx0 < L.nst + 8) *reinterpret_cast<int4*>(dst + idx0) = v;
       }
       curL = L;
-      const bool act = L.k0 + ts < L.k1;
+      const bool act = L.k0 + tid < L.k1;
       cur.c = act ? Q.c : -1;
       cur.r0 = act ? (int)((uint32_t)Q.rp0 - (uint32_t)L.e0) : 0;
       cur.r1 = act ? (int)((uint32_t)Q.rp1 - (uint32_t)L.e0) : 0;
@@ -592,12 +588,12 @@ __global__ __launch_bounds__(kSweepMaxBlock(GN)) void k_sweep(SweepArgs a) {
       const bool bad = __builtin_amdgcn_readfirstlane(s_bad[s & 1]) == gbase + s;
       if (curL.nst == curL.ne && k1 - k0 <= nthr && !bad) {
         const Inflow<GN> in = gather_lds<GN>(cur, stg, smem);
-        finish_fast<GN>(a, B, cur, k0 + ts, in, ring, sinkp);
+        finish_fast<GN>(a, B, cur, k0 + tid, in, ring, sinkp);
         return;
       }
-      for (int k = k0 + ts; k < k1; k += nthr) {
+      for (int k = k0 + tid; k < k1; k += nthr) {
         TaskRec<GN> t;
-        if (k == k0 + ts) t = cur; else load_rec<GN>(a, B, k, e0, t);
+        if (k == k0 + tid) t = cur; else load_rec<GN>(a, B, k, e0, t);
         const Inflow<GN> in = gather<GN, false>(a, B, t, nullptr, eoff, ring, w);
         finish_task<GN>(a, B, t, k, in, ring);
       }

@@ -57,8 +57,8 @@ def byte_model(kernel: str, s: dict) -> float:
     """Algorithmic HBM bytes of ONE launch of `kernel` (what the algorithm must move,
     FP32 fields, int32 ids; not what the implementation happens to move).
 
-    s: C cells, H half-faces, T tasks (C * D), Eu upwind entries (graph edges +
-    periodic inflows), Ed downwind entries (graph edges), G groups, launches per call."""
+    s: C cells, H half-faces, T tasks (C * D), Eu upwind and Ed downwind entries
+    (graph edges), G groups, launches per call."""
     C, H, T, Eu, Ed, G = s["C"], s["H"], s["T"], s["Eu"], s["Ed"], s["G"]
     face = 8 + 4 + 1 + 24.0  # area f64, neighbour i32, image code i8, normal 3 x f64
     if kernel == "count":

@@ -257,9 +257,10 @@ sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, con
  * hold what sweep_forward wrote with the same kappa, emission and opts.
  * Source iterations are differentiated with per-iteration recomputation from
  * the saved direction sums.  Periodic passes (nested order) are differentiated
- * pass by pass in reverse: the adjoint of pass p gets w lambda^{p+1} of the
- * partner cell through every periodic outflow face (summed with FP64 atomics,
- * so the result varies by rounding between runs).  UNSUPPORTED: the merged
+ * pass by pass in reverse: before the reverse sweep of pass p, every task of
+ * a periodic cell gets w lambda^{p+1} of the partner cell through each of its
+ * periodic outflow faces added to its source (a fixed sequence of FP32 FMAs in
+ * face order), so the gradients are the same bits on every run.  UNSUPPORTED: the merged
  * order, pbc_tol and warm_start (a pass count or inflow that the forward
  * decided at run time or took from outside). */
 sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,

@@ -595,6 +595,116 @@ static void adjoint_direction(const orc_mesh* m, const double* om, double eps, i
   }
 }
 
+/* The merged order (periodic boundaries with n_scat > 1 and `merged`): one
+ * sequence of P = max(n_pbc, n_scat) passes, pass p taking its scattering
+ * source from the direction sums of pass p-1 and its periodic inflow from pass
+ * p-1 (pass 0 from zero inflow and no scattering), the loss on the last pass:
+ *   x^p = M^{-1}(S^p + B x^{p-1}),  S^p = L/D + a kappa V jsum^{p-1} / D.
+ * Reverse, p = P-1..0:
+ *   lambda^p_d = M_d^{-T}(r_d g^p + B^T lambda^{p+1}),
+ *   g^{P-1} = the loss's cell-average gradient, g^{p-1} = a kappa V sum_d lambda^p_d / D;
+ *   dL/dL += sum_d lambda^p_d / D;
+ *   dL/dkappa += sum_d dk^p_d + a V (sum_d lambda^p_d) jsum^{p-1} / D  (jsum^{-1} = 0),
+ * plus the loss's own gA (1-a) V jsum^{P-1}.  Every pass is recomputed forward
+ * first, keeping its exit values and direction sums. */
+static int adjoint_merged(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
+                          const double* kappa, const double* emission, int32_t P, double albedo,
+                          int32_t law, const double* gJ, const double* gA, double* dkappa,
+                          double* demission) {
+  const int32_t C = m->n_cells;
+  const int64_t CG = (int64_t)C * G;
+  const int64_t DCG = (int64_t)D * CG;
+  double* xs = (double*)malloc(sizeof(double) * (size_t)(P * DCG));  /* x of every pass */
+  double* js = (double*)malloc(sizeof(double) * (size_t)(P * CG));   /* its direction sums */
+  double* avg = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* lam = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* lam_next = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* dkd = (double*)malloc(sizeof(double) * (size_t)DCG);
+  double* gsrc = (double*)malloc(sizeof(double) * (size_t)CG);
+  double* src = (double*)malloc(sizeof(double) * (size_t)CG);
+  int32_t* qorder = (int32_t*)malloc(sizeof(int32_t) * (size_t)D * C);
+  int status = ORC_OK;
+  if (!xs || !js || !avg || !lam || !lam_next || !dkd || !gsrc || !src || !qorder) status = ORC_ERR_OOM;
+  for (int32_t p = 0; p < P && status == ORC_OK; ++p) {
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t g = 0; g < G; ++g) {
+        const int64_t i = (int64_t)c * G + g;
+        const double prev = p > 0 ? js[(int64_t)(p - 1) * CG + i] : 0.0;
+        src[i] = emission[i] / D + albedo * kappa[i] * m->cell_volume[c] * prev / D;
+      }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t d = 0; d < D; ++d) {
+      int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+      int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
+      double acc[4 * 64];
+      double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
+      memset(a4, 0, sizeof(double) * 4 * (size_t)G);
+      const double* prev = p > 0 ? xs + (int64_t)(p - 1) * DCG + (int64_t)d * CG : NULL;
+      int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, prev,
+                               xs + (int64_t)p * DCG + (int64_t)d * CG, avg + (int64_t)d * CG, a4,
+                               NULL, cnt, q, NULL, qorder + (int64_t)d * C);
+      if (st != ORC_OK) {
+#pragma omp critical
+        status = st;
+      }
+      if (a4 != acc) free(a4);
+      free(cnt);
+      free(q);
+    }
+    for (int64_t i = 0; i < CG; ++i) {
+      double sum = 0.0;
+      for (int32_t d = 0; d < D; ++d) sum += avg[(int64_t)d * CG + i];
+      js[(int64_t)p * CG + i] = sum;
+    }
+  }
+  if (status == ORC_OK) {
+    memset(dkappa, 0, sizeof(double) * (size_t)CG);
+    memset(demission, 0, sizeof(double) * (size_t)CG);
+    for (int32_t c = 0; c < C; ++c)
+      for (int32_t g = 0; g < G; ++g) {
+        const int64_t i = (int64_t)c * G + g;
+        const double V = m->cell_volume[c];
+        gsrc[i] = gJ[i] / (4.0 * M_PI) + gA[i] * (1.0 - albedo) * kappa[i] * V;
+        dkappa[i] += gA[i] * (1.0 - albedo) * V * js[(int64_t)(P - 1) * CG + i];
+      }
+    for (int32_t p = P - 1; p >= 0; --p) {
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int32_t d = 0; d < D; ++d)
+        adjoint_direction(m, dirs + 3 * d, eps, G, law, kappa, gsrc,
+                          p < P - 1 ? lam_next + (int64_t)d * CG : NULL,
+                          xs + (int64_t)p * DCG + (int64_t)d * CG, qorder + (int64_t)d * C,
+                          lam + (int64_t)d * CG, dkd + (int64_t)d * CG);
+      for (int32_t c = 0; c < C; ++c)
+        for (int32_t g = 0; g < G; ++g) {
+          const int64_t i = (int64_t)c * G + g;
+          const double V = m->cell_volume[c];
+          double ls = 0.0, dks = 0.0;
+          for (int32_t d = 0; d < D; ++d) {
+            ls += lam[(int64_t)d * CG + i];
+            dks += dkd[(int64_t)d * CG + i];
+          }
+          const double prev = p > 0 ? js[(int64_t)(p - 1) * CG + i] : 0.0;
+          demission[i] += ls / D;
+          dkappa[i] += dks + albedo * V * ls * prev / D;
+          gsrc[i] = albedo * kappa[i] * V * ls / D;  /* the source gradient of pass p - 1 */
+        }
+      double* t = lam_next;
+      lam_next = lam;
+      lam = t;
+    }
+  }
+  free(xs);
+  free(js);
+  free(avg);
+  free(lam);
+  free(lam_next);
+  free(dkd);
+  free(gsrc);
+  free(src);
+  free(qorder);
+  return status;
+}
+
 /* Gradients of a loss L(J, absorbed) given gJ = dL/dJ and gA = dL/dabsorbed ([C][G]).
  * avg denotes the cell average and x the stored value of adjoint_direction.
  *
@@ -618,10 +728,13 @@ static void adjoint_direction(const orc_mesh* m, const double* om, double eps, i
  * x^p is recomputed from the stored direction sums of iteration i-1. */
 int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
-                double albedo, int32_t n_scat, int32_t law, const double* gJ, const double* gA,
-                double* dkappa, double* demission) {
+                double albedo, int32_t n_scat, int32_t law, int32_t merged, const double* gJ,
+                const double* gA, double* dkappa, double* demission) {
   if (D < 1 || G < 1 || n_scat < 1 || n_pbc < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
   if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
+  if (merged && periodic && n_scat > 1)
+    return adjoint_merged(m, D, dirs, eps, G, kappa, emission, n_pbc > n_scat ? n_pbc : n_scat,
+                          albedo, law, gJ, gA, dkappa, demission);
   const int32_t P = periodic ? n_pbc : 1;
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;

@@ -316,6 +316,40 @@ def test_periodic_adjoint_central_differences(law, albedo, n_scat):
         assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
 
 
+@pytest.mark.parametrize("law,n_pbc,n_scat", [("upwind", 3, 3), ("upwind", 2, 4), ("exp", 4, 2)])
+def test_merged_adjoint_central_differences(law, n_pbc, n_scat):
+    """Adjoint of the merged order (each pass takes its scattering source and its
+    periodic inflow from the pass before): central differences of the merged
+    forward, and different from the nested order's gradients."""
+    w = W.small_random(200, 8, G=1, seed=15, periodic=True, n_pbc=n_pbc, n_src=3, albedo=0.4,
+                       n_scat=n_scat, tau=2.0)
+    w = dict(w, law=law, merge=True, kappa=np.asarray(w["kappa"], np.float64),
+             emission=np.asarray(w["emission"], np.float64))
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    dkn, _ = oracle.adjoint(dict(w, merge=False), gJ, gA)
+    assert _rel(dk, dkn) > 1e-6  # the orders differ, and so do their gradients
+    L = _loss(w)
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for c in rng.choice(200, 8, replace=False):
+        k0 = w["kappa"][c, 0]
+        wp = dict(w, kappa=w["kappa"].copy())
+        wm = dict(w, kappa=w["kappa"].copy())
+        wp["kappa"][c, 0] = k0 * (1 + h)
+        wm["kappa"][c, 0] = k0 * (1 - h)
+        fd = (_loss(wp) - _loss(wm)) / (2 * h * k0)
+        assert abs(fd - dk[c, 0]) <= 1e-6 * abs(dk[c, 0]) + 1e-10 * L / k0
+    for c in w["sources"]:
+        L0 = w["emission"][c, 0]
+        wp = dict(w, emission=w["emission"].copy())
+        wm = dict(w, emission=w["emission"].copy())
+        wp["emission"][c, 0] = L0 * (1 + h)
+        wm["emission"][c, 0] = L0 * (1 - h)
+        fd = (_loss(wp) - _loss(wm)) / (2 * h * L0)
+        assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
+
+
 def test_periodic_adjoint_converges_to_the_cyclic_adjoint():
     """Many passes: the gradients of the passes approach those of the cyclic fixed point."""
     w = W.small_random(180, 8, G=1, seed=3, periodic=True, n_src=3, tau=2.0)

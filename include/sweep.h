@@ -260,9 +260,13 @@ sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, con
  * pass by pass in reverse: before the reverse sweep of pass p, every task of
  * a periodic cell gets w lambda^{p+1} of the partner cell through each of its
  * periodic outflow faces added to its source (a fixed sequence of FP32 FMAs in
- * face order), so the gradients are the same bits on every run.  UNSUPPORTED: the merged
- * order, pbc_tol and warm_start (a pass count or inflow that the forward
- * decided at run time or took from outside). */
+ * face order), so the gradients are the same bits on every run.  The merged
+ * order (opts->merge) is differentiated through its single sequence of passes:
+ * every pass is recomputed, then reversed with its own source gradient (the
+ * loss on the last pass, the scattering source's on the others) and the later
+ * pass's lambda through the periodic faces.  UNSUPPORTED: pbc_tol and
+ * warm_start (a pass count or inflow that the forward decided at run time or
+ * took from outside). */
 sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const float* emission, const sweep_fwd_opts_t* opts,
                              const void* saved, size_t saved_bytes, const float* dL_dJ,

@@ -262,6 +262,7 @@ struct sweep_dag_s {
   Buf blk_mesh, blk_cell0, mesh_off_d, mesh_cells_d, mesh_blk_base;
   // workspaces
   Buf xpass, lam_b;  // periodic adjoint: recomputed passes, the other pass's lambda
+  Buf jpass, jscr;   // merged adjoint: every pass's direction sums; J and absorbed scratch
   Buf phi_a, phi_b, phi_w, jsum_a, jsum_b, partial, lam, gsrc, dk64, de64, tden, tsrc, crec, out_s,
       ion_min;
   // periodic half-faces (built with the DAG; see sweep::PinArgs) and, per call, the
@@ -551,6 +552,33 @@ sweep_status_t run_prep(sweep_dag_t d, int32_t G, const float* kappa, const floa
   ProfScope ps("prep", s);
   HIP_TRY(sweep::launch_prep(q, d->n_blocks, s));
   return SWEEP_OK;
+}
+
+// The direction reduction's arguments that do not change between the passes of
+// a call (the reduction tables must be in place: ensure_reduce_tables).
+sweep::ReduceArgs reduce_args(sweep_dag_t d, int32_t G, const FwdPlan& p, const float* kappa,
+                              const float* emission, float* J, float* absorbed) {
+  sweep::ReduceArgs r{};
+  r.units = d->units_d.as<Unit>();
+  r.D = d->D;
+  r.G = G;
+  r.C_total = d->C_total;
+  r.blk_mesh = d->blk_mesh.as<int32_t>();
+  r.blk_cell0 = d->blk_cell0.as<int32_t>();
+  r.mesh_off = d->mesh_off_d.as<int32_t>();
+  r.mesh_cells = d->mesh_cells_d.as<int32_t>();
+  r.bnd = d->bnd.as<float2>();
+  r.aperp = d->aperp.as<float>();
+  r.law = p.law;
+  r.kappa = kappa;
+  r.emission = emission;
+  r.vol = d->vol.as<float>();
+  r.albedo = p.albedo;
+  r.J = J;
+  r.absorbed = absorbed;
+  r.partial = d->partial.as<double>();
+  r.cells_per_block = d->red_cpb;
+  return r;
 }
 
 // Per-call buffers of the periodic fold: the periodic tasks' own sources and the
@@ -1371,26 +1399,7 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   HIP_TRY(d->tsrc.alloc(4 * (size_t)d->T * G));
   HIP_TRY(d->crec.alloc(8 * (size_t)d->C_total * G));
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
-  sweep::ReduceArgs r{};
-  r.units = d->units_d.as<Unit>();
-  r.D = d->D;
-  r.G = G;
-  r.C_total = d->C_total;
-  r.blk_mesh = d->blk_mesh.as<int32_t>();
-  r.blk_cell0 = d->blk_cell0.as<int32_t>();
-  r.mesh_off = d->mesh_off_d.as<int32_t>();
-  r.mesh_cells = d->mesh_cells_d.as<int32_t>();
-  r.bnd = d->bnd.as<float2>();
-  r.aperp = d->aperp.as<float>();
-  r.law = p.law;
-  r.kappa = kappa;
-  r.emission = emission;
-  r.vol = d->vol.as<float>();
-  r.albedo = p.albedo;
-  r.J = J;
-  r.absorbed = absorbed;
-  r.partial = d->partial.as<double>();
-  r.cells_per_block = d->red_cpb;
+  const sweep::ReduceArgs r = reduce_args(d, G, p, kappa, emission, J, absorbed);
   // source iterations, each made of the periodic passes (or the merged sequence),
   // then the totals
   auto body = [&](hipStream_t st) -> sweep_status_t {
@@ -1511,8 +1520,8 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   FwdPlan p;
   ST_TRY(read_opts(opts, &p));
   const bool periodic = p.boundary == SWEEP_BOUNDARY_PERIODIC;
-  if (periodic && (p.merge && p.n_scat > 1))
-    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint of the merged periodic/scattering order is not implemented");
+  // merged order (sec. 2.7): one sequence of max(n_pbc, n_scat) passes
+  const bool merge = periodic && p.merge && p.n_scat > 1;
   if (periodic && (p.pbc_tol > 0.0 || p.warm))
     return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint needs a fixed number of passes from zero inflow "
                                        "(no pbc_tol, no warm_start)");
@@ -1530,15 +1539,22 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   // P passes per iteration: x^0..x^{P-1}; the last iteration's are in `saved`
   // (x^{P-1} first, the others after the checkpoints), earlier iterations'
   // are recomputed into phi_a (x^{P-1}) and xpass (the others)
-  const int P = periodic ? p.n_pbc : 1;
+  const int P = merge ? std::max(p.n_pbc, p.n_scat) : periodic ? p.n_pbc : 1;
   ST_TRY(ensure_mesh_tables(d));
   ST_TRY(prepare_steps(d, p, G, s));
   HIP_TRY(d->lam.alloc(4 * DCG));
   HIP_TRY(d->gsrc.alloc(4 * CG));
   HIP_TRY(d->dk64.alloc(8 * CG));
   HIP_TRY(d->de64.alloc(8 * CG));
-  if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
-  if (p.n_scat > 1 && P > 1) HIP_TRY(d->xpass.alloc(4 * DCG * (P - 1)));
+  if (merge) {
+    ST_TRY(ensure_reduce_tables(d, G));
+    HIP_TRY(d->xpass.alloc(4 * DCG * P));
+    HIP_TRY(d->jpass.alloc(4 * CG * P));
+    HIP_TRY(d->jscr.alloc(8 * CG));
+  } else {
+    if (p.n_scat > 1) HIP_TRY(d->phi_a.alloc(4 * DCG));
+    if (p.n_scat > 1 && P > 1) HIP_TRY(d->xpass.alloc(4 * DCG * (P - 1)));
+  }
   if (P > 1) HIP_TRY(d->lam_b.alloc(4 * DCG));
   if (periodic) ST_TRY(alloc_periodic(d, G));
   HIP_TRY(d->tden.alloc(4 * (size_t)d->T * G));
@@ -1557,7 +1573,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   // which were saved), run the reverse passes (the last with the loss source, the
   // earlier ones fed through the periodic faces by the later pass's adjoint),
   // accumulate the gradients and the adjoint source of iteration it - 1
-  auto body = [&](hipStream_t st) -> sweep_status_t {
+  auto body_nested = [&](hipStream_t st) -> sweep_status_t {
     HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(),
                                    ckpt(p.n_scat - 1), p.albedo, G, d->C_total,
                                    d->gsrc.as<float>(), d->dk64.as<double>(),
@@ -1621,6 +1637,67 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                    dL_demission, CG, st));
     return SWEEP_OK;
   };
+  // merged order: the passes x^p = M^{-1}(S^p + B x^{p-1}), S^p = L/D + a kappa V
+  // jsum^{p-1}/D, are recomputed first (every exit value and direction sum kept);
+  // then, p = P-1..0, lambda^p = M^{-T}(r g^p + B^T lambda^{p+1}) with g^{P-1} the
+  // loss's and g^{p-1} = a kappa V sum_d lambda^p / D (the adjoint reduction writes
+  // it over g^p), each pass adding its own terms to the gradients
+  auto xm = [&](int ps) -> float* { return d->xpass.as<float>() + (int64_t)ps * DCG; };
+  auto jmp = [&](int ps) -> float* { return d->jpass.as<float>() + (int64_t)ps * CG; };
+  auto body_merged = [&](hipStream_t st) -> sweep_status_t {
+    bool fresh = false;
+    const sweep::ReduceArgs r = reduce_args(d, G, p, kappa, emission, d->jscr.as<float>(),
+                                            d->jscr.as<float>() + CG);
+    for (int ps = 0; ps < P; ++ps) {
+      const float* jprev = ps > 0 ? jmp(ps - 1) : nullptr;
+      ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
+      fresh = true;
+      if (ps > 0) ST_TRY(run_pin(d, false, G, xm(ps - 1), nullptr, fresh, st));
+      ST_TRY(run_sweep(d, false, p, G, xm(ps), st));
+      sweep::ReduceArgs q = r;
+      q.phi = xm(ps);
+      q.jsum_prev = jprev;
+      q.jsum = jmp(ps);
+      HIP_TRY(sweep::launch_reduce(q, d->red_blocks, st));
+    }
+    HIP_TRY(sweep::launch_adj_init(dL_dJ, dL_dabsorbed, kappa, d->vol.as<float>(), jmp(P - 1),
+                                   p.albedo, G, d->C_total, d->gsrc.as<float>(),
+                                   d->dk64.as<double>(), d->de64.as<double>(),
+                                   d->flag.as<int32_t>(), st));
+    for (int ps = P - 1; ps >= 0; --ps) {
+      float* lam_ps = ((P - 1 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>();
+      const float* lam_next = ps == P - 1 ? nullptr
+                                          : (((P - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
+      ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
+      fresh = true;
+      if (lam_next != nullptr) ST_TRY(run_pin(d, true, G, lam_next, nullptr, fresh, st));
+      ST_TRY(run_sweep(d, true, p, G, lam_ps, st));
+      sweep::AdjReduceArgs q{};
+      q.D = d->D;
+      q.G = G;
+      q.C_total = d->C_total;
+      q.law = p.law;
+      q.n_meshes = d->n_meshes;
+      q.mesh_off = d->mesh_off_d.as<int32_t>();
+      q.aperp = d->aperp.as<float>();
+      q.gsrc = d->gsrc.as<float>();
+      q.use_g = 1;
+      q.accumulate = 0;
+      q.lam = lam_ps;
+      q.phi = xm(ps);
+      q.kappa = kappa;
+      q.vol = d->vol.as<float>();
+      q.jsum_prev = ps > 0 ? jmp(ps - 1) : nullptr;
+      q.albedo = p.albedo;
+      q.inv_D = 1.0f / (float)d->D;
+      q.gsrc_next = d->gsrc.as<float>();
+      HIP_TRY(sweep::launch_adj_reduce(q, d->dk64.as<double>(), d->de64.as<double>(), st));
+    }
+    HIP_TRY(sweep::launch_d2f_pair(d->dk64.as<double>(), d->de64.as<double>(), dL_dkappa,
+                                   dL_demission, CG, st));
+    return SWEEP_OK;
+  };
+  auto body = [&](hipStream_t st) -> sweep_status_t { return merge ? body_merged(st) : body_nested(st); };
   if (!p.use_graph) {
     ST_TRY(body(s));
   } else {
@@ -1629,7 +1706,8 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
                                  pkey(dL_dkappa), pkey(dL_demission)};
     opts_key(key, p);
     for (const Buf* b : {&d->lam, &d->gsrc, &d->dk64, &d->de64, &d->phi_a, &d->xpass, &d->lam_b,
-                         &d->pbase, &d->pval, &d->tden, &d->tsrc, &d->crec, &d->out_s})
+                         &d->pbase, &d->pval, &d->tden, &d->tsrc, &d->crec, &d->out_s, &d->jpass,
+                         &d->jscr, &d->partial, &d->mesh_blk_base, &d->blk_mesh, &d->blk_cell0})
       key.push_back(pkey(b->p));
     ST_TRY(run_graph(d, key, s, body));
   }

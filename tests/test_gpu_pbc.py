@@ -9,7 +9,8 @@ pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
 from synth import workloads as W  # noqa: E402
-from tests.test_gpu_parity import _dev, _opts, _sw, assert_field_close, check_forward  # noqa: E402
+from tests.test_gpu_parity import (_dev, _grad_close, _opts, _sw, assert_field_close,  # noqa: E402
+                                   check_forward)
 
 
 @pytest.mark.parametrize("law,n_pbc,n_scat", [("upwind", 3, 5), ("exp", 6, 2), ("upwind", 4, 4)])
@@ -20,6 +21,33 @@ def test_merged_iterations_match_oracle(law, n_pbc, n_scat):
     dag, J, A, tot, ref = check_forward(w, merge=True)
     assert np.allclose(tot[..., 6], ref["totals"][..., 6], rtol=1e-4, atol=1e-6)
     assert np.allclose(tot[..., 5], ref["totals"][..., 5], rtol=1e-4, atol=1e-8 * tot[..., 0].max())
+
+
+@pytest.mark.parametrize("law,n_pbc,n_scat,G", [("upwind", 3, 3, 2), ("upwind", 2, 4, 1), ("exp", 4, 2, 1)])
+def test_merged_adjoint_matches_oracle(law, n_pbc, n_scat, G):
+    """The adjoint of the merged order (every pass recomputed, then reversed with
+    its own scattering source gradient and the later pass's lambda through the
+    periodic faces) against the oracle's, with random loss gradients."""
+    sw = _sw()
+    w = W.small_random(2000, 24, G=G, seed=97 + n_pbc, periodic=True, n_pbc=n_pbc, albedo=0.4,
+                       n_scat=n_scat, n_src=4, tau=2.0)
+    w = dict(w, law=law, merge=True)
+    rng = np.random.default_rng(14)
+    C = len(w["meshes"][0]["cell_volume"])
+    gJ = rng.random((C, G)).astype(np.float32)
+    gA = rng.random((C, G)).astype(np.float32)
+    dk_ref, de_ref = oracle.adjoint(w, gJ, gA)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, merge=True, **_opts(w))
+    dk, de = sw.adjoint(dag, k, e, saved, torch.tensor(gJ, device="cuda"),
+                        torch.tensor(gA, device="cuda"), merge=True, **_opts(w))
+    _grad_close(dk.cpu().numpy(), dk_ref)
+    _grad_close(de.cpu().numpy(), de_ref)
+    # the merged gradients are not the nested order's
+    dkn, _ = sw.adjoint(dag, k, e, sw.forward(dag, k, e, save_for_adjoint=True, **_opts(w))[3],
+                        torch.tensor(gJ, device="cuda"), torch.tensor(gA, device="cuda"), **_opts(w))
+    assert not torch.equal(dk, dkn)
 
 
 def test_merged_equals_nested_without_scattering():

@@ -609,8 +609,8 @@ static void adjoint_direction(const orc_mesh* m, const double* om, double eps, i
  * first, keeping its exit values and direction sums. */
 static int adjoint_merged(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                           const double* kappa, const double* emission, int32_t P, double albedo,
-                          int32_t law, const double* gJ, const double* gA, double* dkappa,
-                          double* demission) {
+                          int32_t law, const double* phi_init, const double* gJ, const double* gA,
+                          double* dkappa, double* demission) {
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
   const int64_t DCG = (int64_t)D * CG;
@@ -639,7 +639,8 @@ static int adjoint_merged(const orc_mesh* m, int32_t D, const double* dirs, doub
       double acc[4 * 64];
       double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
       memset(a4, 0, sizeof(double) * 4 * (size_t)G);
-      const double* prev = p > 0 ? xs + (int64_t)(p - 1) * DCG + (int64_t)d * CG : NULL;
+      const double* prev = p > 0 ? xs + (int64_t)(p - 1) * DCG + (int64_t)d * CG
+                           : phi_init ? phi_init + (int64_t)d * CG : NULL;
       int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, prev,
                                xs + (int64_t)p * DCG + (int64_t)d * CG, avg + (int64_t)d * CG, a4,
                                NULL, cnt, q, NULL, qorder + (int64_t)d * C);
@@ -728,13 +729,14 @@ static int adjoint_merged(const orc_mesh* m, int32_t D, const double* dirs, doub
  * x^p is recomputed from the stored direction sums of iteration i-1. */
 int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
-                double albedo, int32_t n_scat, int32_t law, int32_t merged, const double* gJ,
-                const double* gA, double* dkappa, double* demission) {
+                double albedo, int32_t n_scat, int32_t law, int32_t merged, const double* phi_init,
+                const double* gJ, const double* gA, double* dkappa, double* demission) {
   if (D < 1 || G < 1 || n_scat < 1 || n_pbc < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
   if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
   if (merged && periodic && n_scat > 1)
     return adjoint_merged(m, D, dirs, eps, G, kappa, emission, n_pbc > n_scat ? n_pbc : n_scat,
-                          albedo, law, gJ, gA, dkappa, demission);
+                          albedo, law, periodic ? phi_init : NULL, gJ, gA, dkappa, demission);
+  if (!periodic) phi_init = NULL;
   const int32_t P = periodic ? n_pbc : 1;
   const int32_t C = m->n_cells;
   const int64_t CG = (int64_t)C * G;
@@ -758,7 +760,7 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
       !lsum || !dksum || !qorder)
     return ORC_ERR_OOM;
   int status = orc_forward(m, D, dirs, eps, G, kappa, emission, periodic, P, albedo, n_scat, law,
-                           0, NULL, 0.0, J, Ab, tots, NULL, jsum, NULL);
+                           0, phi_init, 0.0, J, Ab, tots, NULL, jsum, NULL);
   if (status == ORC_OK) {
     memset(dkappa, 0, sizeof(double) * (size_t)CG);
     memset(demission, 0, sizeof(double) * (size_t)CG);
@@ -785,7 +787,10 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
           double acc[4 * 64];
           double* a4 = G <= 64 ? acc : (double*)malloc(sizeof(double) * 4 * (size_t)G);
           memset(a4, 0, sizeof(double) * 4 * (size_t)G);
-          const double* prev = p > 0 ? xs + (int64_t)(p - 1) * DCG + (int64_t)d * CG : NULL;
+          /* warm start: the first pass of the first iteration takes its periodic
+           * inflow from phi_init (held fixed: no gradient flows into it) */
+          const double* prev = p > 0 ? xs + (int64_t)(p - 1) * DCG + (int64_t)d * CG
+                               : (phi_init && it == 0) ? phi_init + (int64_t)d * CG : NULL;
           int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, prev,
                                    xs + (int64_t)p * DCG + (int64_t)d * CG, avg + (int64_t)d * CG,
                                    a4, NULL, cnt, q, NULL, qorder + (int64_t)d * C);

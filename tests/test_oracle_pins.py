@@ -350,6 +350,45 @@ def test_merged_adjoint_central_differences(law, n_pbc, n_scat):
         assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
 
 
+@pytest.mark.parametrize("merge,n_pbc,n_scat", [(False, 3, 1), (False, 2, 3), (True, 2, 3)])
+def test_warm_start_adjoint_central_differences(merge, n_pbc, n_scat):
+    """Warm start (the first pass's periodic inflow taken from an earlier run's
+    exit values, held fixed): adjoint against central differences of the forward
+    with the same inflow, and different from the adjoint from zero inflow."""
+    w = W.small_random(200, 8, G=1, seed=16, periodic=True, n_pbc=n_pbc, n_src=3, albedo=0.4,
+                       n_scat=n_scat, tau=2.0)
+    w = dict(w, merge=merge, kappa=np.asarray(w["kappa"], np.float64),
+             emission=np.asarray(w["emission"], np.float64))
+    warm = oracle.forward(dict(w, kappa=w["kappa"] * 1.3), want_phi=True)["phi"]
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA, phi_init=warm)
+    dk0, _ = oracle.adjoint(w, gJ, gA)
+    assert _rel(dk, dk0) > 1e-6
+
+    def loss(ww):
+        return oracle.forward(ww, phi_init=warm)["absorbed"].sum() / (4 * np.pi)
+
+    L = loss(w)
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    for c in rng.choice(200, 8, replace=False):
+        k0 = w["kappa"][c, 0]
+        wp = dict(w, kappa=w["kappa"].copy())
+        wm = dict(w, kappa=w["kappa"].copy())
+        wp["kappa"][c, 0] = k0 * (1 + h)
+        wm["kappa"][c, 0] = k0 * (1 - h)
+        fd = (loss(wp) - loss(wm)) / (2 * h * k0)
+        assert abs(fd - dk[c, 0]) <= 1e-6 * abs(dk[c, 0]) + 1e-10 * L / k0
+    for c in w["sources"]:
+        L0 = w["emission"][c, 0]
+        wp = dict(w, emission=w["emission"].copy())
+        wm = dict(w, emission=w["emission"].copy())
+        wp["emission"][c, 0] = L0 * (1 + h)
+        wm["emission"][c, 0] = L0 * (1 - h)
+        fd = (loss(wp) - loss(wm)) / (2 * h * L0)
+        assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
+
+
 def test_periodic_adjoint_converges_to_the_cyclic_adjoint():
     """Many passes: the gradients of the passes approach those of the cyclic fixed point."""
     w = W.small_random(180, 8, G=1, seed=3, periodic=True, n_src=3, tau=2.0)

@@ -226,7 +226,9 @@ sweep_status_t sweep_dag_export(sweep_dag_t dag, int32_t* level, int32_t* order,
  * under SWEEP_LAW_EXP) followed by the direction sums sum_d phi of every source
  * iteration ([n_scat][C_total][G] FP32) and, with periodic boundaries (nested
  * order), phi of the passes before the last ([n_pbc - 1][n_dirs][C_total][G]
- * FP32) of the last iteration. */
+ * FP32) of the last iteration; with warm_start and n_scat > 1, then the inflow
+ * the first pass started from ([n_dirs][C_total][G] FP32, for the adjoint's
+ * recomputation of that pass). */
 size_t sweep_saved_bytes(sweep_dag_t dag, int32_t G, const sweep_fwd_opts_t* opts);
 
 /* Forward sweep: n_scat source iterations, each made of n_pbc passes (vacuum:
@@ -264,9 +266,9 @@ sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, con
  * order (opts->merge) is differentiated through its single sequence of passes:
  * every pass is recomputed, then reversed with its own source gradient (the
  * loss on the last pass, the scattering source's on the others) and the later
- * pass's lambda through the periodic faces.  UNSUPPORTED: pbc_tol and
- * warm_start (a pass count or inflow that the forward decided at run time or
- * took from outside). */
+ * pass's lambda through the periodic faces.  A warm start's inflow is held
+ * fixed (no gradient flows into it).  UNSUPPORTED: pbc_tol (a pass count the
+ * forward decided at run time). */
 sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const float* emission, const sweep_fwd_opts_t* opts,
                              const void* saved, size_t saved_bytes, const float* dL_dJ,

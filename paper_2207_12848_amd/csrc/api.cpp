@@ -1321,6 +1321,13 @@ sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, i
   return SWEEP_OK;
 }
 
+// A warm-started call whose adjoint recomputes the first pass (several source
+// iterations, or the merged order) keeps the inflow it started from at the end of
+// `saved` (the forward overwrites the final phi it took it from).
+static bool warm_slot(const sweep_fwd_opts_t* opts) {
+  return opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC && opts->warm_start && opts->n_scat > 1;
+}
+
 size_t sweep_saved_bytes(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
   if (!dag_ok(d) || G < 1) return 0;
   const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
@@ -1329,7 +1336,8 @@ size_t sweep_saved_bytes(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts)
   const bool nested_periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC &&
                                !(opts->merge && n_scat > 1);
   const size_t extra = nested_periodic ? (size_t)std::max(0, opts->n_pbc - 1) * d->D : 0;
-  return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat + extra);
+  const size_t warm = warm_slot(opts) ? (size_t)d->D : 0;
+  return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat + extra + warm);
 }
 
 sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
@@ -1402,9 +1410,14 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   const sweep::ReduceArgs r = reduce_args(d, G, p, kappa, emission, J, absorbed);
   // source iterations, each made of the periodic passes (or the merged sequence),
   // then the totals
+  // the inflow of a warm start kept for the adjoint's recomputation (the last
+  // [n_dirs][C_total][G] of `saved`)
+  float* warm_saved = warm && warm_slot(opts) ? (float*)saved + (need / 4 - DCG) : nullptr;
   auto body = [&](hipStream_t st) -> sweep_status_t {
     if (warm)  // the previous call's final phi, before this call overwrites `saved`
       HIP_TRY(hipMemcpyAsync(d->phi_w.p, saved, 4 * DCG, hipMemcpyDeviceToDevice, st));
+    if (warm_saved != nullptr)
+      HIP_TRY(hipMemcpyAsync(warm_saved, d->phi_w.p, 4 * DCG, hipMemcpyDeviceToDevice, st));
     bool fresh = false;  // tsrc holds the sources run_prep just wrote
     for (int it = 0; it < n_outer; ++it) {
       const float* jprev_it = it > 0 ? ckpt(it - 1) : nullptr;
@@ -1522,9 +1535,8 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   const bool periodic = p.boundary == SWEEP_BOUNDARY_PERIODIC;
   // merged order (sec. 2.7): one sequence of max(n_pbc, n_scat) passes
   const bool merge = periodic && p.merge && p.n_scat > 1;
-  if (periodic && (p.pbc_tol > 0.0 || p.warm))
-    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint needs a fixed number of passes from zero inflow "
-                                       "(no pbc_tol, no warm_start)");
+  if (periodic && p.pbc_tol > 0.0)
+    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint needs a fixed number of passes (no pbc_tol)");
   if (periodic && !d->has_shift)
     return fail(SWEEP_ERR_INVALID_ARG, "periodic boundaries need meshes built with face_shift");
   if (!kappa || !emission || !saved || !dL_dJ || !dL_dabsorbed || !dL_dkappa || !dL_demission)
@@ -1563,6 +1575,10 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   const float* phi_final = (const float*)saved;
   auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
+  // a warm start's inflow (the forward kept it at the end of `saved` when the
+  // first pass has to be recomputed; held fixed: no gradient flows into it)
+  const float* warm_saved =
+      periodic && p.warm && warm_slot(opts) ? (const float*)saved + (need / 4 - DCG) : nullptr;
   auto xp = [&](int it, int ps) -> float* {
     const bool last = it == p.n_scat - 1;
     if (ps == P - 1) return last ? (float*)saved : d->phi_a.as<float>();
@@ -1586,6 +1602,8 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
         fresh = true;
         for (int ps = 0; ps < P; ++ps) {
           if (ps > 0) ST_TRY(run_pin(d, false, G, xp(it, ps - 1), nullptr, fresh, st));
+          else if (it == 0 && warm_saved != nullptr)
+            ST_TRY(run_pin(d, false, G, warm_saved, nullptr, fresh, st));
           ST_TRY(run_sweep(d, false, p, G, xp(it, ps), st));
         }
       }
@@ -1653,6 +1671,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
       ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
       fresh = true;
       if (ps > 0) ST_TRY(run_pin(d, false, G, xm(ps - 1), nullptr, fresh, st));
+      else if (warm_saved != nullptr) ST_TRY(run_pin(d, false, G, warm_saved, nullptr, fresh, st));
       ST_TRY(run_sweep(d, false, p, G, xm(ps), st));
       sweep::ReduceArgs q = r;
       q.phi = xm(ps);

@@ -322,7 +322,7 @@ def test_periodic_adjoint_refuses_what_it_does_not_cover():
     dag = sw.build_dag(w["meshes"], w["dirs"])
     k, e = _dev(w)
     J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic", n_pbc=3)
-    for extra in (dict(pbc_tol=0.1), dict(warm_start=True)):
-        with pytest.raises(sw.SweepError, match="UNSUPPORTED"):
-            sw.adjoint(dag, k, e, saved, torch.ones_like(k), torch.ones_like(k),
-                       boundary="periodic", n_pbc=3, **extra)
+    # the pass count of pbc_tol is decided at run time
+    with pytest.raises(sw.SweepError, match="UNSUPPORTED"):
+        sw.adjoint(dag, k, e, saved, torch.ones_like(k), torch.ones_like(k),
+                   boundary="periodic", n_pbc=3, pbc_tol=0.1)

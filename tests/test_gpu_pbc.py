@@ -83,6 +83,41 @@ def test_warm_start_matches_oracle_and_continues_the_passes():
     assert_field_close(J.cpu().numpy(), J7.cpu().numpy().astype(np.float64), name="J 3+4 vs 7")
 
 
+@pytest.mark.parametrize("merge,n_pbc,n_scat", [(False, 3, 1), (False, 2, 3), (True, 2, 3)])
+def test_warm_start_adjoint_matches_oracle(merge, n_pbc, n_scat):
+    """The adjoint of a warm-started call (the first pass's periodic inflow taken
+    from the workspace's earlier final pass, held fixed) against the oracle's;
+    with several iterations, or merged, the workspace also keeps that inflow for
+    the adjoint's recomputation of the first pass."""
+    import ctypes
+    sw = _sw()
+    G = 2
+    w = W.small_random(2000, 24, G=G, seed=98 + n_pbc, periodic=True, n_pbc=n_pbc, albedo=0.4,
+                       n_scat=n_scat, n_src=4, tau=2.0)
+    w = dict(w, merge=merge)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    opts = dict(_opts(w), merge=merge)
+    need = sw.sweep_saved_bytes(dag.handle, G, ctypes.byref(sw._fwd_opts(warm_start=True, **opts)))
+    saved = torch.empty(need // 4, dtype=torch.float32, device="cuda")
+    k0 = k * 1.3  # the earlier run: other opacities
+    sw.forward(dag, k0, e, saved=saved, **opts)
+    torch.cuda.synchronize()
+    warm = oracle.forward(dict(w, kappa=np.asarray(w["kappa"], np.float64) * 1.3), want_phi=True)["phi"]
+    J, A, tot, _ = sw.forward(dag, k, e, saved=saved, warm_start=True, **opts)
+    rng = np.random.default_rng(15)
+    C = len(w["meshes"][0]["cell_volume"])
+    gJ = rng.random((C, G)).astype(np.float32)
+    gA = rng.random((C, G)).astype(np.float32)
+    dk, de = sw.adjoint(dag, k, e, saved, torch.tensor(gJ, device="cuda"),
+                        torch.tensor(gA, device="cuda"), warm_start=True, **opts)
+    ref = oracle.forward(w, phi_init=warm)
+    assert_field_close(J.cpu().numpy(), ref["J"], name="J warm")
+    dk_ref, de_ref = oracle.adjoint(w, gJ, gA, phi_init=warm)
+    _grad_close(dk.cpu().numpy(), dk_ref)
+    _grad_close(de.cpu().numpy(), de_ref)
+
+
 def test_warm_start_needs_saved():
     sw = _sw()
     w = W.small_random(500, 8, G=1, seed=97, periodic=True)

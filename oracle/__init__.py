@@ -73,7 +73,7 @@ def _load():
         lib.orc_adjoint.restype = ctypes.c_int
         lib.orc_adjoint.argtypes = [P, ctypes.c_int32, P, ctypes.c_double, ctypes.c_int32, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
-                                    ctypes.c_int32, ctypes.c_int32, P, P, P, P, P]
+                                    ctypes.c_int32, ctypes.c_int32, P, ctypes.c_double, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -210,8 +210,9 @@ def forward(w: dict, want_phi: bool = False, want_order: bool = False, eps: floa
 def adjoint(w: dict, gJ: np.ndarray, gA: np.ndarray, eps: float = EPS_TIE, phi_init=None):
     """Gradients (dL/dkappa [C,G], dL/demission [C,G]) of a loss with dL/dJ = gJ and
     dL/dabsorbed = gA, through all source iterations and periodic passes (nested order,
-    or the merged order when w["merge"]; no convergence threshold).  phi_init: the warm
-    start of forward() (held fixed)."""
+    or the merged order when w["merge"]; with w["pbc_tol"], each iteration's passes
+    up to where the forward's stopping test ends them, the count held fixed).
+    phi_init: the warm start of forward() (held fixed)."""
     lib = _load()
     dirs = _c(w["dirs"], np.float64)
     D, G = len(dirs), int(w["G"])
@@ -236,6 +237,7 @@ def adjoint(w: dict, gJ: np.ndarray, gA: np.ndarray, eps: float = EPS_TIE, phi_i
                                _p(_c(em[sl], np.float64)), int(periodic),
                                int(w.get("n_pbc", 1)) if periodic else 1, albedo, n_scat, law,
                                int(bool(w.get("merge", False))), _p(pin),
+                               float(w.get("pbc_tol", 0.0)),
                                _p(_c(gJ[sl], np.float64)), _p(_c(gA[sl], np.float64)), _p(a), _p(b)),
                "adjoint")
         dk[sl], de[sl] = a, b

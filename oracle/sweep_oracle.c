@@ -730,8 +730,10 @@ static int adjoint_merged(const orc_mesh* m, int32_t D, const double* dirs, doub
 int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, int32_t G,
                 const double* kappa, const double* emission, int32_t periodic, int32_t n_pbc,
                 double albedo, int32_t n_scat, int32_t law, int32_t merged, const double* phi_init,
-                const double* gJ, const double* gA, double* dkappa, double* demission) {
+                double pbc_tol, const double* gJ, const double* gA, double* dkappa,
+                double* demission) {
   if (D < 1 || G < 1 || n_scat < 1 || n_pbc < 1 || albedo < 0.0 || albedo >= 1.0) return ORC_ERR_ARG;
+  if (!(pbc_tol >= 0.0) || (merged && pbc_tol > 0.0)) return ORC_ERR_ARG;
   if (law != LAW_UPWIND && law != LAW_EXP) return ORC_ERR_ARG;
   if (merged && periodic && n_scat > 1)
     return adjoint_merged(m, D, dirs, eps, G, kappa, emission, n_pbc > n_scat ? n_pbc : n_scat,
@@ -756,11 +758,16 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   double* lsum = (double*)malloc(sizeof(double) * (size_t)CG);
   double* dksum = (double*)malloc(sizeof(double) * (size_t)CG);
   int32_t* qorder = (int32_t*)malloc(sizeof(int32_t) * (size_t)D * C);
+  /* with pbc_tol: each pass's periodic inflow per direction and, summed over
+   * directions, the previous pass's (the stopping test of the forward) */
+  const int32_t tol = periodic && pbc_tol > 0.0;
+  double* jin = tol ? (double*)malloc(sizeof(double) * (size_t)DCG) : NULL;
+  double* jin_old = tol ? (double*)malloc(sizeof(double) * (size_t)CG) : NULL;
   if (!J || !Ab || !tots || !jsum || !xs || !avg || !lam || !lam_next || !dkd || !gsrc || !src ||
-      !lsum || !dksum || !qorder)
+      !lsum || !dksum || !qorder || (tol && (!jin || !jin_old)))
     return ORC_ERR_OOM;
   int status = orc_forward(m, D, dirs, eps, G, kappa, emission, periodic, P, albedo, n_scat, law,
-                           0, phi_init, 0.0, J, Ab, tots, NULL, jsum, NULL);
+                           0, phi_init, pbc_tol, J, Ab, tots, NULL, jsum, NULL);
   if (status == ORC_OK) {
     memset(dkappa, 0, sizeof(double) * (size_t)CG);
     memset(demission, 0, sizeof(double) * (size_t)CG);
@@ -779,7 +786,19 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
           const double prev = it > 0 ? jsum[(int64_t)(it - 1) * CG + i] : 0.0;
           src[i] = emission[i] / D + albedo * kappa[i] * m->cell_volume[c] * prev / D;
         }
+      /* passes of this iteration: P, or fewer where pbc_tol stopped the forward
+       * (the same test on the same values) */
+      int32_t Pit = P;
+      if (tol) memset(jin, 0, sizeof(double) * (size_t)DCG);
       for (int32_t p = 0; p < P && status == ORC_OK; ++p) {
+        if (tol && p > 0) {
+          for (int64_t i = 0; i < CG; ++i) {
+            double sum = 0.0;
+            for (int32_t d = 0; d < D; ++d) sum += jin[(int64_t)d * CG + i];
+            jin_old[i] = sum;
+          }
+          memset(jin, 0, sizeof(double) * (size_t)DCG);
+        }
 #pragma omp parallel for schedule(dynamic, 1)
         for (int32_t d = 0; d < D; ++d) {
           int32_t* cnt = (int32_t*)malloc(sizeof(int32_t) * (size_t)C);
@@ -793,7 +812,8 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
                                : (phi_init && it == 0) ? phi_init + (int64_t)d * CG : NULL;
           int st = sweep_direction(m, dirs + 3 * d, eps, G, law, kappa, src, prev,
                                    xs + (int64_t)p * DCG + (int64_t)d * CG, avg + (int64_t)d * CG,
-                                   a4, NULL, cnt, q, NULL, qorder + (int64_t)d * C);
+                                   a4, tol ? jin + (int64_t)d * CG : NULL, cnt, q, NULL,
+                                   qorder + (int64_t)d * C);
           if (st != ORC_OK) {
 #pragma omp critical
             status = st;
@@ -802,16 +822,30 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
           free(cnt);
           free(q);
         }
+        if (status == ORC_OK && tol && p > 0) {
+          double emax = 0.0;
+          for (int64_t i = 0; i < CG; ++i) {
+            double jn = 0.0;
+            for (int32_t d = 0; d < D; ++d) jn += jin[(int64_t)d * CG + i];
+            const double jo = jin_old[i];
+            const double e = jn + jo > 0.0 ? fabs(jn - jo) / (jn + jo) : 0.0;
+            if (e > emax) emax = e;
+          }
+          if (emax < pbc_tol) {
+            Pit = p + 1;
+            break;
+          }
+        }
       }
       if (status != ORC_OK) break;
       /* reverse passes */
       memset(lsum, 0, sizeof(double) * (size_t)CG);
       memset(dksum, 0, sizeof(double) * (size_t)CG);
-      for (int32_t p = P - 1; p >= 0; --p) {
+      for (int32_t p = Pit - 1; p >= 0; --p) {
 #pragma omp parallel for schedule(dynamic, 1)
         for (int32_t d = 0; d < D; ++d)
-          adjoint_direction(m, dirs + 3 * d, eps, G, law, kappa, p == P - 1 ? gsrc : NULL,
-                            p < P - 1 ? lam_next + (int64_t)d * CG : NULL,
+          adjoint_direction(m, dirs + 3 * d, eps, G, law, kappa, p == Pit - 1 ? gsrc : NULL,
+                            p < Pit - 1 ? lam_next + (int64_t)d * CG : NULL,
                             xs + (int64_t)p * DCG + (int64_t)d * CG, qorder + (int64_t)d * C,
                             lam + (int64_t)d * CG, dkd + (int64_t)d * CG);
         for (int64_t i = 0; i < CG; ++i) {
@@ -857,6 +891,8 @@ int orc_adjoint(const orc_mesh* m, int32_t D, const double* dirs, double eps, in
   free(lsum);
   free(dksum);
   free(qorder);
+  free(jin);
+  free(jin_old);
   return status;
 }
 

@@ -389,6 +389,45 @@ def test_warm_start_adjoint_central_differences(merge, n_pbc, n_scat):
         assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
 
 
+@pytest.mark.parametrize("tol,n_scat,same_as", [(0.25, 2, 6), (0.3, 3, None)])
+def test_pbc_tol_adjoint_central_differences(tol, n_scat, same_as):
+    """With pbc_tol the forward ends each iteration's passes once E < pbc_tol; the
+    adjoint runs the passes the forward ran (the counts held fixed): central
+    differences of the same forward, and with one count in every iteration the
+    adjoint of that fixed count, exactly."""
+    w = W.small_random(200, 8, G=1, seed=17, periodic=True, n_pbc=10, n_src=3, albedo=0.4,
+                       n_scat=n_scat, tau=2.0)
+    w = dict(w, pbc_tol=tol, kappa=np.asarray(w["kappa"], np.float64),
+             emission=np.asarray(w["emission"], np.float64))
+    gJ, gA = oracle.absorbed_loss_grads(w)
+    dk, de = oracle.adjoint(w, gJ, gA)
+    if same_as is not None:
+        dkf, def_ = oracle.adjoint(dict(w, pbc_tol=0.0, n_pbc=same_as), gJ, gA)
+        assert np.array_equal(dk, dkf) and np.array_equal(de, def_)
+    L = _loss(w)
+    rng = np.random.default_rng(8)
+    # ten passes carry more rounding into the loss than the three of the other
+    # pins: a step of 1e-5 keeps it below the bound (the O(h^2) truncation stays
+    # near 1e-10 relative, and no stopping decision moves)
+    h = 1e-5
+    for c in rng.choice(200, 8, replace=False):
+        k0 = w["kappa"][c, 0]
+        wp = dict(w, kappa=w["kappa"].copy())
+        wm = dict(w, kappa=w["kappa"].copy())
+        wp["kappa"][c, 0] = k0 * (1 + h)
+        wm["kappa"][c, 0] = k0 * (1 - h)
+        fd = (_loss(wp) - _loss(wm)) / (2 * h * k0)
+        assert abs(fd - dk[c, 0]) <= 1e-6 * abs(dk[c, 0]) + 1e-10 * L / k0
+    for c in w["sources"]:
+        L0 = w["emission"][c, 0]
+        wp = dict(w, emission=w["emission"].copy())
+        wm = dict(w, emission=w["emission"].copy())
+        wp["emission"][c, 0] = L0 * (1 + h)
+        wm["emission"][c, 0] = L0 * (1 - h)
+        fd = (_loss(wp) - _loss(wm)) / (2 * h * L0)
+        assert abs(fd - de[c, 0]) <= 1e-6 * abs(de[c, 0])
+
+
 def test_periodic_adjoint_converges_to_the_cyclic_adjoint():
     """Many passes: the gradients of the passes approach those of the cyclic fixed point."""
     w = W.small_random(180, 8, G=1, seed=3, periodic=True, n_src=3, tau=2.0)

@@ -228,7 +228,8 @@ sweep_status_t sweep_dag_export(sweep_dag_t dag, int32_t* level, int32_t* order,
  * order), phi of the passes before the last ([n_pbc - 1][n_dirs][C_total][G]
  * FP32) of the last iteration; with warm_start and n_scat > 1, then the inflow
  * the first pass started from ([n_dirs][C_total][G] FP32, for the adjoint's
- * recomputation of that pass). */
+ * recomputation of that pass); with pbc_tol (nested order, n_pbc > 1), then the
+ * number of passes each iteration ran ([n_scat] FP32). */
 size_t sweep_saved_bytes(sweep_dag_t dag, int32_t G, const sweep_fwd_opts_t* opts);
 
 /* Forward sweep: n_scat source iterations, each made of n_pbc passes (vacuum:
@@ -267,8 +268,10 @@ sweep_status_t sweep_forward(sweep_dag_t dag, int32_t G, const float* kappa, con
  * every pass is recomputed, then reversed with its own source gradient (the
  * loss on the last pass, the scattering source's on the others) and the later
  * pass's lambda through the periodic faces.  A warm start's inflow is held
- * fixed (no gradient flows into it).  UNSUPPORTED: pbc_tol (a pass count the
- * forward decided at run time). */
+ * fixed (no gradient flows into it).  With pbc_tol the adjoint runs the passes
+ * each iteration ran in the forward call (kept in `saved`; the counts are held
+ * fixed); it synchronises `stream` to read them and cannot be captured
+ * (use_graph: INVALID_ARG). */
 sweep_status_t sweep_adjoint(sweep_dag_t dag, int32_t G, const float* kappa,
                              const float* emission, const sweep_fwd_opts_t* opts,
                              const void* saved, size_t saved_bytes, const float* dL_dJ,

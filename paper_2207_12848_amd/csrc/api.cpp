@@ -1321,23 +1321,40 @@ sweep_status_t sweep_dag_export(sweep_dag_t d, int32_t* level, int32_t* order, i
   return SWEEP_OK;
 }
 
-// A warm-started call whose adjoint recomputes the first pass (several source
-// iterations, or the merged order) keeps the inflow it started from at the end of
-// `saved` (the forward overwrites the final phi it took it from).
-static bool warm_slot(const sweep_fwd_opts_t* opts) {
-  return opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC && opts->warm_start && opts->n_scat > 1;
+// Layout of the `saved` workspace in FP32 words: the final pass's phi, the
+// direction sums of every iteration, with periodic boundaries (nested order) the
+// passes before the last; then, for the adjoint, a warm-started call's inflow
+// when the adjoint recomputes the first pass (several source iterations, or the
+// merged order: the forward overwrites the final phi it took it from), and with
+// pbc_tol the passes each iteration ran.
+struct SavedLayout {
+  int64_t words = 0;
+  int64_t warm = -1;    // offset of the warm start's inflow, -1: none
+  int64_t counts = -1;  // offset of the pass counts ([n_scat] FP32), -1: none
+};
+
+SavedLayout saved_layout(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
+  SavedLayout L;
+  const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
+  const bool periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC;
+  const bool merge = periodic && opts->merge && n_scat > 1;
+  const int64_t CG = d->C_total * G, DCG = CG * d->D;
+  const int64_t extra = periodic && !merge ? (int64_t)std::max(0, opts->n_pbc - 1) * DCG : 0;
+  L.words = DCG + n_scat * CG + extra;
+  if (periodic && opts->warm_start && n_scat > 1) {
+    L.warm = L.words;
+    L.words += DCG;
+  }
+  if (periodic && !merge && opts->pbc_tol > 0.0 && opts->n_pbc > 1) {
+    L.counts = L.words;
+    L.words += n_scat;
+  }
+  return L;
 }
 
 size_t sweep_saved_bytes(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
   if (!dag_ok(d) || G < 1) return 0;
-  const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
-  // periodic (nested order; merge only takes effect with n_scat > 1): phi of the
-  // passes before the last, for the adjoint
-  const bool nested_periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC &&
-                               !(opts->merge && n_scat > 1);
-  const size_t extra = nested_periodic ? (size_t)std::max(0, opts->n_pbc - 1) * d->D : 0;
-  const size_t warm = warm_slot(opts) ? (size_t)d->D : 0;
-  return sizeof(float) * (size_t)d->C_total * G * ((size_t)d->D + n_scat + extra + warm);
+  return sizeof(float) * (size_t)saved_layout(d, G, opts).words;
 }
 
 sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const float* emission,
@@ -1410,9 +1427,11 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
   const sweep::ReduceArgs r = reduce_args(d, G, p, kappa, emission, J, absorbed);
   // source iterations, each made of the periodic passes (or the merged sequence),
   // then the totals
-  // the inflow of a warm start kept for the adjoint's recomputation (the last
-  // [n_dirs][C_total][G] of `saved`)
-  float* warm_saved = warm && warm_slot(opts) ? (float*)saved + (need / 4 - DCG) : nullptr;
+  // the inflow of a warm start kept for the adjoint's recomputation, and the
+  // pass counts of pbc_tol (see saved_layout)
+  const SavedLayout lay = saved_layout(d, G, opts);
+  float* warm_saved = saved && warm && lay.warm >= 0 ? (float*)saved + lay.warm : nullptr;
+  float* counts_saved = saved && tol && lay.counts >= 0 ? (float*)saved + lay.counts : nullptr;
   auto body = [&](hipStream_t st) -> sweep_status_t {
     if (warm)  // the previous call's final phi, before this call overwrites `saved`
       HIP_TRY(hipMemcpyAsync(d->phi_w.p, saved, 4 * DCG, hipMemcpyDeviceToDevice, st));
@@ -1471,6 +1490,8 @@ sweep_status_t sweep_forward(sweep_dag_t d, int32_t G, const float* kappa, const
           if (stop) {
             if (dst != phi_final)
               HIP_TRY(hipMemcpyAsync(phi_final, dst, 4 * DCG, hipMemcpyDeviceToDevice, st));
+            if (counts_saved != nullptr)
+              HIP_TRY(sweep::launch_fill_f32(counts_saved + it, 1, (float)(ps + 1), st));
             break;
           }
           prev = dst;
@@ -1535,8 +1556,11 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   const bool periodic = p.boundary == SWEEP_BOUNDARY_PERIODIC;
   // merged order (sec. 2.7): one sequence of max(n_pbc, n_scat) passes
   const bool merge = periodic && p.merge && p.n_scat > 1;
-  if (periodic && p.pbc_tol > 0.0)
-    return fail(SWEEP_ERR_UNSUPPORTED, "the adjoint needs a fixed number of passes (no pbc_tol)");
+  // pbc_tol: the forward keeps the passes each iteration ran (held fixed here)
+  const bool tol = periodic && !merge && p.pbc_tol > 0.0 && p.n_pbc > 1;
+  if (tol && p.use_graph)
+    return fail(SWEEP_ERR_INVALID_ARG, "the adjoint of pbc_tol takes its pass counts from `saved`; "
+                                       "it cannot be captured in a graph (use_graph)");
   if (periodic && !d->has_shift)
     return fail(SWEEP_ERR_INVALID_ARG, "periodic boundaries need meshes built with face_shift");
   if (!kappa || !emission || !saved || !dL_dJ || !dL_dabsorbed || !dL_dkappa || !dL_demission)
@@ -1575,13 +1599,27 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
   HIP_TRY(d->out_s.alloc(4 * (size_t)d->T * G));
   const float* phi_final = (const float*)saved;
   auto ckpt = [&](int it) -> const float* { return (const float*)saved + DCG + (int64_t)it * CG; };
-  // a warm start's inflow (the forward kept it at the end of `saved` when the
-  // first pass has to be recomputed; held fixed: no gradient flows into it)
-  const float* warm_saved =
-      periodic && p.warm && warm_slot(opts) ? (const float*)saved + (need / 4 - DCG) : nullptr;
+  // a warm start's inflow (the forward kept it in `saved` when the first pass has
+  // to be recomputed; held fixed: no gradient flows into it), and with pbc_tol
+  // the passes of every iteration
+  const SavedLayout lay = saved_layout(d, G, opts);
+  const float* warm_saved = periodic && p.warm && lay.warm >= 0 ? (const float*)saved + lay.warm : nullptr;
+  std::vector<int> passes(p.n_scat, P);
+  if (tol) {
+    std::vector<float> cf(p.n_scat);
+    HIP_TRY(hipMemcpyAsync(cf.data(), (const float*)saved + lay.counts, 4 * (size_t)p.n_scat,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int it = 0; it < p.n_scat; ++it) {
+      const int n = (int)cf[it];
+      if (!((float)n == cf[it] && n >= 1 && n <= P))
+        return fail(SWEEP_ERR_INVALID_ARG, "`saved` holds no pass counts of a forward call with pbc_tol");
+      passes[it] = n;
+    }
+  }
   auto xp = [&](int it, int ps) -> float* {
     const bool last = it == p.n_scat - 1;
-    if (ps == P - 1) return last ? (float*)saved : d->phi_a.as<float>();
+    if (ps == passes[it] - 1) return last ? (float*)saved : d->phi_a.as<float>();
     return last ? (float*)saved + DCG + (int64_t)p.n_scat * CG + (int64_t)ps * DCG
                 : d->xpass.as<float>() + (int64_t)ps * DCG;
   };
@@ -1597,24 +1635,25 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
     bool fresh = false;  // tsrc holds the sources run_prep (or the clear) just wrote
     for (int it = p.n_scat - 1; it >= 0; --it) {
       const float* jprev = it > 0 ? ckpt(it - 1) : nullptr;
+      const int Pi = passes[it];  // the passes the forward ran in this iteration
       if (it != p.n_scat - 1) {
         ST_TRY(run_prep(d, G, kappa, emission, nullptr, jprev, p.albedo, p.law, st));
         fresh = true;
-        for (int ps = 0; ps < P; ++ps) {
+        for (int ps = 0; ps < Pi; ++ps) {
           if (ps > 0) ST_TRY(run_pin(d, false, G, xp(it, ps - 1), nullptr, fresh, st));
           else if (it == 0 && warm_saved != nullptr)
             ST_TRY(run_pin(d, false, G, warm_saved, nullptr, fresh, st));
           ST_TRY(run_sweep(d, false, p, G, xp(it, ps), st));
         }
       }
-      for (int ps = P - 1; ps >= 0; --ps) {
-        const bool loss_pass = ps == P - 1;
+      for (int ps = Pi - 1; ps >= 0; --ps) {
+        const bool loss_pass = ps == Pi - 1;
         // pass ps's lambda; through its periodic outflow faces a task takes the later
         // pass's lambda at the partners (the adjoint of the forward pass's periodic
         // inflow, folded into the sources), so the two alternate between two buffers
-        float* lam_ps = ((P - 1 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>();
+        float* lam_ps = ((Pi - 1 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>();
         const float* lam_next = loss_pass ? nullptr
-                                          : (((P - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
+                                          : (((Pi - 2 - ps) & 1) ? d->lam_b.as<float>() : d->lam.as<float>());
         // the passes before the last have no source of their own: the denominators
         // of the loss pass stand and only the sources are cleared
         // (once cleared, the sources stay zero but for the periodic tasks', which
@@ -1622,7 +1661,7 @@ sweep_status_t sweep_adjoint(sweep_dag_t d, int32_t G, const float* kappa,
         if (loss_pass) {
           ST_TRY(run_prep(d, G, kappa, nullptr, d->gsrc.as<float>(), nullptr, p.albedo, p.law, st));
         } else {
-          if (ps == P - 2) {
+          if (ps == Pi - 2) {
             HIP_TRY(sweep::launch_fill_f32(d->tsrc.as<float>(), d->T * G, 0.0f, st));
             fresh = true;
           }

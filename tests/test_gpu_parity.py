@@ -316,13 +316,14 @@ def test_periodic_several_meshes_forward_and_adjoint():
     _grad_close(de.cpu().numpy(), de_ref)
 
 
-def test_periodic_adjoint_refuses_what_it_does_not_cover():
+def test_periodic_adjoint_of_pbc_tol_is_not_captured():
     sw = _sw()
     w = W.small_random(800, 8, seed=61, periodic=True, n_pbc=3)
     dag = sw.build_dag(w["meshes"], w["dirs"])
     k, e = _dev(w)
-    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic", n_pbc=3)
-    # the pass count of pbc_tol is decided at run time
-    with pytest.raises(sw.SweepError, match="UNSUPPORTED"):
+    # pbc_tol's pass counts come from the workspace: no graph capture
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, boundary="periodic", n_pbc=3,
+                                  pbc_tol=0.1)
+    with pytest.raises(sw.SweepError, match="INVALID_ARG"):
         sw.adjoint(dag, k, e, saved, torch.ones_like(k), torch.ones_like(k),
-                   boundary="periodic", n_pbc=3, pbc_tol=0.1)
+                   boundary="periodic", n_pbc=3, pbc_tol=0.1, use_graph=True)

@@ -118,6 +118,37 @@ def test_warm_start_adjoint_matches_oracle(merge, n_pbc, n_scat):
     _grad_close(de.cpu().numpy(), de_ref)
 
 
+@pytest.mark.parametrize("tol,n_scat", [(0.25, 2), (0.3, 3)])
+def test_pbc_tol_adjoint_matches_oracle(tol, n_scat):
+    """pbc_tol ends each iteration's passes once E is below it; the forward keeps
+    the pass counts in the workspace and the adjoint runs those passes (the
+    counts held fixed), against the oracle's adjoint of the same stopping."""
+    sw = _sw()
+    G = 1
+    w = W.small_random(200, 8, G=G, seed=17, periodic=True, n_pbc=10, n_src=3, albedo=0.4,
+                       n_scat=n_scat, tau=2.0)
+    w = dict(w, pbc_tol=tol)
+    dag = sw.build_dag(w["meshes"], w["dirs"])
+    k, e = _dev(w)
+    opts = dict(_opts(w), pbc_tol=tol)
+    J, A, tot, saved = sw.forward(dag, k, e, save_for_adjoint=True, **opts)
+    ref = oracle.forward(w)
+    assert_field_close(J.cpu().numpy(), ref["J"], name="J")  # the same passes ran
+    rng = np.random.default_rng(16)
+    C = len(w["meshes"][0]["cell_volume"])
+    gJ = rng.random((C, G)).astype(np.float32)
+    gA = rng.random((C, G)).astype(np.float32)
+    dk, de = sw.adjoint(dag, k, e, saved, torch.tensor(gJ, device="cuda"),
+                        torch.tensor(gA, device="cuda"), **opts)
+    dk_ref, de_ref = oracle.adjoint(w, gJ, gA)
+    _grad_close(dk.cpu().numpy(), dk_ref)
+    _grad_close(de.cpu().numpy(), de_ref)
+    # a workspace without the counts (a call without pbc_tol) is refused
+    _, _, _, saved0 = sw.forward(dag, k, e, save_for_adjoint=True, **_opts(w))
+    with pytest.raises(sw.SweepError, match="INVALID_ARG"):
+        sw.adjoint(dag, k, e, saved0, torch.ones_like(k), torch.ones_like(k), **opts)
+
+
 def test_warm_start_needs_saved():
     sw = _sw()
     w = W.small_random(500, 8, G=1, seed=97, periodic=True)

@@ -1099,6 +1099,8 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
     HIP_TRY(sweep::launch_kahn(a, lds_cnt, max_cells, s));
   }
   // (no synchronisation here: the depths and the cycle flag are read once, at the end)
+  // the inverse schedule of cells that a cyclic graph leaves out stays -1
+  HIP_TRY(sweep::launch_fill_i32(a.inv, T, -1, s));
   HIP_TRY(sweep::launch_sort_levels(a, s));
   HIP_TRY(sweep::launch_gather_len(a, n_blocks, s));
   // row lengths in schedule order -> row pointers
@@ -1333,7 +1335,7 @@ struct SavedLayout {
   int64_t counts = -1;  // offset of the pass counts ([n_scat] FP32), -1: none
 };
 
-SavedLayout saved_layout(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
+static SavedLayout saved_layout(sweep_dag_t d, int32_t G, const sweep_fwd_opts_t* opts) {
   SavedLayout L;
   const int n_scat = opts ? std::max(1, opts->n_scat) : 1;
   const bool periodic = opts && opts->boundary == SWEEP_BOUNDARY_PERIODIC;

@@ -156,8 +156,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
       if (cell && d < a.D) {
         const double ox = a.dirs[3 * d], oy = a.dirs[3 * d + 1], oz = a.dirs[3 * d + 2];
         const int64_t t = a.units[m * a.D + d].task_base + c;
-        // this direction's signed weights of the tile's faces
-        float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)d * M.n_faces + T.f0;
         int32_t* row = STAGE ? srow + threadIdx.x * W : a.dnw + t * W;  // LDS: [dj][ci][W]
         int32_t* ovf = nullptr;
         int nup = 0, ndn = 0;
@@ -168,9 +166,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
           const int nb = nbr[f];
           const bool periodic = shift != nullptr && shift[f] != 0;
           const float w = face_w(area[f], sv);
-          float ws = __int_as_float(0x7fc00000);  // neither inflow nor outflow
           if (sv > a.eps) {
-            ws = w;
             ap += w;
             if (nb < 0) wall += w;
             else if (periodic) {
@@ -192,11 +188,9 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
               }
               ++ndn;
             }
-          } else if (sv < -a.eps) {
-            ws = -w;
-            if (nb >= 0 && !periodic) ++nup;
+          } else if (sv < -a.eps && nb >= 0 && !periodic) {
+            ++nup;
           }
-          wf[f] = ws;
         }
         if (ovf != nullptr) ovf[0] = ndn - (W - 1);
         if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
@@ -210,6 +204,19 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
         mo = max(mo, ndn);
         eu += (unsigned long long)nup;
         ed += (unsigned long long)ndn;
+      }
+      // the signed weight of every face of the tile for these directions (NaN:
+      // neither inflow nor outflow), consecutive threads on consecutive faces
+      const int nft = (int)T.fp[nc];
+      for (int i = threadIdx.x; i < kDirs * nft; i += kCountThreads) {
+        const int j = i / nft, f = i - j * nft;
+        const int dd = d0 + j;
+        if (dd < a.D) {
+          const double sv = orient(a.dirs[3 * dd], a.dirs[3 * dd + 1], a.dirs[3 * dd + 2], nrm + 3 * f);
+          const float w = face_w(area[f], sv);
+          a.wface[(int64_t)a.D * M.face_off + (int64_t)dd * M.n_faces + T.f0 + f] =
+              sv > a.eps ? w : (sv < -a.eps ? -w : __int_as_float(0x7fc00000));
+        }
       }
       if (STAGE) {
         __syncthreads();
@@ -885,14 +892,17 @@ __global__ void k_face_codes(MeshDev M, int32_t* fcode) {
   fcode[f] = nb < 0 ? -1 : (periodic ? -(nb + 2) : nb);
 }
 
-// Rows of the upwind and downwind lists, in schedule order: each wavefront
-// takes 64 consecutive schedule slots of one unit.  Every lane first loads one
-// slot's task (cell, row pointers, face range); then, 16 slots per round, 16
-// lanes share one task, one face per lane, 16 faces at a time.  Each face's
-// neighbour code and signed weight (from k_count) give its class; a ballot
-// over the 16 lanes gives every entry its place in the row (rows keep the
-// cell's face order).  Consecutive slots write consecutive rows, and the
-// neighbours' schedule positions come from the unit's inverse schedule.
+// Rows of the upwind and downwind lists, which lie in schedule order; the
+// tasks are visited in cell order: each wavefront takes 64 consecutive cells
+// of one unit, so that the face records it reads are contiguous and the
+// neighbours' schedule positions (from the unit's inverse schedule) are
+// gathered from a few lines.  Every lane first loads one cell's task (schedule
+// slot, row pointers, face range); then, 16 cells per round, 16 lanes share
+// one task, one face per lane, 16 faces at a time.  Each face's neighbour code
+// and signed weight (from k_count) give its class; a ballot over the 16 lanes
+// gives every entry its place in the row (rows keep the cell's face order).
+// Cells of one level that are consecutive in id have consecutive slots, so
+// their rows are written next to each other.
 constexpr int kFillBlock = 256;
 
 // Five wavefronts per SIMD: the register budget (at most 102 VGPRs) still
@@ -911,12 +921,13 @@ __global__ __launch_bounds__(kFillBlock) __attribute__((amdgpu_waves_per_eu(5)))
   const float* wf = a.wface + (int64_t)a.D * M.face_off + (int64_t)U.dir * M.n_faces;
   const int kw = (blk - a.blk_base[u]) * kFillBlock + (threadIdx.x & ~63);
   if (kw >= U.n_cells) return;
-  // lane L: the task of slot kw + L (slots past the scheduled tasks of a cyclic
-  // graph, reported after the build, get no row)
-  const int k = kw + lane;
-  const bool kv = k < a.lp[U.lp_base + a.depth[u]];
+  // lane L: the task of cell kw + L (cells left out of the schedule of a cyclic
+  // graph, reported after the build, have slot -1 and get no row)
+  const int cl = kw + lane;
+  const int k = cl < U.n_cells ? inv[cl] : -1;
+  const bool kv = k >= 0 && k < a.lp[U.lp_base + a.depth[u]];
   const int kc = kv ? k : 0;
-  const int c = kv ? a.sched[tb + kc] : 0;
+  const int c = kv ? cl : 0;
   const int64_t eu0 = a.up_ptr[tb + kc];
   const int64_t ed0 = a.dn_ptr[tb + kc];
   const int64_t f0 = M.face_ptr[c];

@@ -964,7 +964,7 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
       fo += meshes[m].n_half_faces;
     }
   }
-  Buf cblk_mesh_d, cblk_c0_d, dnw, stats_d, meshes_d, dirs_d, rowlen_up, rowlen_dn, cnt, inv, depth_d, err_d, len_up, len_dn, scan_tmp;
+  Buf cblk_mesh_d, cblk_c0_d, dnw, stats_d, meshes_d, dirs_d, rowlen_dn, cnt, inv, depth_d, err_d, len_up, len_dn, scan_tmp;
   HIP_TRY(meshes_d.alloc(sizeof(sweep::MeshDev) * n_meshes));
   HIP_TRY(dirs_d.alloc(sizeof(double) * 3 * n_dirs));
   HIP_TRY(D->blk_base.alloc(sizeof(int32_t) * (n_units + 1)));
@@ -979,7 +979,6 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   HIP_TRY(hipMemcpyAsync(D->blk_base.p, blk_base.data(), sizeof(int32_t) * (n_units + 1), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(D->units_d.p, D->units.data(), sizeof(Unit) * n_units, hipMemcpyHostToDevice, s));
   HIP_TRY(D->indeg.alloc(4 * T));
-  HIP_TRY(rowlen_up.alloc(4 * T));
   HIP_TRY(rowlen_dn.alloc(4 * T));
   HIP_TRY(D->aperp.alloc(4 * T));
   HIP_TRY(D->aperp_s.alloc(4 * T));
@@ -1021,7 +1020,6 @@ sweep_status_t sweep_build_dag(const sweep_mesh_t* meshes, int32_t n_meshes, con
   a.n_aligned = n_aligned;
   a.blk_base = D->blk_base.as<int32_t>();
   a.indeg = D->indeg.as<int32_t>();
-  a.rowlen_up = rowlen_up.as<int32_t>();
   a.rowlen_dn = rowlen_dn.as<int32_t>();
   a.aperp = D->aperp.as<float>();
   a.aperp_s = D->aperp_s.as<float>();

@@ -196,7 +196,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(DagBuildArgs a) {
         if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
         for (int q = ndn; q < W; ++q) row[q] = -1;
         a.indeg[t] = nup;
-        a.rowlen_up[t] = nup;
         a.rowlen_dn[t] = ndn;
         a.aperp[t] = (float)ap;
         a.bnd[t] = make_float2((float)wall, (float)per);
@@ -404,7 +403,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count_in(DagBuildArgs a) {
       const int64_t t = a.units[m * a.D + d].task_base + c;
       if (nup >= 15) a.big[atomicAdd(a.big_top, 1)] = t;  // counter too large for 4 bits
       a.indeg[t] = nup;
-      a.rowlen_up[t] = nup;
       mi = max(mi, nup);
       eu += (unsigned long long)nup;
     }
@@ -526,29 +524,41 @@ __global__ __launch_bounds__(kKahnBlock(NCH)) void k_kahn(DagBuildArgs a) {
     }
   }
   __syncthreads();
-  // level 0: cells without upwind dependencies
-  for (int c0 = 0; c0 < C; c0 += nthr) {
-    const int c = c0 + tid;
-    bool ready = false;
-    if (c < C) {
-      if (LDSCNT) {
-        ready = ((nib[c >> 3] >> (4 * (c & 7))) & 15u) == 0u;
-      } else {
-        const int n = a.indeg[tb + c];
-        cnt8[c] = (uint8_t)n;  // below 256 (the host checks the largest in-degree)
-        ready = n == 0;
+  // level 0: cells without upwind dependencies (global counters: the in-degrees
+  // of kInitBatch cells per thread are loaded together, then stored as bytes)
+  constexpr int kInitBatch = LDSCNT ? 1 : 8;
+  for (int c0 = 0; c0 < C; c0 += kInitBatch * nthr) {
+    int n[kInitBatch];
+    if (!LDSCNT) {
+#pragma unroll
+      for (int j = 0; j < kInitBatch; ++j) {
+        const int c = c0 + j * nthr + tid;
+        n[j] = c < C ? a.indeg[tb + c] : -1;
       }
     }
-    const unsigned long long m = __ballot(ready);
-    if (m != 0ull) {
-      const int leader = __ffsll((long long)m) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(&s_cnt[0], __popcll(m));
-      base = __shfl(base, leader);
-      if (ready) {
-        const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
-        if (slot < kFrontierCap) fr[0][slot] = c;
-        else spill[slot] = c;
+#pragma unroll
+    for (int j = 0; j < kInitBatch; ++j) {
+      const int c = c0 + j * nthr + tid;
+      bool ready = false;
+      if (c < C) {
+        if (LDSCNT) {
+          ready = ((nib[c >> 3] >> (4 * (c & 7))) & 15u) == 0u;
+        } else {
+          cnt8[c] = (uint8_t)n[j];  // below 256 (the host checks the largest in-degree)
+          ready = n[j] == 0;
+        }
+      }
+      const unsigned long long m = __ballot(ready);
+      if (m != 0ull) {
+        const int leader = __ffsll((long long)m) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&s_cnt[0], __popcll(m));
+        base = __shfl(base, leader);
+        if (ready) {
+          const int slot = base + __popcll(m & ((1ull << lane) - 1ull));
+          if (slot < kFrontierCap) fr[0][slot] = c;
+          else spill[slot] = c;
+        }
       }
     }
   }
@@ -841,7 +851,7 @@ __global__ __launch_bounds__(kCountBlock) void k_gather_len(DagBuildArgs a) {
   // slots past the scheduled tasks (a cyclic graph, reported after the build) get no row
   const int scheduled = a.lp[U.lp_base + a.depth[u]];
   const int c = k < scheduled ? a.sched[t] : -1;
-  a.len_up[t] = c >= 0 ? a.rowlen_up[U.task_base + c] : 0;
+  a.len_up[t] = c >= 0 ? a.indeg[U.task_base + c] : 0;
   a.len_dn[t] = c >= 0 ? a.rowlen_dn[U.task_base + c] : 0;
   a.aperp_s[t] = c >= 0 ? a.aperp[U.task_base + c] : 0.0f;
   a.vol_s[t] = c >= 0 ? (float)a.meshes[U.mesh].cell_volume[c] : 0.0f;

@@ -69,9 +69,8 @@ struct DagBuildArgs {
   int64_t dn_sentinel;       // offset in dnw of a row of -1 (4 * kRowChunks entries)
   int32_t* stats;            // [0] max in-degree, [1] max out-degree (atomic max)
   unsigned long long* ent_tot;  // [0] upwind-row entries, [1] downwind-row entries (all tasks)
-  // per task, cell order within the unit
+  // per task, cell order within the unit (the upwind row's length is indeg)
   int32_t* indeg;
-  int32_t* rowlen_up;
   int32_t* rowlen_dn;
   float* aperp;
   float* aperp_s;  // the same per task in schedule order (written by k_gather_len)

@@ -755,21 +755,30 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
     const int64_t ci = (int64_t)U.cell_off + a.sched[t];
     const double V = (double)a.vol_s[t];
     const double ap = (double)a.aperp_s[t];
-    for (int g = 0; g < G; ++g) {
-      const float2 r = a.crec[ci * G + g];
+    // denominator and source of one group from the cell's (kappa, source) record
+    auto task = [&](float2 r, float& den_out, float& src_out) {
       const double kap = (double)r.x;
-      const bool exp_law = EXP_LAW;
-      const double den = exp_law ? exp_den(ap, kap * V) : ap + kap * V;
+      const double den = EXP_LAW ? exp_den(ap, kap * V) : ap + kap * V;
       double s = (double)r.y;
-      if (exp_law && a.emission == nullptr) s *= exp_r(ap, kap * V);
+      if (EXP_LAW && a.emission == nullptr) s *= exp_r(ap, kap * V);
       if (!(den > 0.0 && den <= DBL_MAX)) bad |= kErrCell;
-      if (stage) {
-        sden[threadIdx.x * G + g] = (float)den;
-        ssrc[threadIdx.x * G + g] = (float)s;
-      } else {
-        a.tden[t * G + g] = (float)den;
-        a.tsrc[t * G + g] = (float)s;
-      }
+      den_out = (float)den;
+      src_out = (float)s;
+    };
+    if (G == 1) {
+      task(a.crec[ci], sden[threadIdx.x], ssrc[threadIdx.x]);
+    } else if (stage) {
+      // every group's record is loaded before the first is used: unconditional
+      // loads (groups past G reread the last one), and the staged results go to
+      // LDS, so no store orders them
+      float2 r[kPrepStageG];
+#pragma unroll
+      for (int g = 0; g < kPrepStageG; ++g) r[g] = a.crec[ci * G + min(g, G - 1)];
+#pragma unroll
+      for (int g = 0; g < kPrepStageG; ++g)
+        if (g < G) task(r[g], sden[threadIdx.x * G + g], ssrc[threadIdx.x * G + g]);
+    } else {
+      for (int g = 0; g < G; ++g) task(a.crec[ci * G + g], a.tden[t * G + g], a.tsrc[t * G + g]);
     }
   }
   if (stage) {
